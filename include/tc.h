@@ -1,0 +1,183 @@
+/*
+ * tc.h - exact triangle counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libtc.so. It implements the data-parallel hot path of Tom and
+ * Karypis, "A 2D Parallel Triangle Counting Algorithm for Distributed-Memory
+ * Architectures" (ICPP 2019): a simple undirected graph is reordered by
+ * non-decreasing degree, split into its upper triangular part U, and for every
+ * nonzero (i, j) of U the map-based intersection of Section 3.1 counts
+ * c(i, j) = |Adj>(i) & Adj>(j)| (Eq. 1), reduced to the exact total of Eq. 2.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers on the current HIP device (for
+ *    example the data_ptr() of a torch tensor on a ROCm device). Host pointers
+ *    have no prefix.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued on it and outputs are written asynchronously; the caller
+ *    synchronises the stream before reading them, and keeps inputs alive until
+ *    then. Only tc_preprocess and the batch/server set-up calls synchronise.
+ *  - No C++ exception crosses the ABI. On failure an entry point returns a
+ *    non-zero tc_status, leaves its outputs unspecified, allocates nothing
+ *    that outlives the call, and tc_last_error() describes the failure (per
+ *    host thread).
+ *  - A tc_graph is immutable after tc_preprocess, so calls on one graph from
+ *    several streams or threads may run concurrently.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TC_OK = 0,
+  TC_EINVAL = 1,     /* bad argument (null pointer, n <= 0, id out of [0, n), bad mode) */
+  TC_ENOMEM = 2,     /* device or host allocation failed */
+  TC_EDEVICE = 3,    /* a HIP runtime call failed */
+  TC_EOVERFLOW = 4,  /* a size exceeds the library's index widths (see tc_preprocess) */
+  TC_EBUSY = 5,      /* server: no capacity right now */
+  TC_ECANCELED = 6   /* server: request was cancelled */
+} tc_status;
+
+/* Opaque, device-resident preprocessed graph. */
+typedef struct tc_graph tc_graph;
+
+/* Per-edge support modes (tc_edge_support). */
+enum {
+  TC_SUPPORT_FULL = 0,     /* triangles containing the edge; sums to 3T */
+  TC_SUPPORT_ORIENTED = 1  /* c(i, j) of Eq. 1 for the nonzero (i, j) of U; sums to T */
+};
+
+/* Summary of a preprocessed graph (tc_graph_info). */
+typedef struct {
+  int64_t n;               /* vertices */
+  int64_t m_raw;           /* input pairs */
+  int64_t m;               /* edges of the simple graph = nonzeros of U */
+  int64_t wedges_plus;     /* W+ = sum over rows a of C(|U_a|, 2) */
+  int64_t probes;          /* hash lookups tc_count performs: W+ without the
+                              intersections whose hashed row is empty */
+  int64_t tasks;           /* nonzeros (i, j) of U with at least one probe */
+  int64_t max_out_degree;  /* max |U_a| */
+  int64_t device_bytes;    /* device memory held by the handle */
+} tc_info;
+
+/*
+ * tc_preprocess - build the device-resident graph (Section 5.3 and Section 2).
+ *
+ * Input: m_raw pairs (d_src[e], d_dst[e]), int32 vertex ids in [0, n), device
+ * memory owned by the caller. Duplicates, both orientations and self loops are
+ * legal: the pairs are reduced to the simple undirected graph (Section 6.1).
+ * Vertices are ranked by non-decreasing degree, ties by original id (the
+ * counting-sort relabelling of Section 5.3 with a fixed tie order); each edge
+ * {u, v} becomes the nonzero (min rank, max rank) of U (the upper/lower split
+ * of Section 5.3 by global position); rows of U are sorted ascending (required
+ * by Section 5.2, "Eliminating unnecessary intersection operations").
+ *
+ * Output: *out receives a new handle (free with tc_graph_free). The handle
+ * owns its device memory. The call synchronises `stream` once it has read
+ * back the sizes.
+ *
+ * Errors: TC_EINVAL for null pointers, n < 1, m_raw < 0 or an id outside
+ * [0, n) (no handle is returned); TC_EOVERFLOW if the simple graph has 2^31 or
+ * more edges; TC_ENOMEM / TC_EDEVICE on allocation or runtime failure.
+ */
+tc_status tc_preprocess(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int32_t n,
+                        void* stream, tc_graph** out);
+
+/* tc_graph_info - sizes and work counts of a handle (host struct *out). */
+tc_status tc_graph_info(const tc_graph* g, tc_info* out);
+
+/*
+ * tc_graph_export - copy U and the relabelling to caller buffers:
+ * d_row_ptr int64[n + 1], d_col int32[m] (rows sorted ascending, every entry
+ * greater than its row), d_perm int32[n] with d_perm[original id] = rank.
+ * Any of the three may be NULL to skip it. Asynchronous on `stream`.
+ */
+tc_status tc_graph_export(const tc_graph* g, int64_t* d_row_ptr, int32_t* d_col, int32_t* d_perm,
+                          void* stream);
+
+/*
+ * tc_count - exact number of triangles, T of Eq. 2, written to the device
+ * int64 *d_count. Runs the <j,i,k> map-based intersection of Section 3.1: for
+ * every row j of U that some task needs, U_j is hashed in LDS (direct
+ * low-bit addressing with linear probing, Section 5.2 "Modifying the hashing
+ * routine"), and for each nonzero (i, j) the entries of U_i after j are looked
+ * up in it. Asynchronous on `stream`; allocates nothing.
+ */
+tc_status tc_count(const tc_graph* g, int64_t* d_count, void* stream);
+
+/*
+ * tc_edge_support - per-edge triangle values for the m nonzeros of U, in the
+ * order of tc_graph_export's d_col (row-major). mode TC_SUPPORT_FULL: the
+ * number of triangles containing the edge (sum = 3T); TC_SUPPORT_ORIENTED:
+ * c(i, j) of Eq. 1 (sum = T). d_support is int32[m] (caller-owned device
+ * memory, overwritten); d_count (nullable) receives T. Asynchronous; allocates
+ * nothing. TC_EINVAL for an unknown mode or a null d_support with m > 0.
+ */
+tc_status tc_edge_support(const tc_graph* g, int mode, int32_t* d_support, int64_t* d_count,
+                          void* stream);
+
+/*
+ * tc_block_count - one rank's share of the 2D cyclic decomposition of
+ * Section 5.1 at its real shape, for a q x q grid (1 <= q <= 64), rank (x, y)
+ * with 0 <= x, y < q. Under the C[L] task convention of Section 5.1 the rank
+ * owns the tasks (i, j) of U with j % q == x and i % q == y; it hashes the rows
+ * j == x (mod q) and probes the rows i == y (mod q), stored in a rank-local CSR
+ * indexed by v / q (the transformed index of Section 5.1) with a list of
+ * non-empty rows (the doubly sparse traversal of Section 5.2).
+ * d_count (int64) receives the triangles its tasks close; d_per_shift
+ * (nullable, int64[q]) receives, for each shift z of Eq. 5, the part whose
+ * closing vertex k has k % q == (x + y + z) % q. The rank-local structures are
+ * built on `stream` in memory the call allocates and frees (the call
+ * synchronises `stream`).
+ */
+tc_status tc_block_count(const tc_graph* g, int32_t q, int32_t x, int32_t y, int64_t* d_count,
+                         int64_t* d_per_shift, void* stream);
+
+/* ---- batched counting ---------------------------------------------------- */
+
+/* Opaque plan for counting a fixed set of graphs in one persistent launch. */
+typedef struct tc_batch tc_batch;
+
+/*
+ * tc_batch_create - plan one persistent launch over `num_graphs` handles
+ * (host array of handles; graphs may repeat). The work items of all graphs
+ * are merged into one device queue in decreasing size order (largest first).
+ * tuning_json (nullable) overrides the schedule, e.g.
+ * {"waves_per_block": 4, "blocks_per_cu": 8}. The handles must outlive the
+ * plan. Synchronises `stream`.
+ */
+tc_status tc_batch_create(const tc_graph* const* graphs, int32_t num_graphs,
+                          const char* tuning_json, void* stream, tc_batch** out);
+
+/*
+ * tc_batch_count - per-graph exact counts into the device int64[num_graphs]
+ * d_counts (same order as the handles). One kernel launch plus one small
+ * clearing kernel; safe to capture in a HIP graph. Calls that overlap on one
+ * plan race (the plan holds the queue counter).
+ */
+tc_status tc_batch_count(tc_batch* plan, int64_t* d_counts, void* stream);
+
+void tc_batch_free(tc_batch* plan);
+
+/* One-shot convenience: create a plan, count, free it (synchronises). */
+tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
+                           const char* tuning_json, void* stream);
+
+/* ---- misc ----------------------------------------------------------------- */
+
+void tc_graph_free(tc_graph* g);
+const char* tc_status_string(tc_status s);
+/* Message of the last failure on this host thread ("" if none). */
+const char* tc_last_error(void);
+/* Library version string. */
+const char* tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

@@ -1,0 +1,290 @@
+"""Exact triangle counting on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libtc.so`` (the C ABI declared in ``include/tc.h``).
+Every step of the path runs in the library's HIP kernels; this module only
+marshals arguments: torch tensors on a ROCm device provide the memory
+(``data_ptr()``) and ``torch.cuda`` streams the ordering. There is no CPU
+fallback: importing the package without a built ``libtc.so`` raises.
+
+Functions carry the C names: tc_preprocess, tc_graph_info, tc_graph_export,
+tc_count, tc_edge_support, tc_block_count, tc_batch_create, tc_batch_count,
+tc_batch_free, tc_count_batched, tc_graph_free.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
+    "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
+    "tc_count_batched", "tc_graph_free", "TC_SUPPORT_FULL", "TC_SUPPORT_ORIENTED", "library_path",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libtc.so")
+
+TC_OK, TC_EINVAL, TC_ENOMEM, TC_EDEVICE, TC_EOVERFLOW, TC_EBUSY, TC_ECANCELED = range(7)
+TC_SUPPORT_FULL = 0
+TC_SUPPORT_ORIENTED = 1
+
+if not os.path.exists(library_path):
+    raise ImportError(
+        "libtc.so is not built at %s; run `python paper_1907_09575_amd/build.py` "
+        "(or __graft_entry__.build())" % library_path)
+
+_lib = ctypes.CDLL(library_path)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "m_raw", "m", "wedges_plus", "probes", "tasks", "max_out_degree", "device_bytes")]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("tc_preprocess", [_P, _P, _I64, _I32, _P, ctypes.POINTER(_P)])
+_sig("tc_graph_info", [_P, ctypes.POINTER(_Info)])
+_sig("tc_graph_export", [_P, _P, _P, _P, _P])
+_sig("tc_count", [_P, _P, _P])
+_sig("tc_edge_support", [_P, ctypes.c_int, _P, _P, _P])
+_sig("tc_block_count", [_P, _I32, _I32, _I32, _P, _P, _P])
+_sig("tc_batch_create", [ctypes.POINTER(_P), _I32, ctypes.c_char_p, _P, ctypes.POINTER(_P)])
+_sig("tc_batch_count", [_P, _P, _P])
+_sig("tc_batch_free", [_P], None)
+_sig("tc_count_batched", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, _P])
+_sig("tc_graph_free", [_P], None)
+_sig("tc_status_string", [ctypes.c_int], ctypes.c_char_p)
+_sig("tc_last_error", [], ctypes.c_char_p)
+_sig("tc_version", [], ctypes.c_char_p)
+
+
+class TCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.tc_last_error().decode() or _lib.tc_status_string(status).decode()
+        super().__init__("%s failed: %s [%s]" % (where, msg, _lib.tc_status_string(status).decode()))
+
+
+def _check(status: int, where: str):
+    if status != TC_OK:
+        raise TCError(status, where)
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev_ptr(t: torch.Tensor | None, dtype, what: str, numel: int | None = None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s needs %d elements, has %d" % (what, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return _lib.tc_version().decode()
+
+
+class Graph:
+    """Owning wrapper of a tc_graph handle (freed with the object)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        self._info = None
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph already freed")
+        return self._h
+
+    def info(self) -> dict:
+        if self._info is None:
+            self._info = tc_graph_info(self)
+        return self._info
+
+    @property
+    def n(self) -> int:
+        return self.info()["n"]
+
+    @property
+    def m(self) -> int:
+        return self.info()["m"]
+
+    def free(self):
+        if self._h:
+            _lib.tc_graph_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def tc_preprocess(src: torch.Tensor, dst: torch.Tensor, n: int, stream=None) -> Graph:
+    """Build the device-resident graph from int32 device edge arrays."""
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    out = ctypes.c_void_p()
+    _check(_lib.tc_preprocess(_dev_ptr(src, torch.int32, "src"), _dev_ptr(dst, torch.int32, "dst"),
+                                   src.numel(), int(n), _stream(stream), ctypes.byref(out)),
+                "tc_preprocess")
+    return Graph(out.value)
+
+
+def tc_graph_info(g: Graph) -> dict:
+    info = _Info()
+    _check(_lib.tc_graph_info(g.handle, ctypes.byref(info)), "tc_graph_info")
+    return {name: int(getattr(info, name)) for name, _ in _Info._fields_}
+
+
+def tc_graph_export(g: Graph, row_ptr=None, col=None, perm=None, stream=None):
+    """Copy U and the relabelling into device tensors (allocated if None)."""
+    info = g.info()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if row_ptr is None:
+        row_ptr = torch.empty(info["n"] + 1, dtype=torch.int64, device=dev)
+    if col is None:
+        col = torch.empty(max(info["m"], 1), dtype=torch.int32, device=dev)
+    if perm is None:
+        perm = torch.empty(info["n"], dtype=torch.int32, device=dev)
+    _check(_lib.tc_graph_export(g.handle, _dev_ptr(row_ptr, torch.int64, "row_ptr", info["n"] + 1),
+                                _dev_ptr(col, torch.int32, "col", info["m"]),
+                                _dev_ptr(perm, torch.int32, "perm", info["n"]), _stream(stream)),
+           "tc_graph_export")
+    return row_ptr, col[:info["m"]], perm
+
+
+def _count_out(out):
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=torch.device("cuda", torch.cuda.current_device()))
+    return out
+
+
+def tc_count(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Triangle count into a 1-element int64 device tensor (asynchronous)."""
+    out = _count_out(out)
+    _check(_lib.tc_count(g.handle, _dev_ptr(out, torch.int64, "count", 1), _stream(stream)), "tc_count")
+    return out
+
+
+def tc_edge_support(g: Graph, mode: int = TC_SUPPORT_FULL, support: torch.Tensor | None = None,
+                    count: torch.Tensor | None = None, stream=None):
+    """Per-edge support (int32, U order) and optionally the total."""
+    m = g.info()["m"]
+    if support is None:
+        support = torch.empty(max(m, 1), dtype=torch.int32,
+                              device=torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.tc_edge_support(g.handle, int(mode), _dev_ptr(support, torch.int32, "support", m),
+                                _dev_ptr(count, torch.int64, "count", 1), _stream(stream)),
+           "tc_edge_support")
+    return support[:m], count
+
+
+def tc_block_count(g: Graph, q: int, x: int, y: int, count: torch.Tensor | None = None,
+                   per_shift: torch.Tensor | None = None, stream=None):
+    """One rank's block of the q x q cyclic decomposition (count, per-shift)."""
+    count = _count_out(count)
+    _check(_lib.tc_block_count(g.handle, int(q), int(x), int(y), _dev_ptr(count, torch.int64, "count", 1),
+                               _dev_ptr(per_shift, torch.int64, "per_shift", int(q)), _stream(stream)),
+           "tc_block_count")
+    return count, per_shift
+
+
+class Batch:
+    """Owning wrapper of a tc_batch plan; keeps its graphs alive."""
+
+    def __init__(self, handle: int, graphs):
+        self._h = ctypes.c_void_p(handle)
+        self.graphs = list(graphs)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            _lib.tc_batch_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _handles(graphs):
+    arr = (ctypes.c_void_p * max(len(graphs), 1))()
+    for i, g in enumerate(graphs):
+        arr[i] = g.handle.value
+    return arr
+
+
+def _tuning(tuning):
+    if tuning is None:
+        return None
+    if isinstance(tuning, (bytes, str)):
+        return tuning.encode() if isinstance(tuning, str) else tuning
+    import json
+    return json.dumps(tuning).encode()
+
+
+def tc_batch_create(graphs, tuning=None, stream=None) -> Batch:
+    out = ctypes.c_void_p()
+    _check(_lib.tc_batch_create(_handles(graphs), len(graphs), _tuning(tuning), _stream(stream),
+                                ctypes.byref(out)), "tc_batch_create")
+    return Batch(out.value, graphs)
+
+
+def tc_batch_count(plan: Batch, counts: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if counts is None:
+        counts = torch.empty(max(len(plan.graphs), 1), dtype=torch.int64,
+                             device=torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.tc_batch_count(plan.handle, _dev_ptr(counts, torch.int64, "counts", len(plan.graphs)),
+                               _stream(stream)), "tc_batch_count")
+    return counts
+
+
+def tc_batch_free(plan: Batch):
+    plan.free()
+
+
+def tc_count_batched(graphs, counts: torch.Tensor | None = None, tuning=None, stream=None):
+    if counts is None:
+        counts = torch.empty(max(len(graphs), 1), dtype=torch.int64,
+                             device=torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.tc_count_batched(_handles(graphs), len(graphs),
+                                 _dev_ptr(counts, torch.int64, "counts", len(graphs)), _tuning(tuning),
+                                 _stream(stream)), "tc_count_batched")
+    return counts
+
+
+def tc_graph_free(g: Graph):
+    g.free()

@@ -1,0 +1,354 @@
+// tc_count.hip - the map-based intersection of Section 3.1 (<j,i,k> order) and
+// its reductions: exact triangle count (Eq. 2) and per-edge support (Eq. 1).
+//
+// Work unit. For a hashed row b, a task is a nonzero (a, b) of U (a in L_b,
+// the column of b); it probes the entries of U_a after b - all of them exceed
+// b, which is Eq. 1's k > j bound - against a hash of U_b. A hit is a
+// triangle a < b < k. The probes of all tasks of one b form one contiguous
+// range of the global probe index space (tasks grouped by b, prefix-summed by
+// preprocessing).
+//
+// Hash table (Section 5.2, "Modifying the hashing routine"): U_b in LDS,
+// 2^l >= 2 |U_b| slots, slot = k & (2^l - 1) (the direct bitwise AND), linear
+// probing on collision. The build records the longest displacement D; a
+// lookup stops at a match, an empty slot or after D + 1 slots, so a
+// collision-free table (D = 0) costs one LDS read per probe and exactness
+// never depends on the absence of collisions.
+//
+// Probe loop (one wave, flattened over tasks). A wave walks a range of
+// probes 64 at a time, lane l taking probe base + l, so every col[] read is a
+// coalesced run. A window of 64 consecutive tasks sits one per lane (end of
+// the task relative to the wave's position, and the col index its probes
+// start from). The task of lane l is the number of window tasks that end at
+// or before its probe: one ballot counts those ending before the batch, and
+// tasks ending inside the batch are marked in a 64-entry LDS array so that a
+// second ballot plus a masked popcount gives each lane its task; the task's
+// col base is then fetched from its lane with one bpermute.
+//
+// Launch classes (decided in preprocessing from |U_b| and the row's probes):
+//   packs  - light rows b are packed (about 2K probes per pack); one wave per
+//            pack builds each row's table in its private LDS slice in turn.
+//   heavy  - a row's probes are cut into per-wave ranges (8K probes); the 4
+//            waves of a work-group share one table of that row.
+//   global - a row whose table would not fit LDS (|U_b| > 8192): lookups are
+//            binary searches in the sorted U_b in HBM.
+// Reductions: per-lane 32-bit hit counters, wave reduction by xor shuffles,
+// one 64-bit atomic per work-group into the caller's counter (order-free and
+// exact).
+#include "tc_prims.h"
+
+namespace tc {
+
+namespace {
+
+struct Args {
+  const int64_t* __restrict__ row_ptr;
+  const int32_t* __restrict__ col;
+  const uint32_t* __restrict__ tstart;
+  const uint64_t* __restrict__ tprefix;
+  const int64_t* __restrict__ tptr;
+  int64_t T;
+  uint32_t m;  // entries of col (probe positions are checked against it)
+  unsigned long long* count;
+  int32_t* support;
+};
+
+constexpr int kMarkInts = kWaves * 64;  // per-wave 64-entry task-boundary marks
+
+__device__ __forceinline__ uint64_t lanemask_le() { return (2ull << lane_id()) - 1ull; }
+
+// Lookup in an LDS table; returns the slot holding k or -1.
+__device__ __forceinline__ int lds_find(const int32_t* tab, uint32_t mask, int D, int32_t k) {
+  uint32_t h = (uint32_t)k & mask;
+  for (int i = 0; i <= D; ++i) {
+    const int32_t v = tab[h];
+    if (v == k) return (int)h;
+    if (v < 0) return -1;
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+// Lookup by binary search in the sorted row col[rs, rs + d); returns the
+// position of k or -1.
+__device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int64_t rs, int64_t d,
+                                            int32_t k) {
+  int64_t lo = rs, hi = rs + d;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    int32_t v = col[mid];
+    if (v < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < rs + d && col[lo] == k) ? lo : -1;
+}
+
+// Insert U_b = col[rs, rs + d) into a cleared table of S slots; threads
+// tid, tid + nt, ... share the work. Returns this thread's longest
+// displacement. VALS: also store the U position of every key.
+template <bool VALS>
+__device__ int build_table(int32_t* tab, int32_t* val, uint32_t mask, const int32_t* __restrict__ col,
+                           int64_t rs, int64_t d, int tid, int nt) {
+  int md = 0;
+  for (int64_t i = tid; i < d; i += nt) {
+    const int32_t k = col[rs + i];
+    uint32_t h = (uint32_t)k & mask;
+    int disp = 0;
+    while (atomicCAS(&tab[h], -1, k) != -1) {
+      h = (h + 1) & mask;
+      ++disp;
+    }
+    if (VALS) val[h] = (int32_t)(rs + i);
+    md = disp > md ? disp : md;
+  }
+  return md;
+}
+
+// What to do with every probe k (at col position `pos`, task of lane whose
+// first probe is at `ts`): count mode adds the hit; support modes also credit
+// the triangle's edges.
+struct TableRef {
+  const int32_t* tab;
+  const int32_t* val;
+  uint32_t mask;
+  int D;
+  // global fallback
+  int64_t rs, d;
+};
+
+template <int MODE, bool GLOBAL>
+struct Prober {
+  static constexpr bool kNeedTs = MODE != MODE_COUNT;
+  __device__ __forceinline__ static void probe(const Args& A, const TableRef& t, int32_t k,
+                                               uint32_t pos, uint32_t ts, uint32_t& hits) {
+    int64_t other = -1;
+    bool hit;
+    if (GLOBAL) {
+      other = hbm_find(A.col, t.rs, t.d, k);
+      hit = other >= 0;
+    } else {
+      const int slot = lds_find(t.tab, t.mask, t.D, k);
+      hit = slot >= 0;
+      if (MODE == MODE_SUPPORT_FULL && hit) other = t.val[slot];
+    }
+    if (!hit) return;
+    ++hits;
+    if (MODE == MODE_SUPPORT_FULL) {
+      atomicAdd(&A.support[ts - 1], 1);  // edge (a, b): the U entry just before the task's probes
+      atomicAdd(&A.support[pos], 1);     // edge (a, k): the probed entry of U_a
+      atomicAdd(&A.support[other], 1);   // edge (b, k): k's entry in U_b
+    } else if (MODE == MODE_SUPPORT_ORIENTED) {
+      atomicAdd(&A.support[ts - 1], 1);  // c(a, b) of Eq. 1
+    }
+  }
+};
+
+// One wave processes the probes [q, q + len) of the tasks of one hashed row;
+// task t contains probe q.
+template <int MODE, bool GLOBAL>
+__device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
+                           volatile int32_t* mark, uint32_t& tag, uint32_t& hits) {
+  using P = Prober<MODE, GLOBAL>;
+  const int lane = lane_id();
+  const int64_t T = A.T;
+  uint32_t done = 0;
+  while (done < len) {
+    const uint32_t rem = len - done;
+    const int64_t tj = (int64_t)t + lane;
+    const int64_t tjs = tj < T ? tj : T;
+    const int64_t tje = tj + 1 < T ? tj + 1 : T;
+    const uint64_t Ps = A.tprefix[tjs];
+    const uint64_t Pe = A.tprefix[tje];
+    // end of lane's task relative to q, clamped to the remaining range
+    const uint64_t e64 = Pe - q;
+    const uint32_t e = e64 > (uint64_t)rem ? rem : (uint32_t)e64;
+    // col index of relative probe 0 for the lane's task (mod 2^32)
+    const uint32_t tsj = A.tstart[tj < T ? tj : T - 1];
+    const uint32_t cbase = tsj - (uint32_t)(Ps - q);
+    const uint32_t cover = (uint32_t)__shfl((int)e, 63, 64);
+    const bool last = cover == rem;
+    const uint32_t nb = last ? (cover + 63) / 64 : cover / 64;
+    if (nb == 0) break;  // unreachable when every task has a probe; guards progress
+    for (uint32_t bi = 0; bi < nb; ++bi) {
+      const uint32_t base = bi * 64;
+      const uint32_t r = base + (uint32_t)lane;
+      const uint32_t c0 = (uint32_t)__popcll(__ballot(e <= base));
+      const bool inner = e > base && e < base + 64;
+      const uint64_t any_inner = __ballot(inner);
+      uint32_t jl = c0;
+      if (any_inner) {
+        if (inner) mark[e - base] = (int32_t)tag;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t M = __ballot(mark[lane] == (int32_t)tag);
+        ++tag;
+        jl = c0 + (uint32_t)__popcll(M & lanemask_le());
+        jl = jl < 63 ? jl : 63;  // only lanes past the range (r >= rem) can exceed 63
+      }
+      const uint32_t cb = (uint32_t)__shfl((int)cbase, (int)jl, 64);
+      uint32_t ts = 0;
+      if (P::kNeedTs) ts = (uint32_t)__shfl((int)tsj, (int)jl, 64);
+      const uint32_t pos = cb + r;
+      if (r < rem && pos < A.m) {
+        const int32_t k = A.col[pos];
+        P::probe(A, tr, k, pos, ts, hits);
+      }
+    }
+    const uint32_t consumed = last ? rem : nb * 64;
+    t += (uint32_t)__popcll(__ballot(e <= consumed));
+    q += consumed;
+    done += consumed;
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void block_flush(uint32_t hits, unsigned long long* count) {
+  __shared__ unsigned long long s_sum[kWaves];
+  unsigned long long h = wave_sum((unsigned long long)hits);
+  if (lane_id() == 0) s_sum[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0 && count) {
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tot += s_sum[w];
+    if (tot) atomicAdd(count, tot);
+  }
+}
+
+// Packs of light rows: each wave owns a table slice of 2^log2Smax slots.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_count_packs(Args A, const int32_t* __restrict__ rows,
+                                                     const uint32_t* __restrict__ pack_ptr,
+                                                     int64_t n_packs, int log2Smax) {
+  extern __shared__ int32_t smem[];
+  constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  volatile int32_t* mark = smem + wave * 64;
+  const uint32_t Smax = 1u << log2Smax;
+  int32_t* tab = smem + kMarkInts + (size_t)wave * Smax * (VALS ? 2 : 1);
+  int32_t* val = tab + Smax;
+  mark[lane] = -1;
+  uint32_t tag = 0, hits = 0;
+  const int64_t p = (int64_t)blockIdx.x * kWaves + wave;
+  if (p < n_packs) {
+    const uint32_t r0 = pack_ptr[p], r1 = pack_ptr[p + 1];
+    for (uint32_t r = r0; r < r1; ++r) {
+      const int32_t b = rows[r];
+      const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
+      int l = 6;
+      while ((1ll << l) < 2 * d) ++l;
+      const uint32_t S = 1u << l, mask = S - 1;
+      for (uint32_t i = lane; i < S; i += 64) tab[i] = -1;
+      wave_sync_lds();
+      int md = build_table<VALS>(tab, val, mask, A.col, rs, d, lane, 64);
+      md = wave_max(md);
+      wave_sync_lds();
+      const int64_t tl = A.tptr[b], th = A.tptr[b + 1];
+      const uint64_t q0 = A.tprefix[tl], q1 = A.tprefix[th];
+      TableRef tr{tab, val, mask, md, rs, d};
+      wave_probe<MODE, false>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), mark, tag, hits);
+      wave_sync_lds();
+    }
+  }
+  block_flush(hits, A.count);
+}
+
+// Heavy rows: work-group = kWaves consecutive items of the same row b.
+template <int MODE, bool GLOBAL>
+__global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __restrict__ items) {
+  extern __shared__ int32_t smem[];
+  __shared__ int s_D;
+  constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  volatile int32_t* mark = smem + wave * 64;
+  const CountItem* grp = items + (int64_t)blockIdx.x * kWaves;
+  const int32_t b = grp[0].b;
+  const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
+  mark[lane] = -1;
+  uint32_t tag = 0, hits = 0;
+  TableRef tr{nullptr, nullptr, 0, 0, rs, d};
+  if (!GLOBAL) {
+    const uint32_t S = 1u << grp[0].log2S, mask = S - 1;
+    int32_t* tab = smem + kMarkInts;
+    int32_t* val = tab + S;
+    for (uint32_t i = tid; i < S; i += 256) tab[i] = -1;
+    if (tid == 0) s_D = 0;
+    __syncthreads();
+    int md = build_table<VALS>(tab, val, mask, A.col, rs, d, tid, 256);
+    md = wave_max(md);
+    if (lane == 0) atomicMax(&s_D, md);
+    __syncthreads();
+    tr.tab = tab;
+    tr.val = val;
+    tr.mask = mask;
+    tr.D = s_D;
+  }
+  const CountItem it = grp[wave];
+  if (it.len) wave_probe<MODE, GLOBAL>(A, tr, it.t0, it.q0, it.len, mark, tag, hits);
+  block_flush(hits, A.count);
+}
+
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+template <int MODE>
+void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
+  constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
+  const size_t mark_bytes = sizeof(int32_t) * kMarkInts;
+  for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
+    if (g.n_packs[c] == 0) continue;
+    const int l = g.pack_log2S[c];
+    const size_t lds = mark_bytes + sizeof(int32_t) * (size_t)kWaves * ((size_t)1 << l) * (VALS ? 2 : 1);
+    const unsigned grid = (unsigned)div_up(g.n_packs[c], kWaves);
+    if (lds > 65536)
+      TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A, g.pack_rows[c],
+                       g.pack_ptr[c], g.n_packs[c], l);
+  }
+  for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
+    if (g.n_items[c] == 0) continue;
+    const unsigned grid = (unsigned)(g.n_items[c] / kWaves);
+    if (c == CLS_GLOBAL) {
+      hipLaunchKernelGGL((k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes, st, A,
+                         g.items[c]);
+    } else {
+      const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << g.cls_log2S[c]) * (VALS ? 2 : 1);
+      if (lds > 65536)
+        TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL((k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A, g.items[c]);
+    }
+  }
+  TC_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_support,
+                  hipStream_t st) {
+  if (d_count) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, d_count);
+  if (mode != MODE_COUNT && g.m > 0)
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support, g.m);
+  TC_HIP(hipGetLastError());
+  if (g.n_tasks == 0) return;
+  Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tptr, g.n_tasks, (uint32_t)g.m,
+         reinterpret_cast<unsigned long long*>(d_count), d_support};
+  switch (mode) {
+    case MODE_COUNT: launch_mode<MODE_COUNT>(g, A, st); break;
+    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL>(g, A, st); break;
+    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED>(g, A, st); break;
+  }
+}
+
+}  // namespace tc

@@ -1,0 +1,113 @@
+// tc_internal.h - shared host/device declarations of libtc (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+// ---- errors ------------------------------------------------------------------
+// Internal code throws tc::Error; every extern "C" entry point catches it and
+// converts it to a tc_status (no exception crosses the ABI).
+struct Error : std::runtime_error {
+  tc_status status;
+  Error(tc_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define TC_HIP(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) {                                                                \
+      throw ::tc::Error(_e == hipErrorOutOfMemory ? TC_ENOMEM : TC_EDEVICE,                \
+                        std::string(#expr) + ": " + hipGetErrorString(_e) + " (" __FILE__ \
+                        ":" + std::to_string(__LINE__) + ")");                             \
+    }                                                                                      \
+  } while (0)
+
+#define TC_REQUIRE(cond, status, msg)                       \
+  do {                                                      \
+    if (!(cond)) throw ::tc::Error((status), (msg));        \
+  } while (0)
+
+// ---- work items --------------------------------------------------------------
+// One wave's share of the probes of one hashed row b: the probes with global
+// index [q0, q0 + len) of the task list, where task t0 contains probe q0.
+// Items of one launch class are grouped per work-group (WAVES items, same b).
+struct alignas(8) CountItem {
+  int32_t b;       // hashed row (rank)
+  uint32_t t0;     // task containing q0
+  uint64_t q0;     // first global probe index
+  uint32_t len;    // number of probes
+  uint32_t log2S;  // hash table size (slots) = 1 << log2S
+};
+static_assert(sizeof(CountItem) == 24, "CountItem layout");
+
+// Launch classes of the count kernels (see tc_count.hip).
+enum ItemClass : int {
+  CLS_PACK_SMALL = 0,  // packs of light rows b, one wave per pack, table <= 512 slots
+  CLS_PACK_LARGE = 1,  // packs of light rows b, one wave per pack, table <= 4096 slots
+  CLS_WG_SMALL = 2,    // heavy rows, 4 waves share one table <= 1024 slots
+  CLS_WG_LARGE = 3,    // heavy rows, table <= 4096 slots
+  CLS_WG_HUGE = 4,     // heavy rows, table <= 16384 slots
+  CLS_GLOBAL = 5,      // table would not fit LDS: binary search in U_b in HBM
+  NUM_CLASSES = 6
+};
+
+constexpr int kWaves = 4;               // waves per work-group in every count launch
+constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
+constexpr uint32_t kWaveChunk = 8192;   // target probes per wave item of a heavy row
+constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
+constexpr uint64_t kPackTarget = 2048;  // target probes per pack of light rows
+
+// Device-resident graph. All arrays live in one allocation (`arena`).
+struct Graph {
+  int device = 0;
+  int64_t n = 0, m_raw = 0, m = 0, n_tasks = 0;
+  int64_t wedges_plus = 0, probes = 0, max_dplus = 0;
+  int sbits = 1;  // ceil(log2(n)), >= 1
+
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+
+  int64_t* row_ptr = nullptr;   // n + 1, U rows
+  int32_t* col = nullptr;       // m, rows sorted ascending
+  int32_t* perm = nullptr;      // n, perm[original id] = rank
+  int64_t* tptr = nullptr;      // n + 1, tasks of hashed row b: [tptr[b], tptr[b + 1])
+  uint32_t* tstart = nullptr;   // n_tasks, col index of the task's first probe
+  uint64_t* tprefix = nullptr;  // n_tasks + 1, exclusive prefix of task lengths
+
+  // pack classes: packs[c] holds n_packs[c] + 1 offsets into pack_rows[c]
+  int32_t* pack_rows[2] = {nullptr, nullptr};   // light rows b of the class, ascending
+  uint32_t* pack_ptr[2] = {nullptr, nullptr};   // pack p covers pack_rows[pack_ptr[p] .. pack_ptr[p+1])
+  int64_t n_pack_rows[2] = {0, 0};
+  int64_t n_packs[2] = {0, 0};
+  int32_t pack_log2S[2] = {0, 0};               // max table size of the class
+
+  // work-group classes: n_items[c] items (a multiple of kWaves)
+  CountItem* items[NUM_CLASSES] = {};
+  int64_t n_items[NUM_CLASSES] = {};
+  int32_t cls_log2S[NUM_CLASSES] = {};
+};
+
+inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
+
+// ---- launchers implemented in tc_count.hip ---------------------------------
+enum CountMode : int { MODE_COUNT = 0, MODE_SUPPORT_FULL = 1, MODE_SUPPORT_ORIENTED = 2 };
+void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_support,
+                  hipStream_t stream);
+
+inline int ceil_log2_u64(uint64_t x) {
+  int r = 0;
+  while ((1ULL << r) < x) ++r;
+  return r;
+}
+
+}  // namespace tc

@@ -1,0 +1,569 @@
+// tc_preprocess.hip - device preprocessing (Section 5.3 of the paper, on one GPU).
+//
+// Pipeline, all on the caller's stream:
+//   1. canonical keys: each pair {u, v}, u != v, becomes min(u,v) * 2^s + max(u,v)
+//      (s = ceil(log2 n)); self loops and invalid ids become a sentinel.
+//   2. stable LSD radix sort of the 2s-bit keys, adjacent-unique compaction:
+//      the simple undirected graph of Section 2 / Section 6.1.
+//   3. degrees by atomic histogram; rank = position in the order (degree, id)
+//      (a stable radix sort of degree * 2^s + id on the degree bits): the
+//      non-decreasing degree relabelling of Section 5.3.
+//   4. orientation by rank (Section 5.3: the global position stands in for the
+//      degree), radix sort of rank keys -> U in CSR with sorted rows
+//      (Section 5.2 requires sorted rows).
+//   5. tasks (Section 3.1, <j,i,k>): every nonzero (a, b) of U whose row a has
+//      entries after b and whose row b is non-empty probes U_a's entries after b
+//      against a hash of U_b. Tasks are grouped by b (the transpose L = U^T of
+//      Section 3.1), stably, so within one b the rows a ascend; their probe
+//      counts are prefix-summed.
+//   6. work classes and items for the count kernels (see tc_count.hip): rows b
+//      are split by table size and work; light rows are packed, heavy rows are
+//      cut into per-wave probe ranges.
+#include <algorithm>
+#include <memory>
+
+#include "tc_prims.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int kT = 256;
+inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, div_up(n, kT)); }
+
+__global__ void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m,
+                        int64_t n, int s, uint64_t sent, uint64_t* __restrict__ keys,
+                        int* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int64_t u = src[i], v = dst[i];
+  uint64_t key = sent;
+  if (u < 0 || u >= n || v < 0 || v >= n) {
+    atomicOr(err, 1);
+  } else if (u != v) {
+    uint64_t lo = (uint64_t)(u < v ? u : v), hi = (uint64_t)(u < v ? v : u);
+    key = (lo << s) | hi;
+  }
+  keys[i] = key;
+}
+
+__global__ void k_unique_flags(const uint64_t* __restrict__ keys, int64_t m, uint64_t sent,
+                               uint32_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint64_t k = keys[i];
+  flags[i] = (k != sent && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+}
+
+template <class T>
+__global__ void k_compact(const T* __restrict__ in, const uint32_t* __restrict__ flags,
+                          const uint32_t* __restrict__ pos, int64_t m, T* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  if (flags[i]) out[pos[i]] = in[i];
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_degree(const uint64_t* __restrict__ E, int64_t m, int s, uint32_t* __restrict__ deg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t mask = (1ull << s) - 1;
+  uint64_t e = E[i];
+  atomicAdd(&deg[e >> s], 1u);
+  atomicAdd(&deg[e & mask], 1u);
+}
+
+__global__ void k_rank_keys(const uint32_t* __restrict__ deg, int64_t n, int s,
+                            uint64_t* __restrict__ rk) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) rk[v] = ((uint64_t)deg[v] << s) | (uint64_t)v;
+}
+
+__global__ void k_perm(const uint64_t* __restrict__ rk, int64_t n, int s, int32_t* __restrict__ perm) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) perm[rk[r] & ((1ull << s) - 1)] = (int32_t)r;
+}
+
+__global__ void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
+                         const int32_t* __restrict__ perm, uint64_t* __restrict__ okey) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t mask = (1ull << s) - 1;
+  uint64_t e = E[i];
+  uint64_t ru = (uint64_t)perm[e >> s], rv = (uint64_t)perm[e & mask];
+  okey[i] = ru < rv ? ((ru << s) | rv) : ((rv << s) | ru);
+}
+
+// Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
+// with row(i) >= r, row_ptr[n] = m.
+template <class K>
+__global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n,
+                         int64_t* __restrict__ row_ptr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int64_t a = (int64_t)(keys[i] >> s);
+  int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> s);
+  for (int64_t r = prev + 1; r <= a; ++r) row_ptr[r] = i;
+  if (i == m - 1)
+    for (int64_t r = a + 1; r <= n; ++r) row_ptr[r] = m;
+}
+
+__global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32_t* __restrict__ col) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) col[i] = (int32_t)(okey[i] & ((1ull << s) - 1));
+}
+
+__global__ void k_task_flags(const uint64_t* __restrict__ okey, int64_t m, int s,
+                             const int64_t* __restrict__ row_ptr, uint32_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint64_t k = okey[i];
+  int64_t a = (int64_t)(k >> s), b = (int64_t)(k & ((1ull << s) - 1));
+  int64_t after = row_ptr[a + 1] - i - 1;
+  int64_t db = row_ptr[b + 1] - row_ptr[b];
+  flags[i] = (after > 0 && db > 0) ? 1u : 0u;
+}
+
+__global__ void k_task_emit(const uint64_t* __restrict__ okey, int64_t m, int s,
+                            const int64_t* __restrict__ row_ptr, const uint32_t* __restrict__ flags,
+                            const uint32_t* __restrict__ pos, uint32_t* __restrict__ tkey,
+                            uint64_t* __restrict__ tval) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m || !flags[i]) return;
+  uint64_t k = okey[i];
+  int64_t a = (int64_t)(k >> s);
+  uint32_t b = (uint32_t)(k & ((1ull << s) - 1));
+  uint32_t t = pos[i];
+  tkey[t] = b;
+  tval[t] = (uint64_t)(i + 1) | ((uint64_t)row_ptr[a + 1] << 32);
+}
+
+__global__ void k_task_split(const uint64_t* __restrict__ tval, int64_t T,
+                             uint32_t* __restrict__ tstart, uint32_t* __restrict__ tlen) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  uint64_t v = tval[t];
+  uint32_t st = (uint32_t)v, en = (uint32_t)(v >> 32);
+  tstart[t] = st;
+  tlen[t] = en - st;
+}
+
+// W+ = sum_a C(d+(a), 2) and max d+(a).
+__global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ row_ptr, int64_t n,
+                                                   unsigned long long* __restrict__ wplus,
+                                                   unsigned int* __restrict__ maxd) {
+  __shared__ uint64_t s_w[4];
+  __shared__ uint32_t s_m[4];
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t w = 0;
+  uint32_t md = 0;
+  if (a < n) {
+    uint64_t d = (uint64_t)(row_ptr[a + 1] - row_ptr[a]);
+    w = d * (d - (d > 0)) / 2;
+    md = (uint32_t)d;
+  }
+  w = wave_sum(w);
+  md = wave_max(md);
+  if (lane_id() == 0) {
+    s_w[threadIdx.x >> 6] = w;
+    s_m[threadIdx.x >> 6] = md;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tw = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    uint32_t tm = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+    if (tw) atomicAdd(wplus, (unsigned long long)tw);
+    atomicMax(maxd, tm);
+  }
+}
+
+__device__ __forceinline__ int clog2_dev(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+__device__ __forceinline__ int row_log2S(int64_t d) {
+  int l = clog2_dev((uint64_t)(2 * d));
+  return l < 6 ? 6 : l;
+}
+
+// Class of every hashed row b (-1 = no work) and the class's largest table.
+__global__ void k_classify(const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
+                           const int64_t* __restrict__ row_ptr, int64_t n, int8_t* __restrict__ cls,
+                           int* __restrict__ cls_log2S) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+  if (W == 0) {
+    cls[b] = -1;
+    return;
+  }
+  int l = row_log2S(row_ptr[b + 1] - row_ptr[b]);
+  int c;
+  if (l > kMaxLog2S) c = CLS_GLOBAL;
+  else if (l > 12) c = CLS_WG_HUGE;
+  else if (W < kHeavyMin) c = l <= 9 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
+  else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
+  cls[b] = (int8_t)c;
+  atomicMax(&cls_log2S[c], l);
+}
+
+__device__ __forceinline__ uint32_t wg_parts(uint64_t W) {
+  const uint64_t per = (uint64_t)kWaves * kWaveChunk;
+  return (uint32_t)(kWaves * ((W + per - 1) / per));
+}
+
+__global__ void k_class_count(const int8_t* __restrict__ cls, int64_t n, int c,
+                              const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
+                              uint32_t* __restrict__ cnt) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  uint32_t v = 0;
+  if (cls[b] == c) {
+    if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) v = 1;
+    else v = wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]]);
+  }
+  cnt[b] = v;
+}
+
+__global__ void k_class_rows(const int8_t* __restrict__ cls, int64_t n, int c,
+                             const uint32_t* __restrict__ offs, int32_t* __restrict__ rows) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n && cls[b] == c) rows[offs[b]] = (int32_t)b;
+}
+
+__global__ void k_rows_work(const int32_t* __restrict__ rows, int64_t nr,
+                            const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
+                            uint64_t* __restrict__ w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  int64_t b = rows[i];
+  w[i] = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+}
+
+__global__ void k_pack_flags(const uint64_t* __restrict__ pw, int64_t nr, uint64_t target,
+                             uint32_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  flags[i] = (i == 0 || pw[i] / target != pw[i - 1] / target) ? 1u : 0u;
+}
+
+__global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                            int64_t nr, uint32_t* __restrict__ pack_ptr, int64_t np) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nr && flags[i]) pack_ptr[pos[i]] = (uint32_t)i;
+  if (i == 0) pack_ptr[np] = (uint32_t)nr;
+}
+
+// One thread per wave item of a work-group class: find its row b (upper bound
+// in the per-row item offsets), cut the row's probe range evenly and find the
+// task holding the first probe.
+__global__ void k_emit_items(const uint32_t* __restrict__ offs, int64_t n, int64_t total,
+                             const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
+                             const int64_t* __restrict__ row_ptr, CountItem* __restrict__ items) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= total) return;
+  // largest b with offs[b] <= j (offs has n + 1 entries, non-decreasing)
+  int64_t lo = 0, hi = n;  // invariant offs[lo] <= j < offs[hi]
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)offs[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  const int64_t b = lo;
+  const uint64_t parts = offs[b + 1] - offs[b];
+  const uint64_t idx = (uint64_t)(j - (int64_t)offs[b]);
+  const int64_t t_lo = tptr[b], t_hi = tptr[b + 1];
+  const uint64_t P0 = tprefix[t_lo];
+  const uint64_t W = tprefix[t_hi] - P0;
+  const uint64_t per = W / parts, extra = W % parts;
+  const uint64_t q0 = P0 + per * idx + (idx < extra ? idx : extra);
+  const uint64_t q1 = q0 + per + (idx < extra ? 1 : 0);
+  // task t in [t_lo, t_hi) with tprefix[t] <= q0 < tprefix[t+1]
+  int64_t a = t_lo, z = t_hi;  // tprefix[a] <= q0 < tprefix[z] (if q0 < end)
+  while (z - a > 1) {
+    int64_t mid = (a + z) >> 1;
+    if (tprefix[mid] <= q0) a = mid;
+    else z = mid;
+  }
+  CountItem it;
+  it.b = (int32_t)b;
+  it.t0 = (uint32_t)a;
+  it.q0 = q0;
+  it.len = (uint32_t)(q1 - q0);
+  it.log2S = (uint32_t)row_log2S(row_ptr[b + 1] - row_ptr[b]);
+  items[j] = it;
+}
+
+template <class T>
+T read_scalar(const T* d, hipStream_t st) {
+  T h{};
+  TC_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// Allocation owned by the graph (freed by tc_graph_free).
+struct Owned {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <class T>
+  T* alloc(int64_t count) {
+    void* p = nullptr;
+    size_t b = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    TC_HIP(hipMalloc(&p, b));
+    ptrs.push_back(p);
+    bytes += b;
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct GraphImpl : Graph {
+  Owned owned;
+  ~GraphImpl() { owned.release(); }
+};
+
+void destroy_graph(Graph* g) { delete static_cast<GraphImpl*>(g); }
+
+Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n,
+                   hipStream_t st) {
+  std::unique_ptr<GraphImpl> g(new GraphImpl());
+  TC_HIP(hipGetDevice(&g->device));
+  g->n = n;
+  g->m_raw = m_raw;
+  const int s = std::max(1, ceil_log2_u64((uint64_t)n));
+  g->sbits = s;
+  const uint64_t sent = (2 * s >= 64) ? ~0ull : ((1ull << (2 * s)) - 1);
+
+  DevBuf dscal(64);  // device scalars: [0] err (int), [8] m (u32 total), [16] wplus, [24] maxd
+  TC_HIP(hipMemsetAsync(dscal.p, 0, 64, st));
+  int* d_err = reinterpret_cast<int*>(dscal.as<char>());
+  uint32_t* d_tot32 = reinterpret_cast<uint32_t*>(dscal.as<char>() + 8);
+  unsigned long long* d_wplus = reinterpret_cast<unsigned long long*>(dscal.as<char>() + 16);
+  unsigned int* d_maxd = reinterpret_cast<unsigned int*>(dscal.as<char>() + 24);
+  uint64_t* d_tot64 = reinterpret_cast<uint64_t*>(dscal.as<char>() + 32);
+
+  // ---- 1-2: simple graph -------------------------------------------------
+  int64_t m = 0;
+  DevBuf E;
+  {
+    DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
+    DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
+    if (m_raw > 0) {
+      hipLaunchKernelGGL(k_canon, dim3(grid_for(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
+                         sent, ka.as<uint64_t>(), d_err);
+      TC_HIP(hipGetLastError());
+    }
+    TC_REQUIRE(read_scalar(d_err, st) == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
+    bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
+                                           m_raw, 0, 2 * s, st);
+    const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
+    DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
+    DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
+    if (m_raw > 0) {
+      hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted, m_raw, sent,
+                         flags.as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, d_tot32, st);
+      m = read_scalar(d_tot32, st);
+    }
+    TC_REQUIRE(m < (int64_t)0x7FFFFFFF, TC_EOVERFLOW, "tc_preprocess: 2^31 or more edges");
+    E.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
+    if (m > 0)
+      hipLaunchKernelGGL((k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
+                         flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, E.as<uint64_t>());
+    TC_HIP(hipGetLastError());
+    TC_HIP(hipStreamSynchronize(st));
+  }
+  g->m = m;
+
+  // ---- 3: degree order ---------------------------------------------------
+  g->perm = g->owned.alloc<int32_t>(n);
+  {
+    DevBuf deg(sizeof(uint32_t) * (size_t)n);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, 0u);
+    if (m > 0)
+      hipLaunchKernelGGL(k_degree, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
+                         deg.as<uint32_t>());
+    DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
+    hipLaunchKernelGGL(k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
+                       ra.as<uint64_t>());
+    TC_HIP(hipGetLastError());
+    bool alt = radix_sort<uint64_t, NoVal>(ra.as<uint64_t>(), rb.as<uint64_t>(), nullptr, nullptr, n,
+                                           s, 2 * s, st);
+    hipLaunchKernelGGL(k_perm, dim3(grid_for(n)), dim3(kT), 0, st,
+                       alt ? rb.as<uint64_t>() : ra.as<uint64_t>(), n, s, g->perm);
+    TC_HIP(hipGetLastError());
+    TC_HIP(hipStreamSynchronize(st));
+  }
+
+  // ---- 4: orient, U in CSR -------------------------------------------------
+  g->row_ptr = g->owned.alloc<int64_t>(n + 1);
+  g->col = g->owned.alloc<int32_t>(m);
+  DevBuf ok(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
+  const uint64_t* okey = ok.as<uint64_t>();
+  {
+    if (m > 0) {
+      hipLaunchKernelGGL(k_orient, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
+                         g->perm, ok.as<uint64_t>());
+      TC_HIP(hipGetLastError());
+      // E's buffer is the ping-pong partner
+      bool alt = radix_sort<uint64_t, NoVal>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
+                                             0, 2 * s, st);
+      if (alt) okey = E.as<uint64_t>();
+      hipLaunchKernelGGL((k_bounds<uint64_t>), dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, n,
+                         g->row_ptr);
+      hipLaunchKernelGGL(k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
+    } else {
+      hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->row_ptr, n + 1,
+                         (int64_t)0);
+    }
+    hipLaunchKernelGGL(k_row_stats, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n, d_wplus, d_maxd);
+    TC_HIP(hipGetLastError());
+  }
+
+  // ---- 5: tasks grouped by hashed row b -----------------------------------
+  int64_t T = 0;
+  g->tptr = g->owned.alloc<int64_t>(n + 1);
+  {
+    DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
+    DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
+    if (m > 0) {
+      hipLaunchKernelGGL(k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
+                         flags.as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m, d_tot32, st);
+      T = read_scalar(d_tot32, st);
+    }
+    g->n_tasks = T;
+    g->tstart = g->owned.alloc<uint32_t>(T);
+    g->tprefix = g->owned.alloc<uint64_t>(T + 1);
+    if (T > 0) {
+      DevBuf tk(sizeof(uint32_t) * (size_t)T), tk2(sizeof(uint32_t) * (size_t)T);
+      DevBuf tv(sizeof(uint64_t) * (size_t)T), tv2(sizeof(uint64_t) * (size_t)T);
+      hipLaunchKernelGGL(k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
+                         flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
+      TC_HIP(hipGetLastError());
+      bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tk2.as<uint32_t>(), tv.as<uint64_t>(),
+                                                tv2.as<uint64_t>(), T, 0, s, st);
+      const uint32_t* skey = alt ? tk2.as<uint32_t>() : tk.as<uint32_t>();
+      const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv.as<uint64_t>();
+      DevBuf tlen(sizeof(uint32_t) * (size_t)T);
+      hipLaunchKernelGGL(k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T, g->tstart,
+                         tlen.as<uint32_t>());
+      device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
+      hipLaunchKernelGGL((k_bounds<uint32_t>), dim3(grid_for(T)), dim3(kT), 0, st, skey, T, 0, n,
+                         g->tptr);
+      TC_HIP(hipGetLastError());
+      g->probes = (int64_t)read_scalar(g->tprefix + T, st);
+    } else {
+      hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->tptr, n + 1, (int64_t)0);
+      TC_HIP(hipMemsetAsync(g->tprefix, 0, sizeof(uint64_t), st));
+      g->probes = 0;
+    }
+    g->wedges_plus = (int64_t)read_scalar(reinterpret_cast<uint64_t*>(d_wplus), st);
+    g->max_dplus = (int64_t)read_scalar(reinterpret_cast<uint32_t*>(d_maxd), st);
+  }
+  E.release();
+  ok.release();
+
+  // ---- 6: work classes ------------------------------------------------------
+  if (T > 0) {
+    DevBuf cls(sizeof(int8_t) * (size_t)n);
+    DevBuf clsl(sizeof(int) * NUM_CLASSES);
+    TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(kT), 0, st, g->tptr, g->tprefix,
+                       g->row_ptr, n, cls.as<int8_t>(), clsl.as<int>());
+    TC_HIP(hipGetLastError());
+    int h_cl[NUM_CLASSES];
+    TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipStreamSynchronize(st));
+    DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
+    for (int c = 0; c < NUM_CLASSES; ++c) {
+      g->cls_log2S[c] = h_cl[c];
+      hipLaunchKernelGGL(k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                         g->tptr, g->tprefix, cnt.as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
+                                           offs.as<uint32_t>() + n, st);
+      const int64_t total = read_scalar(offs.as<uint32_t>() + n, st);
+      if (total == 0) continue;
+      if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
+        int32_t* rows = g->owned.alloc<int32_t>(total);
+        hipLaunchKernelGGL(k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                           offs.as<uint32_t>(), rows);
+        DevBuf w(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
+        hipLaunchKernelGGL(k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tptr,
+                           g->tprefix, w.as<uint64_t>());
+        device_excl_scan<uint64_t, uint64_t>(w.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
+        DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
+        hipLaunchKernelGGL(k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
+                           total, (uint64_t)kPackTarget, pf.as<uint32_t>());
+        device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
+        const int64_t np = read_scalar(d_tot32, st);
+        uint32_t* pack_ptr = g->owned.alloc<uint32_t>(np + 1);
+        hipLaunchKernelGGL(k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
+                           pp.as<uint32_t>(), total, pack_ptr, np);
+        TC_HIP(hipGetLastError());
+        TC_HIP(hipStreamSynchronize(st));
+        g->pack_rows[c] = rows;
+        g->pack_ptr[c] = pack_ptr;
+        g->n_pack_rows[c] = total;
+        g->n_packs[c] = np;
+        g->pack_log2S[c] = h_cl[c];
+      } else {
+        CountItem* items = g->owned.alloc<CountItem>(total);
+        hipLaunchKernelGGL(k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(), n,
+                           total, g->tptr, g->tprefix, g->row_ptr, items);
+        TC_HIP(hipGetLastError());
+        TC_HIP(hipStreamSynchronize(st));
+        g->items[c] = items;
+        g->n_items[c] = total;
+      }
+    }
+  }
+  TC_HIP(hipStreamSynchronize(st));
+  g->arena_bytes = g->owned.bytes;
+  return g.release();
+}
+
+}  // namespace tc
+
+extern "C" tc_status tc_preprocess(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw,
+                                   int32_t n, void* stream, tc_graph** out) {
+  try {
+    TC_REQUIRE(out != nullptr, TC_EINVAL, "tc_preprocess: out is NULL");
+    *out = nullptr;
+    TC_REQUIRE(n >= 1, TC_EINVAL, "tc_preprocess: n must be >= 1");
+    TC_REQUIRE(m_raw >= 0, TC_EINVAL, "tc_preprocess: m_raw must be >= 0");
+    TC_REQUIRE(m_raw == 0 || (d_src != nullptr && d_dst != nullptr), TC_EINVAL,
+               "tc_preprocess: null edge arrays");
+    TC_REQUIRE(m_raw < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW, "tc_preprocess: m_raw >= 2^32 - 1");
+    tc::Graph* g = tc::build_graph(d_src, d_dst, m_raw, n, static_cast<hipStream_t>(stream));
+    *out = reinterpret_cast<tc_graph*>(g);
+    tc::set_last_error("");
+    return TC_OK;
+  } catch (const tc::Error& e) {
+    tc::set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    tc::set_last_error("tc_preprocess: host allocation failed");
+    return TC_ENOMEM;
+  } catch (const std::exception& e) {
+    tc::set_last_error(e.what());
+    return TC_EDEVICE;
+  }
+}

@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit-exact.
+
+Every value compared here is an integer (counts, CSR arrays, per-edge support,
+work counts), so the bar is equality.
+"""
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import smallgraphs as sg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1907_09575_amd as tc
+    torch.cuda.set_device(0)
+    return tc
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda")
+
+
+def gpu_graph(tc, src, dst, n):
+    print("case n=%d m_raw=%d" % (n, len(src)), flush=True)
+    return tc.tc_preprocess(dev(src), dev(dst), n)
+
+
+def gpu_count(tc, g):
+    c = tc.tc_count(g)
+    torch.cuda.synchronize()
+    return int(c.item())
+
+
+def gpu_support(tc, g, mode):
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    s, _ = tc.tc_edge_support(g, mode, count=cnt)
+    torch.cuda.synchronize()
+    return int(cnt.item()), s.cpu().numpy()
+
+
+def check_full(tc, src, dst, n, support=True):
+    U = oracle.preprocess(src, dst, n)
+    g = gpu_graph(tc, src, dst, n)
+    rp, col, perm = tc.tc_graph_export(g)
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), U.rank)
+    assert np.array_equal(rp.cpu().numpy(), U.row_ptr)
+    assert np.array_equal(col.cpu().numpy(), U.col)
+    info = g.info()
+    w = oracle.wedges(U)
+    assert info["m"] == U.m
+    assert info["wedges_plus"] == w["wedges_plus"]
+    assert info["probes"] == w["probes"]
+    assert info["tasks"] == w["tasks"]
+    T = oracle.count(U)
+    assert gpu_count(tc, g) == T
+    if support:
+        for mode in (oracle.MODE_FULL, oracle.MODE_ORIENTED):
+            Tr, s_ref = oracle.support(U, mode)
+            Tg, s = gpu_support(tc, g, mode)
+            assert Tg == Tr == T
+            assert np.array_equal(s, s_ref), "support mode %d differs" % mode
+    return g, T
+
+
+@pytest.mark.parametrize("name,make,expected", sg.CLOSED_FORMS, ids=[c[0] for c in sg.CLOSED_FORMS])
+def test_closed_forms(tc, name, make, expected):
+    s, d, n = make()
+    g, T = check_full(tc, s, d, n)
+    assert T == expected
+
+
+def test_support_closed_forms(tc):
+    m = 37
+    s, d, n = sg.wheel(m)
+    g = gpu_graph(tc, s, d, n)
+    _, sup = gpu_support(tc, g, tc.TC_SUPPORT_FULL)
+    rp, col, perm = tc.tc_graph_export(g)
+    inv = np.empty(n, np.int64)
+    inv[perm.cpu().numpy()] = np.arange(n)
+    rp = rp.cpu().numpy()
+    col = col.cpu().numpy()
+    for a in range(n):
+        for p in range(rp[a], rp[a + 1]):
+            spoke = 0 in (inv[a], inv[col[p]])
+            assert sup[p] == (2 if spoke else 1)
+    s, d, n = sg.complete(50)
+    g = gpu_graph(tc, s, d, n)
+    _, sup = gpu_support(tc, g, tc.TC_SUPPORT_FULL)
+    assert set(sup.tolist()) == {48}
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_small(tc, seed):
+    s, d, n = sg.random_graph(60 + 20 * seed, 0.15, 200 + seed)
+    check_full(tc, *sg.messy(s, d, n, seed=seed))
+
+
+def test_er_config(tc):
+    # Erdos-Renyi G(n=4096, m=32768), seed 1
+    n = 4096
+    s, d = graphgen.er(n, 32768, seed=1)
+    check_full(tc, s, d, n)
+
+
+@pytest.mark.parametrize("scale,seed", [(8, 1), (12, 2), (14, 3), (16, 4)])
+def test_rmat_small(tc, scale, seed):
+    s, d = graphgen.rmat(scale, seed=seed)
+    check_full(tc, s, d, 1 << scale)
+
+
+def test_rmat_non_power_of_two(tc):
+    n = 50000
+    s, d = graphgen.rmat(graphgen.scale_for(n), n=n, m=16 * n, seed=8)
+    check_full(tc, s, d, n)
+
+
+def test_rmat_scale20(tc):
+    s, d = graphgen.rmat(20, seed=1)
+    check_full(tc, s, d, 1 << 20)
+
+
+def test_edge_cases(tc):
+    # empty edge list
+    g = gpu_graph(tc, np.zeros(0, np.int32), np.zeros(0, np.int32), 10)
+    assert gpu_count(tc, g) == 0
+    assert g.info()["m"] == 0
+    # one vertex
+    g = gpu_graph(tc, np.zeros(0, np.int32), np.zeros(0, np.int32), 1)
+    assert gpu_count(tc, g) == 0
+    # only self loops and duplicates of one edge
+    s = np.array([3, 3, 4, 1, 2, 1], np.int32)
+    d = np.array([3, 3, 4, 2, 1, 2], np.int32)
+    g = gpu_graph(tc, s, d, 5)
+    assert g.info()["m"] == 1 and gpu_count(tc, g) == 0
+    # a triangle given 40 times in every orientation
+    tri = np.array([[0, 1], [1, 2], [2, 0], [1, 0], [2, 1], [0, 2]] * 40, np.int32)
+    g = gpu_graph(tc, tri[:, 0], tri[:, 1], 3)
+    assert gpu_count(tc, g) == 1
+    _, sup = gpu_support(tc, g, tc.TC_SUPPORT_FULL)
+    assert sup.tolist() == [1, 1, 1]
+
+
+def test_invalid_ids_rejected(tc):
+    for s, d, n in [([0, 5], [1, 2], 5), ([-1], [0], 3), ([0], [2 ** 31 - 1], 4)]:
+        with pytest.raises(tc.TCError) as e:
+            tc.tc_preprocess(dev(s), dev(d), n)
+        assert e.value.status == 1
+
+
+def test_repeatable_and_concurrent_streams(tc):
+    s, d = graphgen.rmat(15, seed=21)
+    g = gpu_graph(tc, s, d, 1 << 15)
+    T = gpu_count(tc, g)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for st in streams:
+        with torch.cuda.stream(st):
+            outs.append(tc.tc_count(g, stream=st))
+    torch.cuda.synchronize()
+    assert all(int(o.item()) == T for o in outs)
+    for _ in range(3):
+        assert gpu_count(tc, g) == T
+
+
+def test_hbm_fallback_rows(tc):
+    # K_n with n - 1 > 8192 out-neighbours on the first rows: their tables do
+    # not fit LDS and take the binary-search path; T = C(n, 3) exactly.
+    n = 8300
+    iu = np.triu_indices(n, 1)
+    g = gpu_graph(tc, iu[0].astype(np.int32), iu[1].astype(np.int32), n)
+    assert g.info()["max_out_degree"] == n - 1
+    assert gpu_count(tc, g) == comb(n, 3)
+    T, sup = gpu_support(tc, g, tc.TC_SUPPORT_ORIENTED)
+    assert T == comb(n, 3)
+    # oriented c(a, b) in K_n with ranks = ids: n - 1 - b for every a < b
+    rp, col, _ = tc.tc_graph_export(g)
+    col = col.cpu().numpy()
+    assert np.array_equal(sup, (n - 1 - col).astype(np.int32))
