@@ -16,14 +16,15 @@
 // never depends on the absence of collisions.
 //
 // Probe loop (one wave, flattened over tasks). A wave walks a range of
-// probes 64 at a time, lane l taking probe base + l, so every col[] read is a
-// coalesced run. A window of 64 consecutive tasks sits one per lane (end of
-// the task relative to the wave's position, and the col index its probes
-// start from). The task of lane l is the number of window tasks that end at
-// or before its probe: one ballot counts those ending before the batch, and
-// tasks ending inside the batch are marked in a 64-entry LDS array so that a
-// second ballot plus a masked popcount gives each lane its task; the task's
-// col base is then fetched from its lane with one bpermute.
+// probes in batches of 64, lane l taking probe base + l, so every col[] read
+// is a coalesced run; kU batches form a super-batch whose loads and lookups
+// are all in flight together. A window of 64 consecutive tasks sits one per
+// lane (end of the task relative to the wave's position, and the col index its
+// probes start from). The task of a probe is the number of window tasks that
+// end at or before it: one ballot counts those ending before the super-batch,
+// and the tasks ending inside it set bits of a small per-wave LDS bitmap whose
+// masked popcounts give each lane its task; the task's col base is then
+// fetched from its lane with one bpermute.
 //
 // Launch classes (decided in preprocessing from |U_b| and the row's probes):
 //   packs  - light rows b are packed (about 2K probes per pack); one wave per
@@ -53,21 +54,11 @@ struct Args {
   int32_t* support;
 };
 
-constexpr int kMarkInts = kWaves * 64;  // per-wave 64-entry task-boundary marks
+constexpr int kU = 8;                   // 64-probe batches per super-batch
+constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bits)
+constexpr int kMarkInts = kWaves * kBmWords;
 
 __device__ __forceinline__ uint64_t lanemask_le() { return (2ull << lane_id()) - 1ull; }
-
-// Lookup in an LDS table; returns the slot holding k or -1.
-__device__ __forceinline__ int lds_find(const int32_t* tab, uint32_t mask, int D, int32_t k) {
-  uint32_t h = (uint32_t)k & mask;
-  for (int i = 0; i <= D; ++i) {
-    const int32_t v = tab[h];
-    if (v == k) return (int)h;
-    if (v < 0) return -1;
-    h = (h + 1) & mask;
-  }
-  return -1;
-}
 
 // Lookup by binary search in the sorted row col[rs, rs + d); returns the
 // position of k or -1.
@@ -119,38 +110,48 @@ struct TableRef {
 template <int MODE, bool GLOBAL>
 struct Prober {
   static constexpr bool kNeedTs = MODE != MODE_COUNT;
-  __device__ __forceinline__ static void probe(const Args& A, const TableRef& t, int32_t k,
-                                               uint32_t pos, uint32_t ts, uint32_t& hits) {
-    int64_t other = -1;
-    bool hit;
-    if (GLOBAL) {
-      other = hbm_find(A.col, t.rs, t.d, k);
-      hit = other >= 0;
-    } else {
-      const int slot = lds_find(t.tab, t.mask, t.D, k);
-      hit = slot >= 0;
-      if (MODE == MODE_SUPPORT_FULL && hit) other = t.val[slot];
-    }
-    if (!hit) return;
+  // A hit: k = col[pos] was found in U_b at `where` (an LDS slot, or for the
+  // HBM fallback the position in col). ts is the first probe position of the
+  // task, so ts - 1 is the U entry of the task's own edge (a, b).
+  __device__ __forceinline__ static void credit(const Args& A, const TableRef& t, int where,
+                                                uint32_t pos, uint32_t ts, uint32_t& hits) {
     ++hits;
+    // indices are checked against m so that no credit can leave the array
     if (MODE == MODE_SUPPORT_FULL) {
-      atomicAdd(&A.support[ts - 1], 1);  // edge (a, b): the U entry just before the task's probes
-      atomicAdd(&A.support[pos], 1);     // edge (a, k): the probed entry of U_a
-      atomicAdd(&A.support[other], 1);   // edge (b, k): k's entry in U_b
+      const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
+      if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
+      atomicAdd(&A.support[pos], 1);                          // edge (a, k): probed entry of U_a
+      if (other < A.m) atomicAdd(&A.support[other], 1);       // edge (b, k): k's entry in U_b
     } else if (MODE == MODE_SUPPORT_ORIENTED) {
-      atomicAdd(&A.support[ts - 1], 1);  // c(a, b) of Eq. 1
+      if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
     }
   }
 };
 
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
 // task t contains probe q.
-template <int MODE, bool GLOBAL>
+//
+// The range is walked window by window: a window is the next 64 tasks (one per
+// lane) and covers their probes exactly. Inside a window the probes go in
+// super-batches of 64 * U (lane l takes probes sb + 64 u + l, u < U), so each
+// lane has U independent col[] loads and U table lookups in flight. The task
+// of a probe r is c0 + (number of task ends in (sb, r]): c0 by one ballot, the
+// ends inside the super-batch as bits of a per-wave LDS bitmap `bm`
+// (U * 64 bits), read back word-wise and counted with masked popcounts.
+template <int MODE, bool GLOBAL, int U>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
-                           volatile int32_t* mark, uint32_t& tag, uint32_t& hits) {
+                           uint32_t* bm, uint32_t& hits) {
   using P = Prober<MODE, GLOBAL>;
+  constexpr uint32_t SB = 64u * U;
   const int lane = lane_id();
   const int64_t T = A.T;
+  const uint64_t le = lanemask_le();
   uint32_t done = 0;
   while (done < len) {
     const uint32_t rem = len - done;
@@ -159,54 +160,96 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     const int64_t tje = tj + 1 < T ? tj + 1 : T;
     const uint64_t Ps = A.tprefix[tjs];
     const uint64_t Pe = A.tprefix[tje];
-    // end of lane's task relative to q, clamped to the remaining range
+    // end of the lane's task relative to q, clamped to the remaining range
     const uint64_t e64 = Pe - q;
     const uint32_t e = e64 > (uint64_t)rem ? rem : (uint32_t)e64;
     // col index of relative probe 0 for the lane's task (mod 2^32)
     const uint32_t tsj = A.tstart[tj < T ? tj : T - 1];
     const uint32_t cbase = tsj - (uint32_t)(Ps - q);
-    const uint32_t cover = (uint32_t)__shfl((int)e, 63, 64);
-    const bool last = cover == rem;
-    const uint32_t nb = last ? (cover + 63) / 64 : cover / 64;
-    if (nb == 0) break;  // unreachable when every task has a probe; guards progress
-    for (uint32_t bi = 0; bi < nb; ++bi) {
-      const uint32_t base = bi * 64;
-      const uint32_t r = base + (uint32_t)lane;
-      const uint32_t c0 = (uint32_t)__popcll(__ballot(e <= base));
-      const bool inner = e > base && e < base + 64;
-      const uint64_t any_inner = __ballot(inner);
-      uint32_t jl = c0;
-      if (any_inner) {
-        if (inner) mark[e - base] = (int32_t)tag;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint64_t M = __ballot(mark[lane] == (int32_t)tag);
-        ++tag;
-        jl = c0 + (uint32_t)__popcll(M & lanemask_le());
-        jl = jl < 63 ? jl : 63;  // only lanes past the range (r >= rem) can exceed 63
+    const uint32_t lim = (uint32_t)__shfl((int)e, 63, 64);  // probes of this window
+    if (lim == 0) break;  // unreachable when every task has a probe; guards progress
+    for (uint32_t sb = 0; sb < lim; sb += SB) {
+      const uint32_t c0 = (uint32_t)__popcll(__ballot(e <= sb));
+      const bool inner = e > sb && e < sb + SB;
+      uint32_t jl[U];
+      if (__ballot(inner) == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) jl[u] = c0;
+      } else {
+        if (inner) atomicOr(&bm[(e - sb) >> 5], 1u << ((e - sb) & 31));
+        wave_sync_lds();
+        uint32_t pre = c0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t M = (uint64_t)bm[2 * u] | ((uint64_t)bm[2 * u + 1] << 32);
+          const uint32_t j = pre + (uint32_t)__popcll(M & le);
+          jl[u] = j < 63 ? j : 63;  // only lanes past the window (r >= lim) can exceed 63
+          pre += (uint32_t)__popcll(M);
+        }
+        wave_sync_lds();
+        if (lane < (int)(SB / 32)) bm[lane] = 0;
+        wave_sync_lds();
       }
-      const uint32_t cb = (uint32_t)__shfl((int)cbase, (int)jl, 64);
-      uint32_t ts = 0;
-      if (P::kNeedTs) ts = (uint32_t)__shfl((int)tsj, (int)jl, 64);
-      const uint32_t pos = cb + r;
-      if (r < rem && pos < A.m) {
-        const int32_t k = A.col[pos];
-        P::probe(A, tr, k, pos, ts, hits);
+      uint32_t pos[U];
+      bool ok[U];
+      int32_t k[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t r = sb + 64u * u + (uint32_t)lane;
+        pos[u] = (uint32_t)__shfl((int)cbase, (int)jl[u], 64) + r;
+        ok[u] = r < lim && pos[u] < A.m;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) k[u] = ok[u] ? A.col[pos[u]] : -1;
+      // task start of every probe (support modes), read across lanes while all
+      // lanes are active: a bpermute must not run under a divergent mask
+      uint32_t ts[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        ts[u] = P::kNeedTs ? (uint32_t)__shfl((int)tsj, (int)jl[u], 64) : 0u;
+      if constexpr (!GLOBAL) {
+        // first slot of every lookup at once, then the (rare) probe chains
+        int32_t v[U];
+        uint32_t h[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          h[u] = (uint32_t)k[u] & tr.mask;
+          v[u] = tr.tab[h[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!ok[u]) continue;
+          int slot = -1;
+          if (v[u] == k[u]) {
+            slot = (int)h[u];
+          } else if (v[u] >= 0 && tr.D > 0) {
+            uint32_t hh = h[u];
+            for (int i = 1; i <= tr.D; ++i) {
+              hh = (hh + 1) & tr.mask;
+              const int32_t w = tr.tab[hh];
+              if (w == k[u]) {
+                slot = (int)hh;
+                break;
+              }
+              if (w < 0) break;
+            }
+          }
+          if (slot >= 0) P::credit(A, tr, slot, pos[u], ts[u], hits);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t where = ok[u] ? hbm_find(A.col, tr.rs, tr.d, k[u]) : -1;
+          if (where >= 0) P::credit(A, tr, (int)where, pos[u], ts[u], hits);
+        }
       }
     }
-    const uint32_t consumed = last ? rem : nb * 64;
-    t += (uint32_t)__popcll(__ballot(e <= consumed));
-    q += consumed;
-    done += consumed;
+    t += (uint32_t)__popcll(__ballot(e <= lim));
+    q += lim;
+    done += lim;
   }
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ void block_flush(uint32_t hits, unsigned long long* count) {
   __shared__ unsigned long long s_sum[kWaves];
@@ -229,12 +272,12 @@ __global__ __launch_bounds__(256) void k_count_packs(Args A, const int32_t* __re
   extern __shared__ int32_t smem[];
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  volatile int32_t* mark = smem + wave * 64;
+  uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
   const uint32_t Smax = 1u << log2Smax;
   int32_t* tab = smem + kMarkInts + (size_t)wave * Smax * (VALS ? 2 : 1);
   int32_t* val = tab + Smax;
-  mark[lane] = -1;
-  uint32_t tag = 0, hits = 0;
+  if (lane < kBmWords) bm[lane] = 0;
+  uint32_t hits = 0;
   const int64_t p = (int64_t)blockIdx.x * kWaves + wave;
   if (p < n_packs) {
     const uint32_t r0 = pack_ptr[p], r1 = pack_ptr[p + 1];
@@ -252,7 +295,7 @@ __global__ __launch_bounds__(256) void k_count_packs(Args A, const int32_t* __re
       const int64_t tl = A.tptr[b], th = A.tptr[b + 1];
       const uint64_t q0 = A.tprefix[tl], q1 = A.tprefix[th];
       TableRef tr{tab, val, mask, md, rs, d};
-      wave_probe<MODE, false>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), mark, tag, hits);
+      wave_probe<MODE, false, kU>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), bm, hits);
       wave_sync_lds();
     }
   }
@@ -266,12 +309,12 @@ __global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __
   __shared__ int s_D;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  volatile int32_t* mark = smem + wave * 64;
+  uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
   const CountItem* grp = items + (int64_t)blockIdx.x * kWaves;
   const int32_t b = grp[0].b;
   const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
-  mark[lane] = -1;
-  uint32_t tag = 0, hits = 0;
+  if (lane < kBmWords) bm[lane] = 0;
+  uint32_t hits = 0;
   TableRef tr{nullptr, nullptr, 0, 0, rs, d};
   if (!GLOBAL) {
     const uint32_t S = 1u << grp[0].log2S, mask = S - 1;
@@ -290,7 +333,8 @@ __global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __
     tr.D = s_D;
   }
   const CountItem it = grp[wave];
-  if (it.len) wave_probe<MODE, GLOBAL>(A, tr, it.t0, it.q0, it.len, mark, tag, hits);
+  wave_sync_lds();
+  if (it.len) wave_probe<MODE, GLOBAL, kU>(A, tr, it.t0, it.q0, it.len, bm, hits);
   block_flush(hits, A.count);
 }
 

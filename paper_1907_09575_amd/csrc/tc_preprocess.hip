@@ -104,17 +104,19 @@ __global__ void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
 }
 
 // Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
-// with row(i) >= r, row_ptr[n] = m.
+// with row(i) >= r (binary search per row), so row_ptr[n] = m.
 template <class K>
 __global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n,
                          int64_t* __restrict__ row_ptr) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  int64_t a = (int64_t)(keys[i] >> s);
-  int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> s);
-  for (int64_t r = prev + 1; r <= a; ++r) row_ptr[r] = i;
-  if (i == m - 1)
-    for (int64_t r = a + 1; r <= n; ++r) row_ptr[r] = m;
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)(keys[mid] >> s) < r) lo = mid + 1;
+    else hi = mid;
+  }
+  row_ptr[r] = lo;
 }
 
 __global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32_t* __restrict__ col) {
@@ -197,25 +199,30 @@ __device__ __forceinline__ int row_log2S(int64_t d) {
   return l < 6 ? 6 : l;
 }
 
-// Class of every hashed row b (-1 = no work) and the class's largest table.
-__global__ void k_classify(const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
-                           const int64_t* __restrict__ row_ptr, int64_t n, int8_t* __restrict__ cls,
-                           int* __restrict__ cls_log2S) {
+// Class of every hashed row b (-1 = no work) and the class's largest table
+// (maxima reduced per wave before one atomic per wave and class).
+__global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tptr,
+                                                  const uint64_t* __restrict__ tprefix,
+                                                  const int64_t* __restrict__ row_ptr, int64_t n,
+                                                  int8_t* __restrict__ cls, int* __restrict__ cls_log2S) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
-  if (W == 0) {
-    cls[b] = -1;
-    return;
+  int c = -1, l = 0;
+  if (b < n) {
+    uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+    if (W > 0) {
+      l = row_log2S(row_ptr[b + 1] - row_ptr[b]);
+      if (l > kMaxLog2S) c = CLS_GLOBAL;
+      else if (l > 12) c = CLS_WG_HUGE;
+      else if (W < kHeavyMin) c = l <= 9 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
+      else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
+    }
+    cls[b] = (int8_t)c;
   }
-  int l = row_log2S(row_ptr[b + 1] - row_ptr[b]);
-  int c;
-  if (l > kMaxLog2S) c = CLS_GLOBAL;
-  else if (l > 12) c = CLS_WG_HUGE;
-  else if (W < kHeavyMin) c = l <= 9 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
-  else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
-  cls[b] = (int8_t)c;
-  atomicMax(&cls_log2S[c], l);
+#pragma unroll
+  for (int k = 0; k < NUM_CLASSES; ++k) {
+    int mk = wave_max(c == k ? l : 0);
+    if (lane_id() == 0 && mk > 0) atomicMax(&cls_log2S[k], mk);
+  }
 }
 
 __device__ __forceinline__ uint32_t wg_parts(uint64_t W) {
@@ -426,7 +433,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       bool alt = radix_sort<uint64_t, NoVal>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
                                              0, 2 * s, st);
       if (alt) okey = E.as<uint64_t>();
-      hipLaunchKernelGGL((k_bounds<uint64_t>), dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, n,
+      hipLaunchKernelGGL((k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
       hipLaunchKernelGGL(k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
     } else {
@@ -466,7 +473,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       hipLaunchKernelGGL(k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T, g->tstart,
                          tlen.as<uint32_t>());
       device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
-      hipLaunchKernelGGL((k_bounds<uint32_t>), dim3(grid_for(T)), dim3(kT), 0, st, skey, T, 0, n,
+      hipLaunchKernelGGL((k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, skey, T, 0, n,
                          g->tptr);
       TC_HIP(hipGetLastError());
       g->probes = (int64_t)read_scalar(g->tprefix + T, st);
