@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark: exact triangle counting of an RMAT scale-24 graph on one MI355X.
+
+One step = the whole single-graph hot path on a resident input: tc_preprocess
+(raw int32 edge list in HBM -> simple graph -> degree order -> upper CSR ->
+tasks and work items) + tc_count (exact int64 total) + tc_graph_free. The
+input is a seeded synthetic RMAT graph (a, b, c, d = 0.57, 0.19, 0.19, 0.05,
+edge factor 16), the shape of the paper's Graph500 inputs. `value` is raw input
+pairs per second over whole steps; the count phase alone (the paper's tct) and
+preprocessing (ppt) are reported beside it.
+
+Roofline: every library launch in the timed steps is bracketed by HIP events
+(tc_timer_attach); the kernel with the largest total time is the dominant one
+and its algorithmic bytes per launch over its average event
+time give `achieved`.
+
+cpu_baseline: the CPU oracle (plain C, list-based intersection) timed end to
+end (its own preprocessing + count) on a bounded sample: the RMAT graph of the
+same generator at a smaller scale (default 20, 1/16 of the pairs).
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--scale 24]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact-count edges/s + HBM GB/s vs peak, RMAT scale 24; batched/served vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_count_rmat24.json")
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--scale", type=int, default=24)
+    p.add_argument("--edge-factor", type=int, default=16)
+    p.add_argument("--seed", type=int, default=1)
+    p.add_argument("--cpu-scale", type=int, default=20)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
+    p.add_argument("--gen-threads", type=int, default=16)
+    return p.parse_args()
+
+
+def count_kernel_bytes(stats: dict, cls: str) -> int:
+    """Algorithmic bytes of one launch of count:<cls>: every probe reads one
+    int32 of U (4 B); every hashed row is read once to build its table (4 B per
+    key) and its row bounds and task range once (32 B); every task reads its
+    start (4 B) and its prefix entry (8 B)."""
+    s = stats[cls]
+    return 4 * s["probes"] + 4 * s["table_keys"] + 12 * s["tasks"] + 32 * s["rows"]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("tc_count.hip", "tc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1907_09575_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
+    was taken on the current count-kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_digest") != source_digest():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scale: int, edge_factor: int, seed: int, threads: int, bench_scale: int):
+    import graphgen
+    import oracle
+
+    src, dst = graphgen.rmat(scale, edge_factor=edge_factor, seed=seed, threads=threads)
+    n = 1 << scale
+    t0 = time.perf_counter()
+    U = oracle.preprocess(src, dst, n)
+    t1 = time.perf_counter()
+    T = oracle.count(U, threads=threads)
+    t2 = time.perf_counter()
+    return {
+        "value": len(src) / (t2 - t0),
+        "unit": "edges/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "RMAT scale %d (same generator and parameters, %d raw pairs = 1/%d of the benchmark "
+                  "input), oracle preprocessing + count end to end; count phase alone %.3g edges/s "
+                  "(m=%d, T=%d, %.2f s + %.2f s)" % (
+                      scale, len(src), 1 << max(0, bench_scale - scale), U.m / (t2 - t1), U.m, T,
+                      t1 - t0, t2 - t1),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the count would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1907_09575_amd as tc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = 1 << args.scale
+    print("generating RMAT scale %d ..." % args.scale, file=sys.stderr, flush=True)
+    src_h, dst_h = graphgen.rmat(args.scale, edge_factor=args.edge_factor, seed=args.seed,
+                                 threads=args.gen_threads)
+    m_raw = len(src_h)
+    src = torch.from_numpy(src_h).to(dev)
+    dst = torch.from_numpy(dst_h).to(dev)
+    del src_h, dst_h
+    out = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step():
+        g = tc.tc_preprocess(src, dst, n)
+        tc.tc_count(g, out)
+        return g
+
+    for i in range(args.warmup):
+        g = step()
+        torch.cuda.synchronize()
+        print("warmup %d: T=%d" % (i, int(out.item())), file=sys.stderr, flush=True)
+        info = g.info()
+        cstats = tc.tc_graph_class_stats(g)
+        g.free()
+
+    timer = tc.Timer(capacity=16384)
+    counts = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with timer:
+        for i in range(args.steps):
+            g = step()
+            counts.append(out.clone())
+            g.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = timer.summary()
+    timer.free()
+    counts = [int(c.item()) for c in counts]
+    assert len(set(counts)) == 1, "counts differ between steps: %s" % counts
+    T = counts[0]
+    if args.warmup == 0:
+        g = step()
+        torch.cuda.synchronize()
+        info = g.info()
+        cstats = tc.tc_graph_class_stats(g)
+        g.free()
+
+    step_s = (t1 - t0) / args.steps
+    count_ms = sum(v["total_ms"] for k, v in kern.items() if k.startswith("count:")) / args.steps
+    pre_kernel_ms = sum(v["total_ms"] for k, v in kern.items()
+                        if not k.startswith("count:") and not k.startswith("_") and k != "zero_i64") / args.steps
+    pre_ms = step_s * 1e3 - count_ms  # wall time of the step outside the count kernels
+    launches = {k: v for k, v in kern.items() if not k.startswith("_")}
+    dom = max(launches, key=lambda k: launches[k]["total_ms"])
+    roofline = None
+    if dom.startswith("count:"):
+        cls = dom.split(":", 1)[1]
+        bytes_per_launch = count_kernel_bytes(cstats, cls)
+        avg_s = launches[dom]["avg_ms"] / 1e3
+        achieved = bytes_per_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(dom), "algorithmic_bytes_per_launch": bytes_per_launch,
+                    "avg_launch_ms": round(launches[dom]["avg_ms"], 4)}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": None, "traffic": None,
+                    "note": "dominant kernel is not a count kernel"}
+
+    # whole count phase against the same roofline
+    count_bytes = sum(count_kernel_bytes(cstats, c) for c in cstats if cstats[c]["rows"])
+    result = {
+        "metric": METRIC,
+        "value": m_raw / step_s,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "rmat%d_ef%d_preprocess_count" % (args.scale, args.edge_factor),
+                   "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "n": n, "m_raw": m_raw, "seed": args.seed,
+                   "parallelism": "single_gpu"},
+        "roofline": roofline,
+        "triangles": T,
+        "m": info["m"],
+        "wedges_plus": info["wedges_plus"],
+        "probes": info["probes"],
+        "count_ms": count_ms,
+        "preprocess_ms": pre_ms,
+        "preprocess_kernel_ms": pre_kernel_ms,
+        "count_edges_per_s": info["m"] / (count_ms / 1e3) if count_ms > 0 else None,
+        "count_raw_edges_per_s": m_raw / (count_ms / 1e3) if count_ms > 0 else None,
+        "count_probes_per_s": info["probes"] / (count_ms / 1e3) if count_ms > 0 else None,
+        "count_phase_alg_GBps": count_bytes / (count_ms / 1e3) / 1e9 if count_ms > 0 else None,
+        "kernels_top": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"]}
+                        for k, v in sorted(launches.items(), key=lambda kv: -kv[1]["total_ms"])[:6]},
+    }
+    if not args.no_cpu_baseline:
+        print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        result["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, threads,
+                                              args.scale)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -167,6 +167,47 @@ void tc_batch_free(tc_batch* plan);
 tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
                            const char* tuning_json, void* stream);
 
+/* ---- work classes and phase timers (profiling) ------------------------------ */
+
+/* tc_count splits the hashed rows j into work classes, one kernel launch each:
+ * 0 pack_small / 1 pack_large - light rows packed, one wave per pack;
+ * 2 wg_small / 3 wg_large / 4 wg_huge - heavy rows, a work-group's four waves
+ *   share one LDS table of the row; 5 global - rows whose table exceeds LDS,
+ *   looked up by binary search in HBM. */
+#define TC_NUM_CLASSES 6
+
+typedef struct {
+  int64_t workgroups;   /* work-groups of the class's launch */
+  int64_t rows;         /* hashed rows j in the class */
+  int64_t table_keys;   /* sum of |U_j| over those rows (table build reads) */
+  int64_t tasks;        /* nonzeros (i, j) whose probes the class performs */
+  int64_t probes;       /* lookups the class performs */
+  int64_t table_slots;  /* largest table of the class (slots) */
+} tc_class_stats;
+
+/* Per-class work of a graph (host array of TC_NUM_CLASSES entries). */
+tc_status tc_graph_class_stats(const tc_graph* g, tc_class_stats* out);
+/* Name of a class ("pack_small", ...) or NULL. */
+const char* tc_class_name(int32_t cls);
+
+/* Phase timer: while attached to the calling host thread, every kernel the
+ * library launches from that thread is bracketed by two HIP events recorded
+ * on the launch's stream and tagged with the kernel's name (count kernels as
+ * "count:<class>", "support_full:<class>", ...). Up to `capacity` launches are
+ * recorded; later ones are counted as dropped. */
+typedef struct tc_timer tc_timer;
+tc_status tc_timer_create(int32_t capacity, tc_timer** out);
+/* Attach `t` to the calling thread (NULL detaches). */
+tc_status tc_timer_attach(tc_timer* t);
+/* Waits for the recorded events and writes a JSON object
+ * {"<name>": {"launches": n, "total_ms": x, "avg_ms": y, "min_ms": a,
+ *  "max_ms": b}, ..., "_dropped": d} into buf (NUL-terminated; TC_EINVAL if
+ * it does not fit). */
+tc_status tc_timer_summary(tc_timer* t, char* buf, int64_t buf_bytes);
+/* Forget recorded launches (events are reused). */
+tc_status tc_timer_reset(tc_timer* t);
+void tc_timer_free(tc_timer* t);
+
 /* ---- misc ----------------------------------------------------------------- */
 
 void tc_graph_free(tc_graph* g);

@@ -20,7 +20,8 @@ import torch
 __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
-    "tc_count_batched", "tc_graph_free", "TC_SUPPORT_FULL", "TC_SUPPORT_ORIENTED", "library_path",
+    "tc_count_batched", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
+    "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +30,7 @@ library_path = os.path.join(_HERE, "libtc.so")
 TC_OK, TC_EINVAL, TC_ENOMEM, TC_EDEVICE, TC_EOVERFLOW, TC_EBUSY, TC_ECANCELED = range(7)
 TC_SUPPORT_FULL = 0
 TC_SUPPORT_ORIENTED = 1
+TC_NUM_CLASSES = 6
 
 if not os.path.exists(library_path):
     raise ImportError(
@@ -64,6 +66,13 @@ _sig("tc_batch_count", [_P, _P, _P])
 _sig("tc_batch_free", [_P], None)
 _sig("tc_count_batched", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, _P])
 _sig("tc_graph_free", [_P], None)
+_sig("tc_graph_class_stats", [_P, _P])
+_sig("tc_class_name", [_I32], ctypes.c_char_p)
+_sig("tc_timer_create", [_I32, ctypes.POINTER(_P)])
+_sig("tc_timer_attach", [_P])
+_sig("tc_timer_summary", [_P, ctypes.c_char_p, _I64])
+_sig("tc_timer_reset", [_P])
+_sig("tc_timer_free", [_P], None)
 _sig("tc_status_string", [ctypes.c_int], ctypes.c_char_p)
 _sig("tc_last_error", [], ctypes.c_char_p)
 _sig("tc_version", [], ctypes.c_char_p)
@@ -288,3 +297,62 @@ def tc_count_batched(graphs, counts: torch.Tensor | None = None, tuning=None, st
 
 def tc_graph_free(g: Graph):
     g.free()
+
+
+class _ClassStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "workgroups", "rows", "table_keys", "tasks", "probes", "table_slots")]
+
+
+def tc_graph_class_stats(g: Graph) -> dict:
+    """{class name: {workgroups, rows, table_keys, tasks, probes, table_slots}}."""
+    arr = (_ClassStats * TC_NUM_CLASSES)()
+    _check(_lib.tc_graph_class_stats(g.handle, ctypes.cast(arr, _P)), "tc_graph_class_stats")
+    out = {}
+    for c in range(TC_NUM_CLASSES):
+        out[_lib.tc_class_name(c).decode()] = {n: int(getattr(arr[c], n)) for n, _ in _ClassStats._fields_}
+    return out
+
+
+class Timer:
+    """Phase timer: HIP events around every library launch made by this thread
+    while attached (use as a context manager)."""
+
+    def __init__(self, capacity: int = 4096):
+        h = ctypes.c_void_p()
+        _check(_lib.tc_timer_create(int(capacity), ctypes.byref(h)), "tc_timer_create")
+        self._h = h
+
+    def attach(self):
+        _check(_lib.tc_timer_attach(self._h), "tc_timer_attach")
+
+    @staticmethod
+    def detach():
+        _check(_lib.tc_timer_attach(None), "tc_timer_attach")
+
+    def __enter__(self):
+        self.attach()
+        return self
+
+    def __exit__(self, *exc):
+        self.detach()
+
+    def summary(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(_lib.tc_timer_summary(self._h, buf, len(buf)), "tc_timer_summary")
+        return json.loads(buf.value.decode())
+
+    def reset(self):
+        _check(_lib.tc_timer_reset(self._h), "tc_timer_reset")
+
+    def free(self):
+        if self._h:
+            _lib.tc_timer_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -7,6 +7,9 @@
 
 namespace tc {
 
+const char* const kClassNames[NUM_CLASSES] = {"pack_small", "pack_large", "wg_small",
+                                              "wg_large",   "wg_huge",    "global"};
+
 static thread_local std::string g_last_error;
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -83,6 +86,27 @@ tc_status tc_edge_support(const tc_graph* gh, int mode, int32_t* d_support, int6
     tc::launch_count(g, mode == TC_SUPPORT_FULL ? tc::MODE_SUPPORT_FULL : tc::MODE_SUPPORT_ORIENTED,
                      d_count, d_support, st);
   })
+}
+
+tc_status tc_graph_class_stats(const tc_graph* gh, tc_class_stats* out) {
+  TC_API_GUARD({
+    TC_REQUIRE(gh && out, TC_EINVAL, "tc_graph_class_stats: null argument");
+    const tc::Graph& g = *tc::G(gh);
+    for (int c = 0; c < tc::NUM_CLASSES; ++c) {
+      tc_class_stats& o = out[c];
+      const bool pack = c == tc::CLS_PACK_SMALL || c == tc::CLS_PACK_LARGE;
+      o.workgroups = pack ? (g.n_packs[c] + tc::kWaves - 1) / tc::kWaves : g.n_items[c] / tc::kWaves;
+      o.rows = g.cls_stats[c][0];
+      o.table_keys = g.cls_stats[c][1];
+      o.tasks = g.cls_stats[c][2];
+      o.probes = g.cls_stats[c][3];
+      o.table_slots = g.cls_stats[c][0] ? (int64_t)1 << g.cls_log2S[c] : 0;
+    }
+  })
+}
+
+const char* tc_class_name(int32_t cls) {
+  return (cls >= 0 && cls < tc::NUM_CLASSES) ? tc::kClassNames[cls] : nullptr;
 }
 
 void tc_graph_free(tc_graph* gh) {

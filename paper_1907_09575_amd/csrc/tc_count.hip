@@ -80,17 +80,28 @@ __device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int
 template <bool VALS>
 __device__ int build_table(int32_t* tab, int32_t* val, uint32_t mask, const int32_t* __restrict__ col,
                            int64_t rs, int64_t d, int tid, int nt) {
+  // keys are fetched kB at a time so that their loads overlap, then inserted
+  constexpr int kB = 8;
   int md = 0;
-  for (int64_t i = tid; i < d; i += nt) {
-    const int32_t k = col[rs + i];
-    uint32_t h = (uint32_t)k & mask;
-    int disp = 0;
-    while (atomicCAS(&tab[h], -1, k) != -1) {
-      h = (h + 1) & mask;
-      ++disp;
+  for (int64_t i0 = tid; i0 < d; i0 += (int64_t)kB * nt) {
+    int32_t key[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int64_t i = i0 + (int64_t)j * nt;
+      key[j] = i < d ? col[rs + i] : -1;
     }
-    if (VALS) val[h] = (int32_t)(rs + i);
-    md = disp > md ? disp : md;
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      if (key[j] < 0) continue;
+      uint32_t h = (uint32_t)key[j] & mask;
+      int disp = 0;
+      while (atomicCAS(&tab[h], -1, key[j]) != -1) {
+        h = (h + 1) & mask;
+        ++disp;
+      }
+      if (VALS) val[h] = (int32_t)(rs + i0 + (int64_t)j * nt);
+      md = disp > md ? disp : md;
+    }
   }
   return md;
 }
@@ -345,6 +356,15 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// launch names seen by the phase timer: "<mode>:<class>"
+const char* const kLaunchNames[3][NUM_CLASSES] = {
+    {"count:pack_small", "count:pack_large", "count:wg_small", "count:wg_large", "count:wg_huge",
+     "count:global"},
+    {"support_full:pack_small", "support_full:pack_large", "support_full:wg_small",
+     "support_full:wg_large", "support_full:wg_huge", "support_full:global"},
+    {"support_oriented:pack_small", "support_oriented:pack_large", "support_oriented:wg_small",
+     "support_oriented:wg_large", "support_oriented:wg_huge", "support_oriented:global"}};
+
 template <int MODE>
 void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
@@ -357,21 +377,21 @@ void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A, g.pack_rows[c],
+    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A, g.pack_rows[c],
                        g.pack_ptr[c], g.n_packs[c], l);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (g.n_items[c] == 0) continue;
     const unsigned grid = (unsigned)(g.n_items[c] / kWaves);
     if (c == CLS_GLOBAL) {
-      hipLaunchKernelGGL((k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes, st, A,
+      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes, st, A,
                          g.items[c]);
     } else {
       const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << g.cls_log2S[c]) * (VALS ? 2 : 1);
       if (lds > 65536)
         TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL((k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A, g.items[c]);
+      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A, g.items[c]);
     }
   }
   TC_HIP(hipGetLastError());
@@ -381,9 +401,9 @@ void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
 
 void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_support,
                   hipStream_t st) {
-  if (d_count) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, d_count);
+  if (d_count) TC_LAUNCH("zero_i64", k_zero_i64, dim3(1), dim3(1), 0, st, d_count);
   if (mode != MODE_COUNT && g.m > 0)
-    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support, g.m);
+    TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support, g.m);
   TC_HIP(hipGetLastError());
   if (g.n_tasks == 0) return;
   Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tptr, g.n_tasks, (uint32_t)g.m,

@@ -37,6 +37,23 @@ void set_last_error(const std::string& msg);
     if (!(cond)) throw ::tc::Error((status), (msg));        \
   } while (0)
 
+// ---- launches -----------------------------------------------------------------
+// Every kernel launch goes through TC_LAUNCH so that an attached phase timer
+// (tc_timer_attach) can bracket it with events.
+struct LaunchScope {
+  int slot = -1;
+  void* timer = nullptr;
+  hipStream_t st = nullptr;
+  LaunchScope(const char* name, hipStream_t s);
+  ~LaunchScope();
+};
+
+#define TC_LAUNCH(name, kern, grid, block, lds, st, ...)          \
+  do {                                                           \
+    ::tc::LaunchScope _tc_ls((name), (st));                      \
+    hipLaunchKernelGGL(kern, grid, block, lds, st, __VA_ARGS__); \
+  } while (0)
+
 // ---- work items --------------------------------------------------------------
 // One wave's share of the probes of one hashed row b: the probes with global
 // index [q0, q0 + len) of the task list, where task t0 contains probe q0.
@@ -63,9 +80,9 @@ enum ItemClass : int {
 
 constexpr int kWaves = 4;               // waves per work-group in every count launch
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
-constexpr uint32_t kWaveChunk = 8192;   // target probes per wave item of a heavy row
-constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
-constexpr uint64_t kPackTarget = 2048;  // target probes per pack of light rows
+constexpr uint32_t kWaveChunk = 32768;  // target probes per wave item of a heavy row
+constexpr uint64_t kHeavyMin = 8192;    // rows with fewer probes than this are packed
+constexpr uint64_t kPackTarget = 8192;  // target probes per pack of light rows
 
 // Device-resident graph. All arrays live in one allocation (`arena`).
 struct Graph {
@@ -95,7 +112,12 @@ struct Graph {
   CountItem* items[NUM_CLASSES] = {};
   int64_t n_items[NUM_CLASSES] = {};
   int32_t cls_log2S[NUM_CLASSES] = {};
+
+  // per class: rows, table keys, tasks, probes (host copy)
+  int64_t cls_stats[NUM_CLASSES][4] = {};
 };
+
+extern const char* const kClassNames[NUM_CLASSES];
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 

@@ -5,7 +5,8 @@
 //      (s = ceil(log2 n)); self loops and invalid ids become a sentinel.
 //   2. stable LSD radix sort of the 2s-bit keys, adjacent-unique compaction:
 //      the simple undirected graph of Section 2 / Section 6.1.
-//   3. degrees by atomic histogram; rank = position in the order (degree, id)
+//   3. degrees from run lengths of the sorted keys (lower endpoints) and of a
+//      radix-sorted copy of the upper endpoints; rank = position in the order (degree, id)
 //      (a stable radix sort of degree * 2^s + id on the degree bits): the
 //      non-decreasing degree relabelling of Section 5.3.
 //   4. orientation by rank (Section 5.3: the global position stands in for the
@@ -73,13 +74,17 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_degree(const uint64_t* __restrict__ E, int64_t m, int s, uint32_t* __restrict__ deg) {
+__global__ void k_hi_keys(const uint64_t* __restrict__ E, int64_t m, int s, uint32_t* __restrict__ hk) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint64_t mask = (1ull << s) - 1;
-  uint64_t e = E[i];
-  atomicAdd(&deg[e >> s], 1u);
-  atomicAdd(&deg[e & mask], 1u);
+  if (i < m) hk[i] = (uint32_t)(E[i] & ((1ull << s) - 1));
+}
+
+// deg(v) = (edges whose lower endpoint is v) + (edges whose upper endpoint is v),
+// both read off row pointers of sorted key lists.
+__global__ void k_deg_from_bounds(const int64_t* __restrict__ lo_ptr, const int64_t* __restrict__ hi_ptr,
+                                  int64_t n, uint32_t* __restrict__ deg) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) deg[v] = (uint32_t)((lo_ptr[v + 1] - lo_ptr[v]) + (hi_ptr[v + 1] - hi_ptr[v]));
 }
 
 __global__ void k_rank_keys(const uint32_t* __restrict__ deg, int64_t n, int s,
@@ -223,6 +228,45 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
     int mk = wave_max(c == k ? l : 0);
     if (lane_id() == 0 && mk > 0) atomicMax(&cls_log2S[k], mk);
   }
+}
+
+// Per-class sums (rows, table keys, tasks, probes): LDS accumulation per
+// block, one partial row per block, then a column reduction.
+constexpr int kStatCols = NUM_CLASSES * 4;
+
+__global__ __launch_bounds__(256) void k_class_stats(const int8_t* __restrict__ cls, int64_t n,
+                                                     const int64_t* __restrict__ tptr,
+                                                     const uint64_t* __restrict__ tprefix,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     unsigned long long* __restrict__ partial) {
+  __shared__ unsigned long long acc[kStatCols];
+  if (threadIdx.x < kStatCols) acc[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) {
+    const int c = cls[b];
+    if (c >= 0) {
+      atomicAdd(&acc[c * 4 + 0], 1ull);
+      atomicAdd(&acc[c * 4 + 1], (unsigned long long)(row_ptr[b + 1] - row_ptr[b]));
+      atomicAdd(&acc[c * 4 + 2], (unsigned long long)(tptr[b + 1] - tptr[b]));
+      atomicAdd(&acc[c * 4 + 3], (unsigned long long)(tprefix[tptr[b + 1]] - tprefix[tptr[b]]));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatCols) partial[(int64_t)blockIdx.x * kStatCols + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cols(const unsigned long long* __restrict__ partial,
+                                                     int64_t rows, int cols,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long s_w[4];
+  const int c = blockIdx.x;
+  unsigned long long v = 0;
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) v += partial[r * cols + c];
+  v = wave_sum(v);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
 __device__ __forceinline__ uint32_t wg_parts(uint64_t W) {
@@ -373,7 +417,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     if (m_raw > 0) {
-      hipLaunchKernelGGL(k_canon, dim3(grid_for(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
+      TC_LAUNCH("canon", k_canon, dim3(grid_for(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
                          sent, ka.as<uint64_t>(), d_err);
       TC_HIP(hipGetLastError());
     }
@@ -384,7 +428,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
     if (m_raw > 0) {
-      hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted, m_raw, sent,
+      TC_LAUNCH("unique_flags", k_unique_flags, dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted, m_raw, sent,
                          flags.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, d_tot32, st);
       m = read_scalar(d_tot32, st);
@@ -392,7 +436,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     TC_REQUIRE(m < (int64_t)0x7FFFFFFF, TC_EOVERFLOW, "tc_preprocess: 2^31 or more edges");
     E.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
     if (m > 0)
-      hipLaunchKernelGGL((k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
+      TC_LAUNCH("compact", (k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
                          flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, E.as<uint64_t>());
     TC_HIP(hipGetLastError());
     TC_HIP(hipStreamSynchronize(st));
@@ -403,17 +447,33 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   g->perm = g->owned.alloc<int32_t>(n);
   {
     DevBuf deg(sizeof(uint32_t) * (size_t)n);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, 0u);
-    if (m > 0)
-      hipLaunchKernelGGL(k_degree, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
-                         deg.as<uint32_t>());
+    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, 0u);
+    if (m > 0) {
+      // E is sorted by (lo, hi): lower-endpoint counts are run lengths; upper
+      // endpoints are counted after a radix sort of their ids (no atomics)
+      DevBuf lo_ptr(sizeof(int64_t) * (size_t)(n + 1)), hi_ptr(sizeof(int64_t) * (size_t)(n + 1));
+      TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, E.as<uint64_t>(),
+                         m, s, n, lo_ptr.as<int64_t>());
+      DevBuf ha(sizeof(uint32_t) * (size_t)m), hb(sizeof(uint32_t) * (size_t)m);
+      TC_LAUNCH("hi_keys", k_hi_keys, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
+                         ha.as<uint32_t>());
+      TC_HIP(hipGetLastError());
+      bool halt = radix_sort<uint32_t, NoVal>(ha.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
+                                              0, s, st);
+      TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st,
+                         halt ? hb.as<uint32_t>() : ha.as<uint32_t>(), m, 0, n, hi_ptr.as<int64_t>());
+      TC_LAUNCH("deg_from_bounds", k_deg_from_bounds, dim3(grid_for(n)), dim3(kT), 0, st, lo_ptr.as<int64_t>(),
+                         hi_ptr.as<int64_t>(), n, deg.as<uint32_t>());
+      TC_HIP(hipGetLastError());
+      TC_HIP(hipStreamSynchronize(st));
+    }
     DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
-    hipLaunchKernelGGL(k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
+    TC_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
                        ra.as<uint64_t>());
     TC_HIP(hipGetLastError());
     bool alt = radix_sort<uint64_t, NoVal>(ra.as<uint64_t>(), rb.as<uint64_t>(), nullptr, nullptr, n,
                                            s, 2 * s, st);
-    hipLaunchKernelGGL(k_perm, dim3(grid_for(n)), dim3(kT), 0, st,
+    TC_LAUNCH("perm", k_perm, dim3(grid_for(n)), dim3(kT), 0, st,
                        alt ? rb.as<uint64_t>() : ra.as<uint64_t>(), n, s, g->perm);
     TC_HIP(hipGetLastError());
     TC_HIP(hipStreamSynchronize(st));
@@ -426,21 +486,21 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   const uint64_t* okey = ok.as<uint64_t>();
   {
     if (m > 0) {
-      hipLaunchKernelGGL(k_orient, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
+      TC_LAUNCH("orient", k_orient, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
                          g->perm, ok.as<uint64_t>());
       TC_HIP(hipGetLastError());
       // E's buffer is the ping-pong partner
       bool alt = radix_sort<uint64_t, NoVal>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
                                              0, 2 * s, st);
       if (alt) okey = E.as<uint64_t>();
-      hipLaunchKernelGGL((k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
+      TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
-      hipLaunchKernelGGL(k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
+      TC_LAUNCH("col", k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
     } else {
-      hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->row_ptr, n + 1,
+      TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->row_ptr, n + 1,
                          (int64_t)0);
     }
-    hipLaunchKernelGGL(k_row_stats, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n, d_wplus, d_maxd);
+    TC_LAUNCH("row_stats", k_row_stats, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n, d_wplus, d_maxd);
     TC_HIP(hipGetLastError());
   }
 
@@ -451,7 +511,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     if (m > 0) {
-      hipLaunchKernelGGL(k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
+      TC_LAUNCH("task_flags", k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
                          flags.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m, d_tot32, st);
       T = read_scalar(d_tot32, st);
@@ -462,7 +522,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     if (T > 0) {
       DevBuf tk(sizeof(uint32_t) * (size_t)T), tk2(sizeof(uint32_t) * (size_t)T);
       DevBuf tv(sizeof(uint64_t) * (size_t)T), tv2(sizeof(uint64_t) * (size_t)T);
-      hipLaunchKernelGGL(k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
+      TC_LAUNCH("task_emit", k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
                          flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
       TC_HIP(hipGetLastError());
       bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tk2.as<uint32_t>(), tv.as<uint64_t>(),
@@ -470,15 +530,15 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       const uint32_t* skey = alt ? tk2.as<uint32_t>() : tk.as<uint32_t>();
       const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv.as<uint64_t>();
       DevBuf tlen(sizeof(uint32_t) * (size_t)T);
-      hipLaunchKernelGGL(k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T, g->tstart,
+      TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T, g->tstart,
                          tlen.as<uint32_t>());
       device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
-      hipLaunchKernelGGL((k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, skey, T, 0, n,
+      TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, skey, T, 0, n,
                          g->tptr);
       TC_HIP(hipGetLastError());
       g->probes = (int64_t)read_scalar(g->tprefix + T, st);
     } else {
-      hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->tptr, n + 1, (int64_t)0);
+      TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->tptr, n + 1, (int64_t)0);
       TC_HIP(hipMemsetAsync(g->tprefix, 0, sizeof(uint64_t), st));
       g->probes = 0;
     }
@@ -493,16 +553,27 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf cls(sizeof(int8_t) * (size_t)n);
     DevBuf clsl(sizeof(int) * NUM_CLASSES);
     TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(kT), 0, st, g->tptr, g->tprefix,
+    TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, g->tptr, g->tprefix,
                        g->row_ptr, n, cls.as<int8_t>(), clsl.as<int>());
     TC_HIP(hipGetLastError());
     int h_cl[NUM_CLASSES];
     TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
-    TC_HIP(hipStreamSynchronize(st));
+    {
+      const int64_t nb = (int64_t)grid_for(n);
+      DevBuf part(sizeof(unsigned long long) * (size_t)nb * kStatCols);
+      DevBuf sums(sizeof(unsigned long long) * kStatCols);
+      TC_LAUNCH("class_stats", k_class_stats, dim3((unsigned)nb), dim3(kT), 0, st, cls.as<int8_t>(), n,
+                g->tptr, g->tprefix, g->row_ptr, part.as<unsigned long long>());
+      TC_LAUNCH("reduce_cols", k_reduce_cols, dim3(kStatCols), dim3(kT), 0, st,
+                part.as<unsigned long long>(), nb, kStatCols, sums.as<unsigned long long>());
+      TC_HIP(hipGetLastError());
+      TC_HIP(hipMemcpyAsync(&g->cls_stats[0][0], sums.p, sizeof(g->cls_stats), hipMemcpyDeviceToHost, st));
+      TC_HIP(hipStreamSynchronize(st));
+    }
     DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
     for (int c = 0; c < NUM_CLASSES; ++c) {
       g->cls_log2S[c] = h_cl[c];
-      hipLaunchKernelGGL(k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+      TC_LAUNCH("class_count", k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
                          g->tptr, g->tprefix, cnt.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
                                            offs.as<uint32_t>() + n, st);
@@ -510,19 +581,19 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       if (total == 0) continue;
       if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
         int32_t* rows = g->owned.alloc<int32_t>(total);
-        hipLaunchKernelGGL(k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+        TC_LAUNCH("class_rows", k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
                            offs.as<uint32_t>(), rows);
         DevBuf w(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
-        hipLaunchKernelGGL(k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tptr,
+        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tptr,
                            g->tprefix, w.as<uint64_t>());
         device_excl_scan<uint64_t, uint64_t>(w.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
         DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
-        hipLaunchKernelGGL(k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
+        TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
                            total, (uint64_t)kPackTarget, pf.as<uint32_t>());
         device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
         const int64_t np = read_scalar(d_tot32, st);
         uint32_t* pack_ptr = g->owned.alloc<uint32_t>(np + 1);
-        hipLaunchKernelGGL(k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
+        TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
                            pp.as<uint32_t>(), total, pack_ptr, np);
         TC_HIP(hipGetLastError());
         TC_HIP(hipStreamSynchronize(st));
@@ -533,7 +604,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
         g->pack_log2S[c] = h_cl[c];
       } else {
         CountItem* items = g->owned.alloc<CountItem>(total);
-        hipLaunchKernelGGL(k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(), n,
+        TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(), n,
                            total, g->tptr, g->tprefix, g->row_ptr, items);
         TC_HIP(hipGetLastError());
         TC_HIP(hipStreamSynchronize(st));

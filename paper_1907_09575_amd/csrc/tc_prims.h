@@ -177,10 +177,10 @@ void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStrea
   }
   int64_t nb = div_up(n, kScanTile);
   DevBuf part(sizeof(Tout) * (size_t)nb);
-  hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
+  TC_LAUNCH("scan_reduce", (k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
                      part.as<Tout>());
-  hipLaunchKernelGGL((k_scan_partials<Tout>), dim3(1), dim3(256), 0, st, part.as<Tout>(), nb, total);
-  hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
+  TC_LAUNCH("scan_partials", (k_scan_partials<Tout>), dim3(1), dim3(256), 0, st, part.as<Tout>(), nb, total);
+  TC_LAUNCH("scan_final", (k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
                      part.as<Tout>(), out);
   TC_HIP(hipGetLastError());
   TC_HIP(hipStreamSynchronize(st));  // `part` is freed on return
@@ -328,15 +328,15 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
   for (int shift = bit_lo; shift < bit_hi; shift += 8) {
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
-    hipLaunchKernelGGL((k_rs_hist<K>), dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, dmask,
+    TC_LAUNCH("rs_hist", (k_rs_hist<K>), dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, dmask,
                        hist.as<uint32_t>(), nb);
-    hipLaunchKernelGGL((k_scan_reduce<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
+    TC_LAUNCH("scan_reduce", (k_scan_reduce<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
                        hist.as<uint32_t>(), hn, part.as<uint32_t>());
-    hipLaunchKernelGGL((k_scan_partials<uint32_t>), dim3(1), dim3(256), 0, st, part.as<uint32_t>(),
+    TC_LAUNCH("scan_partials", (k_scan_partials<uint32_t>), dim3(1), dim3(256), 0, st, part.as<uint32_t>(),
                        pnb, (uint32_t*)nullptr);
-    hipLaunchKernelGGL((k_scan_final<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
+    TC_LAUNCH("scan_final", (k_scan_final<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
                        hist.as<uint32_t>(), hn, part.as<uint32_t>(), offs.as<uint32_t>());
-    hipLaunchKernelGGL((k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, st, ka, kb, va, vb, n,
+    TC_LAUNCH("rs_scatter", (k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, st, ka, kb, va, vb, n,
                        shift, dmask, hist.as<uint32_t>(), offs.as<uint32_t>(), nb);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
