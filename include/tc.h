@@ -81,8 +81,9 @@ typedef struct {
  * back the sizes.
  *
  * Errors: TC_EINVAL for null pointers, n < 1, m_raw < 0 or an id outside
- * [0, n) (no handle is returned); TC_EOVERFLOW if the simple graph has 2^31 or
- * more edges; TC_ENOMEM / TC_EDEVICE on allocation or runtime failure.
+ * [0, n) (no handle is returned); TC_EOVERFLOW if the simple graph has 2^30 or
+ * more edges (probe reads use 32-bit byte offsets into U); TC_ENOMEM /
+ * TC_EDEVICE on allocation or runtime failure.
  */
 tc_status tc_preprocess(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int32_t n,
                         void* stream, tc_graph** out);

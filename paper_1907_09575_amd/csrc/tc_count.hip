@@ -8,30 +8,36 @@
 // range of the global probe index space (tasks grouped by b, prefix-summed by
 // preprocessing).
 //
-// Hash table (Section 5.2, "Modifying the hashing routine"): U_b in LDS,
-// 2^l >= 2 |U_b| slots, slot = k & (2^l - 1) (the direct bitwise AND), linear
-// probing on collision. The build records the longest displacement D; a
-// lookup stops at a match, an empty slot or after D + 1 slots, so a
-// collision-free table (D = 0) costs one LDS read per probe and exactness
-// never depends on the absence of collisions.
+// Hash table (Section 5.2, "Modifying the hashing routine"): U_b in LDS in
+// buckets of four 32-bit slots, bucket = k & (buckets - 1) (the direct bitwise
+// AND of the paper), at least 4 |U_b| slots. A key goes to the first free slot
+// of its bucket or, if the bucket is full, of the next ones; slots fill left
+// to right, so a lookup reads one bucket with a single 16-byte LDS read and
+// stops there unless the bucket is full. The build records the longest bucket
+// displacement D, which bounds every lookup; exactness never depends on the
+// absence of collisions.
 //
 // Probe loop (one wave, flattened over tasks). A wave walks a range of
 // probes in batches of 64, lane l taking probe base + l, so every col[] read
 // is a coalesced run; kU batches form a super-batch whose loads and lookups
 // are all in flight together. A window of 64 consecutive tasks sits one per
 // lane (end of the task relative to the wave's position, and the col index its
-// probes start from). The task of a probe is the number of window tasks that
-// end at or before it: one ballot counts those ending before the super-batch,
-// and the tasks ending inside it set bits of a small per-wave LDS bitmap whose
-// masked popcounts give each lane its task; the task's col base is then
-// fetched from its lane with one bpermute.
+// probes start from); the next window is prefetched while the current one is
+// probed. The task of a probe r is c0 (tasks ended at or before the
+// super-batch start, one ballot) plus the number of task ends inside the
+// super-batch that lie at or before r: ends set bits of a per-wave LDS bitmap,
+// whose words are read back as wave-uniform masks and counted per lane with
+// mbcnt. The task's col base then comes from its lane by one bpermute.
+// Probe reads are raw buffer loads with a 32-bit byte offset; a lane past the
+// range gets an offset beyond the buffer and reads 0, which is never a key of
+// U_b (every key exceeds b >= 0), so it needs no branch.
 //
 // Launch classes (decided in preprocessing from |U_b| and the row's probes):
-//   packs  - light rows b are packed (about 2K probes per pack); one wave per
+//   packs  - light rows b are packed (about 4K probes per pack); one wave per
 //            pack builds each row's table in its private LDS slice in turn.
-//   heavy  - a row's probes are cut into per-wave ranges (8K probes); the 4
+//   heavy  - a row's probes are cut into per-wave ranges (16K probes); the 4
 //            waves of a work-group share one table of that row.
-//   global - a row whose table would not fit LDS (|U_b| > 8192): lookups are
+//   global - a row whose table would not fit LDS (|U_b| > 4096): lookups are
 //            binary searches in the sorted U_b in HBM.
 // Reductions: per-lane 32-bit hit counters, wave reduction by xor shuffles,
 // one 64-bit atomic per work-group into the caller's counter (order-free and
@@ -49,7 +55,7 @@ struct Args {
   const uint64_t* __restrict__ tprefix;
   const int64_t* __restrict__ tptr;
   int64_t T;
-  uint32_t m;  // entries of col (probe positions are checked against it)
+  uint32_t m;  // entries of col
   unsigned long long* count;
   int32_t* support;
 };
@@ -57,8 +63,25 @@ struct Args {
 constexpr int kU = 8;                   // 64-probe batches per super-batch
 constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bits)
 constexpr int kMarkInts = kWaves * kBmWords;
+constexpr int32_t kEmpty = -1;
+constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // byte offset past any col buffer
 
-__device__ __forceinline__ uint64_t lanemask_le() { return (2ull << lane_id()) - 1ull; }
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const int32_t* col, uint32_t m) {
+  // raw buffer over col[0, m): stride 0, num_records = bytes; reads at or past
+  // the end return 0
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(col), (short)0, (int)(m * 4u),
+                                           0x00020000);
+}
+
+__device__ __forceinline__ int32_t col_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
 
 // Lookup by binary search in the sorted row col[rs, rs + d); returns the
 // position of k or -1.
@@ -74,193 +97,209 @@ __device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int
   return (lo < rs + d && col[lo] == k) ? lo : -1;
 }
 
-// Insert U_b = col[rs, rs + d) into a cleared table of S slots; threads
-// tid, tid + nt, ... share the work. Returns this thread's longest
-// displacement. VALS: also store the U position of every key.
+// Insert U_b = col[rs, rs + d) into a cleared bucketed table of (bmask + 1)
+// buckets; threads tid, tid + nt, ... share the work. Returns this thread's
+// longest bucket displacement. VALS: also store every key's U position.
 template <bool VALS>
-__device__ int build_table(int32_t* tab, int32_t* val, uint32_t mask, const int32_t* __restrict__ col,
+__device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int32_t* __restrict__ col,
                            int64_t rs, int64_t d, int tid, int nt) {
-  // keys are fetched kB at a time so that their loads overlap, then inserted
-  constexpr int kB = 8;
+  constexpr int kB = 8;  // keys fetched at once so that their loads overlap
   int md = 0;
   for (int64_t i0 = tid; i0 < d; i0 += (int64_t)kB * nt) {
     int32_t key[kB];
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const int64_t i = i0 + (int64_t)j * nt;
-      key[j] = i < d ? col[rs + i] : -1;
+      key[j] = i < d ? col[rs + i] : kEmpty;
     }
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
-      if (key[j] < 0) continue;
-      uint32_t h = (uint32_t)key[j] & mask;
+      if (key[j] == kEmpty) continue;
+      uint32_t bk = (uint32_t)key[j] & bmask;
       int disp = 0;
-      while (atomicCAS(&tab[h], -1, key[j]) != -1) {
-        h = (h + 1) & mask;
+      int slot = -1;
+      while (true) {
+#pragma unroll
+        for (int s = 0; s < kBucket; ++s) {
+          if (slot < 0 && atomicCAS(&tab[bk * kBucket + s], kEmpty, key[j]) == kEmpty)
+            slot = (int)(bk * kBucket + s);
+        }
+        if (slot >= 0) break;
+        bk = (bk + 1) & bmask;
         ++disp;
       }
-      if (VALS) val[h] = (int32_t)(rs + i0 + (int64_t)j * nt);
+      if (VALS) val[slot] = (int32_t)(rs + i0 + (int64_t)j * nt);
       md = disp > md ? disp : md;
     }
   }
   return md;
 }
 
-// What to do with every probe k (at col position `pos`, task of lane whose
-// first probe is at `ts`): count mode adds the hit; support modes also credit
-// the triangle's edges.
 struct TableRef {
-  const int32_t* tab;
-  const int32_t* val;
-  uint32_t mask;
+  const int32_t* tab;  // (bmask + 1) * kBucket slots
+  const int32_t* val;  // U positions (support mode)
+  uint32_t bmask;
   int D;
-  // global fallback
-  int64_t rs, d;
+  int64_t rs, d;  // the row itself (HBM fallback)
 };
 
+// A hit: k = col[pos] was found in U_b at `where` (an LDS slot, or for the HBM
+// fallback its position in col); ts is the first probe position of the task,
+// so ts - 1 is the U entry of the task's own edge (a, b).
 template <int MODE, bool GLOBAL>
-struct Prober {
-  static constexpr bool kNeedTs = MODE != MODE_COUNT;
-  // A hit: k = col[pos] was found in U_b at `where` (an LDS slot, or for the
-  // HBM fallback the position in col). ts is the first probe position of the
-  // task, so ts - 1 is the U entry of the task's own edge (a, b).
-  __device__ __forceinline__ static void credit(const Args& A, const TableRef& t, int where,
-                                                uint32_t pos, uint32_t ts, uint32_t& hits) {
-    ++hits;
-    // indices are checked against m so that no credit can leave the array
-    if (MODE == MODE_SUPPORT_FULL) {
-      const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
-      if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
-      atomicAdd(&A.support[pos], 1);                          // edge (a, k): probed entry of U_a
-      if (other < A.m) atomicAdd(&A.support[other], 1);       // edge (b, k): k's entry in U_b
-    } else if (MODE == MODE_SUPPORT_ORIENTED) {
-      if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
-    }
+__device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos,
+                                       uint32_t ts) {
+  // indices are checked against m so that no credit can leave the array
+  if (MODE == MODE_SUPPORT_FULL) {
+    const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
+    if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
+    if (pos < A.m) atomicAdd(&A.support[pos], 1);          // edge (a, k): probed entry of U_a
+    if (other < A.m) atomicAdd(&A.support[other], 1);      // edge (b, k): k's entry in U_b
+  } else if (MODE == MODE_SUPPORT_ORIENTED) {
+    if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
   }
-};
+}
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
+  return v.x == k ? 0 : v.y == k ? 1 : v.z == k ? 2 : v.w == k ? 3 : -1;
 }
 
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
 // task t contains probe q.
-//
-// The range is walked window by window: a window is the next 64 tasks (one per
-// lane) and covers their probes exactly. Inside a window the probes go in
-// super-batches of 64 * U (lane l takes probes sb + 64 u + l, u < U), so each
-// lane has U independent col[] loads and U table lookups in flight. The task
-// of a probe r is c0 + (number of task ends in (sb, r]): c0 by one ballot, the
-// ends inside the super-batch as bits of a per-wave LDS bitmap `bm`
-// (U * 64 bits), read back word-wise and counted with masked popcounts.
-template <int MODE, bool GLOBAL, int U>
+template <int MODE, bool GLOBAL>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
                            uint32_t* bm, uint32_t& hits) {
-  using P = Prober<MODE, GLOBAL>;
-  constexpr uint32_t SB = 64u * U;
+  constexpr bool kNeedTs = MODE != MODE_COUNT;
+  constexpr uint32_t SB = 64u * kU;
   const int lane = lane_id();
   const int64_t T = A.T;
-  const uint64_t le = lanemask_le();
+  const __amdgpu_buffer_rsrc_t rsrc = col_rsrc(A.col, A.m);
+  const int4* tab4 = reinterpret_cast<const int4*>(tr.tab);
+
+  // window of tasks t .. t + 63, one per lane: start and end prefix, col start
+  auto fetch = [&](int64_t tj, uint64_t& Ps, uint64_t& Pe, uint32_t& ts) {
+    Ps = A.tprefix[tj < T ? tj : T];
+    Pe = A.tprefix[tj + 1 < T ? tj + 1 : T];
+    ts = A.tstart[tj < T ? tj : T - 1];
+  };
+  uint64_t Ps, Pe;
+  uint32_t tsj;
+  fetch((int64_t)t + lane, Ps, Pe, tsj);
+
   uint32_t done = 0;
   while (done < len) {
     const uint32_t rem = len - done;
-    const int64_t tj = (int64_t)t + lane;
-    const int64_t tjs = tj < T ? tj : T;
-    const int64_t tje = tj + 1 < T ? tj + 1 : T;
-    const uint64_t Ps = A.tprefix[tjs];
-    const uint64_t Pe = A.tprefix[tje];
     // end of the lane's task relative to q, clamped to the remaining range
     const uint64_t e64 = Pe - q;
     const uint32_t e = e64 > (uint64_t)rem ? rem : (uint32_t)e64;
     // col index of relative probe 0 for the lane's task (mod 2^32)
-    const uint32_t tsj = A.tstart[tj < T ? tj : T - 1];
     const uint32_t cbase = tsj - (uint32_t)(Ps - q);
     const uint32_t lim = (uint32_t)__shfl((int)e, 63, 64);  // probes of this window
     if (lim == 0) break;  // unreachable when every task has a probe; guards progress
+    const bool more = lim < rem;
+    uint64_t nPs = 0, nPe = 0;
+    uint32_t ntsj = 0;
+    if (more) fetch((int64_t)t + 64 + lane, nPs, nPe, ntsj);  // next window, in flight meanwhile
+
     for (uint32_t sb = 0; sb < lim; sb += SB) {
       const uint32_t c0 = (uint32_t)__popcll(__ballot(e <= sb));
-      const bool inner = e > sb && e < sb + SB;
-      uint32_t jl[U];
+      const bool inner = e > sb && e <= sb + SB;
+      uint32_t jl[kU];
       if (__ballot(inner) == 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) jl[u] = c0;
+        for (int u = 0; u < kU; ++u) jl[u] = c0;
       } else {
-        if (inner) atomicOr(&bm[(e - sb) >> 5], 1u << ((e - sb) & 31));
+        // bit p set <=> some task ends right after probe sb + p
+        if (inner) atomicOr(&bm[(e - sb - 1) >> 5], 1u << ((e - sb - 1) & 31));
         wave_sync_lds();
         uint32_t pre = c0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint64_t M = (uint64_t)bm[2 * u] | ((uint64_t)bm[2 * u + 1] << 32);
-          const uint32_t j = pre + (uint32_t)__popcll(M & le);
-          jl[u] = j < 63 ? j : 63;  // only lanes past the window (r >= lim) can exceed 63
-          pre += (uint32_t)__popcll(M);
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t lo = __builtin_amdgcn_readfirstlane(bm[2 * u]);
+          const uint32_t hi = __builtin_amdgcn_readfirstlane(bm[2 * u + 1]);
+          jl[u] = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, pre));
+          pre += (uint32_t)__builtin_popcount(lo) + (uint32_t)__builtin_popcount(hi);
         }
         wave_sync_lds();
         if (lane < (int)(SB / 32)) bm[lane] = 0;
         wave_sync_lds();
       }
-      uint32_t pos[U];
-      bool ok[U];
-      int32_t k[U];
+      uint32_t pos[kU], ts[kU];
+      int32_t k[kU];
+      bool ok[kU];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < kU; ++u) {
+        // ds_bpermute uses lane index bits only, so lanes past the window
+        // (jl >= 64, never used) wrap harmlessly
         const uint32_t r = sb + 64u * u + (uint32_t)lane;
-        pos[u] = (uint32_t)__shfl((int)cbase, (int)jl[u], 64) + r;
-        ok[u] = r < lim && pos[u] < A.m;
+        pos[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)cbase) + r;
+        ok[u] = r < lim;
+        ts[u] = kNeedTs ? (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)tsj) : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) k[u] = ok[u] ? A.col[pos[u]] : -1;
-      // task start of every probe (support modes), read across lanes while all
-      // lanes are active: a bpermute must not run under a divergent mask
-      uint32_t ts[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        ts[u] = P::kNeedTs ? (uint32_t)__shfl((int)tsj, (int)jl[u], 64) : 0u;
+      for (int u = 0; u < kU; ++u) k[u] = col_load(rsrc, ok[u] ? pos[u] * 4u : kOffNone);
+
       if constexpr (!GLOBAL) {
-        // first slot of every lookup at once, then the (rare) probe chains
-        int32_t v[U];
-        uint32_t h[U];
+        uint32_t bk[kU];
+        int4 v[kU];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          h[u] = (uint32_t)k[u] & tr.mask;
-          v[u] = tr.tab[h[u]];
+        for (int u = 0; u < kU; ++u) {
+          bk[u] = (uint32_t)k[u] & tr.bmask;
+          v[u] = tab4[bk[u]];
         }
+        bool unres[kU];
+        bool any_unres = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (!ok[u]) continue;
-          int slot = -1;
-          if (v[u] == k[u]) {
-            slot = (int)h[u];
-          } else if (v[u] >= 0 && tr.D > 0) {
-            uint32_t hh = h[u];
-            for (int i = 1; i <= tr.D; ++i) {
-              hh = (hh + 1) & tr.mask;
-              const int32_t w = tr.tab[hh];
-              if (w == k[u]) {
-                slot = (int)hh;
-                break;
+        for (int u = 0; u < kU; ++u) {
+          const int j = match_slot(v[u], k[u]);
+          if (j >= 0) {
+            ++hits;
+            if (MODE != MODE_COUNT) credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u]);
+          }
+          unres[u] = ok[u] && j < 0 && v[u].w != kEmpty;
+          any_unres |= unres[u];
+        }
+        // full first bucket: continue into the next ones (bounded by D)
+        if (tr.D > 0 && __ballot(any_unres)) {
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            uint32_t b2 = bk[u];
+            for (int i = 1; i <= tr.D && unres[u]; ++i) {
+              b2 = (b2 + 1) & tr.bmask;
+              const int4 w = tab4[b2];
+              const int j = match_slot(w, k[u]);
+              if (j >= 0) {
+                ++hits;
+                if (MODE != MODE_COUNT)
+                  credit<MODE, false>(A, tr, (int)(b2 * kBucket + j), pos[u], ts[u]);
+                unres[u] = false;
+              } else if (w.w == kEmpty) {
+                unres[u] = false;
               }
-              if (w < 0) break;
             }
           }
-          if (slot >= 0) P::credit(A, tr, slot, pos[u], ts[u], hits);
         }
       } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < kU; ++u) {
           const int64_t where = ok[u] ? hbm_find(A.col, tr.rs, tr.d, k[u]) : -1;
-          if (where >= 0) P::credit(A, tr, (int)where, pos[u], ts[u], hits);
+          if (where >= 0) {
+            ++hits;
+            if (MODE != MODE_COUNT) credit<MODE, true>(A, tr, (int)where, pos[u], ts[u]);
+          }
         }
       }
     }
-    t += (uint32_t)__popcll(__ballot(e <= lim));
+    if (more) {
+      t += 64;  // a window that is not the last covers exactly its 64 tasks
+      Ps = nPs;
+      Pe = nPe;
+      tsj = ntsj;
+    }
     q += lim;
     done += lim;
   }
 }
-
 
 __device__ __forceinline__ void block_flush(uint32_t hits, unsigned long long* count) {
   __shared__ unsigned long long s_sum[kWaves];
@@ -295,18 +334,17 @@ __global__ __launch_bounds__(256) void k_count_packs(Args A, const int32_t* __re
     for (uint32_t r = r0; r < r1; ++r) {
       const int32_t b = rows[r];
       const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
-      int l = 6;
-      while ((1ll << l) < 2 * d) ++l;
-      const uint32_t S = 1u << l, mask = S - 1;
-      for (uint32_t i = lane; i < S; i += 64) tab[i] = -1;
+      const uint32_t S = 1u << table_log2(d);
+      for (uint32_t i = lane; i < S; i += 64) tab[i] = kEmpty;
       wave_sync_lds();
-      int md = build_table<VALS>(tab, val, mask, A.col, rs, d, lane, 64);
+      const uint32_t bmask = S / kBucket - 1;
+      int md = build_table<VALS>(tab, val, bmask, A.col, rs, d, lane, 64);
       md = wave_max(md);
       wave_sync_lds();
       const int64_t tl = A.tptr[b], th = A.tptr[b + 1];
       const uint64_t q0 = A.tprefix[tl], q1 = A.tprefix[th];
-      TableRef tr{tab, val, mask, md, rs, d};
-      wave_probe<MODE, false, kU>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), bm, hits);
+      TableRef tr{tab, val, bmask, md, rs, d};
+      wave_probe<MODE, false>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), bm, hits);
       wave_sync_lds();
     }
   }
@@ -328,24 +366,25 @@ __global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __
   uint32_t hits = 0;
   TableRef tr{nullptr, nullptr, 0, 0, rs, d};
   if (!GLOBAL) {
-    const uint32_t S = 1u << grp[0].log2S, mask = S - 1;
+    const uint32_t S = 1u << grp[0].log2S;
     int32_t* tab = smem + kMarkInts;
     int32_t* val = tab + S;
-    for (uint32_t i = tid; i < S; i += 256) tab[i] = -1;
+    for (uint32_t i = tid; i < S; i += 256) tab[i] = kEmpty;
     if (tid == 0) s_D = 0;
     __syncthreads();
-    int md = build_table<VALS>(tab, val, mask, A.col, rs, d, tid, 256);
+    const uint32_t bmask = S / kBucket - 1;
+    int md = build_table<VALS>(tab, val, bmask, A.col, rs, d, tid, 256);
     md = wave_max(md);
     if (lane == 0) atomicMax(&s_D, md);
     __syncthreads();
     tr.tab = tab;
     tr.val = val;
-    tr.mask = mask;
+    tr.bmask = bmask;
     tr.D = s_D;
   }
-  const CountItem it = grp[wave];
   wave_sync_lds();
-  if (it.len) wave_probe<MODE, GLOBAL, kU>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  const CountItem it = grp[wave];
+  if (it.len) wave_probe<MODE, GLOBAL>(A, tr, it.t0, it.q0, it.len, bm, hits);
   block_flush(hits, A.count);
 }
 
@@ -377,21 +416,22 @@ void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A, g.pack_rows[c],
-                       g.pack_ptr[c], g.n_packs[c], l);
+    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A,
+              g.pack_rows[c], g.pack_ptr[c], g.n_packs[c], l);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (g.n_items[c] == 0) continue;
     const unsigned grid = (unsigned)(g.n_items[c] / kWaves);
     if (c == CLS_GLOBAL) {
-      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes, st, A,
-                         g.items[c]);
+      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes,
+                st, A, g.items[c]);
     } else {
       const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << g.cls_log2S[c]) * (VALS ? 2 : 1);
       if (lds > 65536)
         TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A, g.items[c]);
+      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A,
+                g.items[c]);
     }
   }
   TC_HIP(hipGetLastError());
@@ -403,7 +443,8 @@ void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_s
                   hipStream_t st) {
   if (d_count) TC_LAUNCH("zero_i64", k_zero_i64, dim3(1), dim3(1), 0, st, d_count);
   if (mode != MODE_COUNT && g.m > 0)
-    TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support, g.m);
+    TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support,
+              g.m);
   TC_HIP(hipGetLastError());
   if (g.n_tasks == 0) return;
   Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tptr, g.n_tasks, (uint32_t)g.m,

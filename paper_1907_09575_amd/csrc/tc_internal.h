@@ -69,20 +69,31 @@ static_assert(sizeof(CountItem) == 24, "CountItem layout");
 
 // Launch classes of the count kernels (see tc_count.hip).
 enum ItemClass : int {
-  CLS_PACK_SMALL = 0,  // packs of light rows b, one wave per pack, table <= 512 slots
-  CLS_PACK_LARGE = 1,  // packs of light rows b, one wave per pack, table <= 4096 slots
+  CLS_PACK_SMALL = 0,  // packs of light rows b, one wave per pack, table <= 256 slots
+  CLS_PACK_LARGE = 1,  // packs of light rows b, one wave per pack, table <= 1024 slots
   CLS_WG_SMALL = 2,    // heavy rows, 4 waves share one table <= 1024 slots
   CLS_WG_LARGE = 3,    // heavy rows, table <= 4096 slots
-  CLS_WG_HUGE = 4,     // heavy rows, table <= 16384 slots
+  CLS_WG_HUGE = 4,     // table <= 16384 slots (any row too large for the above)
   CLS_GLOBAL = 5,      // table would not fit LDS: binary search in U_b in HBM
   NUM_CLASSES = 6
 };
 
 constexpr int kWaves = 4;               // waves per work-group in every count launch
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
-constexpr uint32_t kWaveChunk = 32768;  // target probes per wave item of a heavy row
-constexpr uint64_t kHeavyMin = 8192;    // rows with fewer probes than this are packed
-constexpr uint64_t kPackTarget = 8192;  // target probes per pack of light rows
+constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
+constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
+constexpr uint64_t kPackTarget = 4096;  // target probes per pack of light rows
+constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
+constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte offsets into U
+
+// Slots of the LDS hash table of a row with d keys: a power of two >= 4 d
+// (load factor <= 1/4, so almost every lookup ends in its first bucket), at
+// least 64.
+__host__ __device__ inline int table_log2(int64_t d) {
+  int l = 6;
+  while ((1ll << l) < 4 * d) ++l;
+  return l;
+}
 
 // Device-resident graph. All arrays live in one allocation (`arena`).
 struct Graph {

@@ -193,17 +193,6 @@ __global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ r
   }
 }
 
-__device__ __forceinline__ int clog2_dev(uint64_t x) {
-  int r = 0;
-  while ((1ull << r) < x) ++r;
-  return r;
-}
-
-__device__ __forceinline__ int row_log2S(int64_t d) {
-  int l = clog2_dev((uint64_t)(2 * d));
-  return l < 6 ? 6 : l;
-}
-
 // Class of every hashed row b (-1 = no work) and the class's largest table
 // (maxima reduced per wave before one atomic per wave and class).
 __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tptr,
@@ -215,10 +204,10 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
   if (b < n) {
     uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
     if (W > 0) {
-      l = row_log2S(row_ptr[b + 1] - row_ptr[b]);
+      l = table_log2(row_ptr[b + 1] - row_ptr[b]);
       if (l > kMaxLog2S) c = CLS_GLOBAL;
       else if (l > 12) c = CLS_WG_HUGE;
-      else if (W < kHeavyMin) c = l <= 9 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
+      else if (W < kHeavyMin && l <= 10) c = l <= 8 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
       else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
     }
     cls[b] = (int8_t)c;
@@ -352,7 +341,7 @@ __global__ void k_emit_items(const uint32_t* __restrict__ offs, int64_t n, int64
   it.t0 = (uint32_t)a;
   it.q0 = q0;
   it.len = (uint32_t)(q1 - q0);
-  it.log2S = (uint32_t)row_log2S(row_ptr[b + 1] - row_ptr[b]);
+  it.log2S = (uint32_t)table_log2(row_ptr[b + 1] - row_ptr[b]);
   items[j] = it;
 }
 
@@ -433,7 +422,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, d_tot32, st);
       m = read_scalar(d_tot32, st);
     }
-    TC_REQUIRE(m < (int64_t)0x7FFFFFFF, TC_EOVERFLOW, "tc_preprocess: 2^31 or more edges");
+    TC_REQUIRE(m <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
     E.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
     if (m > 0)
       TC_LAUNCH("compact", (k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
