@@ -227,6 +227,9 @@ def main():
         "count_raw_edges_per_s": m_raw / (count_ms / 1e3) if count_ms > 0 else None,
         "count_probes_per_s": info["probes"] / (count_ms / 1e3) if count_ms > 0 else None,
         "count_phase_alg_GBps": count_bytes / (count_ms / 1e3) / 1e9 if count_ms > 0 else None,
+        "classes": {c: {"probes": v["probes"], "rows": v["rows"], "tasks": v["tasks"],
+                        "workgroups": v["workgroups"], "table_slots": v["table_slots"]}
+                    for c, v in cstats.items() if v["rows"]},
         "kernels_top": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"]}
                         for k, v in sorted(launches.items(), key=lambda kv: -kv[1]["total_ms"])[:6]},
     }

@@ -53,7 +53,8 @@ struct Args {
   const int32_t* __restrict__ col;
   const uint32_t* __restrict__ tstart;
   const uint64_t* __restrict__ tprefix;
-  const int64_t* __restrict__ tptr;
+  const uint32_t* __restrict__ tbeg;
+  const uint32_t* __restrict__ tend;
   int64_t T;
   uint32_t m;  // entries of col
   unsigned long long* count;
@@ -136,12 +137,19 @@ __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int
 }
 
 struct TableRef {
-  const int32_t* tab;  // (bmask + 1) * kBucket slots
+  const int32_t* tab;  // (bmask + 1) * kBucket slots (a pack: all its rows' tables)
   const int32_t* val;  // U positions (support mode)
   uint32_t bmask;
   int D;
   int64_t rs, d;  // the row itself (HBM fallback)
+  // packs: row i of the pack owns tasks [row_t0[i], row_t0[i + 1]) and the
+  // table at bucket (desc & 0xFFFF) with (desc >> 16) + 1 buckets
+  const uint32_t* row_t0;
+  const uint32_t* row_desc;
+  int nrows;
 };
+
+enum TableKind : int { TK_SINGLE = 0, TK_MULTI = 1, TK_GLOBAL = 2 };
 
 // A hit: k = col[pos] was found in U_b at `where` (an LDS slot, or for the HBM
 // fallback its position in col); ts is the first probe position of the task,
@@ -166,9 +174,11 @@ __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
 
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
 // task t contains probe q.
-template <int MODE, bool GLOBAL>
+template <int MODE, int KIND>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
                            uint32_t* bm, uint32_t& hits) {
+  constexpr bool GLOBAL = KIND == TK_GLOBAL;
+  constexpr bool MULTI = KIND == TK_MULTI;
   constexpr bool kNeedTs = MODE != MODE_COUNT;
   constexpr uint32_t SB = 64u * kU;
   const int lane = lane_id();
@@ -176,15 +186,16 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
   const __amdgpu_buffer_rsrc_t rsrc = col_rsrc(A.col, A.m);
   const int4* tab4 = reinterpret_cast<const int4*>(tr.tab);
 
-  // window of tasks t .. t + 63, one per lane: start and end prefix, col start
-  auto fetch = [&](int64_t tj, uint64_t& Ps, uint64_t& Pe, uint32_t& ts) {
-    Ps = A.tprefix[tj < T ? tj : T];
+  // window of tasks t .. t + 63, one per lane: end prefix and col start (the
+  // start prefix of a task is the end prefix of the previous one)
+  auto fetch = [&](int64_t tj, uint64_t& Pe, uint32_t& ts) {
     Pe = A.tprefix[tj + 1 < T ? tj + 1 : T];
     ts = A.tstart[tj < T ? tj : T - 1];
   };
-  uint64_t Ps, Pe;
+  uint64_t Pe;
   uint32_t tsj;
-  fetch((int64_t)t + lane, Ps, Pe, tsj);
+  fetch((int64_t)t + lane, Pe, tsj);
+  uint64_t P0 = A.tprefix[t];  // start prefix of the window's first task
 
   uint32_t done = 0;
   while (done < len) {
@@ -192,14 +203,29 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     // end of the lane's task relative to q, clamped to the remaining range
     const uint64_t e64 = Pe - q;
     const uint32_t e = e64 > (uint64_t)rem ? rem : (uint32_t)e64;
-    // col index of relative probe 0 for the lane's task (mod 2^32)
-    const uint32_t cbase = tsj - (uint32_t)(Ps - q);
+    // start of the lane's task relative to q (wraps below q for lane 0 when the
+    // range begins inside its task), so cbase = col index of relative probe 0
+    const uint32_t e_prev = (uint32_t)__shfl_up((int)(uint32_t)e64, 1, 64);
+    const uint32_t s_rel = lane == 0 ? (uint32_t)(P0 - q) : e_prev;
+    const uint32_t cbase = tsj - s_rel;
     const uint32_t lim = (uint32_t)__shfl((int)e, 63, 64);  // probes of this window
     if (lim == 0) break;  // unreachable when every task has a probe; guards progress
+    // packs: the table of the lane's task (last row whose first task <= it)
+    uint32_t tdesc = 0;
+    if constexpr (MULTI) {
+      const uint32_t tj = t + (uint32_t)lane;
+      int lo = 0, hi = tr.nrows;  // row_t0[lo] <= tj (lanes past the pack clamp to the last row)
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tr.row_t0[mid] <= tj) lo = mid;
+        else hi = mid;
+      }
+      tdesc = tr.row_desc[lo];
+    }
     const bool more = lim < rem;
-    uint64_t nPs = 0, nPe = 0;
+    uint64_t nPe = 0;
     uint32_t ntsj = 0;
-    if (more) fetch((int64_t)t + 64 + lane, nPs, nPe, ntsj);  // next window, in flight meanwhile
+    if (more) fetch((int64_t)t + 64 + lane, nPe, ntsj);  // next window, in flight meanwhile
 
     for (uint32_t sb = 0; sb < lim; sb += SB) {
       const uint32_t c0 = (uint32_t)__popcll(__ballot(e <= sb));
@@ -224,7 +250,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
         if (lane < (int)(SB / 32)) bm[lane] = 0;
         wave_sync_lds();
       }
-      uint32_t pos[kU], ts[kU];
+      uint32_t pos[kU], ts[kU], bbase[kU], bmask[kU];
       int32_t k[kU];
       bool ok[kU];
 #pragma unroll
@@ -235,43 +261,58 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
         pos[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)cbase) + r;
         ok[u] = r < lim;
         ts[u] = kNeedTs ? (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)tsj) : 0u;
+        if constexpr (MULTI) {
+          const uint32_t dsc = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)tdesc);
+          bbase[u] = dsc & 0xFFFFu;
+          bmask[u] = dsc >> 16;
+        } else {
+          bbase[u] = 0;
+          bmask[u] = tr.bmask;
+        }
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) k[u] = col_load(rsrc, ok[u] ? pos[u] * 4u : kOffNone);
 
       if constexpr (!GLOBAL) {
+        // buckets are read in groups of kG so that the 16-byte results of one
+        // group fit the register budget of 8 waves per SIMD
+        constexpr int kG = 2;
         uint32_t bk[kU];
-        int4 v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          bk[u] = (uint32_t)k[u] & tr.bmask;
-          v[u] = tab4[bk[u]];
-        }
         bool unres[kU];
         bool any_unres = false;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int j = match_slot(v[u], k[u]);
-          if (j >= 0) {
-            ++hits;
-            if (MODE != MODE_COUNT) credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u]);
+        for (int g0 = 0; g0 < kU; g0 += kG) {
+          int4 v[kG];
+#pragma unroll
+          for (int u = g0; u < g0 + kG; ++u) {
+            bk[u] = bbase[u] + ((uint32_t)k[u] & bmask[u]);
+            v[u - g0] = tab4[bk[u]];
           }
-          unres[u] = ok[u] && j < 0 && v[u].w != kEmpty;
-          any_unres |= unres[u];
+#pragma unroll
+          for (int u = g0; u < g0 + kG; ++u) {
+            const int j = match_slot(v[u - g0], k[u]);
+            if (j >= 0) {
+              ++hits;
+              if (MODE != MODE_COUNT)
+                credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u]);
+            }
+            unres[u] = ok[u] && j < 0 && v[u - g0].w != kEmpty;
+            any_unres |= unres[u];
+          }
         }
         // full first bucket: continue into the next ones (bounded by D)
         if (tr.D > 0 && __ballot(any_unres)) {
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
-            uint32_t b2 = bk[u];
+            uint32_t b2 = bk[u] - bbase[u];
             for (int i = 1; i <= tr.D && unres[u]; ++i) {
-              b2 = (b2 + 1) & tr.bmask;
-              const int4 w = tab4[b2];
+              b2 = (b2 + 1) & bmask[u];
+              const int4 w = tab4[bbase[u] + b2];
               const int j = match_slot(w, k[u]);
               if (j >= 0) {
                 ++hits;
                 if (MODE != MODE_COUNT)
-                  credit<MODE, false>(A, tr, (int)(b2 * kBucket + j), pos[u], ts[u]);
+                  credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u]);
                 unres[u] = false;
               } else if (w.w == kEmpty) {
                 unres[u] = false;
@@ -292,7 +333,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     }
     if (more) {
       t += 64;  // a window that is not the last covers exactly its 64 tasks
-      Ps = nPs;
+      P0 = q + lim;
       Pe = nPe;
       tsj = ntsj;
     }
@@ -314,47 +355,122 @@ __device__ __forceinline__ void block_flush(uint32_t hits, unsigned long long* c
   }
 }
 
-// Packs of light rows: each wave owns a table slice of 2^log2Smax slots.
+// Packs of light rows (one work-group each): up to kPackRows rows, one per
+// thread for its metadata; all their tables are built together in LDS (keys
+// flattened over the work-group), then the pack's probe range - the tasks of
+// its rows are contiguous - is split over the 4 waves and probed flattened,
+// each task looking up its own row's table.
+constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_count_packs(Args A, const int32_t* __restrict__ rows,
-                                                     const uint32_t* __restrict__ pack_ptr,
-                                                     int64_t n_packs, int log2Smax) {
-  extern __shared__ int32_t smem[];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
+void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
+                   uint32_t pack_slots) {
+  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
+  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
+  __shared__ int s_D;
+  __shared__ uint32_t s_w[4], s_w2[4];
+  __shared__ uint32_t s_tend;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
-  const uint32_t Smax = 1u << log2Smax;
-  int32_t* tab = smem + kMarkInts + (size_t)wave * Smax * (VALS ? 2 : 1);
-  int32_t* val = tab + Smax;
+  uint32_t* row_t0 = reinterpret_cast<uint32_t*>(smem) + kMarkInts;
+  uint32_t* row_desc = row_t0 + kPackRows;
+  uint32_t* row_k0 = row_desc + kPackRows;  // kPackRows + 1 entries
+  int32_t* tab = smem + kMarkInts + kPackMetaWords + 3;  // + 3 keeps 16-byte alignment
+  int32_t* val = tab + pack_slots;
   if (lane < kBmWords) bm[lane] = 0;
-  uint32_t hits = 0;
-  const int64_t p = (int64_t)blockIdx.x * kWaves + wave;
-  if (p < n_packs) {
-    const uint32_t r0 = pack_ptr[p], r1 = pack_ptr[p + 1];
-    for (uint32_t r = r0; r < r1; ++r) {
-      const int32_t b = rows[r];
-      const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
-      const uint32_t S = 1u << table_log2(d);
-      for (uint32_t i = lane; i < S; i += 64) tab[i] = kEmpty;
-      wave_sync_lds();
-      const uint32_t bmask = S / kBucket - 1;
-      int md = build_table<VALS>(tab, val, bmask, A.col, rs, d, lane, 64);
-      md = wave_max(md);
-      wave_sync_lds();
-      const int64_t tl = A.tptr[b], th = A.tptr[b + 1];
-      const uint64_t q0 = A.tprefix[tl], q1 = A.tprefix[th];
-      TableRef tr{tab, val, bmask, md, rs, d};
-      wave_probe<MODE, false>(A, tr, (uint32_t)tl, q0, (uint32_t)(q1 - q0), bm, hits);
-      wave_sync_lds();
+
+  const uint32_t r0 = pack_ptr[blockIdx.x], r1 = pack_ptr[blockIdx.x + 1];
+  const int nr = (int)(r1 - r0);  // 1 .. kPackRows
+  uint32_t d = 0, S = 0, rs = 0;
+  if (tid < nr) {
+    const int32_t b = rows[r0 + tid];
+    const int64_t rs64 = A.row_ptr[b];
+    rs = (uint32_t)rs64;
+    d = (uint32_t)(A.row_ptr[b + 1] - rs64);
+    S = 1u << pack_table_log2(d);
+    row_t0[tid] = A.tbeg[b];
+    if (tid == nr - 1) s_tend = A.tend[b];
+  }
+  uint32_t S_tot, K_tot;
+  const uint32_t off = block_excl_scan(S, s_w, S_tot);
+  const uint32_t k0 = block_excl_scan(d, s_w2, K_tot);
+  if (tid < nr) {
+    row_desc[tid] = (off / kBucket) | ((S / kBucket - 1) << 16);
+    row_k0[tid] = k0;
+  }
+  if (tid == 0) {
+    row_k0[nr] = K_tot;
+    s_D = 0;
+  }
+  for (uint32_t i = tid; i < S_tot; i += 256) tab[i] = kEmpty;
+  __syncthreads();
+
+  // build: key x of the pack belongs to the last row i with row_k0[i] <= x;
+  // this thread also remembers its own row's start (rows are few per thread)
+  __shared__ uint32_t s_rs[kPackRows];
+  if (tid < nr) s_rs[tid] = rs;
+  __syncthreads();
+  int md = 0;
+  for (uint32_t x = tid; x < K_tot; x += 256) {
+    int lo = 0, hi = nr;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (row_k0[mid] <= x) lo = mid;
+      else hi = mid;
     }
+    const uint32_t p = s_rs[lo] + (x - row_k0[lo]);
+    const int32_t key = A.col[p];
+    const uint32_t dsc = row_desc[lo];
+    const uint32_t base = dsc & 0xFFFFu, bmask = dsc >> 16;
+    uint32_t bk = (uint32_t)key & bmask;
+    int disp = 0, slot = -1;
+    while (true) {
+#pragma unroll
+      for (int s2 = 0; s2 < kBucket; ++s2) {
+        if (slot < 0 && atomicCAS(&tab[(base + bk) * kBucket + s2], kEmpty, key) == kEmpty)
+          slot = (int)((base + bk) * kBucket + s2);
+      }
+      if (slot >= 0) break;
+      bk = (bk + 1) & bmask;
+      ++disp;
+    }
+    if (VALS) val[slot] = (int32_t)p;
+    md = disp > md ? disp : md;
+  }
+  md = wave_max(md);
+  if (lane == 0) atomicMax(&s_D, md);
+  __syncthreads();
+
+  TableRef tr{tab, val, 0, s_D, 0, 0, row_t0, row_desc, nr};
+  // the pack's probes [q0, q1), a quarter per wave
+  const uint32_t t_lo = row_t0[0], t_hi = s_tend;
+  const uint64_t q0 = A.tprefix[t_lo], q1 = A.tprefix[t_hi];
+  const uint64_t W = q1 - q0;
+  const uint64_t wq0 = q0 + W * (uint64_t)wave / kWaves, wq1 = q0 + W * (uint64_t)(wave + 1) / kWaves;
+  uint32_t hits = 0;
+  if (wq1 > wq0) {
+    // task holding wq0: 64-ary search, tprefix[lo] <= wq0 < tprefix[hi]
+    uint32_t lo = t_lo, hi = t_hi;
+    while (hi - lo > 1) {
+      const uint32_t step = (hi - lo + 63) / 64;
+      const uint32_t idx = lo + (uint32_t)lane * step;
+      const bool le = idx < hi && A.tprefix[idx] <= wq0;
+      const uint32_t c = (uint32_t)__popcll(__ballot(le));  // >= 1: lane 0 samples lo
+      lo = lo + (c - 1) * step;
+      hi = lo + step < hi ? lo + step : hi;
+    }
+    wave_probe<MODE, TK_MULTI>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
   }
   block_flush(hits, A.count);
 }
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
 template <int MODE, bool GLOBAL>
-__global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __restrict__ items) {
-  extern __shared__ int32_t smem[];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 8 : 4))) void k_count_items(Args A, const CountItem* __restrict__ items) {
+  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
+  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
   __shared__ int s_D;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -364,7 +480,7 @@ __global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __
   const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
   if (lane < kBmWords) bm[lane] = 0;
   uint32_t hits = 0;
-  TableRef tr{nullptr, nullptr, 0, 0, rs, d};
+  TableRef tr{nullptr, nullptr, 0, 0, rs, d, nullptr, nullptr, 0};
   if (!GLOBAL) {
     const uint32_t S = 1u << grp[0].log2S;
     int32_t* tab = smem + kMarkInts;
@@ -384,7 +500,7 @@ __global__ __launch_bounds__(256) void k_count_items(Args A, const CountItem* __
   }
   wave_sync_lds();
   const CountItem it = grp[wave];
-  if (it.len) wave_probe<MODE, GLOBAL>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE>(A, tr, it.t0, it.q0, it.len, bm, hits);
   block_flush(hits, A.count);
 }
 
@@ -410,14 +526,15 @@ void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
   const size_t mark_bytes = sizeof(int32_t) * kMarkInts;
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
     if (g.n_packs[c] == 0) continue;
-    const int l = g.pack_log2S[c];
-    const size_t lds = mark_bytes + sizeof(int32_t) * (size_t)kWaves * ((size_t)1 << l) * (VALS ? 2 : 1);
-    const unsigned grid = (unsigned)div_up(g.n_packs[c], kWaves);
+    // a pack's tables take at most kPackSlots plus one row's table
+    const uint32_t slots = kPackSlots + (1u << g.pack_log2S[c]);
+    const size_t lds = sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 +
+                                          (size_t)slots * (VALS ? 2 : 1));
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3(grid), dim3(256), lds, st, A,
-              g.pack_rows[c], g.pack_ptr[c], g.n_packs[c], l);
+    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3((unsigned)g.n_packs[c]), dim3(256), lds,
+              st, A, g.pack_rows[c], g.pack_ptr[c], slots);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (g.n_items[c] == 0) continue;
@@ -447,7 +564,7 @@ void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_s
               g.m);
   TC_HIP(hipGetLastError());
   if (g.n_tasks == 0) return;
-  Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tptr, g.n_tasks, (uint32_t)g.m,
+  Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tbeg, g.tend, g.n_tasks, (uint32_t)g.m,
          reinterpret_cast<unsigned long long*>(d_count), d_support};
   switch (mode) {
     case MODE_COUNT: launch_mode<MODE_COUNT>(g, A, st); break;

@@ -69,8 +69,8 @@ static_assert(sizeof(CountItem) == 24, "CountItem layout");
 
 // Launch classes of the count kernels (see tc_count.hip).
 enum ItemClass : int {
-  CLS_PACK_SMALL = 0,  // packs of light rows b, one wave per pack, table <= 256 slots
-  CLS_PACK_LARGE = 1,  // packs of light rows b, one wave per pack, table <= 1024 slots
+  CLS_PACK_SMALL = 0,  // packs of light rows b (one work-group each), table <= 256 slots
+  CLS_PACK_LARGE = 1,  // packs of light rows b, table <= 1024 slots
   CLS_WG_SMALL = 2,    // heavy rows, 4 waves share one table <= 1024 slots
   CLS_WG_LARGE = 3,    // heavy rows, table <= 4096 slots
   CLS_WG_HUGE = 4,     // table <= 16384 slots (any row too large for the above)
@@ -82,7 +82,9 @@ constexpr int kWaves = 4;               // waves per work-group in every count l
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
 constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
 constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
-constexpr uint64_t kPackTarget = 4096;  // target probes per pack of light rows
+constexpr uint64_t kPackTarget = 16384; // target probes per pack of light rows (one work-group)
+constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + one row's table)
+constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
 constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte offsets into U
 
@@ -91,6 +93,13 @@ constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte 
 // least 64.
 __host__ __device__ inline int table_log2(int64_t d) {
   int l = 6;
+  while ((1ll << l) < 4 * d) ++l;
+  return l;
+}
+
+// Packs of light rows give each row its own table, >= 4 d slots, at least 16.
+__host__ __device__ inline int pack_table_log2(int64_t d) {
+  int l = 4;
   while ((1ll << l) < 4 * d) ++l;
   return l;
 }
@@ -108,7 +117,8 @@ struct Graph {
   int64_t* row_ptr = nullptr;   // n + 1, U rows
   int32_t* col = nullptr;       // m, rows sorted ascending
   int32_t* perm = nullptr;      // n, perm[original id] = rank
-  int64_t* tptr = nullptr;      // n + 1, tasks of hashed row b: [tptr[b], tptr[b + 1])
+  uint32_t* tbeg = nullptr;     // n, tasks of hashed row b: [tbeg[b], tend[b]) (class-major order)
+  uint32_t* tend = nullptr;     // n
   uint32_t* tstart = nullptr;   // n_tasks, col index of the task's first probe
   uint64_t* tprefix = nullptr;  // n_tasks + 1, exclusive prefix of task lengths
 
@@ -117,7 +127,7 @@ struct Graph {
   uint32_t* pack_ptr[2] = {nullptr, nullptr};   // pack p covers pack_rows[pack_ptr[p] .. pack_ptr[p+1])
   int64_t n_pack_rows[2] = {0, 0};
   int64_t n_packs[2] = {0, 0};
-  int32_t pack_log2S[2] = {0, 0};               // max table size of the class
+  int32_t pack_log2S[2] = {0, 0};               // largest row table of the class (log2 slots)
 
   // work-group classes: n_items[c] items (a multiple of kWaves)
   CountItem* items[NUM_CLASSES] = {};

@@ -15,11 +15,12 @@
 //   5. tasks (Section 3.1, <j,i,k>): every nonzero (a, b) of U whose row a has
 //      entries after b and whose row b is non-empty probes U_a's entries after b
 //      against a hash of U_b. Tasks are grouped by b (the transpose L = U^T of
-//      Section 3.1), stably, so within one b the rows a ascend; their probe
-//      counts are prefix-summed.
+//      Section 3.1), stably, so within one b the rows a ascend.
 //   6. work classes and items for the count kernels (see tc_count.hip): rows b
-//      are split by table size and work; light rows are packed, heavy rows are
-//      cut into per-wave probe ranges.
+//      are split by table size and work; the tasks are reordered class-major
+//      (and their probe counts prefix-summed) so that each class, and each pack
+//      of consecutive light rows, owns one contiguous task range; light rows
+//      are packed, heavy rows are cut into per-wave probe ranges.
 #include <algorithm>
 #include <memory>
 
@@ -224,7 +225,8 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
 constexpr int kStatCols = NUM_CLASSES * 4;
 
 __global__ __launch_bounds__(256) void k_class_stats(const int8_t* __restrict__ cls, int64_t n,
-                                                     const int64_t* __restrict__ tptr,
+                                                     const uint32_t* __restrict__ tbeg,
+                                                     const uint32_t* __restrict__ tend,
                                                      const uint64_t* __restrict__ tprefix,
                                                      const int64_t* __restrict__ row_ptr,
                                                      unsigned long long* __restrict__ partial) {
@@ -237,8 +239,8 @@ __global__ __launch_bounds__(256) void k_class_stats(const int8_t* __restrict__ 
     if (c >= 0) {
       atomicAdd(&acc[c * 4 + 0], 1ull);
       atomicAdd(&acc[c * 4 + 1], (unsigned long long)(row_ptr[b + 1] - row_ptr[b]));
-      atomicAdd(&acc[c * 4 + 2], (unsigned long long)(tptr[b + 1] - tptr[b]));
-      atomicAdd(&acc[c * 4 + 3], (unsigned long long)(tprefix[tptr[b + 1]] - tprefix[tptr[b]]));
+      atomicAdd(&acc[c * 4 + 2], (unsigned long long)(tend[b] - tbeg[b]));
+      atomicAdd(&acc[c * 4 + 3], (unsigned long long)(tprefix[tend[b]] - tprefix[tbeg[b]]));
     }
   }
   __syncthreads();
@@ -264,16 +266,53 @@ __device__ __forceinline__ uint32_t wg_parts(uint64_t W) {
 }
 
 __global__ void k_class_count(const int8_t* __restrict__ cls, int64_t n, int c,
-                              const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
-                              uint32_t* __restrict__ cnt) {
+                              const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
+                              const uint64_t* __restrict__ tprefix, uint32_t* __restrict__ cnt) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   uint32_t v = 0;
   if (cls[b] == c) {
     if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) v = 1;
-    else v = wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]]);
+    else v = wg_parts(tprefix[tend[b]] - tprefix[tbeg[b]]);
   }
   cnt[b] = v;
+}
+
+// Tasks of row b if it is in class c, else 0 (b-order task bounds).
+__global__ void k_class_tasks(const int8_t* __restrict__ cls, int64_t n, int c,
+                              const int64_t* __restrict__ tb_ptr, uint32_t* __restrict__ cnt) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) cnt[b] = cls[b] == c ? (uint32_t)(tb_ptr[b + 1] - tb_ptr[b]) : 0u;
+}
+
+// Class-major task range of each row of class c: base + its class-local offset.
+__global__ void k_row_begin(const int8_t* __restrict__ cls, int64_t n, int c,
+                            const uint32_t* __restrict__ offs, uint32_t base,
+                            const int64_t* __restrict__ tb_ptr, uint32_t* __restrict__ tbeg,
+                            uint32_t* __restrict__ tend) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const int cb = cls[b];
+  if (cb == c) {
+    tbeg[b] = base + offs[b];
+    tend[b] = base + offs[b] + (uint32_t)(tb_ptr[b + 1] - tb_ptr[b]);
+  } else if (cb < 0 && c == 0) {
+    tbeg[b] = 0;  // no tasks
+    tend[b] = 0;
+  }
+}
+
+// Move task t (b order) to its class-major position.
+__global__ void k_task_permute(int64_t T, const uint32_t* __restrict__ tb_row,
+                               const int64_t* __restrict__ tb_ptr, const uint32_t* __restrict__ tbeg,
+                               const uint32_t* __restrict__ tb_start, const uint32_t* __restrict__ tb_len,
+                               uint32_t* __restrict__ tstart, uint32_t* __restrict__ tlen) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const uint32_t b = tb_row[t];
+  const int64_t nt = (int64_t)tbeg[b] + (t - tb_ptr[b]);
+  tstart[nt] = tb_start[t];
+  tlen[nt] = tb_len[t];
 }
 
 __global__ void k_class_rows(const int8_t* __restrict__ cls, int64_t n, int c,
@@ -283,19 +322,28 @@ __global__ void k_class_rows(const int8_t* __restrict__ cls, int64_t n, int c,
 }
 
 __global__ void k_rows_work(const int32_t* __restrict__ rows, int64_t nr,
-                            const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
-                            uint64_t* __restrict__ w) {
+                            const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
+                            const uint64_t* __restrict__ tprefix, const int64_t* __restrict__ row_ptr,
+                            uint64_t* __restrict__ w, uint32_t* __restrict__ slots) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nr) return;
   int64_t b = rows[i];
-  w[i] = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+  w[i] = tprefix[tend[b]] - tprefix[tbeg[b]];
+  slots[i] = 1u << pack_table_log2(row_ptr[b + 1] - row_ptr[b]);
 }
 
-__global__ void k_pack_flags(const uint64_t* __restrict__ pw, int64_t nr, uint64_t target,
-                             uint32_t* __restrict__ flags) {
+// A pack starts at row i when the running probe total, the running table
+// slots or the row index enters a new multiple of its budget; so a pack holds
+// at most kPackRows rows, at most kPackSlots slots plus one row's table, and
+// at most kPackTarget probes plus one row's.
+__global__ void k_pack_flags(const uint64_t* __restrict__ pw, const uint32_t* __restrict__ ps,
+                             int64_t nr, uint32_t* __restrict__ flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nr) return;
-  flags[i] = (i == 0 || pw[i] / target != pw[i - 1] / target) ? 1u : 0u;
+  flags[i] = (i == 0 || pw[i] / kPackTarget != pw[i - 1] / kPackTarget ||
+              ps[i] / kPackSlots != ps[i - 1] / kPackSlots || i / kPackRows != (i - 1) / kPackRows)
+                 ? 1u
+                 : 0u;
 }
 
 __global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
@@ -309,7 +357,8 @@ __global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* 
 // in the per-row item offsets), cut the row's probe range evenly and find the
 // task holding the first probe.
 __global__ void k_emit_items(const uint32_t* __restrict__ offs, int64_t n, int64_t total,
-                             const int64_t* __restrict__ tptr, const uint64_t* __restrict__ tprefix,
+                             const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
+                             const uint64_t* __restrict__ tprefix,
                              const int64_t* __restrict__ row_ptr, CountItem* __restrict__ items) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= total) return;
@@ -323,7 +372,7 @@ __global__ void k_emit_items(const uint32_t* __restrict__ offs, int64_t n, int64
   const int64_t b = lo;
   const uint64_t parts = offs[b + 1] - offs[b];
   const uint64_t idx = (uint64_t)(j - (int64_t)offs[b]);
-  const int64_t t_lo = tptr[b], t_hi = tptr[b + 1];
+  const int64_t t_lo = tbeg[b], t_hi = tend[b];
   const uint64_t P0 = tprefix[t_lo];
   const uint64_t W = tprefix[t_hi] - P0;
   const uint64_t per = W / parts, extra = W % parts;
@@ -385,6 +434,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
                    hipStream_t st) {
   std::unique_ptr<GraphImpl> g(new GraphImpl());
   TC_HIP(hipGetDevice(&g->device));
+  TempStream temps(st);  // temporaries are stream-ordered on st
   g->n = n;
   g->m_raw = m_raw;
   const int s = std::max(1, ceil_log2_u64((uint64_t)n));
@@ -412,7 +462,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     }
     TC_REQUIRE(read_scalar(d_err, st) == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
     bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
-                                           m_raw, 0, 2 * s, st);
+                                           m_raw, 0, 2 * s, st, "dedup");
     const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
     DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
@@ -428,7 +478,6 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       TC_LAUNCH("compact", (k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
                          flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, E.as<uint64_t>());
     TC_HIP(hipGetLastError());
-    TC_HIP(hipStreamSynchronize(st));
   }
   g->m = m;
 
@@ -448,24 +497,22 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
                          ha.as<uint32_t>());
       TC_HIP(hipGetLastError());
       bool halt = radix_sort<uint32_t, NoVal>(ha.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
-                                              0, s, st);
+                                              0, s, st, "degree");
       TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st,
                          halt ? hb.as<uint32_t>() : ha.as<uint32_t>(), m, 0, n, hi_ptr.as<int64_t>());
       TC_LAUNCH("deg_from_bounds", k_deg_from_bounds, dim3(grid_for(n)), dim3(kT), 0, st, lo_ptr.as<int64_t>(),
                          hi_ptr.as<int64_t>(), n, deg.as<uint32_t>());
       TC_HIP(hipGetLastError());
-      TC_HIP(hipStreamSynchronize(st));
     }
     DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
     TC_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
                        ra.as<uint64_t>());
     TC_HIP(hipGetLastError());
     bool alt = radix_sort<uint64_t, NoVal>(ra.as<uint64_t>(), rb.as<uint64_t>(), nullptr, nullptr, n,
-                                           s, 2 * s, st);
+                                           s, 2 * s, st, "rank");
     TC_LAUNCH("perm", k_perm, dim3(grid_for(n)), dim3(kT), 0, st,
                        alt ? rb.as<uint64_t>() : ra.as<uint64_t>(), n, s, g->perm);
     TC_HIP(hipGetLastError());
-    TC_HIP(hipStreamSynchronize(st));
   }
 
   // ---- 4: orient, U in CSR -------------------------------------------------
@@ -480,7 +527,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       TC_HIP(hipGetLastError());
       // E's buffer is the ping-pong partner
       bool alt = radix_sort<uint64_t, NoVal>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
-                                             0, 2 * s, st);
+                                             0, 2 * s, st, "orient");
       if (alt) okey = E.as<uint64_t>();
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
@@ -494,14 +541,18 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   }
 
   // ---- 5: tasks grouped by hashed row b -----------------------------------
+  // Built in b order first (tb_* temporaries); step 6 reorders them class-major.
   int64_t T = 0;
-  g->tptr = g->owned.alloc<int64_t>(n + 1);
+  g->tbeg = g->owned.alloc<uint32_t>(n);
+  g->tend = g->owned.alloc<uint32_t>(n);
+  DevBuf tb_ptr(sizeof(int64_t) * (size_t)(n + 1));  // tasks of row b: [tb_ptr[b], tb_ptr[b + 1])
+  DevBuf tb_row, tb_start, tb_len, tb_prefix;         // per task (b order): row, first probe, probes
   {
     DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     if (m > 0) {
       TC_LAUNCH("task_flags", k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
-                         flags.as<uint32_t>());
+                flags.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m, d_tot32, st);
       T = read_scalar(d_tot32, st);
     }
@@ -509,25 +560,31 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     g->tstart = g->owned.alloc<uint32_t>(T);
     g->tprefix = g->owned.alloc<uint64_t>(T + 1);
     if (T > 0) {
+      tb_row.alloc(sizeof(uint32_t) * (size_t)T);
+      tb_start.alloc(sizeof(uint32_t) * (size_t)T);
+      tb_len.alloc(sizeof(uint32_t) * (size_t)T);
+      tb_prefix.alloc(sizeof(uint64_t) * (size_t)(T + 1));
       DevBuf tk(sizeof(uint32_t) * (size_t)T), tk2(sizeof(uint32_t) * (size_t)T);
       DevBuf tv(sizeof(uint64_t) * (size_t)T), tv2(sizeof(uint64_t) * (size_t)T);
       TC_LAUNCH("task_emit", k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
-                         flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
+                flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
       TC_HIP(hipGetLastError());
       bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tk2.as<uint32_t>(), tv.as<uint64_t>(),
-                                                tv2.as<uint64_t>(), T, 0, s, st);
+                                                tv2.as<uint64_t>(), T, 0, s, st, "tasks");
       const uint32_t* skey = alt ? tk2.as<uint32_t>() : tk.as<uint32_t>();
       const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv.as<uint64_t>();
-      DevBuf tlen(sizeof(uint32_t) * (size_t)T);
-      TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T, g->tstart,
-                         tlen.as<uint32_t>());
-      device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
+      TC_HIP(hipMemcpyAsync(tb_row.p, skey, sizeof(uint32_t) * (size_t)T, hipMemcpyDeviceToDevice, st));
+      TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T,
+                tb_start.as<uint32_t>(), tb_len.as<uint32_t>());
+      device_excl_scan<uint32_t, uint64_t>(tb_len.as<uint32_t>(), tb_prefix.as<uint64_t>(), T,
+                                           tb_prefix.as<uint64_t>() + T, st);
       TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, skey, T, 0, n,
-                         g->tptr);
+                tb_ptr.as<int64_t>());
       TC_HIP(hipGetLastError());
-      g->probes = (int64_t)read_scalar(g->tprefix + T, st);
+      g->probes = (int64_t)read_scalar(tb_prefix.as<uint64_t>() + T, st);
     } else {
-      TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->tptr, n + 1, (int64_t)0);
+      TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, g->tbeg, n, 0u);
+      TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, g->tend, n, 0u);
       TC_HIP(hipMemsetAsync(g->tprefix, 0, sizeof(uint64_t), st));
       g->probes = 0;
     }
@@ -542,17 +599,45 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf cls(sizeof(int8_t) * (size_t)n);
     DevBuf clsl(sizeof(int) * NUM_CLASSES);
     TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
-    TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, g->tptr, g->tprefix,
-                       g->row_ptr, n, cls.as<int8_t>(), clsl.as<int>());
+    TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, tb_ptr.as<int64_t>(),
+              tb_prefix.as<uint64_t>(), g->row_ptr, n, cls.as<int8_t>(), clsl.as<int>());
     TC_HIP(hipGetLastError());
     int h_cl[NUM_CLASSES];
     TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
+    // class-major task order: the rows of class 0 (ascending b), then class 1,
+    // ...; each row keeps its tasks in b order, so every class - and every pack
+    // of consecutive rows of a class - owns one contiguous task range
+    {
+      DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
+      uint32_t base = 0;
+      for (int c = 0; c < NUM_CLASSES; ++c) {
+        TC_LAUNCH("class_tasks", k_class_tasks, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n,
+                  c, tb_ptr.as<int64_t>(), cnt.as<uint32_t>());
+        device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
+                                             offs.as<uint32_t>() + n, st);
+        TC_LAUNCH("row_begin", k_row_begin, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                  offs.as<uint32_t>(), base, tb_ptr.as<int64_t>(), g->tbeg, g->tend);
+        base += read_scalar(offs.as<uint32_t>() + n, st);
+      }
+      TC_REQUIRE((int64_t)base == T, TC_EDEVICE, "tc_preprocess: class-major task order lost tasks");
+      DevBuf tlen(sizeof(uint32_t) * (size_t)T);
+      TC_LAUNCH("task_permute", k_task_permute, dim3(grid_for(T)), dim3(kT), 0, st, T,
+                tb_row.as<uint32_t>(), tb_ptr.as<int64_t>(), g->tbeg, tb_start.as<uint32_t>(),
+                tb_len.as<uint32_t>(), g->tstart, tlen.as<uint32_t>());
+      device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
+      TC_HIP(hipGetLastError());
+    }
+    tb_row.release();
+    tb_start.release();
+    tb_len.release();
+    tb_prefix.release();
+    tb_ptr.release();
     {
       const int64_t nb = (int64_t)grid_for(n);
       DevBuf part(sizeof(unsigned long long) * (size_t)nb * kStatCols);
       DevBuf sums(sizeof(unsigned long long) * kStatCols);
       TC_LAUNCH("class_stats", k_class_stats, dim3((unsigned)nb), dim3(kT), 0, st, cls.as<int8_t>(), n,
-                g->tptr, g->tprefix, g->row_ptr, part.as<unsigned long long>());
+                g->tbeg, g->tend, g->tprefix, g->row_ptr, part.as<unsigned long long>());
       TC_LAUNCH("reduce_cols", k_reduce_cols, dim3(kStatCols), dim3(kT), 0, st,
                 part.as<unsigned long long>(), nb, kStatCols, sums.as<unsigned long long>());
       TC_HIP(hipGetLastError());
@@ -563,7 +648,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     for (int c = 0; c < NUM_CLASSES; ++c) {
       g->cls_log2S[c] = h_cl[c];
       TC_LAUNCH("class_count", k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                         g->tptr, g->tprefix, cnt.as<uint32_t>());
+                         g->tbeg, g->tend, g->tprefix, cnt.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
                                            offs.as<uint32_t>() + n, st);
       const int64_t total = read_scalar(offs.as<uint32_t>() + n, st);
@@ -573,19 +658,20 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
         TC_LAUNCH("class_rows", k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
                            offs.as<uint32_t>(), rows);
         DevBuf w(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
-        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tptr,
-                           g->tprefix, w.as<uint64_t>());
+        DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
+        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tbeg,
+                  g->tend, g->tprefix, g->row_ptr, w.as<uint64_t>(), sl.as<uint32_t>());
         device_excl_scan<uint64_t, uint64_t>(w.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
+        device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
         DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
         TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
-                           total, (uint64_t)kPackTarget, pf.as<uint32_t>());
+                  psl.as<uint32_t>(), total, pf.as<uint32_t>());
         device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
         const int64_t np = read_scalar(d_tot32, st);
         uint32_t* pack_ptr = g->owned.alloc<uint32_t>(np + 1);
         TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
                            pp.as<uint32_t>(), total, pack_ptr, np);
         TC_HIP(hipGetLastError());
-        TC_HIP(hipStreamSynchronize(st));
         g->pack_rows[c] = rows;
         g->pack_ptr[c] = pack_ptr;
         g->n_pack_rows[c] = total;
@@ -594,9 +680,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       } else {
         CountItem* items = g->owned.alloc<CountItem>(total);
         TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(), n,
-                           total, g->tptr, g->tprefix, g->row_ptr, items);
+                           total, g->tbeg, g->tend, g->tprefix, g->row_ptr, items);
         TC_HIP(hipGetLastError());
-        TC_HIP(hipStreamSynchronize(st));
         g->items[c] = items;
         g->n_items[c] = total;
       }

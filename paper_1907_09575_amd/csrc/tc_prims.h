@@ -5,6 +5,7 @@
 // All kernels use 256-thread work-groups (4 wave64 waves).
 #pragma once
 
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -140,19 +141,41 @@ __global__ __launch_bounds__(256) void k_scan_final(const Tin* __restrict__ in, 
   }
 }
 
-// RAII device buffer (hipMalloc / hipFree).
+// Stream that preprocessing temporaries are ordered on (set by TempStream).
+// While one is set, DevBuf allocates with hipMallocAsync and frees with
+// hipFreeAsync on it, from the device's default memory pool (which keeps
+// freed blocks for reuse), so freeing a temporary needs no synchronisation.
+struct TempCtx {
+  bool active = false;
+  hipStream_t st = nullptr;
+};
+TempCtx& temp_ctx();
+
+struct TempStream {
+  TempCtx prev;
+  explicit TempStream(hipStream_t st);
+  ~TempStream() { temp_ctx() = prev; }
+};
+
+// Device buffer owned by one scope.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t st = nullptr;
+  bool async = false;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   void alloc(size_t b) {
     release();
     bytes = b;
-    if (b) TC_HIP(hipMalloc(&p, b));
+    if (!b) return;
+    st = temp_ctx().st;
+    async = temp_ctx().active;
+    if (async) TC_HIP(hipMallocAsync(&p, b, st));
+    else TC_HIP(hipMalloc(&p, b));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(async ? hipFreeAsync(p, st) : hipFree(p));
     p = nullptr;
     bytes = 0;
   }
@@ -164,6 +187,9 @@ struct DevBuf {
     return static_cast<T*>(p);
   }
 };
+
+// Stable C string for a launch name built at run time.
+const char* intern_name(const std::string& s);
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -183,7 +209,6 @@ void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStrea
   TC_LAUNCH("scan_final", (k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
                      part.as<Tout>(), out);
   TC_HIP(hipGetLastError());
-  TC_HIP(hipStreamSynchronize(st));  // `part` is freed on return
 }
 
 // ---------------------------------------------------------------------------
@@ -312,7 +337,9 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const K* __restrict__ kin, K
 // elements; returns true if the sorted data ended in the *_alt buffers.
 template <class K, class V>
 bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                hipStream_t st) {
+                hipStream_t st, const char* name) {
+  const char* n_hist = intern_name(std::string("rs_hist:") + name);
+  const char* n_scat = intern_name(std::string("rs_scatter:") + name);
   if (n <= 1 || bit_hi <= bit_lo) return false;
   TC_REQUIRE(n < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW, "radix_sort: more than 2^32-1 keys");
   const int64_t nb = div_up(n, kSortTile);
@@ -328,7 +355,7 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
   for (int shift = bit_lo; shift < bit_hi; shift += 8) {
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
-    TC_LAUNCH("rs_hist", (k_rs_hist<K>), dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, dmask,
+    TC_LAUNCH(n_hist, (k_rs_hist<K>), dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, dmask,
                        hist.as<uint32_t>(), nb);
     TC_LAUNCH("scan_reduce", (k_scan_reduce<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
                        hist.as<uint32_t>(), hn, part.as<uint32_t>());
@@ -336,14 +363,13 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
                        pnb, (uint32_t*)nullptr);
     TC_LAUNCH("scan_final", (k_scan_final<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
                        hist.as<uint32_t>(), hn, part.as<uint32_t>(), offs.as<uint32_t>());
-    TC_LAUNCH("rs_scatter", (k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, st, ka, kb, va, vb, n,
+    TC_LAUNCH(n_scat, (k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, st, ka, kb, va, vb, n,
                        shift, dmask, hist.as<uint32_t>(), offs.as<uint32_t>(), nb);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
     alt = !alt;
   }
-  TC_HIP(hipStreamSynchronize(st));  // workspaces are freed on return
   return alt;
 }
 

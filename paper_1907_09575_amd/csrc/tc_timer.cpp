@@ -2,11 +2,12 @@
 // while a timer is attached to the calling host thread.
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
 
-#include "tc_internal.h"
+#include "tc_prims.h"
 
 struct tc_timer {
   std::vector<hipEvent_t> ev;       // 2 per slot
@@ -19,6 +20,38 @@ struct tc_timer {
 namespace tc {
 
 static thread_local tc_timer* t_active = nullptr;
+
+const char* intern_name(const std::string& s) {
+  static std::mutex mu;
+  static std::set<std::string> names;
+  std::lock_guard<std::mutex> lk(mu);
+  return names.insert(s).first->c_str();
+}
+
+TempCtx& temp_ctx() {
+  static thread_local TempCtx c;
+  return c;
+}
+
+TempStream::TempStream(hipStream_t st) : prev(temp_ctx()) {
+  // keep freed pool memory cached for the next preprocessing call (once per device)
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!done.count(dev)) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+      done.insert(dev);
+    }
+  }
+  temp_ctx().active = true;
+  temp_ctx().st = st;
+}
 
 LaunchScope::LaunchScope(const char* name, hipStream_t s) : st(s) {
   tc_timer* t = t_active;
