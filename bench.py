@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     p.add_argument("--gen-threads", type=int, default=16)
+    p.add_argument("--kernels-json", default=None, help="write the full per-kernel timer summary here")
     return p.parse_args()
 
 
@@ -165,6 +166,9 @@ def main():
     t1 = time.perf_counter()
     kern = timer.summary()
     timer.free()
+    if args.kernels_json:
+        with open(args.kernels_json, "w") as f:
+            json.dump(kern, f, indent=1)
     counts = [int(c.item()) for c in counts]
     assert len(set(counts)) == 1, "counts differ between steps: %s" % counts
     T = counts[0]
