@@ -72,6 +72,8 @@ def _load():
     lib.oc_wedges.restype = None
     lib.oc_block_counts.argtypes = [P, P, I64, I64, P, P]
     lib.oc_block_counts.restype = None
+    lib.oc_block_count_one.argtypes = [P, P, I64, I64, I64, I64, P]
+    lib.oc_block_count_one.restype = I64
     lib.oc_pair_common.argtypes = [P, P, I64, I64]
     lib.oc_pair_common.restype = I64
     lib.oc_build_adjacency.argtypes = [P, P, I64, I64, P, P]
@@ -171,6 +173,14 @@ def block_counts(U: Upper, q: int):
     _load().oc_block_counts(U.row_ptr.ctypes.data, U.col.ctypes.data, U.n, int(q), B.ctypes.data,
                             S.ctypes.data)
     return B.reshape(q, q), S.reshape(q, q, q)
+
+
+def block_count_one(U: Upper, q: int, x: int, y: int):
+    """(B[x][y], per_shift[q]) for rank (x, y) alone (Section 5.1, Eq. 5)."""
+    S = np.zeros(q, np.int64)
+    B = _load().oc_block_count_one(U.row_ptr.ctypes.data, U.col.ctypes.data, U.n, int(q), int(x), int(y),
+                                   S.ctypes.data)
+    return int(B), S
 
 
 @dataclass

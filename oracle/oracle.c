@@ -40,6 +40,7 @@
  *                     tasks (i, j) with j % q == x and i % q == y; shift z of
  *                     Eq. 5 contributes the triangles whose closing vertex k has
  *                     k % q == (x + y + z) % q.
+ *   oc_block_count_one  the same for one rank (x, y) only.
  *   oc_pair_common    |Adj(u) & Adj(v)| for one pair by joint traversal of the
  *                     two full sorted adjacency lists (the definition of a
  *                     triangle in Section 2), for spot checks on large graphs.
@@ -279,6 +280,36 @@ void oc_block_counts(const int64_t* row_ptr, const int32_t* col, int64_t n, int6
       }
     }
   }
+}
+
+/* One rank's share of the same decomposition: rank (x, y) alone, for graphs
+ * where all q * q blocks would take too long. Visits only the rows i with
+ * i % q == y and their entries j with j % q == x; per_shift[z] as above.
+ * Returns B[x][y]. */
+int64_t oc_block_count_one(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t q, int64_t x,
+                           int64_t y, int64_t* per_shift) {
+  int64_t total = 0;
+  for (int64_t z = 0; z < q; ++z) per_shift[z] = 0;
+  for (int64_t i = y; i < n; i += q) {
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int64_t j = col[p];
+      if (j % q != x) continue;
+      int64_t a = row_ptr[i], ae = row_ptr[i + 1], b = row_ptr[j], be = row_ptr[j + 1];
+      while (a < ae && b < be) {
+        if (col[a] < col[b]) ++a;
+        else if (col[a] > col[b]) ++b;
+        else {
+          int64_t z = ((col[a] % q) - x - y) % q;
+          if (z < 0) z += q;
+          per_shift[z]++;
+          total++;
+          ++a;
+          ++b;
+        }
+      }
+    }
+  }
+  return total;
 }
 
 /* ---------------------------------------------------------------------------

@@ -44,8 +44,8 @@ tc_status tc_graph_info(const tc_graph* gh, tc_info* out) {
     out->m_raw = g.m_raw;
     out->m = g.m;
     out->wedges_plus = g.wedges_plus;
-    out->probes = g.probes;
-    out->tasks = g.n_tasks;
+    out->probes = g.w.probes;
+    out->tasks = g.w.n_tasks;
     out->max_out_degree = g.max_dplus;
     out->device_bytes = (int64_t)g.arena_bytes;
   })
@@ -70,7 +70,8 @@ tc_status tc_graph_export(const tc_graph* gh, int64_t* d_row_ptr, int32_t* d_col
 tc_status tc_count(const tc_graph* gh, int64_t* d_count, void* stream) {
   TC_API_GUARD({
     TC_REQUIRE(gh && d_count, TC_EINVAL, "tc_count: null argument");
-    tc::launch_count(*tc::G(gh), tc::MODE_COUNT, d_count, nullptr, static_cast<hipStream_t>(stream));
+    tc::launch_count(tc::graph_view(*tc::G(gh)), tc::MODE_COUNT, d_count, nullptr, nullptr,
+                     static_cast<hipStream_t>(stream));
   })
 }
 
@@ -83,8 +84,9 @@ tc_status tc_edge_support(const tc_graph* gh, int mode, int32_t* d_support, int6
     const tc::Graph& g = *tc::G(gh);
     TC_REQUIRE(d_support || g.m == 0, TC_EINVAL, "tc_edge_support: null support array");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    tc::launch_count(g, mode == TC_SUPPORT_FULL ? tc::MODE_SUPPORT_FULL : tc::MODE_SUPPORT_ORIENTED,
-                     d_count, d_support, st);
+    tc::launch_count(tc::graph_view(g),
+                     mode == TC_SUPPORT_FULL ? tc::MODE_SUPPORT_FULL : tc::MODE_SUPPORT_ORIENTED, d_count,
+                     d_support, nullptr, st);
   })
 }
 
@@ -95,12 +97,12 @@ tc_status tc_graph_class_stats(const tc_graph* gh, tc_class_stats* out) {
     for (int c = 0; c < tc::NUM_CLASSES; ++c) {
       tc_class_stats& o = out[c];
       const bool pack = c == tc::CLS_PACK_SMALL || c == tc::CLS_PACK_LARGE;
-      o.workgroups = pack ? (g.n_packs[c] + tc::kWaves - 1) / tc::kWaves : g.n_items[c] / tc::kWaves;
-      o.rows = g.cls_stats[c][0];
-      o.table_keys = g.cls_stats[c][1];
-      o.tasks = g.cls_stats[c][2];
-      o.probes = g.cls_stats[c][3];
-      o.table_slots = g.cls_stats[c][0] ? (int64_t)1 << g.cls_log2S[c] : 0;
+      o.workgroups = pack ? g.w.n_packs[c] : g.w.n_items[c] / tc::kWaves;
+      o.rows = g.w.cls_stats[c][0];
+      o.table_keys = g.w.cls_stats[c][1];
+      o.tasks = g.w.cls_stats[c][2];
+      o.probes = g.w.cls_stats[c][3];
+      o.table_slots = g.w.cls_stats[c][0] ? (int64_t)1 << g.w.cls_log2S[c] : 0;
     }
   })
 }

@@ -49,8 +49,9 @@ namespace tc {
 namespace {
 
 struct Args {
-  const int64_t* __restrict__ row_ptr;
-  const int32_t* __restrict__ col;
+  const int64_t* __restrict__ row_ptr;  // hash side: rows b
+  const int32_t* __restrict__ hcol;     // hash side: sorted entries of each row b
+  const int32_t* __restrict__ col;      // probe side (the tasks' probes; U itself for a graph)
   const uint32_t* __restrict__ tstart;
   const uint64_t* __restrict__ tprefix;
   const uint32_t* __restrict__ tbeg;
@@ -59,6 +60,8 @@ struct Args {
   uint32_t m;  // entries of col
   unsigned long long* count;
   int32_t* support;
+  unsigned long long* per_shift;  // MODE_BLOCK: q counters
+  int32_t q, xy;                  // MODE_BLOCK: grid size, (x + y) % q
 };
 
 constexpr int kU = 8;                   // 64-probe batches per super-batch
@@ -154,11 +157,22 @@ enum TableKind : int { TK_SINGLE = 0, TK_MULTI = 1, TK_GLOBAL = 2 };
 // A hit: k = col[pos] was found in U_b at `where` (an LDS slot, or for the HBM
 // fallback its position in col); ts is the first probe position of the task,
 // so ts - 1 is the U entry of the task's own edge (a, b).
+// Per-shift triangle counters of one work-group (MODE_BLOCK).
+__device__ unsigned int* shift_counters() {
+  __shared__ unsigned int s_shift[64];
+  return s_shift;
+}
+
 template <int MODE, bool GLOBAL>
 __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos,
-                                       uint32_t ts) {
+                                       uint32_t ts, int32_t k) {
   // indices are checked against m so that no credit can leave the array
-  if (MODE == MODE_SUPPORT_FULL) {
+  if (MODE == MODE_BLOCK) {
+    // shift z of Eq. 5 closes the triangle with k = x + y + z (mod q)
+    int z = (int)((uint32_t)k % (uint32_t)A.q) - A.xy;
+    if (z < 0) z += A.q;
+    atomicAdd(&shift_counters()[z], 1u);
+  } else if (MODE == MODE_SUPPORT_FULL) {
     const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
     if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
     if (pos < A.m) atomicAdd(&A.support[pos], 1);          // edge (a, k): probed entry of U_a
@@ -179,7 +193,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
                            uint32_t* bm, uint32_t& hits) {
   constexpr bool GLOBAL = KIND == TK_GLOBAL;
   constexpr bool MULTI = KIND == TK_MULTI;
-  constexpr bool kNeedTs = MODE != MODE_COUNT;
+  constexpr bool kNeedTs = MODE == MODE_SUPPORT_FULL || MODE == MODE_SUPPORT_ORIENTED;
   constexpr uint32_t SB = 64u * kU;
   const int lane = lane_id();
   const int64_t T = A.T;
@@ -294,7 +308,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
             if (j >= 0) {
               ++hits;
               if (MODE != MODE_COUNT)
-                credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u]);
+                credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
             }
             unres[u] = ok[u] && j < 0 && v[u - g0].w != kEmpty;
             any_unres |= unres[u];
@@ -312,7 +326,8 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               if (j >= 0) {
                 ++hits;
                 if (MODE != MODE_COUNT)
-                  credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u]);
+                  credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u],
+                                      k[u]);
                 unres[u] = false;
               } else if (w.w == kEmpty) {
                 unres[u] = false;
@@ -323,10 +338,10 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
       } else {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          const int64_t where = ok[u] ? hbm_find(A.col, tr.rs, tr.d, k[u]) : -1;
+          const int64_t where = ok[u] ? hbm_find(A.hcol, tr.rs, tr.d, k[u]) : -1;
           if (where >= 0) {
             ++hits;
-            if (MODE != MODE_COUNT) credit<MODE, true>(A, tr, (int)where, pos[u], ts[u]);
+            if (MODE != MODE_COUNT) credit<MODE, true>(A, tr, (int)where, pos[u], ts[u], k[u]);
           }
         }
       }
@@ -342,17 +357,29 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
   }
 }
 
-__device__ __forceinline__ void block_flush(uint32_t hits, unsigned long long* count) {
+template <int MODE>
+__device__ __forceinline__ void block_flush(uint32_t hits, const Args& A) {
   __shared__ unsigned long long s_sum[kWaves];
   unsigned long long h = wave_sum((unsigned long long)hits);
   if (lane_id() == 0) s_sum[threadIdx.x >> 6] = h;
   __syncthreads();
-  if (threadIdx.x == 0 && count) {
+  if (threadIdx.x == 0 && A.count) {
     unsigned long long tot = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) tot += s_sum[w];
-    if (tot) atomicAdd(count, tot);
+    if (tot) atomicAdd(A.count, tot);
   }
+  if (MODE == MODE_BLOCK && A.per_shift && (int)threadIdx.x < A.q) {
+    const unsigned int c = shift_counters()[threadIdx.x];
+    if (c) atomicAdd(&A.per_shift[threadIdx.x], (unsigned long long)c);
+  }
+}
+
+// Clear the work-group's shift counters (MODE_BLOCK); a barrier follows in
+// every kernel before any credit.
+template <int MODE>
+__device__ __forceinline__ void block_init() {
+  if (MODE == MODE_BLOCK && threadIdx.x < 64) shift_counters()[threadIdx.x] = 0;
 }
 
 // Packs of light rows (one work-group each): up to kPackRows rows, one per
@@ -380,6 +407,7 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
   int32_t* tab = smem + kMarkInts + kPackMetaWords + 3;  // + 3 keeps 16-byte alignment
   int32_t* val = tab + pack_slots;
   if (lane < kBmWords) bm[lane] = 0;
+  block_init<MODE>();
 
   const uint32_t r0 = pack_ptr[blockIdx.x], r1 = pack_ptr[blockIdx.x + 1];
   const int nr = (int)(r1 - r0);  // 1 .. kPackRows
@@ -421,7 +449,7 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
       else hi = mid;
     }
     const uint32_t p = s_rs[lo] + (x - row_k0[lo]);
-    const int32_t key = A.col[p];
+    const int32_t key = A.hcol[p];
     const uint32_t dsc = row_desc[lo];
     const uint32_t base = dsc & 0xFFFFu, bmask = dsc >> 16;
     uint32_t bk = (uint32_t)key & bmask;
@@ -463,7 +491,7 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
     }
     wave_probe<MODE, TK_MULTI>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
   }
-  block_flush(hits, A.count);
+  block_flush<MODE>(hits, A);
 }
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
@@ -479,9 +507,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   const int32_t b = grp[0].b;
   const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
   if (lane < kBmWords) bm[lane] = 0;
+  block_init<MODE>();
   uint32_t hits = 0;
   TableRef tr{nullptr, nullptr, 0, 0, rs, d, nullptr, nullptr, 0};
-  if (!GLOBAL) {
+  if (GLOBAL) {
+    __syncthreads();  // shift counters cleared before any credit
+  } else {
     const uint32_t S = 1u << grp[0].log2S;
     int32_t* tab = smem + kMarkInts;
     int32_t* val = tab + S;
@@ -489,7 +520,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
     if (tid == 0) s_D = 0;
     __syncthreads();
     const uint32_t bmask = S / kBucket - 1;
-    int md = build_table<VALS>(tab, val, bmask, A.col, rs, d, tid, 256);
+    int md = build_table<VALS>(tab, val, bmask, A.hcol, rs, d, tid, 256);
     md = wave_max(md);
     if (lane == 0) atomicMax(&s_D, md);
     __syncthreads();
@@ -501,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   wave_sync_lds();
   const CountItem it = grp[wave];
   if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE>(A, tr, it.t0, it.q0, it.len, bm, hits);
-  block_flush(hits, A.count);
+  block_flush<MODE>(hits, A);
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
@@ -512,64 +543,78 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
 }
 
 // launch names seen by the phase timer: "<mode>:<class>"
-const char* const kLaunchNames[3][NUM_CLASSES] = {
+const char* const kLaunchNames[4][NUM_CLASSES] = {
     {"count:pack_small", "count:pack_large", "count:wg_small", "count:wg_large", "count:wg_huge",
      "count:global"},
     {"support_full:pack_small", "support_full:pack_large", "support_full:wg_small",
      "support_full:wg_large", "support_full:wg_huge", "support_full:global"},
     {"support_oriented:pack_small", "support_oriented:pack_large", "support_oriented:wg_small",
-     "support_oriented:wg_large", "support_oriented:wg_huge", "support_oriented:global"}};
+     "support_oriented:wg_large", "support_oriented:wg_huge", "support_oriented:global"},
+    {"block:pack_small", "block:pack_large", "block:wg_small", "block:wg_large", "block:wg_huge",
+     "block:global"}};
 
 template <int MODE>
-void launch_mode(const Graph& g, const Args& A, hipStream_t st) {
+void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const size_t mark_bytes = sizeof(int32_t) * kMarkInts;
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
-    if (g.n_packs[c] == 0) continue;
+    if (w.n_packs[c] == 0) continue;
     // a pack's tables take at most kPackSlots plus one row's table
-    const uint32_t slots = kPackSlots + (1u << g.pack_log2S[c]);
+    const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
     const size_t lds = sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 +
                                           (size_t)slots * (VALS ? 2 : 1));
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3((unsigned)g.n_packs[c]), dim3(256), lds,
-              st, A, g.pack_rows[c], g.pack_ptr[c], slots);
+    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3((unsigned)w.n_packs[c]), dim3(256), lds,
+              st, A, w.pack_rows[c], w.pack_ptr[c], slots);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
-    if (g.n_items[c] == 0) continue;
-    const unsigned grid = (unsigned)(g.n_items[c] / kWaves);
+    if (w.n_items[c] == 0) continue;
+    const unsigned grid = (unsigned)(w.n_items[c] / kWaves);
     if (c == CLS_GLOBAL) {
       TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes,
-                st, A, g.items[c]);
+                st, A, w.items[c]);
     } else {
-      const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << g.cls_log2S[c]) * (VALS ? 2 : 1);
+      const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << w.cls_log2S[c]) * (VALS ? 2 : 1);
       if (lds > 65536)
         TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A,
-                g.items[c]);
+                w.items[c]);
     }
   }
   TC_HIP(hipGetLastError());
 }
 
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
 
-void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_support,
-                  hipStream_t st) {
+void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t* d_support,
+                  int64_t* d_per_shift, hipStream_t st) {
+  const WorkSet& w = *v.w;
   if (d_count) TC_LAUNCH("zero_i64", k_zero_i64, dim3(1), dim3(1), 0, st, d_count);
-  if (mode != MODE_COUNT && g.m > 0)
-    TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(g.m, 256)), dim3(256), 0, st, d_support,
-              g.m);
+  if ((mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED) && v.pm > 0)
+    TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(v.pm, 256)), dim3(256), 0, st, d_support,
+              v.pm);
+  if (mode == MODE_BLOCK && d_per_shift)
+    TC_LAUNCH("zero_u64", k_zero_u64, dim3(1), dim3(64), 0, st,
+              reinterpret_cast<unsigned long long*>(d_per_shift), (int64_t)v.q);
   TC_HIP(hipGetLastError());
-  if (g.n_tasks == 0) return;
-  Args A{g.row_ptr, g.col, g.tstart, g.tprefix, g.tbeg, g.tend, g.n_tasks, (uint32_t)g.m,
-         reinterpret_cast<unsigned long long*>(d_count), d_support};
+  if (w.n_tasks == 0) return;
+  TC_REQUIRE(v.pm <= kMaxEdges, TC_EOVERFLOW, "launch_count: probe side exceeds 2^30 entries");
+  Args A{v.hrow_ptr, v.hcol, v.pcol, w.tstart, w.tprefix, w.tbeg, w.tend, w.n_tasks, (uint32_t)v.pm,
+         reinterpret_cast<unsigned long long*>(d_count), d_support,
+         reinterpret_cast<unsigned long long*>(d_per_shift), v.q, v.xy};
   switch (mode) {
-    case MODE_COUNT: launch_mode<MODE_COUNT>(g, A, st); break;
-    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL>(g, A, st); break;
-    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED>(g, A, st); break;
+    case MODE_COUNT: launch_mode<MODE_COUNT>(w, A, st); break;
+    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL>(w, A, st); break;
+    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED>(w, A, st); break;
+    case MODE_BLOCK: launch_mode<MODE_BLOCK>(w, A, st); break;
   }
 }
 

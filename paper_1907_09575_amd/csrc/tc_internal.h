@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "../../include/tc.h"
 
@@ -104,27 +105,43 @@ __host__ __device__ inline int pack_table_log2(int64_t d) {
   return l;
 }
 
-// Device-resident graph. All arrays live in one allocation (`arena`).
-struct Graph {
-  int device = 0;
-  int64_t n = 0, m_raw = 0, m = 0, n_tasks = 0;
-  int64_t wedges_plus = 0, probes = 0, max_dplus = 0;
-  int sbits = 1;  // ceil(log2(n)), >= 1
+// Allocations owned by a graph or a temporary work set (freed together).
+struct Owned {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <class T>
+  T* alloc(int64_t count) {
+    void* p = nullptr;
+    size_t b = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess)
+      throw Error(e == hipErrorOutOfMemory ? TC_ENOMEM : TC_EDEVICE,
+                  std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(p);
+    bytes += b;
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~Owned() { release(); }
+};
 
-  void* arena = nullptr;
-  size_t arena_bytes = 0;
-
-  int64_t* row_ptr = nullptr;   // n + 1, U rows
-  int32_t* col = nullptr;       // m, rows sorted ascending
-  int32_t* perm = nullptr;      // n, perm[original id] = rank
-  uint32_t* tbeg = nullptr;     // n, tasks of hashed row b: [tbeg[b], tend[b]) (class-major order)
-  uint32_t* tend = nullptr;     // n
-  uint32_t* tstart = nullptr;   // n_tasks, col index of the task's first probe
+// Tasks of a set of hashed rows and the work units of the count kernels.
+// Hashed rows are 0 .. nrows - 1 (ranks for a graph, rank-local rows for one
+// rank's block); a task's probes are entries of the probe-side CSR.
+struct WorkSet {
+  int64_t nrows = 0, n_tasks = 0, probes = 0;
+  uint32_t* tbeg = nullptr;     // nrows, tasks of hashed row b: [tbeg[b], tend[b]) (class-major order)
+  uint32_t* tend = nullptr;     // nrows
+  uint32_t* tstart = nullptr;   // n_tasks, probe-side index of the task's first probe
   uint64_t* tprefix = nullptr;  // n_tasks + 1, exclusive prefix of task lengths
 
-  // pack classes: packs[c] holds n_packs[c] + 1 offsets into pack_rows[c]
+  // pack classes: pack p covers pack_rows[c][pack_ptr[c][p] .. pack_ptr[c][p+1])
   int32_t* pack_rows[2] = {nullptr, nullptr};   // light rows b of the class, ascending
-  uint32_t* pack_ptr[2] = {nullptr, nullptr};   // pack p covers pack_rows[pack_ptr[p] .. pack_ptr[p+1])
+  uint32_t* pack_ptr[2] = {nullptr, nullptr};
   int64_t n_pack_rows[2] = {0, 0};
   int64_t n_packs[2] = {0, 0};
   int32_t pack_log2S[2] = {0, 0};               // largest row table of the class (log2 slots)
@@ -138,14 +155,59 @@ struct Graph {
   int64_t cls_stats[NUM_CLASSES][4] = {};
 };
 
+// Device-resident graph: U in CSR (rank space) and its work set.
+struct Graph {
+  int device = 0;
+  int64_t n = 0, m_raw = 0, m = 0;
+  int64_t wedges_plus = 0, max_dplus = 0;
+  int sbits = 1;  // ceil(log2(n)), >= 1
+  size_t arena_bytes = 0;
+
+  int64_t* row_ptr = nullptr;  // n + 1, U rows
+  int32_t* col = nullptr;      // m, rows sorted ascending
+  int32_t* perm = nullptr;     // n, perm[original id] = rank
+  WorkSet w;
+};
+
 extern const char* const kClassNames[NUM_CLASSES];
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
 // ---- launchers implemented in tc_count.hip ---------------------------------
-enum CountMode : int { MODE_COUNT = 0, MODE_SUPPORT_FULL = 1, MODE_SUPPORT_ORIENTED = 2 };
-void launch_count(const Graph& g, CountMode mode, int64_t* d_count, int32_t* d_support,
-                  hipStream_t stream);
+enum CountMode : int {
+  MODE_COUNT = 0,
+  MODE_SUPPORT_FULL = 1,
+  MODE_SUPPORT_ORIENTED = 2,
+  MODE_BLOCK = 3  // count plus per-shift split of one rank's block (Eq. 5)
+};
+
+// What the count kernels read: the hash side (rows b, their sorted entries),
+// the probe side (entries probed by tasks) and the work set.
+struct CountView {
+  const int64_t* hrow_ptr;
+  const int32_t* hcol;
+  const int32_t* pcol;
+  int64_t pm;  // entries of pcol
+  const WorkSet* w;
+  int32_t q = 1, xy = 0;  // MODE_BLOCK: grid size and (x + y) % q
+};
+
+void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t* d_support,
+                  int64_t* d_per_shift, hipStream_t stream);
+
+inline CountView graph_view(const Graph& g) {
+  return CountView{g.row_ptr, g.col, g.col, g.m, &g.w, 1, 0};
+}
+
+// ---- work-set construction (tc_preprocess.hip) --------------------------------
+// From T tasks in hashed-row order (tb_row = row of each task, tb_ptr = row
+// bounds, tb_start / tb_len = first probe and probe count, tb_prefix = their
+// exclusive prefix with the total at [T]): classes, class-major order, packs
+// and items. hrow_ptr gives |U_b| of every hashed row.
+void build_work(WorkSet& w, Owned& own, int64_t nrows, const int64_t* hrow_ptr, int64_t T,
+                const uint32_t* tb_row, const int64_t* tb_ptr, const uint32_t* tb_start,
+                const uint32_t* tb_len, const uint64_t* tb_prefix, hipStream_t st);
+
 
 inline int ceil_log2_u64(uint64_t x) {
   int r = 0;

@@ -402,30 +402,10 @@ T read_scalar(const T* d, hipStream_t st) {
   return h;
 }
 
-// Allocation owned by the graph (freed by tc_graph_free).
-struct Owned {
-  std::vector<void*> ptrs;
-  size_t bytes = 0;
-  template <class T>
-  T* alloc(int64_t count) {
-    void* p = nullptr;
-    size_t b = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
-    TC_HIP(hipMalloc(&p, b));
-    ptrs.push_back(p);
-    bytes += b;
-    return static_cast<T*>(p);
-  }
-  void release() {
-    for (void* p : ptrs) (void)hipFree(p);
-    ptrs.clear();
-  }
-};
-
 }  // namespace
 
 struct GraphImpl : Graph {
   Owned owned;
-  ~GraphImpl() { owned.release(); }
 };
 
 void destroy_graph(Graph* g) { delete static_cast<GraphImpl*>(g); }
@@ -541,52 +521,23 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   }
 
   // ---- 5: tasks grouped by hashed row b -----------------------------------
-  // Built in b order first (tb_* temporaries); step 6 reorders them class-major.
-  int64_t T = 0;
-  g->tbeg = g->owned.alloc<uint32_t>(n);
-  g->tend = g->owned.alloc<uint32_t>(n);
-  DevBuf tb_ptr(sizeof(int64_t) * (size_t)(n + 1));  // tasks of row b: [tb_ptr[b], tb_ptr[b + 1])
-  DevBuf tb_row, tb_start, tb_len, tb_prefix;         // per task (b order): row, first probe, probes
+  TaskLists tl;
   {
     DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
+    int64_t T = 0;
     if (m > 0) {
       TC_LAUNCH("task_flags", k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
                 flags.as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m, d_tot32, st);
       T = read_scalar(d_tot32, st);
     }
-    g->n_tasks = T;
-    g->tstart = g->owned.alloc<uint32_t>(T);
-    g->tprefix = g->owned.alloc<uint64_t>(T + 1);
     if (T > 0) {
-      tb_row.alloc(sizeof(uint32_t) * (size_t)T);
-      tb_start.alloc(sizeof(uint32_t) * (size_t)T);
-      tb_len.alloc(sizeof(uint32_t) * (size_t)T);
-      tb_prefix.alloc(sizeof(uint64_t) * (size_t)(T + 1));
-      DevBuf tk(sizeof(uint32_t) * (size_t)T), tk2(sizeof(uint32_t) * (size_t)T);
-      DevBuf tv(sizeof(uint64_t) * (size_t)T), tv2(sizeof(uint64_t) * (size_t)T);
+      DevBuf tk(sizeof(uint32_t) * (size_t)T), tv(sizeof(uint64_t) * (size_t)T);
       TC_LAUNCH("task_emit", k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
                 flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
       TC_HIP(hipGetLastError());
-      bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tk2.as<uint32_t>(), tv.as<uint64_t>(),
-                                                tv2.as<uint64_t>(), T, 0, s, st, "tasks");
-      const uint32_t* skey = alt ? tk2.as<uint32_t>() : tk.as<uint32_t>();
-      const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv.as<uint64_t>();
-      TC_HIP(hipMemcpyAsync(tb_row.p, skey, sizeof(uint32_t) * (size_t)T, hipMemcpyDeviceToDevice, st));
-      TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T,
-                tb_start.as<uint32_t>(), tb_len.as<uint32_t>());
-      device_excl_scan<uint32_t, uint64_t>(tb_len.as<uint32_t>(), tb_prefix.as<uint64_t>(), T,
-                                           tb_prefix.as<uint64_t>() + T, st);
-      TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, skey, T, 0, n,
-                tb_ptr.as<int64_t>());
-      TC_HIP(hipGetLastError());
-      g->probes = (int64_t)read_scalar(tb_prefix.as<uint64_t>() + T, st);
-    } else {
-      TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, g->tbeg, n, 0u);
-      TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, g->tend, n, 0u);
-      TC_HIP(hipMemsetAsync(g->tprefix, 0, sizeof(uint64_t), st));
-      g->probes = 0;
+      sort_tasks(tl, tk.as<uint32_t>(), tv.as<uint64_t>(), T, n, s, st, "tasks");
     }
     g->wedges_plus = (int64_t)read_scalar(reinterpret_cast<uint64_t*>(d_wplus), st);
     g->max_dplus = (int64_t)read_scalar(reinterpret_cast<uint32_t*>(d_maxd), st);
@@ -595,101 +546,146 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   ok.release();
 
   // ---- 6: work classes ------------------------------------------------------
-  if (T > 0) {
-    DevBuf cls(sizeof(int8_t) * (size_t)n);
-    DevBuf clsl(sizeof(int) * NUM_CLASSES);
-    TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
-    TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, tb_ptr.as<int64_t>(),
-              tb_prefix.as<uint64_t>(), g->row_ptr, n, cls.as<int8_t>(), clsl.as<int>());
-    TC_HIP(hipGetLastError());
-    int h_cl[NUM_CLASSES];
-    TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
-    // class-major task order: the rows of class 0 (ascending b), then class 1,
-    // ...; each row keeps its tasks in b order, so every class - and every pack
-    // of consecutive rows of a class - owns one contiguous task range
-    {
-      DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
-      uint32_t base = 0;
-      for (int c = 0; c < NUM_CLASSES; ++c) {
-        TC_LAUNCH("class_tasks", k_class_tasks, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n,
-                  c, tb_ptr.as<int64_t>(), cnt.as<uint32_t>());
-        device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
-                                             offs.as<uint32_t>() + n, st);
-        TC_LAUNCH("row_begin", k_row_begin, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                  offs.as<uint32_t>(), base, tb_ptr.as<int64_t>(), g->tbeg, g->tend);
-        base += read_scalar(offs.as<uint32_t>() + n, st);
-      }
-      TC_REQUIRE((int64_t)base == T, TC_EDEVICE, "tc_preprocess: class-major task order lost tasks");
-      DevBuf tlen(sizeof(uint32_t) * (size_t)T);
-      TC_LAUNCH("task_permute", k_task_permute, dim3(grid_for(T)), dim3(kT), 0, st, T,
-                tb_row.as<uint32_t>(), tb_ptr.as<int64_t>(), g->tbeg, tb_start.as<uint32_t>(),
-                tb_len.as<uint32_t>(), g->tstart, tlen.as<uint32_t>());
-      device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), g->tprefix, T, g->tprefix + T, st);
-      TC_HIP(hipGetLastError());
-    }
-    tb_row.release();
-    tb_start.release();
-    tb_len.release();
-    tb_prefix.release();
-    tb_ptr.release();
-    {
-      const int64_t nb = (int64_t)grid_for(n);
-      DevBuf part(sizeof(unsigned long long) * (size_t)nb * kStatCols);
-      DevBuf sums(sizeof(unsigned long long) * kStatCols);
-      TC_LAUNCH("class_stats", k_class_stats, dim3((unsigned)nb), dim3(kT), 0, st, cls.as<int8_t>(), n,
-                g->tbeg, g->tend, g->tprefix, g->row_ptr, part.as<unsigned long long>());
-      TC_LAUNCH("reduce_cols", k_reduce_cols, dim3(kStatCols), dim3(kT), 0, st,
-                part.as<unsigned long long>(), nb, kStatCols, sums.as<unsigned long long>());
-      TC_HIP(hipGetLastError());
-      TC_HIP(hipMemcpyAsync(&g->cls_stats[0][0], sums.p, sizeof(g->cls_stats), hipMemcpyDeviceToHost, st));
-      TC_HIP(hipStreamSynchronize(st));
-    }
-    DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
-    for (int c = 0; c < NUM_CLASSES; ++c) {
-      g->cls_log2S[c] = h_cl[c];
-      TC_LAUNCH("class_count", k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                         g->tbeg, g->tend, g->tprefix, cnt.as<uint32_t>());
-      device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
-                                           offs.as<uint32_t>() + n, st);
-      const int64_t total = read_scalar(offs.as<uint32_t>() + n, st);
-      if (total == 0) continue;
-      if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
-        int32_t* rows = g->owned.alloc<int32_t>(total);
-        TC_LAUNCH("class_rows", k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                           offs.as<uint32_t>(), rows);
-        DevBuf w(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
-        DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
-        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, g->tbeg,
-                  g->tend, g->tprefix, g->row_ptr, w.as<uint64_t>(), sl.as<uint32_t>());
-        device_excl_scan<uint64_t, uint64_t>(w.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
-        device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
-        DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
-        TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
-                  psl.as<uint32_t>(), total, pf.as<uint32_t>());
-        device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
-        const int64_t np = read_scalar(d_tot32, st);
-        uint32_t* pack_ptr = g->owned.alloc<uint32_t>(np + 1);
-        TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
-                           pp.as<uint32_t>(), total, pack_ptr, np);
-        TC_HIP(hipGetLastError());
-        g->pack_rows[c] = rows;
-        g->pack_ptr[c] = pack_ptr;
-        g->n_pack_rows[c] = total;
-        g->n_packs[c] = np;
-        g->pack_log2S[c] = h_cl[c];
-      } else {
-        CountItem* items = g->owned.alloc<CountItem>(total);
-        TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(), n,
-                           total, g->tbeg, g->tend, g->tprefix, g->row_ptr, items);
-        TC_HIP(hipGetLastError());
-        g->items[c] = items;
-        g->n_items[c] = total;
-      }
-    }
-  }
+  build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
+             tl.start.as<uint32_t>(), tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), st);
   TC_HIP(hipStreamSynchronize(st));
   g->arena_bytes = g->owned.bytes;
   return g.release();
+}
+
+void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
+                hipStream_t st, const char* name) {
+  tl.T = T;
+  tl.ptr.alloc(sizeof(int64_t) * (size_t)(nrows + 1));
+  if (T == 0) {
+    TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(nrows + 1)), dim3(kT), 0, st, tl.ptr.as<int64_t>(),
+              nrows + 1, (int64_t)0);
+    return;
+  }
+  tl.row.alloc(sizeof(uint32_t) * (size_t)T);
+  tl.start.alloc(sizeof(uint32_t) * (size_t)T);
+  tl.len.alloc(sizeof(uint32_t) * (size_t)T);
+  tl.prefix.alloc(sizeof(uint64_t) * (size_t)(T + 1));
+  DevBuf tv2(sizeof(uint64_t) * (size_t)T);
+  // the row array doubles as the key ping-pong buffer
+  bool alt = radix_sort<uint32_t, uint64_t>(tk, tl.row.as<uint32_t>(), tv, tv2.as<uint64_t>(), T, 0,
+                                            key_bits, st, name);
+  const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv;
+  if (!alt)
+    TC_HIP(hipMemcpyAsync(tl.row.p, tk, sizeof(uint32_t) * (size_t)T, hipMemcpyDeviceToDevice, st));
+  TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T,
+            tl.start.as<uint32_t>(), tl.len.as<uint32_t>());
+  device_excl_scan<uint32_t, uint64_t>(tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), T,
+                                       tl.prefix.as<uint64_t>() + T, st);
+  TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nrows + 1)), dim3(kT), 0, st,
+            tl.row.as<uint32_t>(), T, 0, nrows, tl.ptr.as<int64_t>());
+  TC_HIP(hipGetLastError());
+}
+
+void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int64_t T,
+                const uint32_t* tb_row, const int64_t* tb_ptr, const uint32_t* tb_start,
+                const uint32_t* tb_len, const uint64_t* tb_prefix, hipStream_t st) {
+  w.nrows = n;
+  w.n_tasks = T;
+  w.tbeg = own.alloc<uint32_t>(n);
+  w.tend = own.alloc<uint32_t>(n);
+  w.tstart = own.alloc<uint32_t>(T);
+  w.tprefix = own.alloc<uint64_t>(T + 1);
+  DevBuf dscal(64);
+  uint32_t* d_tot32 = dscal.as<uint32_t>();
+  uint64_t* d_tot64 = reinterpret_cast<uint64_t*>(dscal.as<char>() + 32);
+  if (T == 0) {
+    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tbeg, n, 0u);
+    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tend, n, 0u);
+    TC_HIP(hipMemsetAsync(w.tprefix, 0, sizeof(uint64_t), st));
+    w.probes = 0;
+    return;
+  }
+  w.probes = (int64_t)read_scalar(tb_prefix + T, st);
+  DevBuf cls(sizeof(int8_t) * (size_t)n);
+  DevBuf clsl(sizeof(int) * NUM_CLASSES);
+  TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
+  TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
+            cls.as<int8_t>(), clsl.as<int>());
+  TC_HIP(hipGetLastError());
+  int h_cl[NUM_CLASSES];
+  TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
+  // class-major task order: the rows of class 0 (ascending b), then class 1,
+  // ...; each row keeps its tasks in b order, so every class - and every pack
+  // of consecutive rows of a class - owns one contiguous task range
+  {
+    DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
+    uint32_t base = 0;
+    for (int c = 0; c < NUM_CLASSES; ++c) {
+      TC_LAUNCH("class_tasks", k_class_tasks, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                tb_ptr, cnt.as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
+                                           offs.as<uint32_t>() + n, st);
+      TC_LAUNCH("row_begin", k_row_begin, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                offs.as<uint32_t>(), base, tb_ptr, w.tbeg, w.tend);
+      base += read_scalar(offs.as<uint32_t>() + n, st);
+    }
+    TC_REQUIRE((int64_t)base == T, TC_EDEVICE, "build_work: class-major task order lost tasks");
+    DevBuf tlen(sizeof(uint32_t) * (size_t)T);
+    TC_LAUNCH("task_permute", k_task_permute, dim3(grid_for(T)), dim3(kT), 0, st, T, tb_row, tb_ptr,
+              w.tbeg, tb_start, tb_len, w.tstart, tlen.as<uint32_t>());
+    device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), w.tprefix, T, w.tprefix + T, st);
+    TC_HIP(hipGetLastError());
+  }
+  {
+    const int64_t nb = (int64_t)grid_for(n);
+    DevBuf part(sizeof(unsigned long long) * (size_t)nb * kStatCols);
+    DevBuf sums(sizeof(unsigned long long) * kStatCols);
+    TC_LAUNCH("class_stats", k_class_stats, dim3((unsigned)nb), dim3(kT), 0, st, cls.as<int8_t>(), n,
+              w.tbeg, w.tend, w.tprefix, hrow_ptr, part.as<unsigned long long>());
+    TC_LAUNCH("reduce_cols", k_reduce_cols, dim3(kStatCols), dim3(kT), 0, st,
+              part.as<unsigned long long>(), nb, kStatCols, sums.as<unsigned long long>());
+    TC_HIP(hipGetLastError());
+    TC_HIP(hipMemcpyAsync(&w.cls_stats[0][0], sums.p, sizeof(w.cls_stats), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipStreamSynchronize(st));
+  }
+  DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
+  for (int c = 0; c < NUM_CLASSES; ++c) {
+    w.cls_log2S[c] = h_cl[c];
+    TC_LAUNCH("class_count", k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+              w.tbeg, w.tend, w.tprefix, cnt.as<uint32_t>());
+    device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
+                                         offs.as<uint32_t>() + n, st);
+    const int64_t total = read_scalar(offs.as<uint32_t>() + n, st);
+    if (total == 0) continue;
+    if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
+      int32_t* rows = own.alloc<int32_t>(total);
+      TC_LAUNCH("class_rows", k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
+                offs.as<uint32_t>(), rows);
+      DevBuf wk(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
+      DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
+      TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, w.tbeg,
+                w.tend, w.tprefix, hrow_ptr, wk.as<uint64_t>(), sl.as<uint32_t>());
+      device_excl_scan<uint64_t, uint64_t>(wk.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
+      device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
+      DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
+      TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
+                psl.as<uint32_t>(), total, pf.as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
+      const int64_t np = read_scalar(d_tot32, st);
+      uint32_t* pack_ptr = own.alloc<uint32_t>(np + 1);
+      TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
+                pp.as<uint32_t>(), total, pack_ptr, np);
+      TC_HIP(hipGetLastError());
+      w.pack_rows[c] = rows;
+      w.pack_ptr[c] = pack_ptr;
+      w.n_pack_rows[c] = total;
+      w.n_packs[c] = np;
+      w.pack_log2S[c] = h_cl[c];
+    } else {
+      CountItem* items = own.alloc<CountItem>(total);
+      TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(),
+                n, total, w.tbeg, w.tend, w.tprefix, hrow_ptr, items);
+      TC_HIP(hipGetLastError());
+      w.items[c] = items;
+      w.n_items[c] = total;
+    }
+  }
 }
 
 }  // namespace tc

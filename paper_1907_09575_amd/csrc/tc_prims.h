@@ -373,4 +373,20 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
   return alt;
 }
 
+// Tasks in hashed-row order (the input of build_work).
+struct TaskLists {
+  int64_t T = 0;
+  DevBuf row;     // uint32 [T]: hashed row of each task
+  DevBuf start;   // uint32 [T]: first probe (probe-side index)
+  DevBuf len;     // uint32 [T]: probes
+  DevBuf prefix;  // uint64 [T + 1]: exclusive prefix of len, total at [T]
+  DevBuf ptr;     // int64 [nrows + 1]: tasks of row b are [ptr[b], ptr[b + 1])
+};
+
+// Sort T emitted tasks (keys = hashed row in [0, 2^key_bits), values =
+// first probe | end << 32) stably by row and fill `tl`. tk / tv are consumed
+// as sort buffers.
+void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
+                hipStream_t st, const char* name);
+
 }  // namespace tc

@@ -2,10 +2,6 @@
 #include "tc_internal.h"
 
 extern "C" {
-tc_status tc_block_count(const tc_graph*, int32_t, int32_t, int32_t, int64_t*, int64_t*, void*) {
-  tc::set_last_error("tc_block_count: not implemented in this build");
-  return TC_EINVAL;
-}
 tc_status tc_batch_create(const tc_graph* const*, int32_t, const char*, void*, tc_batch** out) {
   if (out) *out = nullptr;
   tc::set_last_error("tc_batch_create: not implemented in this build");

@@ -63,6 +63,15 @@ def test_argument_validation_without_device(lib):
     assert lib.tc_edge_support(None, 0, None, None, None) == 1
     lib.tc_last_error.restype = ctypes.c_char_p
     assert b"null" in lib.tc_last_error()
+    I32 = ctypes.c_int32
+    lib.tc_block_count.argtypes = [P, I32, I32, I32, P, P, P]
+    assert lib.tc_block_count(None, 2, 0, 0, None, None, None) == 1
+    # the grid is checked before the handle is touched (a dummy handle is
+    # never dereferenced on these paths)
+    dummy = P(16)
+    for q, x, y in [(0, 0, 0), (65, 0, 0), (13, 13, 0), (13, 0, -1)]:
+        assert lib.tc_block_count(dummy, q, x, y, dummy, None, None) == 1
+    assert b"grid" in lib.tc_last_error() or b"q must" in lib.tc_last_error()
     lib.tc_graph_free.argtypes = [P]
     lib.tc_graph_free(None)  # no-op
 

@@ -186,3 +186,90 @@ def test_hbm_fallback_rows(tc):
     rp, col, _ = tc.tc_graph_export(g)
     col = col.cpu().numpy()
     assert np.array_equal(sup, (n - 1 - col).astype(np.int32))
+
+
+# ------------------------------------------------ one rank's block (Eq. 5) --
+
+def gpu_block(tc, g, q, x, y):
+    ps = torch.full((q,), -1, dtype=torch.int64, device="cuda")
+    c, _ = tc.tc_block_count(g, q, x, y, per_shift=ps)
+    torch.cuda.synchronize()
+    return int(c.item()), ps.cpu().numpy()
+
+
+def check_blocks(tc, g, U, q):
+    B, S = oracle.block_counts(U, q)
+    for x in range(q):
+        for y in range(q):
+            b, s = gpu_block(tc, g, q, x, y)
+            assert b == B[x, y], "block (%d, %d) of q=%d" % (x, y, q)
+            assert np.array_equal(s, S[x, y]), "shifts of block (%d, %d) of q=%d" % (x, y, q)
+    return B
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 13])
+def test_block_small_graphs(tc, q):
+    cases = [sg.complete(12), sg.wheel(30), sg.messy(*sg.random_graph(70, 0.2, 31), seed=3),
+             (*graphgen.rmat(10, seed=5), 1 << 10), sg.complete(5)]
+    for s, d, n in cases:
+        U = oracle.preprocess(s, d, n)
+        g = gpu_graph(tc, s, d, n)
+        B = check_blocks(tc, g, U, q)
+        assert int(B.sum()) == oracle.count(U)
+
+
+def test_block_rmat16_q13(tc):
+    s, d = graphgen.rmat(16, seed=6)
+    U = oracle.preprocess(s, d, 1 << 16)
+    g = gpu_graph(tc, s, d, 1 << 16)
+    check_blocks(tc, g, U, 13)
+
+
+def test_block_rmat20_q13(tc):
+    # sampled ranks against the oracle one by one; the whole grid sums to T
+    s, d = graphgen.rmat(20, seed=1)
+    U = oracle.preprocess(s, d, 1 << 20)
+    g = gpu_graph(tc, s, d, 1 << 20)
+    for x, y in [(0, 0), (3, 9), (12, 12), (7, 1)]:
+        b1, s1 = oracle.block_count_one(U, 13, x, y)
+        b, sh = gpu_block(tc, g, 13, x, y)
+        assert b == b1 and np.array_equal(sh, s1), (x, y)
+    total = 0
+    for x in range(13):
+        for y in range(13):
+            b, sh = gpu_block(tc, g, 13, x, y)
+            assert int(sh.sum()) == b
+            total += b
+    assert total == gpu_count(tc, g) == oracle.count(U)
+
+
+def test_block_hbm_fallback_rows(tc):
+    # K_n, ranks = ids: rank (x, y) counts i < j < k with i % q == y,
+    # j % q == x and shift z taking k % q == (x + y + z) % q; the first hashed
+    # rows have more than 4096 entries and take the binary-search path
+    n, q = 8300, 2
+    iu = np.triu_indices(n, 1)
+    g = gpu_graph(tc, iu[0].astype(np.int32), iu[1].astype(np.int32), n)
+    v = np.arange(n)
+    for x in range(q):
+        for y in range(q):
+            b, sh = gpu_block(tc, g, q, x, y)
+            exp = np.zeros(q, np.int64)
+            for z in range(q):
+                c = (x + y + z) % q
+                below = np.cumsum(v % q == y) - (v % q == y)       # i < j with i % q == y
+                above = np.cumsum((v % q == c)[::-1])[::-1] - (v % q == c)  # k > j with k % q == c
+                jm = v % q == x
+                exp[z] = int((below[jm] * above[jm]).sum())
+            assert np.array_equal(sh, exp), (x, y)
+            assert b == int(exp.sum())
+
+
+def test_block_tiny_grid_larger_than_graph(tc):
+    # q > n: most ranks own no rows at all
+    s, d, n = sg.complete(5)
+    U = oracle.preprocess(s, d, n)
+    g = gpu_graph(tc, s, d, n)
+    check_blocks(tc, g, U, 13)
+    b, sh = gpu_block(tc, g, 64, 63, 63)
+    assert b == 0 and not sh.any()

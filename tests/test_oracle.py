@@ -246,6 +246,11 @@ def test_block_counts(q):
     assert np.array_equal(S, Sb)
     if q == 1:
         assert B[0, 0] == T
+    for x in range(q):
+        for y in range(q):
+            b1, s1 = oracle.block_count_one(U, q, x, y)
+            assert b1 == Bb[x, y]
+            assert np.array_equal(s1, Sb[x, y])
 
 
 # ----------------------------------------------------------- pair common --
