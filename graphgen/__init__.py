@@ -135,6 +135,14 @@ class GraphSpec:
         return rmat(scale_for(self.n), seed=self.seed, n=self.n, m=self.m, threads=threads)
 
 
+def generate_many(specs, threads: int = 16):
+    """Edge lists of many specs, generated concurrently (the C generators run
+    without the GIL); the output of each spec does not depend on threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(lambda s: s.generate(threads=1), specs))
+
+
 def batch_specs(count: int = 4096, seed: int = 1, nmin: int = 64, nmax: int = 65536,
                 er_deg=(8.0, 64.0), rmat_ef=(8.0, 32.0), seed_base: int = 1000):
     """Uneven batch: n log-uniform in [nmin, nmax]; even index ER with average

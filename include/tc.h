@@ -145,28 +145,50 @@ typedef struct tc_batch tc_batch;
 
 /*
  * tc_batch_create - plan one persistent launch over `num_graphs` handles
- * (host array of handles; graphs may repeat). The work items of all graphs
- * are merged into one device queue in decreasing size order (largest first).
- * tuning_json (nullable) overrides the schedule, e.g.
- * {"waves_per_block": 4, "blocks_per_cu": 8}. The handles must outlive the
- * plan. Synchronises `stream`.
+ * (host array of handles; graphs may repeat). The work units of every graph
+ * (the packs and item groups its own tc_count would launch) are merged into
+ * one device queue, by default largest first (longest-processing-time order).
+ * tuning_json (nullable) is a flat JSON object choosing the schedule:
+ *   "blocks_per_cu" (int, 0 = as many as LDS allows), "lds_cap_log2" (int in
+ *   [6, 14]: item rows whose table exceeds 2^cap slots are looked up in HBM
+ *   instead of LDS), "order" ("lpt" | "input"), "graph" (1 = launch through a
+ *   captured HIP graph, 0 = plain launches); tc_batch_autotune's output is
+ *   accepted as is. Unknown keys: TC_EINVAL. The handles must outlive the
+ *   plan. Synchronises `stream`.
  */
 tc_status tc_batch_create(const tc_graph* const* graphs, int32_t num_graphs,
                           const char* tuning_json, void* stream, tc_batch** out);
 
 /*
  * tc_batch_count - per-graph exact counts into the device int64[num_graphs]
- * d_counts (same order as the handles). One kernel launch plus one small
- * clearing kernel; safe to capture in a HIP graph. Calls that overlap on one
+ * d_counts (same order as the handles), equal to tc_count's. Two kernels: one
+ * clears the counts and the queue counter, one persistent launch drains the
+ * queue; with "graph": 1 they run as one HIP graph (captured on the first call
+ * for a given d_counts), and when `stream` is itself being captured they are
+ * recorded into the caller's graph. Asynchronous. Calls that overlap on one
  * plan race (the plan holds the queue counter).
  */
 tc_status tc_batch_count(tc_batch* plan, int64_t* d_counts, void* stream);
 
 void tc_batch_free(tc_batch* plan);
 
+/* The plan's schedule and size as JSON (units, grid, LDS bytes, ...) into the
+ * host buffer out[cap]; TC_EINVAL if it does not fit. */
+tc_status tc_batch_describe(const tc_batch* plan, char* out, size_t cap);
+
 /* One-shot convenience: create a plan, count, free it (synchronises). */
 tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
                            const char* tuning_json, void* stream);
+
+/*
+ * tc_batch_autotune - time candidate schedules (LDS caps that change the
+ * plan x unit orders x blocks per CU) on these graphs and write
+ * {"best": {...}, "candidates": [...]} into the host buffer out_json[cap];
+ * "best" can be passed to tc_batch_create. Synchronises `stream`; allocates
+ * and frees its own scratch.
+ */
+tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, void* stream,
+                            char* out_json, size_t cap);
 
 /* ---- work classes and phase timers (profiling) ------------------------------ */
 

@@ -8,7 +8,7 @@ fallback: importing the package without a built ``libtc.so`` raises.
 
 Functions carry the C names: tc_preprocess, tc_graph_info, tc_graph_export,
 tc_count, tc_edge_support, tc_block_count, tc_batch_create, tc_batch_count,
-tc_batch_free, tc_count_batched, tc_graph_free.
+tc_batch_free, tc_batch_describe, tc_count_batched, tc_batch_autotune, tc_graph_free.
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
-    "tc_count_batched", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
+    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
@@ -65,6 +65,8 @@ _sig("tc_batch_create", [ctypes.POINTER(_P), _I32, ctypes.c_char_p, _P, ctypes.P
 _sig("tc_batch_count", [_P, _P, _P])
 _sig("tc_batch_free", [_P], None)
 _sig("tc_count_batched", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, _P])
+_sig("tc_batch_describe", [_P, ctypes.c_char_p, ctypes.c_size_t])
+_sig("tc_batch_autotune", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_graph_free", [_P], None)
 _sig("tc_graph_class_stats", [_P, _P])
 _sig("tc_class_name", [_I32], ctypes.c_char_p)
@@ -283,6 +285,23 @@ def tc_batch_count(plan: Batch, counts: torch.Tensor | None = None, stream=None)
 
 def tc_batch_free(plan: Batch):
     plan.free()
+
+
+def tc_batch_describe(plan: Batch) -> dict:
+    """The plan's schedule and size (units, grid, LDS bytes, ...)."""
+    import json
+    buf = ctypes.create_string_buffer(1024)
+    _check(_lib.tc_batch_describe(plan.handle, buf, len(buf)), "tc_batch_describe")
+    return json.loads(buf.value.decode())
+
+
+def tc_batch_autotune(graphs, stream=None) -> dict:
+    """Time candidate schedules on these graphs: {"best": {...}, "candidates": [...]}."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.tc_batch_autotune(_handles(graphs), len(graphs), _stream(stream), buf, len(buf)),
+           "tc_batch_autotune")
+    return json.loads(buf.value.decode())
 
 
 def tc_count_batched(graphs, counts: torch.Tensor | None = None, tuning=None, stream=None):

@@ -1,0 +1,515 @@
+// tc_batch.hip - batched counting of many preprocessed graphs in one
+// persistent launch, its plan (work units of every graph in one device queue),
+// HIP-graph capture of the launch, and the schedule autotuner.
+//
+// The units are exactly the work units the single-graph launches run (packs
+// of light rows, work-groups of items of heavy rows), so every per-graph count
+// is the same integer as tc_count's. The plan orders them largest first
+// (longest-processing-time order) so that the persistent work-groups finish
+// together; the tuner picks the schedule on the actual batch:
+//   blocks_per_cu - resident work-groups per compute unit (grid size);
+//   lds_cap_log2  - largest table kept in LDS: item rows above it (the
+//                   heaviest row bucket) are looked up in HBM instead, which
+//                   shrinks the kernel's LDS and raises occupancy;
+//   order         - "lpt" (largest unit first) or "input" (graph order);
+//   graph         - 1: launch through a captured HIP graph, 0: plain launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cctype>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+
+#include "tc_prims.h"
+
+namespace tc {
+
+namespace {
+
+struct Tuning {
+  int blocks_per_cu = 0;  // 0: as many as LDS allows, at most kMaxBlocksPerCU
+  int lds_cap_log2 = kMaxLog2S;
+  bool lpt = true;
+  bool graph = true;
+};
+
+constexpr int kMaxBlocksPerCU = 8;
+constexpr size_t kLdsPerCU = 160 * 1024;
+
+// A flat JSON object of integers and strings, e.g.
+// {"blocks_per_cu": 4, "lds_cap_log2": 13, "order": "lpt", "graph": 1}.
+// Unknown keys and malformed text are errors (TC_EINVAL).
+std::map<std::string, std::string> parse_flat_json(const char* js) {
+  std::map<std::string, std::string> kv;
+  const char* p = js;
+  auto ws = [&] { while (*p && std::isspace((unsigned char)*p)) ++p; };
+  auto fail = [&](const char* what) {
+    throw Error(TC_EINVAL, std::string("tuning json: ") + what + " near '" + std::string(p).substr(0, 20) + "'");
+  };
+  auto str = [&]() {
+    if (*p != '"') fail("expected a string");
+    ++p;
+    std::string s;
+    while (*p && *p != '"') s += *p++;
+    if (*p != '"') fail("unterminated string");
+    ++p;
+    return s;
+  };
+  ws();
+  if (*p != '{') fail("expected '{'");
+  ++p;
+  ws();
+  if (*p == '}') return kv;
+  while (true) {
+    ws();
+    std::string k = str();
+    ws();
+    if (*p != ':') fail("expected ':'");
+    ++p;
+    ws();
+    std::string v;
+    if (*p == '"') {
+      v = str();
+    } else {
+      while (*p && (std::isalnum((unsigned char)*p) || *p == '-' || *p == '+' || *p == '.')) v += *p++;
+      if (v.empty()) fail("expected a value");
+    }
+    kv[k] = v;
+    ws();
+    if (*p == ',') {
+      ++p;
+      continue;
+    }
+    if (*p == '}') break;
+    fail("expected ',' or '}'");
+  }
+  return kv;
+}
+
+int to_int(const std::string& k, const std::string& v) {
+  char* end = nullptr;
+  long x = std::strtol(v.c_str(), &end, 10);
+  TC_REQUIRE(end && *end == '\0' && !v.empty(), TC_EINVAL, "tuning json: " + k + " must be an integer");
+  return (int)x;
+}
+
+Tuning parse_tuning(const char* js) {
+  Tuning t;
+  if (!js || !*js) return t;
+  for (const auto& kv : parse_flat_json(js)) {
+    const std::string& k = kv.first;
+    const std::string& v = kv.second;
+    if (k == "blocks_per_cu") {
+      t.blocks_per_cu = to_int(k, v);
+      TC_REQUIRE(t.blocks_per_cu >= 0 && t.blocks_per_cu <= 64, TC_EINVAL,
+                 "tuning json: blocks_per_cu outside [0, 64]");
+    } else if (k == "lds_cap_log2") {
+      t.lds_cap_log2 = to_int(k, v);
+      TC_REQUIRE(t.lds_cap_log2 >= 6 && t.lds_cap_log2 <= kMaxLog2S, TC_EINVAL,
+                 "tuning json: lds_cap_log2 outside [6, 14]");
+    } else if (k == "order") {
+      TC_REQUIRE(v == "lpt" || v == "input", TC_EINVAL, "tuning json: order must be \"lpt\" or \"input\"");
+      t.lpt = v == "lpt";
+    } else if (k == "graph") {
+      t.graph = to_int(k, v) != 0;
+    } else if (k == "waves_per_block") {
+      TC_REQUIRE(to_int(k, v) == kWaves, TC_EINVAL, "tuning json: waves_per_block must be 4");
+    } else if (k == "ms" || k == "units" || k == "hbm_units" || k == "grid" || k == "lds_bytes") {
+      // descriptive keys of the tuner's own output, accepted so that it can be passed back
+    } else {
+      throw Error(TC_EINVAL, "tuning json: unknown key \"" + k + "\"");
+    }
+  }
+  return t;
+}
+
+// Per graph entry of the plan: where its units come from (device copy).
+struct BatchSrc {
+  const int32_t* pack_rows[2];
+  const uint32_t* pack_ptr[2];
+  const CountItem* items[4];  // classes wg_small, wg_large, wg_huge, global
+  const uint32_t* tbeg;
+  const uint32_t* tend;
+  const uint64_t* tprefix;
+  const int64_t* row_ptr;
+  uint32_t n_packs[2];
+  uint32_t pack_slots[2];
+  uint32_t n_groups[4];
+  int32_t kind[4];  // BatchKind of each item class under the plan's LDS cap
+  uint64_t unit_off;
+};
+
+// One work-group per graph entry: emit its units and their weights (probes
+// plus per-row overheads; the LPT key is the complement of the weight).
+__global__ __launch_bounds__(256) void k_batch_units(const BatchSrc* __restrict__ src, BatchUnit* __restrict__ units,
+                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ idx) {
+  const BatchSrc& s = src[blockIdx.x];
+  const uint32_t np0 = s.n_packs[0], np1 = s.n_packs[1];
+  uint32_t total = np0 + np1;
+  for (int c = 0; c < 4; ++c) total += s.n_groups[c];
+  for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) {
+    BatchUnit u;
+    uint64_t wgt = 0;
+    u.graph = (int32_t)blockIdx.x;
+    if (j < np0 + np1) {
+      const int c = j < np0 ? 0 : 1;
+      const uint32_t p = j < np0 ? j : j - np0;
+      const uint32_t r0 = s.pack_ptr[c][p], r1 = s.pack_ptr[c][p + 1];
+      const int32_t b0 = s.pack_rows[c][r0], b1 = s.pack_rows[c][r1 - 1];
+      wgt = s.tprefix[s.tend[b1]] - s.tprefix[s.tbeg[b0]] + 64ull * (r1 - r0);
+      u.p0 = s.pack_rows[c];
+      u.p1 = s.pack_ptr[c];
+      u.index = p;
+      u.slots = s.pack_slots[c];
+      u.kind = BK_PACK;
+    } else {
+      uint32_t r = j - np0 - np1;
+      int c = 0;
+      while (r >= s.n_groups[c]) r -= s.n_groups[c++];
+      const CountItem* g = s.items[c] + (uint64_t)r * kWaves;
+      for (int w = 0; w < kWaves; ++w) wgt += g[w].len;
+      const int32_t b = g[0].b;
+      wgt += (uint64_t)(s.row_ptr[b + 1] - s.row_ptr[b]);
+      u.p0 = g;
+      u.p1 = nullptr;
+      u.index = r;
+      u.slots = 0;
+      u.kind = s.kind[c];
+    }
+    const uint64_t o = s.unit_off + j;
+    units[o] = u;
+    key[o] = 0xFFFFFFFFu - (uint32_t)(wgt < 0xFFFFFFFFull ? wgt : 0xFFFFFFFFull);
+    idx[o] = (uint32_t)o;
+  }
+}
+
+__global__ void k_gather_units(const BatchUnit* __restrict__ in, const uint32_t* __restrict__ order, int64_t n,
+                               BatchUnit* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[order[i]];
+}
+
+}  // namespace
+
+struct BatchPlan {
+  int device = 0;
+  int64_t n_graphs = 0, n_units = 0, hbm_units = 0;
+  int bpc = 0;  // resident work-groups per compute unit the grid was sized for
+  unsigned grid = 0;
+  size_t lds = 0;
+  int cus = 0;
+  Tuning tun;
+  Owned own;
+  CountArgs* d_args = nullptr;
+  BatchUnit* d_units = nullptr;
+  unsigned int* d_queue = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t* exec_counts = nullptr;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    exec_counts = nullptr;
+  }
+  ~BatchPlan() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tuning_json, hipStream_t st) {
+  std::unique_ptr<BatchPlan> P(new BatchPlan());
+  P->tun = parse_tuning(tuning_json);
+  TC_HIP(hipGetDevice(&P->device));
+  TC_HIP(hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device));
+  P->n_graphs = num;
+  const Tuning& t = P->tun;
+
+  std::vector<CountArgs> args((size_t)std::max(num, 1));
+  std::vector<BatchSrc> srcs((size_t)std::max(num, 1));
+  size_t lds = 0;
+  uint64_t off = 0;
+  int64_t hbm_units = 0;
+  for (int32_t i = 0; i < num; ++i) {
+    TC_REQUIRE(graphs[i] != nullptr, TC_EINVAL, "tc_batch_create: null graph handle");
+    const Graph& g = *G(graphs[i]);
+    TC_REQUIRE(g.device == P->device, TC_EINVAL, "tc_batch_create: graph built on another device");
+    const WorkSet& w = g.w;
+    CountArgs& A = args[(size_t)i];
+    std::memset(&A, 0, sizeof(A));
+    A.row_ptr = g.row_ptr;
+    A.hcol = g.col;
+    A.col = g.col;
+    A.tstart = w.tstart;
+    A.tprefix = w.tprefix;
+    A.tbeg = w.tbeg;
+    A.tend = w.tend;
+    A.T = w.n_tasks;
+    A.m = (uint32_t)g.m;
+    A.q = 1;
+    BatchSrc& s = srcs[(size_t)i];
+    std::memset(&s, 0, sizeof(s));
+    s.tbeg = w.tbeg;
+    s.tend = w.tend;
+    s.tprefix = w.tprefix;
+    s.row_ptr = g.row_ptr;
+    s.unit_off = off;
+    if (w.n_tasks == 0) continue;  // no units: the count stays 0
+    for (int c = 0; c < 2; ++c) {
+      s.pack_rows[c] = w.pack_rows[c];
+      s.pack_ptr[c] = w.pack_ptr[c];
+      s.n_packs[c] = (uint32_t)w.n_packs[c];
+      if (w.n_packs[c] == 0) continue;
+      s.pack_slots[c] = kPackSlots + (1u << w.pack_log2S[c]);
+      lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], false));
+      off += (uint64_t)w.n_packs[c];
+    }
+    for (int c = 0; c < 4; ++c) {
+      const int cls = CLS_WG_SMALL + c;
+      s.items[c] = w.items[cls];
+      s.n_groups[c] = (uint32_t)(w.n_items[cls] / kWaves);
+      if (s.n_groups[c] == 0) continue;
+      const bool hbm = cls == CLS_GLOBAL || w.cls_log2S[cls] > t.lds_cap_log2;
+      s.kind[c] = hbm ? BK_ITEMS_HBM : BK_ITEMS;
+      lds = std::max(lds, items_lds_bytes(hbm ? -1 : w.cls_log2S[cls], false));
+      if (hbm) hbm_units += s.n_groups[c];
+      off += s.n_groups[c];
+    }
+  }
+  TC_REQUIRE(off < 0xFFFFFFF0ull, TC_EOVERFLOW, "tc_batch_create: more than 2^32 work units");
+  P->n_units = (int64_t)off;
+  P->hbm_units = hbm_units;
+  P->lds = std::max(lds, items_lds_bytes(-1, false));
+  int bpc = t.blocks_per_cu;
+  if (bpc == 0) bpc = (int)std::max<size_t>(1, std::min<size_t>(kMaxBlocksPerCU, kLdsPerCU / P->lds));
+  P->bpc = bpc;
+  P->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(P->n_units, (int64_t)bpc * P->cus));
+  batch_kernel_lds(P->lds);
+
+  P->d_args = P->own.alloc<CountArgs>(std::max(num, 1));
+  P->d_units = P->own.alloc<BatchUnit>(std::max<int64_t>(P->n_units, 1));
+  P->d_queue = P->own.alloc<unsigned int>(1);
+  TC_HIP(hipMemcpyAsync(P->d_args, args.data(), sizeof(CountArgs) * (size_t)num, hipMemcpyHostToDevice, st));
+  if (P->n_units > 0) {
+    TempStream temps(st);
+    DevBuf dsrc(sizeof(BatchSrc) * (size_t)num);
+    TC_HIP(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(BatchSrc) * (size_t)num, hipMemcpyHostToDevice, st));
+    const int64_t n = P->n_units;
+    DevBuf raw(sizeof(BatchUnit) * (size_t)n);
+    DevBuf key(sizeof(uint32_t) * (size_t)n), key2(sizeof(uint32_t) * (size_t)n);
+    DevBuf idx(sizeof(uint32_t) * (size_t)n), idx2(sizeof(uint32_t) * (size_t)n);
+    TC_LAUNCH("batch_units", k_batch_units, dim3((unsigned)num), dim3(256), 0, st, dsrc.as<BatchSrc>(),
+              raw.as<BatchUnit>(), key.as<uint32_t>(), idx.as<uint32_t>());
+    TC_HIP(hipGetLastError());
+    const uint32_t* order = idx.as<uint32_t>();
+    if (t.lpt) {
+      bool alt = radix_sort<uint32_t, uint32_t>(key.as<uint32_t>(), key2.as<uint32_t>(), idx.as<uint32_t>(),
+                                                idx2.as<uint32_t>(), n, 0, 32, st, "batch_lpt");
+      order = alt ? idx2.as<uint32_t>() : idx.as<uint32_t>();
+    }
+    TC_LAUNCH("batch_gather", k_gather_units, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st,
+              raw.as<BatchUnit>(), order, n, P->d_units);
+    TC_HIP(hipGetLastError());
+  }
+  TC_HIP(hipStreamSynchronize(st));
+  TC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  return P.release();
+}
+
+void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TC_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    // the caller is capturing: record the two launches into its graph
+    launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st, false);
+    return;
+  }
+  if (!P.tun.graph) {
+    launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st, true);
+    return;
+  }
+  if (!P.exec || P.exec_counts != d_counts) {
+    P.drop_graph();
+    TC_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds,
+                   P.cap_stream, false);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(P.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    TC_HIP(hipStreamEndCapture(P.cap_stream, &P.graph));
+    TC_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    P.exec_counts = d_counts;
+  }
+  LaunchScope ls("batch:graph", st);
+  TC_HIP(hipGraphLaunch(P.exec, st));
+}
+
+std::string plan_json(const BatchPlan& P, double ms) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf),
+                "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\", \"graph\": %d, "
+                "\"units\": %lld, \"hbm_units\": %lld, \"grid\": %u, \"lds_bytes\": %zu, \"ms\": %.4f}",
+                P.bpc, P.tun.lds_cap_log2, P.tun.lpt ? "lpt" : "input", P.tun.graph ? 1 : 0,
+                (long long)P.n_units, (long long)P.hbm_units, P.grid, P.lds, ms);
+  return buf;
+}
+
+template <class F>
+tc_status guard(const char* where, F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return TC_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error(std::string(where) + ": host allocation failed");
+    return TC_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return TC_EDEVICE;
+  }
+}
+
+void copy_out(const std::string& s, char* out, size_t cap) {
+  TC_REQUIRE(out != nullptr && cap > s.size(), TC_EINVAL, "output buffer too small for the JSON text");
+  std::memcpy(out, s.c_str(), s.size() + 1);
+}
+
+}  // namespace
+
+}  // namespace tc
+
+struct tc_batch {
+  tc::BatchPlan* p;
+};
+
+extern "C" {
+
+tc_status tc_batch_create(const tc_graph* const* graphs, int32_t num_graphs, const char* tuning_json,
+                          void* stream, tc_batch** out) {
+  return tc::guard("tc_batch_create", [&] {
+    TC_REQUIRE(out != nullptr, TC_EINVAL, "tc_batch_create: out is NULL");
+    *out = nullptr;
+    TC_REQUIRE(num_graphs >= 0, TC_EINVAL, "tc_batch_create: num_graphs < 0");
+    TC_REQUIRE(num_graphs == 0 || graphs != nullptr, TC_EINVAL, "tc_batch_create: null graph list");
+    std::unique_ptr<tc::BatchPlan> p(tc::make_plan(graphs, num_graphs, tuning_json,
+                                                   static_cast<hipStream_t>(stream)));
+    *out = new tc_batch{p.release()};
+  });
+}
+
+tc_status tc_batch_count(tc_batch* plan, int64_t* d_counts, void* stream) {
+  return tc::guard("tc_batch_count", [&] {
+    TC_REQUIRE(plan != nullptr && plan->p != nullptr, TC_EINVAL, "tc_batch_count: null plan");
+    TC_REQUIRE(d_counts != nullptr || plan->p->n_graphs == 0, TC_EINVAL, "tc_batch_count: null counts");
+    if (plan->p->n_graphs == 0) return;
+    tc::plan_count(*plan->p, d_counts, static_cast<hipStream_t>(stream));
+  });
+}
+
+void tc_batch_free(tc_batch* plan) {
+  if (!plan) return;
+  delete plan->p;
+  delete plan;
+}
+
+tc_status tc_batch_describe(const tc_batch* plan, char* out, size_t cap) {
+  return tc::guard("tc_batch_describe", [&] {
+    TC_REQUIRE(plan != nullptr && plan->p != nullptr, TC_EINVAL, "tc_batch_describe: null plan");
+    tc::copy_out(tc::plan_json(*plan->p, 0.0), out, cap);
+  });
+}
+
+tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
+                           const char* tuning_json, void* stream) {
+  tc_batch* plan = nullptr;
+  tc_status s = tc_batch_create(graphs, num_graphs, tuning_json, stream, &plan);
+  if (s != TC_OK) return s;
+  s = tc_batch_count(plan, d_counts, stream);
+  if (s == TC_OK) {
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+      tc::set_last_error(std::string("tc_count_batched: ") + hipGetErrorString(e));
+      s = TC_EDEVICE;
+    }
+  }
+  tc_batch_free(plan);
+  return s;
+}
+
+tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, void* stream, char* out_json,
+                            size_t cap) {
+  return tc::guard("tc_batch_autotune", [&] {
+    TC_REQUIRE(num_graphs > 0 && graphs != nullptr, TC_EINVAL, "tc_batch_autotune: no graphs");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // candidate schedules: LDS caps that change the plan, then grid sizes and orders
+    int max_log2 = 0;
+    for (int32_t i = 0; i < num_graphs; ++i) {
+      TC_REQUIRE(graphs[i] != nullptr, TC_EINVAL, "tc_batch_autotune: null graph handle");
+      const tc::WorkSet& w = tc::G(graphs[i])->w;
+      for (int c = tc::CLS_WG_SMALL; c <= tc::CLS_WG_HUGE; ++c)
+        if (w.n_items[c]) max_log2 = std::max(max_log2, w.cls_log2S[c]);
+    }
+    std::vector<int> caps = {tc::kMaxLog2S};
+    for (int c : {12, 10})
+      if (c < max_log2) caps.push_back(c);
+    const int bpcs[] = {2, 4, 6, 8};
+    int64_t* d_counts = nullptr;
+    TC_HIP(hipMalloc(&d_counts, sizeof(int64_t) * (size_t)num_graphs));
+    std::unique_ptr<int64_t, void (*)(int64_t*)> hold(d_counts, [](int64_t* p) { (void)hipFree(p); });
+    hipEvent_t e0, e1;
+    TC_HIP(hipEventCreate(&e0));
+    TC_HIP(hipEventCreate(&e1));
+    std::string best, all = "[";
+    double best_ms = 1e30;
+    for (int cap_log2 : caps) {
+      for (int lpt = 1; lpt >= 0; --lpt) {
+        for (int bpc : bpcs) {
+          char js[160];
+          std::snprintf(js, sizeof(js), "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\"}", bpc,
+                        cap_log2, lpt ? "lpt" : "input");
+          std::unique_ptr<tc::BatchPlan> P(tc::make_plan(graphs, num_graphs, js, st));
+          tc::plan_count(*P, d_counts, st);  // warm-up (and graph capture)
+          double ms = 1e30;
+          for (int r = 0; r < 3; ++r) {
+            TC_HIP(hipEventRecord(e0, st));
+            tc::plan_count(*P, d_counts, st);
+            TC_HIP(hipEventRecord(e1, st));
+            TC_HIP(hipEventSynchronize(e1));
+            float f = 0;
+            TC_HIP(hipEventElapsedTime(&f, e0, e1));
+            ms = std::min(ms, (double)f);
+          }
+          std::string j = tc::plan_json(*P, ms);
+          all += (all.size() > 1 ? ", " : "") + j;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = j;
+          }
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    all += "]";
+    // the best schedule's keys first, then every candidate
+    std::string res = "{\"best\": " + best + ", \"candidates\": " + all + "}";
+    tc::copy_out(res, out_json, cap);
+  });
+}
+
+}  // extern "C"

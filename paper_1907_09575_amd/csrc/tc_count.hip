@@ -48,21 +48,7 @@ namespace tc {
 
 namespace {
 
-struct Args {
-  const int64_t* __restrict__ row_ptr;  // hash side: rows b
-  const int32_t* __restrict__ hcol;     // hash side: sorted entries of each row b
-  const int32_t* __restrict__ col;      // probe side (the tasks' probes; U itself for a graph)
-  const uint32_t* __restrict__ tstart;
-  const uint64_t* __restrict__ tprefix;
-  const uint32_t* __restrict__ tbeg;
-  const uint32_t* __restrict__ tend;
-  int64_t T;
-  uint32_t m;  // entries of col
-  unsigned long long* count;
-  int32_t* support;
-  unsigned long long* per_shift;  // MODE_BLOCK: q counters
-  int32_t q, xy;                  // MODE_BLOCK: grid size, (x + y) % q
-};
+using Args = CountArgs;
 
 constexpr int kU = 8;                   // 64-probe batches per super-batch
 constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bits)
@@ -390,11 +376,9 @@ __device__ __forceinline__ void block_init() {
 constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
 
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
-void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
-                   uint32_t pack_slots) {
-  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
+__device__ __forceinline__ void pack_body(const Args& A, const int32_t* __restrict__ rows,
+                                          const uint32_t* __restrict__ pack_ptr, uint32_t pack,
+                                          uint32_t pack_slots, int32_t* smem) {
   __shared__ int s_D;
   __shared__ uint32_t s_w[4], s_w2[4];
   __shared__ uint32_t s_tend;
@@ -409,7 +393,7 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
   if (lane < kBmWords) bm[lane] = 0;
   block_init<MODE>();
 
-  const uint32_t r0 = pack_ptr[blockIdx.x], r1 = pack_ptr[blockIdx.x + 1];
+  const uint32_t r0 = pack_ptr[pack], r1 = pack_ptr[pack + 1];
   const int nr = (int)(r1 - r0);  // 1 .. kPackRows
   uint32_t d = 0, S = 0, rs = 0;
   if (tid < nr) {
@@ -494,16 +478,21 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
   block_flush<MODE>(hits, A);
 }
 
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
+void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
+                   uint32_t pack_slots) {
+  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
+  pack_body<MODE>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
+}
+
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
 template <int MODE, bool GLOBAL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 8 : 4))) void k_count_items(Args A, const CountItem* __restrict__ items) {
-  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
+__device__ __forceinline__ void items_body(const Args& A, const CountItem* __restrict__ grp, int32_t* smem) {
   __shared__ int s_D;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
-  const CountItem* grp = items + (int64_t)blockIdx.x * kWaves;
   const int32_t b = grp[0].b;
   const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
   if (lane < kBmWords) bm[lane] = 0;
@@ -535,6 +524,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   block_flush<MODE>(hits, A);
 }
 
+template <int MODE, bool GLOBAL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 8 : 4)))
+void k_count_items(Args A, const CountItem* __restrict__ items) {
+  extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
+  items_body<MODE, GLOBAL>(A, items + (int64_t)blockIdx.x * kWaves, reinterpret_cast<int32_t*>(smem4));
+}
+
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
@@ -556,13 +552,12 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
 template <int MODE>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
-  const size_t mark_bytes = sizeof(int32_t) * kMarkInts;
+  const size_t mark_bytes = items_lds_bytes(-1, VALS);
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
     if (w.n_packs[c] == 0) continue;
     // a pack's tables take at most kPackSlots plus one row's table
     const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
-    const size_t lds = sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 +
-                                          (size_t)slots * (VALS ? 2 : 1));
+    const size_t lds = pack_lds_bytes(slots, VALS);
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -576,7 +571,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
       TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes,
                 st, A, w.items[c]);
     } else {
-      const size_t lds = mark_bytes + sizeof(int32_t) * ((size_t)1 << w.cls_log2S[c]) * (VALS ? 2 : 1);
+      const size_t lds = items_lds_bytes(w.cls_log2S[c], VALS);
       if (lds > 65536)
         TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -592,7 +587,72 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// Batched count: clears the per-graph counters and the unit queue (a kernel,
+// not a memset, so that the pair can be captured in a HIP graph).
+__global__ void k_batch_clear(unsigned long long* counts, int64_t n, unsigned int* queue) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = 0;
+  if (i == 0) *queue = 0;
+}
+
+// Persistent work-groups pull units from one queue until it is empty (every
+// work-group reaches the exit once the counter passes n_units); the units
+// were ordered when the plan was made (largest first by default). Each unit
+// runs the same body as its class's own kernel with its graph's arguments.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__ units, uint32_t n_units,
+                   unsigned int* __restrict__ queue, unsigned long long* __restrict__ counts) {
+  extern __shared__ int4 smem4[];
+  int32_t* smem = reinterpret_cast<int32_t*>(smem4);
+  __shared__ uint32_t s_unit;
+  for (;;) {
+    __syncthreads();  // the previous unit is done with LDS and s_unit
+    if (threadIdx.x == 0) s_unit = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t u = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: unit loads go scalar
+    if (u >= n_units) break;
+    const BatchUnit bu = units[u];
+    Args A = gargs[bu.graph];
+    A.count = counts + bu.graph;
+    if (bu.kind == BK_PACK) {
+      pack_body<MODE_COUNT>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+    } else if (bu.kind == BK_ITEMS) {
+      items_body<MODE_COUNT, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+    } else {
+      items_body<MODE_COUNT, true>(A, static_cast<const CountItem*>(bu.p0), smem);
+    }
+  }
+}
+
 }  // namespace
+
+size_t pack_lds_bytes(uint32_t slots, bool vals) {
+  return sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 + (size_t)slots * (vals ? 2 : 1));
+}
+
+size_t items_lds_bytes(int log2S, bool vals) {
+  return sizeof(int32_t) * ((size_t)kMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * (vals ? 2 : 1)));
+}
+
+void launch_batch(const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units, int64_t n_out,
+                  unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds, hipStream_t st,
+                  bool timed) {
+  auto* counts = reinterpret_cast<unsigned long long*>(d_counts);
+  const unsigned cg = (unsigned)std::max<int64_t>(1, div_up(n_out, 256));
+  if (timed) {
+    TC_LAUNCH("batch_clear", k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
+    if (n_units > 0)
+      TC_LAUNCH("count:batch", k_count_batch, dim3(grid), dim3(256), lds, st, d_args, d_units,
+                (uint32_t)n_units, d_queue, counts);
+  } else {
+    // inside a stream capture: no timer events
+    hipLaunchKernelGGL(k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
+    if (n_units > 0)
+      hipLaunchKernelGGL(k_count_batch, dim3(grid), dim3(256), lds, st, d_args, d_units, (uint32_t)n_units,
+                         d_queue, counts);
+  }
+  TC_HIP(hipGetLastError());
+}
 
 void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t* d_support,
                   int64_t* d_per_shift, hipStream_t st) {
@@ -616,6 +676,12 @@ void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t*
     case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED>(w, A, st); break;
     case MODE_BLOCK: launch_mode<MODE_BLOCK>(w, A, st); break;
   }
+}
+
+void batch_kernel_lds(size_t lds) {
+  if (lds > 65536)
+    TC_HIP(hipFuncSetAttribute((const void*)k_count_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
 }
 
 }  // namespace tc

@@ -195,6 +195,53 @@ struct CountView {
 void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t* d_support,
                   int64_t* d_per_shift, hipStream_t stream);
 
+// Kernel arguments of the count kernels (one hashed side, one probe side and
+// the task arrays of a work set).
+struct CountArgs {
+  const int64_t* __restrict__ row_ptr;  // hash side: rows b
+  const int32_t* __restrict__ hcol;     // hash side: sorted entries of each row b
+  const int32_t* __restrict__ col;      // probe side (the tasks' probes; U itself for a graph)
+  const uint32_t* __restrict__ tstart;
+  const uint64_t* __restrict__ tprefix;
+  const uint32_t* __restrict__ tbeg;
+  const uint32_t* __restrict__ tend;
+  int64_t T;
+  uint32_t m;  // entries of col
+  unsigned long long* count;
+  int32_t* support;
+  unsigned long long* per_shift;  // MODE_BLOCK: q counters
+  int32_t q, xy;                  // MODE_BLOCK: grid size, (x + y) % q
+};
+
+// ---- batched persistent count (tc_count.hip kernel, tc_batch.cpp plan) -------
+// One unit of the persistent launch: a pack of light rows, a work-group of
+// kWaves items sharing an LDS table, or such a group whose row is looked up
+// in HBM.
+enum BatchKind : int32_t { BK_PACK = 0, BK_ITEMS = 1, BK_ITEMS_HBM = 2 };
+
+struct alignas(16) BatchUnit {
+  const void* p0;      // pack: rows of the class; items: the group's first item
+  const uint32_t* p1;  // pack: pack_ptr of the class
+  uint32_t index;      // pack: pack number
+  uint32_t slots;      // pack: table slots reserved for the pack
+  int32_t graph;       // entry of the plan's graph list (and of the output)
+  int32_t kind;        // BatchKind
+};
+static_assert(sizeof(BatchUnit) == 32, "BatchUnit layout");
+
+// Launch the persistent count over n_units units (queue: device counter,
+// counts: int64 per graph entry; both cleared by the same call's first kernel).
+void launch_batch(const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units, int64_t n_out,
+                  unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds, hipStream_t st,
+                  bool timed);
+// Allow the persistent kernel `lds` bytes of dynamic LDS (call outside any capture).
+void batch_kernel_lds(size_t lds);
+// Dynamic LDS bytes of a pack work-group with `slots` table slots, and of an
+// item work-group with a 2^log2S-slot table (log2S < 0: no table, HBM lookups);
+// vals: tables also hold U positions (full support).
+size_t pack_lds_bytes(uint32_t slots, bool vals);
+size_t items_lds_bytes(int log2S, bool vals);
+
 inline CountView graph_view(const Graph& g) {
   return CountView{g.row_ptr, g.col, g.col, g.m, &g.w, 1, 0};
 }

@@ -1,0 +1,175 @@
+"""GPU parity of the batched persistent count (tc_batch_* / tc_count_batched).
+
+Every per-graph count of a batch must be the same integer as the oracle's (and
+therefore as tc_count's) under every schedule: LDS caps that move heavy rows
+to HBM lookups, both unit orders, any grid size, plain launches, the plan's own
+HIP graph and a graph captured by the caller.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import smallgraphs as sg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1907_09575_amd as tc
+    torch.cuda.set_device(0)
+    return tc
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda")
+
+
+def build_graphs(tc, edge_lists):
+    """(graphs, oracle counts) for a list of (src, dst, n)."""
+    graphs, want = [], []
+    for s, d, n in edge_lists:
+        graphs.append(tc.tc_preprocess(dev(s), dev(d), n))
+        want.append(oracle.count(oracle.preprocess(s, d, n)))
+    torch.cuda.synchronize()
+    return graphs, np.array(want, np.int64)
+
+
+def batch_counts(tc, graphs, tuning=None):
+    plan = tc.tc_batch_create(graphs, tuning=tuning)
+    out = torch.full((len(graphs),), -1, dtype=torch.int64, device="cuda")
+    tc.tc_batch_count(plan, out)
+    torch.cuda.synchronize()
+    desc = tc.tc_batch_describe(plan)
+    res = out.cpu().numpy()
+    # a second call on the same plan (replays its HIP graph) gives the same counts
+    out2 = torch.full((len(graphs),), -1, dtype=torch.int64, device="cuda")
+    tc.tc_batch_count(plan, out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), res)
+    plan.free()
+    return res, desc
+
+
+@pytest.fixture(scope="module")
+def mixed(tc):
+    # an uneven mix: the batch recipe at smaller sizes, closed forms, an empty
+    # graph and RMAT graphs with heavy rows (item classes, some beyond 4096 slots)
+    specs = graphgen.batch_specs(160, seed=3, nmin=64, nmax=8192)
+    lists = [(*e, sp.n) for sp, e in zip(specs, graphgen.generate_many(specs, 8))]
+    lists += [sg.complete(40), sg.wheel(50), (np.zeros(0, np.int32), np.zeros(0, np.int32), 7)]
+    lists += [(*graphgen.rmat(s, seed=40 + s), 1 << s) for s in (12, 14, 16)]
+    print("mixed batch: %d graphs" % len(lists), flush=True)
+    return build_graphs(tc, lists)
+
+
+def test_batch_default_schedule(tc, mixed):
+    graphs, want = mixed
+    got, desc = batch_counts(tc, graphs)
+    assert np.array_equal(got, want)
+    assert desc["units"] > 0 and desc["grid"] > 0
+
+
+@pytest.mark.parametrize("tuning", [
+    {"order": "input"},
+    {"order": "lpt", "blocks_per_cu": 1},
+    {"blocks_per_cu": 8, "lds_cap_log2": 12},
+    {"lds_cap_log2": 10, "order": "input"},
+    {"lds_cap_log2": 6},          # every item group looks its row up in HBM
+    {"graph": 0},                 # plain launches instead of the plan's HIP graph
+])
+def test_batch_schedules(tc, mixed, tuning):
+    graphs, want = mixed
+    got, desc = batch_counts(tc, graphs, tuning)
+    assert np.array_equal(got, want), tuning
+    if tuning.get("lds_cap_log2") == 6:
+        assert desc["hbm_units"] > 0
+
+
+def test_batch_repeated_handles_and_single(tc, mixed):
+    graphs, want = mixed
+    idx = [5, 5, 0, len(graphs) - 1, 5, 3]
+    got, _ = batch_counts(tc, [graphs[i] for i in idx])
+    assert np.array_equal(got, want[idx])
+    got, _ = batch_counts(tc, [graphs[-1]])
+    assert got[0] == want[-1]
+
+
+def test_count_batched_one_shot(tc, mixed):
+    graphs, want = mixed
+    out = tc.tc_count_batched(graphs, tuning={"order": "lpt"})
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_batch_captured_by_caller(tc, mixed):
+    # the caller captures tc_batch_count into its own graph; every replay,
+    # with eager work and synchronisations between them, gives the counts
+    graphs, want = mixed
+    plan = tc.tc_batch_create(graphs)
+    out = torch.full((len(graphs),), -1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tc.tc_batch_count(plan, out, stream=s)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        tc.tc_batch_count(plan, out, stream=torch.cuda.current_stream())
+    for r in range(4):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), "replay %d" % r
+        # eager work between replays
+        assert int(tc.tc_count(graphs[-1]).item()) == want[-1]
+    plan.free()
+
+
+def test_batch_autotune_roundtrip(tc, mixed):
+    graphs, want = mixed
+    res = tc.tc_batch_autotune(graphs)
+    best = res["best"]
+    assert len(res["candidates"]) >= 8
+    assert all(c["ms"] > 0 for c in res["candidates"])
+    got, desc = batch_counts(tc, graphs, best)
+    assert np.array_equal(got, want)
+    assert desc["lds_cap_log2"] == best["lds_cap_log2"] and desc["order"] == best["order"]
+
+
+def test_batch_invalid_tuning(tc, mixed):
+    graphs, _ = mixed
+    for bad in ['{"blocks_per_cu": 4, "nope": 1}', '{"order": "fifo"}', '{"lds_cap_log2": 3}',
+                '{"blocks_per_cu": x}', 'not json', '{"graph": 1,}']:
+        with pytest.raises(tc.TCError) as e:
+            tc.tc_batch_create(graphs[:3], tuning=bad)
+        assert e.value.status == 1, bad
+
+
+def test_batch_full_config(tc):
+    # the full batch: 4096 graphs, n log-uniform in [64, 65536], half ER (avg
+    # degree 8-64) and half RMAT (edge factor 8-32); every count equals the
+    # plain per-graph tc_count, and sampled graphs equal the oracle
+    specs = graphgen.batch_specs(4096)
+    print("generating 4096 graphs", flush=True)
+    lists = graphgen.generate_many(specs, 16)
+    graphs = []
+    for sp, (s, d) in zip(specs, lists):
+        graphs.append(tc.tc_preprocess(dev(s), dev(d), sp.n))
+    torch.cuda.synchronize()
+    print("preprocessed", flush=True)
+    plain = torch.empty(len(graphs), dtype=torch.int64, device="cuda")
+    for i, g in enumerate(graphs):
+        tc.tc_count(g, plain[i:i + 1])
+    got, desc = batch_counts(tc, graphs)
+    assert np.array_equal(got, plain.cpu().numpy())
+    print("batched == plain over %d graphs, %d units" % (len(graphs), desc["units"]), flush=True)
+    order = np.argsort([sp.m for sp in specs])
+    for i in list(order[:: len(order) // 12]) + [int(order[-1])]:
+        s, d = lists[i]
+        assert got[i] == oracle.count(oracle.preprocess(s, d, specs[i].n)), i
