@@ -26,6 +26,7 @@
 #ifndef TC_H
 #define TC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -189,6 +190,70 @@ tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, in
  */
 tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, void* stream,
                             char* out_json, size_t cap);
+
+/* ---- served form: a request loop with continuous batching ------------------- */
+
+/*
+ * A server owns a scheduler thread and a pool of preprocessing threads on the
+ * device current at tc_server_create. Requests (count or support of one
+ * graph, given as a host edge list) are admitted in arrival order while the
+ * in-flight requests stay within `max_slots` and their estimated device
+ * footprint (edge list, preprocessing temporaries, the graph, the support
+ * array) fits `hbm_budget_bytes` together with the cached graphs; cached
+ * graphs no request uses are evicted least recently used first when room is
+ * needed. Admitted requests are preprocessed concurrently on the pool's
+ * streams; on every scheduler tick all requests whose graph is ready run in
+ * one persistent launch per operation (tc_batch's kernel and work units), so
+ * requests that arrive while a tick runs are preprocessed meanwhile and join
+ * the next tick. Results are the same integers as tc_count/tc_edge_support.
+ * A request with a non-zero graph_key keeps its graph cached on the device:
+ * later requests with that key skip preprocessing (their edge list may be
+ * NULL while the key is resident).
+ */
+typedef struct tc_server tc_server;
+
+enum { TC_REQ_COUNT = 0, TC_REQ_SUPPORT_FULL = 1, TC_REQ_SUPPORT_ORIENTED = 2 };
+
+typedef struct {
+  int32_t op;           /* TC_REQ_* */
+  int32_t n;            /* vertices (ids in [0, n)) */
+  int64_t m_raw;        /* pairs in src/dst (support ops: also the capacity of support_out) */
+  const int32_t* src;   /* host arrays, kept alive by the caller until the request is done */
+  const int32_t* dst;
+  uint64_t graph_key;   /* 0: not cached; else the caller's name for this graph */
+  int32_t* support_out; /* support ops: host int32[m_raw]; receives the first m entries (U order) */
+} tc_request;
+
+typedef struct {
+  tc_status status;     /* TC_OK, or the request's failure (TC_ECANCELED if cancelled) */
+  int32_t cache_hit;    /* 1 if the graph was resident (no preprocessing) */
+  int64_t count;        /* triangles */
+  int64_t m;            /* edges of the simple graph (entries written to support_out) */
+  double t_submit;      /* seconds on the server's clock: submitted, admitted, */
+  double t_admit;       /*   graph ready, result visible to the host */
+  double t_ready;
+  double t_done;
+} tc_result;
+
+/* options_json (nullable), flat object: "prep_threads" (default 4),
+ * "lds_cap_log2" and "blocks_per_cu" (the batch schedule of every tick). */
+tc_status tc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const char* options_json,
+                           tc_server** out);
+/* Queue a request; *ticket identifies it. TC_EINVAL for a malformed request. */
+tc_status tc_server_submit(tc_server* s, const tc_request* req, int64_t* ticket);
+/* Result of a ticket: TC_OK and *out filled (the ticket is consumed) once it is
+ * done; TC_EBUSY if not done yet and wait == 0 (wait != 0 blocks until done);
+ * TC_EINVAL for an unknown ticket. */
+tc_status tc_server_poll(tc_server* s, int64_t ticket, int32_t wait, tc_result* out);
+/* Cancel a request not yet admitted (its result: TC_ECANCELED); TC_EBUSY if it
+ * is already admitted. */
+tc_status tc_server_cancel(tc_server* s, int64_t ticket);
+/* Counters (requests, ticks, cache hits, evictions, peak reserved bytes, ...)
+ * as JSON into the host buffer out[cap]. */
+tc_status tc_server_stats(tc_server* s, char* out, size_t cap);
+/* Stop the threads (pending requests are cancelled, admitted ones finish) and
+ * free every device allocation of the server. */
+void tc_server_destroy(tc_server* s);
 
 /* ---- work classes and phase timers (profiling) ------------------------------ */
 

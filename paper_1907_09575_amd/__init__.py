@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
-    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
+    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "Server", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
@@ -312,6 +312,114 @@ def tc_count_batched(graphs, counts: torch.Tensor | None = None, tuning=None, st
                                  _dev_ptr(counts, torch.int64, "counts", len(graphs)), _tuning(tuning),
                                  _stream(stream)), "tc_count_batched")
     return counts
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("n", ctypes.c_int32), ("m_raw", ctypes.c_int64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("graph_key", ctypes.c_uint64),
+                ("support_out", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cache_hit", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_ready", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+TC_REQ_COUNT, TC_REQ_SUPPORT_FULL, TC_REQ_SUPPORT_ORIENTED = 0, 1, 2
+_OPS = {"count": TC_REQ_COUNT, "support": TC_REQ_SUPPORT_FULL, "support_full": TC_REQ_SUPPORT_FULL,
+        "support_oriented": TC_REQ_SUPPORT_ORIENTED}
+
+_sig("tc_server_create", [_I64, _I32, ctypes.c_char_p, ctypes.POINTER(_P)])
+_sig("tc_server_submit", [_P, ctypes.POINTER(_Request), ctypes.POINTER(_I64)])
+_sig("tc_server_poll", [_P, _I64, _I32, ctypes.POINTER(_Result)])
+_sig("tc_server_cancel", [_P, _I64])
+_sig("tc_server_stats", [_P, ctypes.c_char_p, ctypes.c_size_t])
+_sig("tc_server_destroy", [_P], None)
+
+
+class Server:
+    """The served form (tc_server_*): submit count/support requests of host
+    edge lists; results come back by ticket. Host arrays are kept alive here
+    until their request is polled."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, options=None):
+        import json
+        out = ctypes.c_void_p()
+        opts = None if options is None else json.dumps(options).encode()
+        _check(_lib.tc_server_create(int(budget_bytes), int(max_slots), opts, ctypes.byref(out)),
+               "tc_server_create")
+        self._h = out
+        self._keep = {}
+
+    def submit(self, op, src, dst, n: int, key: int = 0, support_out=None) -> int:
+        import numpy as np
+        opc = _OPS[op] if isinstance(op, str) else int(op)
+        src = None if src is None else np.ascontiguousarray(src, dtype=np.int32)
+        dst = None if dst is None else np.ascontiguousarray(dst, dtype=np.int32)
+        m_raw = 0 if src is None else len(src)
+        if opc != TC_REQ_COUNT and support_out is None:
+            support_out = np.empty(max(m_raw, 1), dtype=np.int32)
+        if support_out is not None:
+            assert support_out.dtype == np.int32 and support_out.flags.c_contiguous
+            if src is None:
+                m_raw = len(support_out)
+        req = _Request(opc, int(n), int(m_raw), None if src is None else src.ctypes.data,
+                       None if dst is None else dst.ctypes.data, int(key),
+                       None if support_out is None else support_out.ctypes.data)
+        t = ctypes.c_int64()
+        _check(_lib.tc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "tc_server_submit")
+        self._keep[t.value] = (src, dst, support_out)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """dict of the result, or None if not done (wait=False). A failed
+        request gives status != 0 and the library's message in "error"."""
+        r = _Result()
+        st = _lib.tc_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(r))
+        if st == TC_EBUSY:
+            return None
+        _check(st, "tc_server_poll")
+        src, dst, sup = self._keep.pop(int(ticket), (None, None, None))
+        out = {"status": r.status, "cache_hit": bool(r.cache_hit), "count": r.count, "m": r.m,
+               "t_submit": r.t_submit, "t_admit": r.t_admit, "t_ready": r.t_ready, "t_done": r.t_done}
+        if r.status != TC_OK:
+            out["error"] = _lib.tc_last_error().decode(errors="replace")
+        if sup is not None and r.status == TC_OK:
+            out["support"] = sup[:r.m]
+        return out
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was cancelled (or had already finished)."""
+        st = _lib.tc_server_cancel(self._h, int(ticket))
+        if st == TC_EBUSY:
+            return False
+        _check(st, "tc_server_cancel")
+        return True
+
+    def stats(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(2048)
+        _check(_lib.tc_server_stats(self._h, buf, len(buf)), "tc_server_stats")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            _lib.tc_server_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tc_graph_free(g: Graph):

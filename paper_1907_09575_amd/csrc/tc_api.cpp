@@ -14,8 +14,6 @@ static thread_local std::string g_last_error;
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
-void destroy_graph(Graph* g);
-
 }  // namespace tc
 
 #define TC_API_GUARD(body)                                   \

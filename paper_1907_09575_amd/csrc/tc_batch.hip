@@ -195,6 +195,8 @@ __global__ void k_gather_units(const BatchUnit* __restrict__ in, const uint32_t*
 
 struct BatchPlan {
   int device = 0;
+  CountMode mode = MODE_COUNT;
+  std::vector<std::pair<int32_t*, int64_t>> support;  // arrays cleared before each launch
   int64_t n_graphs = 0, n_units = 0, hbm_units = 0;
   int bpc = 0;  // resident work-groups per compute unit the grid was sized for
   unsigned grid = 0;
@@ -223,24 +225,28 @@ struct BatchPlan {
   }
 };
 
-namespace {
-
-BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tuning_json, hipStream_t st) {
+BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, const char* tuning_json,
+                     hipStream_t st) {
+  TC_REQUIRE(mode == MODE_COUNT || mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED, TC_EINVAL,
+             "batch plan: unsupported mode");
+  TC_REQUIRE(num >= 0 && num < (1ll << 31), TC_EINVAL, "batch plan: bad number of graphs");
   std::unique_ptr<BatchPlan> P(new BatchPlan());
   P->tun = parse_tuning(tuning_json);
+  P->mode = mode;
+  const bool vals = mode == MODE_SUPPORT_FULL;
   TC_HIP(hipGetDevice(&P->device));
   TC_HIP(hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device));
   P->n_graphs = num;
   const Tuning& t = P->tun;
 
-  std::vector<CountArgs> args((size_t)std::max(num, 1));
-  std::vector<BatchSrc> srcs((size_t)std::max(num, 1));
+  std::vector<CountArgs> args((size_t)std::max<int64_t>(num, 1));
+  std::vector<BatchSrc> srcs((size_t)std::max<int64_t>(num, 1));
   size_t lds = 0;
   uint64_t off = 0;
   int64_t hbm_units = 0;
-  for (int32_t i = 0; i < num; ++i) {
-    TC_REQUIRE(graphs[i] != nullptr, TC_EINVAL, "tc_batch_create: null graph handle");
-    const Graph& g = *G(graphs[i]);
+  for (int64_t i = 0; i < num; ++i) {
+    TC_REQUIRE(entries[i].g != nullptr, TC_EINVAL, "batch plan: null graph handle");
+    const Graph& g = *entries[i].g;
     TC_REQUIRE(g.device == P->device, TC_EINVAL, "tc_batch_create: graph built on another device");
     const WorkSet& w = g.w;
     CountArgs& A = args[(size_t)i];
@@ -255,6 +261,11 @@ BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tun
     A.T = w.n_tasks;
     A.m = (uint32_t)g.m;
     A.q = 1;
+    if (mode != MODE_COUNT) {
+      TC_REQUIRE(entries[i].support != nullptr || g.m == 0, TC_EINVAL, "batch plan: null support array");
+      A.support = entries[i].support;
+      if (g.m > 0) P->support.emplace_back(entries[i].support, g.m);
+    }
     BatchSrc& s = srcs[(size_t)i];
     std::memset(&s, 0, sizeof(s));
     s.tbeg = w.tbeg;
@@ -269,7 +280,7 @@ BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tun
       s.n_packs[c] = (uint32_t)w.n_packs[c];
       if (w.n_packs[c] == 0) continue;
       s.pack_slots[c] = kPackSlots + (1u << w.pack_log2S[c]);
-      lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], false));
+      lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], vals));
       off += (uint64_t)w.n_packs[c];
     }
     for (int c = 0; c < 4; ++c) {
@@ -279,7 +290,7 @@ BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tun
       if (s.n_groups[c] == 0) continue;
       const bool hbm = cls == CLS_GLOBAL || w.cls_log2S[cls] > t.lds_cap_log2;
       s.kind[c] = hbm ? BK_ITEMS_HBM : BK_ITEMS;
-      lds = std::max(lds, items_lds_bytes(hbm ? -1 : w.cls_log2S[cls], false));
+      lds = std::max(lds, items_lds_bytes(hbm ? -1 : w.cls_log2S[cls], vals));
       if (hbm) hbm_units += s.n_groups[c];
       off += s.n_groups[c];
     }
@@ -287,14 +298,14 @@ BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tun
   TC_REQUIRE(off < 0xFFFFFFF0ull, TC_EOVERFLOW, "tc_batch_create: more than 2^32 work units");
   P->n_units = (int64_t)off;
   P->hbm_units = hbm_units;
-  P->lds = std::max(lds, items_lds_bytes(-1, false));
+  P->lds = std::max(lds, items_lds_bytes(-1, vals));
   int bpc = t.blocks_per_cu;
   if (bpc == 0) bpc = (int)std::max<size_t>(1, std::min<size_t>(kMaxBlocksPerCU, kLdsPerCU / P->lds));
   P->bpc = bpc;
   P->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(P->n_units, (int64_t)bpc * P->cus));
-  batch_kernel_lds(P->lds);
+  batch_kernel_lds(mode, P->lds);
 
-  P->d_args = P->own.alloc<CountArgs>(std::max(num, 1));
+  P->d_args = P->own.alloc<CountArgs>(std::max<int64_t>(num, 1));
   P->d_units = P->own.alloc<BatchUnit>(std::max<int64_t>(P->n_units, 1));
   P->d_queue = P->own.alloc<unsigned int>(1);
   TC_HIP(hipMemcpyAsync(P->d_args, args.data(), sizeof(CountArgs) * (size_t)num, hipMemcpyHostToDevice, st));
@@ -320,28 +331,41 @@ BatchPlan* make_plan(const tc_graph* const* graphs, int32_t num, const char* tun
     TC_HIP(hipGetLastError());
   }
   TC_HIP(hipStreamSynchronize(st));
-  TC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   return P.release();
 }
+
+namespace {
+
+void plan_launch(BatchPlan& P, int64_t* d_counts, hipStream_t st, bool timed) {
+  for (const auto& z : P.support) zero_i32(z.first, z.second, st, timed);
+  launch_batch(P.mode, P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st,
+               timed);
+}
+
+}  // namespace
+
+void free_plan(BatchPlan* P) { delete P; }
+
+int64_t plan_units(const BatchPlan& P) { return P.n_units; }
 
 void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   TC_HIP(hipStreamIsCapturing(st, &cs));
   if (cs != hipStreamCaptureStatusNone) {
-    // the caller is capturing: record the two launches into its graph
-    launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st, false);
+    // the caller is capturing: record the launches into its graph
+    plan_launch(P, d_counts, st, false);
     return;
   }
   if (!P.tun.graph) {
-    launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st, true);
+    plan_launch(P, d_counts, st, true);
     return;
   }
   if (!P.exec || P.exec_counts != d_counts) {
     P.drop_graph();
+    if (!P.cap_stream) TC_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
     TC_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
     try {
-      launch_batch(P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds,
-                   P.cap_stream, false);
+      plan_launch(P, d_counts, P.cap_stream, false);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(P.cap_stream, &g);
@@ -355,6 +379,8 @@ void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st) {
   LaunchScope ls("batch:graph", st);
   TC_HIP(hipGraphLaunch(P.exec, st));
 }
+
+namespace {
 
 std::string plan_json(const BatchPlan& P, double ms) {
   char buf[512];
@@ -406,7 +432,9 @@ tc_status tc_batch_create(const tc_graph* const* graphs, int32_t num_graphs, con
     *out = nullptr;
     TC_REQUIRE(num_graphs >= 0, TC_EINVAL, "tc_batch_create: num_graphs < 0");
     TC_REQUIRE(num_graphs == 0 || graphs != nullptr, TC_EINVAL, "tc_batch_create: null graph list");
-    std::unique_ptr<tc::BatchPlan> p(tc::make_plan(graphs, num_graphs, tuning_json,
+    std::vector<tc::PlanEntry> e((size_t)num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) e[(size_t)i] = tc::PlanEntry{tc::G(graphs[i]), nullptr};
+    std::unique_ptr<tc::BatchPlan> p(tc::make_plan(e.data(), num_graphs, tc::MODE_COUNT, tuning_json,
                                                    static_cast<hipStream_t>(stream)));
     *out = new tc_batch{p.release()};
   });
@@ -468,6 +496,8 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
     for (int c : {12, 10})
       if (c < max_log2) caps.push_back(c);
     const int bpcs[] = {2, 4, 6, 8};
+    std::vector<tc::PlanEntry> ents((size_t)num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) ents[(size_t)i] = tc::PlanEntry{tc::G(graphs[i]), nullptr};
     int64_t* d_counts = nullptr;
     TC_HIP(hipMalloc(&d_counts, sizeof(int64_t) * (size_t)num_graphs));
     std::unique_ptr<int64_t, void (*)(int64_t*)> hold(d_counts, [](int64_t* p) { (void)hipFree(p); });
@@ -482,7 +512,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
           char js[160];
           std::snprintf(js, sizeof(js), "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\"}", bpc,
                         cap_log2, lpt ? "lpt" : "input");
-          std::unique_ptr<tc::BatchPlan> P(tc::make_plan(graphs, num_graphs, js, st));
+          std::unique_ptr<tc::BatchPlan> P(tc::make_plan(ents.data(), num_graphs, tc::MODE_COUNT, js, st));
           tc::plan_count(*P, d_counts, st);  // warm-up (and graph capture)
           double ms = 1e30;
           for (int r = 0; r < 3; ++r) {

@@ -599,7 +599,8 @@ __global__ void k_batch_clear(unsigned long long* counts, int64_t n, unsigned in
 // work-group reaches the exit once the counter passes n_units); the units
 // were ordered when the plan was made (largest first by default). Each unit
 // runs the same body as its class's own kernel with its graph's arguments.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
 void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__ units, uint32_t n_units,
                    unsigned int* __restrict__ queue, unsigned long long* __restrict__ counts) {
   extern __shared__ int4 smem4[];
@@ -615,13 +616,26 @@ void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__
     Args A = gargs[bu.graph];
     A.count = counts + bu.graph;
     if (bu.kind == BK_PACK) {
-      pack_body<MODE_COUNT>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+      pack_body<MODE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
     } else if (bu.kind == BK_ITEMS) {
-      items_body<MODE_COUNT, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+      items_body<MODE, false>(A, static_cast<const CountItem*>(bu.p0), smem);
     } else {
-      items_body<MODE_COUNT, true>(A, static_cast<const CountItem*>(bu.p0), smem);
+      items_body<MODE, true>(A, static_cast<const CountItem*>(bu.p0), smem);
     }
   }
+}
+
+template <int MODE>
+void launch_batch_mode(const Args* d_args, const BatchUnit* d_units, int64_t n_units, unsigned int* d_queue,
+                       unsigned long long* counts, unsigned grid, size_t lds, hipStream_t st, bool timed) {
+  static const char* const kNames[3] = {"count:batch", "support_full:batch", "support_oriented:batch"};
+  if (n_units == 0) return;
+  if (timed)
+    TC_LAUNCH(kNames[MODE], k_count_batch<MODE>, dim3(grid), dim3(256), lds, st, d_args, d_units,
+              (uint32_t)n_units, d_queue, counts);
+  else
+    hipLaunchKernelGGL(k_count_batch<MODE>, dim3(grid), dim3(256), lds, st, d_args, d_units,
+                       (uint32_t)n_units, d_queue, counts);
 }
 
 }  // namespace
@@ -634,22 +648,26 @@ size_t items_lds_bytes(int log2S, bool vals) {
   return sizeof(int32_t) * ((size_t)kMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * (vals ? 2 : 1)));
 }
 
-void launch_batch(const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units, int64_t n_out,
-                  unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds, hipStream_t st,
-                  bool timed) {
+void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,
+                  int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds,
+                  hipStream_t st, bool timed) {
+  TC_REQUIRE(mode == MODE_COUNT || mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED, TC_EINVAL,
+             "launch_batch: unsupported mode");
   auto* counts = reinterpret_cast<unsigned long long*>(d_counts);
   const unsigned cg = (unsigned)std::max<int64_t>(1, div_up(n_out, 256));
-  if (timed) {
-    TC_LAUNCH("batch_clear", k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
-    if (n_units > 0)
-      TC_LAUNCH("count:batch", k_count_batch, dim3(grid), dim3(256), lds, st, d_args, d_units,
-                (uint32_t)n_units, d_queue, counts);
-  } else {
-    // inside a stream capture: no timer events
-    hipLaunchKernelGGL(k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
-    if (n_units > 0)
-      hipLaunchKernelGGL(k_count_batch, dim3(grid), dim3(256), lds, st, d_args, d_units, (uint32_t)n_units,
-                         d_queue, counts);
+  if (timed) TC_LAUNCH("batch_clear", k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
+  else hipLaunchKernelGGL(k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
+  switch (mode) {
+    case MODE_COUNT:
+      launch_batch_mode<MODE_COUNT>(d_args, d_units, n_units, d_queue, counts, grid, lds, st, timed);
+      break;
+    case MODE_SUPPORT_FULL:
+      launch_batch_mode<MODE_SUPPORT_FULL>(d_args, d_units, n_units, d_queue, counts, grid, lds, st, timed);
+      break;
+    default:
+      launch_batch_mode<MODE_SUPPORT_ORIENTED>(d_args, d_units, n_units, d_queue, counts, grid, lds, st,
+                                               timed);
+      break;
   }
   TC_HIP(hipGetLastError());
 }
@@ -678,10 +696,18 @@ void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t*
   }
 }
 
-void batch_kernel_lds(size_t lds) {
-  if (lds > 65536)
-    TC_HIP(hipFuncSetAttribute((const void*)k_count_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+void batch_kernel_lds(CountMode mode, size_t lds) {
+  if (lds <= 65536) return;
+  const void* f = mode == MODE_COUNT          ? (const void*)k_count_batch<MODE_COUNT>
+                  : mode == MODE_SUPPORT_FULL ? (const void*)k_count_batch<MODE_SUPPORT_FULL>
+                                              : (const void*)k_count_batch<MODE_SUPPORT_ORIENTED>;
+  TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+}
+
+void zero_i32(int32_t* p, int64_t n, hipStream_t st, bool timed) {
+  if (n <= 0) return;
+  if (timed) TC_LAUNCH("zero_i32", k_zero_i32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, p, n);
+  else hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st, p, n);
 }
 
 }  // namespace tc

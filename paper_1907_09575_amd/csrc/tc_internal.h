@@ -171,6 +171,11 @@ struct Graph {
 
 extern const char* const kClassNames[NUM_CLASSES];
 
+// Build a graph from a device edge list on `st` (tc_preprocess without the
+// argument checks; synchronises st) and free one.
+Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n, hipStream_t st);
+void destroy_graph(Graph* g);
+
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
 // ---- launchers implemented in tc_count.hip ---------------------------------
@@ -229,13 +234,36 @@ struct alignas(16) BatchUnit {
 };
 static_assert(sizeof(BatchUnit) == 32, "BatchUnit layout");
 
-// Launch the persistent count over n_units units (queue: device counter,
-// counts: int64 per graph entry; both cleared by the same call's first kernel).
-void launch_batch(const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units, int64_t n_out,
-                  unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds, hipStream_t st,
-                  bool timed);
-// Allow the persistent kernel `lds` bytes of dynamic LDS (call outside any capture).
-void batch_kernel_lds(size_t lds);
+// Launch the persistent count in `mode` (count or a support mode) over n_units
+// units (queue: device counter, counts: int64 per graph entry; both cleared
+// by the same call's first kernel; support arrays are the entries' CountArgs
+// and must be cleared by the caller). timed: through TC_LAUNCH (not inside a
+// capture).
+void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,
+                  int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds,
+                  hipStream_t st, bool timed);
+// Allow the persistent kernel of `mode` `lds` bytes of dynamic LDS (call
+// outside any capture).
+void batch_kernel_lds(CountMode mode, size_t lds);
+// Batch plans (tc_batch.hip): one persistent launch over many graphs in one
+// mode; support modes write each entry's own support array (cleared by every
+// launch of the plan). tuning_json as tc_batch_create's. Synchronises st.
+struct BatchPlan;
+struct PlanEntry {
+  const Graph* g;
+  int32_t* support;  // device int32[g->m] for support modes, else null
+};
+BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, const char* tuning_json,
+                     hipStream_t st);
+// Launch the plan on st (its own HIP graph, or recorded into the caller's
+// capture); per-entry counts go to d_counts[num].
+void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st);
+int64_t plan_units(const BatchPlan& P);
+void free_plan(BatchPlan* P);
+
+// Clear an int32 device array by a kernel (timed: through TC_LAUNCH).
+void zero_i32(int32_t* p, int64_t n, hipStream_t st, bool timed);
+
 // Dynamic LDS bytes of a pack work-group with `slots` table slots, and of an
 // item work-group with a 2^log2S-slot table (log2S < 0: no table, HBM lookups);
 // vals: tables also hold U positions (full support).

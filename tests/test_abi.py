@@ -72,6 +72,22 @@ def test_argument_validation_without_device(lib):
     for q, x, y in [(0, 0, 0), (65, 0, 0), (13, 13, 0), (13, 0, -1)]:
         assert lib.tc_block_count(dummy, q, x, y, dummy, None, None) == 1
     assert b"grid" in lib.tc_last_error() or b"q must" in lib.tc_last_error()
+    # batch and server entry points validate before touching the device
+    lib.tc_batch_create.argtypes = [P, I32, ctypes.c_char_p, P, ctypes.POINTER(P)]
+    assert lib.tc_batch_create(None, -1, None, None, ctypes.byref(out)) == 1
+    assert lib.tc_batch_create(None, 2, None, None, ctypes.byref(out)) == 1
+    assert lib.tc_batch_create(None, 0, b'{"order": "fifo"}', None, ctypes.byref(out)) == 1
+    assert b"order" in lib.tc_last_error()
+    lib.tc_server_create.argtypes = [ctypes.c_int64, I32, ctypes.c_char_p, ctypes.POINTER(P)]
+    assert lib.tc_server_create(0, 4, None, ctypes.byref(out)) == 1
+    assert lib.tc_server_create(1 << 30, 0, None, ctypes.byref(out)) == 1
+    assert lib.tc_server_create(1 << 30, 4, b'{"prep_threads": 0}', ctypes.byref(out)) == 1
+    lib.tc_server_submit.argtypes = [P, P, P]
+    assert lib.tc_server_submit(None, None, None) == 1
+    lib.tc_server_poll.argtypes = [P, ctypes.c_int64, I32, P]
+    assert lib.tc_server_poll(None, 1, 0, None) == 1
+    lib.tc_server_destroy.argtypes = [P]
+    lib.tc_server_destroy(None)  # no-op
     lib.tc_graph_free.argtypes = [P]
     lib.tc_graph_free(None)  # no-op
 
