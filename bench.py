@@ -51,6 +51,14 @@ def parse():
                    help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     p.add_argument("--gen-threads", type=int, default=16)
     p.add_argument("--kernels-json", default=None, help="write the full per-kernel timer summary here")
+    p.add_argument("--no-block", action="store_true", help="skip the 13x13 block grid of the graph")
+    p.add_argument("--block-q", type=int, default=13)
+    p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
+    p.add_argument("--batch-graphs", type=int, default=4096)
+    p.add_argument("--no-serve", action="store_true", help="skip served vs plain FIFO")
+    p.add_argument("--serve-requests", type=int, default=1000)
+    p.add_argument("--serve-warmup", type=int, default=100)
+    p.add_argument("--serve-slots", type=int, default=64)
     return p.parse_args()
 
 
@@ -105,6 +113,235 @@ def cpu_baseline(scale: int, edge_factor: int, seed: int, threads: int, bench_sc
                   "(m=%d, T=%d, %.2f s + %.2f s)" % (
                       scale, len(src), 1 << max(0, bench_scale - scale), U.m / (t2 - t1), U.m, T,
                       t1 - t0, t2 - t1),
+    }
+
+
+def pct(vals, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(vals, dtype=np.float64), q)) if len(vals) else None
+
+
+def bench_block(tc, g, T, q):
+    """One rank's block of the q x q cyclic grid at the graph's real shape:
+    every rank once (their sum must be T, per-shift parts must sum to each
+    block), then block (0, 0) and the slowest rank timed again."""
+    import torch
+    ps = torch.empty(q, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    total, times = 0, {}
+    for x in range(q):
+        for y in range(q):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tc.tc_block_count(g, q, x, y, cnt, ps)
+            torch.cuda.synchronize()
+            times[(x, y)] = time.perf_counter() - t0
+            b = int(cnt.item())
+            assert int(ps.sum().item()) == b, "per-shift parts do not sum to block (%d, %d)" % (x, y)
+            total += b
+    assert total == T, "blocks sum to %d, not T = %d" % (total, T)
+    slow = max(times, key=times.get)
+    out = {"q": q, "grid_sum_equals_T": True, "grid_wall_s": round(sum(times.values()), 3)}
+    for name, (x, y) in (("block_0_0", (0, 0)), ("block_slowest", slow)):
+        timer = tc.Timer(capacity=4096)
+        reps = 3
+        with timer:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tc.tc_block_count(g, q, x, y, cnt, ps)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+        k = timer.summary()
+        timer.free()
+        count_ms = sum(v["total_ms"] for kk, v in k.items() if kk.startswith("block:")) / reps
+        out[name] = {"x": x, "y": y, "count": int(cnt.item()), "per_shift": ps.cpu().tolist(),
+                     "ms_total": round(wall * 1e3, 3), "count_kernel_ms": round(count_ms, 3)}
+    return out
+
+
+def bench_batch(tc, args):
+    """4096 uneven graphs: one persistent launch (autotuned schedule) against
+    the plain loop of tc_count calls on one stream, both on preprocessed
+    handles; counts must agree exactly."""
+    import ctypes
+    import numpy as np
+    import torch
+    import graphgen
+    specs = graphgen.batch_specs(args.batch_graphs)
+    print("batch: generating %d graphs ..." % len(specs), file=sys.stderr, flush=True)
+    lists = graphgen.generate_many(specs, args.gen_threads)
+    m_raw = sum(len(a) for a, _ in lists)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graphs = []
+    for sp, (a, b) in zip(specs, lists):
+        graphs.append(tc.tc_preprocess(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), sp.n))
+    torch.cuda.synchronize()
+    pre_s = time.perf_counter() - t0
+    del lists
+    m_total = sum(g.m for g in graphs)
+    n = len(graphs)
+    stream = torch.cuda.current_stream()
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    plain = torch.empty(n, dtype=torch.int64, device="cuda")
+    base = plain.data_ptr()
+    handles = [g.handle for g in graphs]
+    lib = tc._lib
+
+    def plain_loop():
+        for i in range(n):
+            lib.tc_count(handles[i], ctypes.c_void_p(base + 8 * i), sptr)
+
+    plain_loop()
+    torch.cuda.synchronize()
+    plain_times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        plain_loop()
+        torch.cuda.synchronize()
+        plain_times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    tune = tc.tc_batch_autotune(graphs)
+    tune_s = time.perf_counter() - t0
+    plan = tc.tc_batch_create(graphs, tuning=tune["best"])
+    desc = tc.tc_batch_describe(plan)
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    tc.tc_batch_count(plan, out)
+    torch.cuda.synchronize()
+    reps = 5
+    timer = tc.Timer(capacity=64)
+    with timer:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tc.tc_batch_count(plan, out)
+        torch.cuda.synchronize()
+        batch_s = (time.perf_counter() - t0) / reps
+    k = timer.summary()
+    timer.free()
+    assert torch.equal(out, plain), "batched counts differ from the plain loop"
+    kern_ms = k.get("batch:graph", {}).get("avg_ms")
+    bytes_total = 0
+    for g in graphs:
+        cs = tc.tc_graph_class_stats(g)
+        bytes_total += sum(count_kernel_bytes(cs, c) for c in cs if cs[c]["rows"])
+    plain_s = min(plain_times)
+    res = {
+        "graphs": n, "m_raw": m_raw, "m": m_total, "triangles": int(out.sum().item()),
+        "preprocess_s": round(pre_s, 3),
+        "plain_loop_ms": round(plain_s * 1e3, 3), "batched_ms": round(batch_s * 1e3, 3),
+        "plain_graphs_per_s": n / plain_s, "batched_graphs_per_s": n / batch_s,
+        "plain_edges_per_s": m_total / plain_s, "batched_edges_per_s": m_total / batch_s,
+        "speedup_vs_plain": plain_s / batch_s,
+        "batched_kernel_ms": kern_ms,
+        "batched_alg_GBps": bytes_total / (kern_ms / 1e3) / 1e9 if kern_ms else None,
+        "batched_hbm_frac": bytes_total / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS if kern_ms else None,
+        "schedule": desc, "autotune_s": round(tune_s, 2), "autotune_candidates": len(tune["candidates"]),
+        "counts_equal_plain": True,
+    }
+    plan.free()
+    for g in graphs:
+        g.free()
+    return res
+
+
+def bench_served(tc, args):
+    """Serving: a Poisson trace of count/support requests (lognormal sizes,
+    ER/RMAT, 30% re-queries). Capacity = closed-loop graphs/s of the server
+    on the mix; then the trace arrives open-loop at 0.8 x capacity, against
+    a plain FIFO (tc_preprocess + tc_count / tc_edge_support one at a time)
+    on the same arrival times. Latency = result on host - arrival."""
+    import numpy as np
+    import torch
+    import graphgen
+    total = args.serve_warmup + args.serve_requests
+    reqs = graphgen.serving_trace(total, rate_per_s=1.0, seed=7)
+    distinct = {}
+    for r in reqs:
+        distinct.setdefault(r.spec.seed, r.spec)
+    print("serve: generating %d graphs for %d requests ..." % (len(distinct), total), file=sys.stderr,
+          flush=True)
+    keys = list(distinct)
+    edges = dict(zip(keys, graphgen.generate_many([distinct[k] for k in keys], args.gen_threads)))
+    warm, meas = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
+    budget = 96 << 30
+    opts = {"prep_threads": 4}
+
+    def submit_all(srv, rs, arrivals=None):
+        t0 = time.perf_counter()
+        tickets = []
+        for i, r in enumerate(rs):
+            if arrivals is not None:
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            a, b = edges[r.spec.seed]
+            tickets.append(srv.submit(r.op, a, b, r.spec.n, key=r.spec.seed))
+        return [srv.poll(t) for t in tickets], t0
+
+    # closed loop: everything queued at once
+    with tc.Server(budget, max_slots=args.serve_slots, options=opts) as srv:
+        submit_all(srv, warm)
+        t0 = time.perf_counter()
+        res, _ = submit_all(srv, meas)
+        closed_s = time.perf_counter() - t0
+        assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:2]
+        ref = [(r["count"], r.get("support")) for r in res]
+    capacity = len(meas) / closed_s
+    lam = 0.8 * capacity
+    arr = [r.arrival_s / lam for r in meas]
+    arr = [a - arr[0] for a in arr]
+    # open loop at 0.8 x capacity
+    with tc.Server(budget, max_slots=args.serve_slots, options=opts) as srv:
+        submit_all(srv, warm)
+        res, _ = submit_all(srv, meas, arr)
+        st = srv.stats()
+    lat = [r["t_done"] - r["t_submit"] for r in res]
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    for (c, sup), r in zip(ref, res):
+        assert r["status"] == 0 and r["count"] == c
+        if sup is not None:
+            assert np.array_equal(sup, r["support"])
+    # plain FIFO on the same arrival times, one request at a time
+    dev = torch.device("cuda")
+
+    def plain_one(r):
+        a, b = edges[r.spec.seed]
+        g = tc.tc_preprocess(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), r.spec.n)
+        if r.op == "count":
+            c = int(tc.tc_count(g).item())
+        else:
+            cnt = torch.empty(1, dtype=torch.int64, device=dev)
+            sup, _ = tc.tc_edge_support(g, tc.TC_SUPPORT_FULL, count=cnt)
+            sup.cpu()
+            c = int(cnt.item())
+        g.free()
+        return c
+
+    for r in warm[:20]:
+        plain_one(r)
+    torch.cuda.synchronize()
+    fifo_lat, fifo_counts = [], []
+    t0 = time.perf_counter()
+    for i, r in enumerate(meas):
+        dt = arr[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        fifo_counts.append(plain_one(r))
+        fifo_lat.append(time.perf_counter() - t0 - arr[i])
+    fifo_span = time.perf_counter() - t0
+    assert fifo_counts == [c for c, _ in ref], "FIFO counts differ from the served counts"
+    return {
+        "requests": len(meas), "warmup": len(warm), "distinct_graphs": len(distinct),
+        "closed_loop_graphs_per_s": capacity, "arrival_rate_per_s": lam,
+        "served_graphs_per_s": len(meas) / span, "served_p50_ms": pct(lat, 50) * 1e3,
+        "served_p99_ms": pct(lat, 99) * 1e3,
+        "fifo_graphs_per_s": len(meas) / fifo_span, "fifo_p50_ms": pct(fifo_lat, 50) * 1e3,
+        "fifo_p99_ms": pct(fifo_lat, 99) * 1e3,
+        "p99_speedup_vs_fifo": pct(fifo_lat, 99) / pct(lat, 99),
+        "results_equal_closed_open_fifo": True,
+        "server": {k: st[k] for k in ("ticks", "tick_requests", "max_tick_requests", "cache_hits",
+                                      "evicted", "peak_reserved_bytes", "prep_threads", "max_slots")},
     }
 
 
@@ -237,6 +474,19 @@ def main():
         "kernels_top": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"]}
                         for k, v in sorted(launches.items(), key=lambda kv: -kv[1]["total_ms"])[:6]},
     }
+    if not args.no_block:
+        print("block grid q=%d ..." % args.block_q, file=sys.stderr, flush=True)
+        g = step()
+        torch.cuda.synchronize()
+        result["block"] = bench_block(tc, g, T, args.block_q)
+        g.free()
+    del src, dst
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batched"] = bench_batch(tc, args)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        result["served"] = bench_served(tc, args)
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         threads = max(1, min(16, os.cpu_count() or 1))
