@@ -168,6 +168,12 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
   }
 }
 
+// Count mode needs only whether the bucket holds k: an OR of four compares
+// (no slot index, no branch).
+__device__ __forceinline__ bool bucket_has(const int4& v, int32_t k) {
+  return (v.x == k) | (v.y == k) | (v.z == k) | (v.w == k);
+}
+
 __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
   return v.x == k ? 0 : v.y == k ? 1 : v.z == k ? 2 : v.w == k ? 3 : -1;
 }
@@ -290,13 +296,19 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
           }
 #pragma unroll
           for (int u = g0; u < g0 + kG; ++u) {
-            const int j = match_slot(v[u - g0], k[u]);
-            if (j >= 0) {
-              ++hits;
-              if (MODE != MODE_COUNT)
+            bool found;
+            if constexpr (MODE == MODE_COUNT) {
+              found = bucket_has(v[u - g0], k[u]);
+              hits += found ? 1u : 0u;
+            } else {
+              const int j = match_slot(v[u - g0], k[u]);
+              found = j >= 0;
+              if (found) {
+                ++hits;
                 credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
+              }
             }
-            unres[u] = ok[u] && j < 0 && v[u - g0].w != kEmpty;
+            unres[u] = ok[u] & !found & (v[u - g0].w != kEmpty);
             any_unres |= unres[u];
           }
         }
@@ -308,16 +320,16 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
             for (int i = 1; i <= tr.D && unres[u]; ++i) {
               b2 = (b2 + 1) & bmask[u];
               const int4 w = tab4[bbase[u] + b2];
-              const int j = match_slot(w, k[u]);
-              if (j >= 0) {
-                ++hits;
-                if (MODE != MODE_COUNT)
-                  credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u],
-                                      k[u]);
-                unres[u] = false;
-              } else if (w.w == kEmpty) {
-                unres[u] = false;
+              bool found;
+              if constexpr (MODE == MODE_COUNT) {
+                found = bucket_has(w, k[u]);
+              } else {
+                const int j = match_slot(w, k[u]);
+                found = j >= 0;
+                if (found) credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
               }
+              hits += found ? 1u : 0u;
+              unres[u] = !found & (w.w != kEmpty);
             }
           }
         }
