@@ -23,7 +23,6 @@ Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--scale 24]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -71,14 +70,6 @@ def count_kernel_bytes(stats: dict, cls: str) -> int:
     return 4 * s["probes"] + 4 * s["table_keys"] + 12 * s["tasks"] + 32 * s["rows"]
 
 
-def source_digest() -> str:
-    h = hashlib.sha256()
-    for name in ("tc_count.hip", "tc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1907_09575_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed PMC summary, if it
     was taken on the current count-kernel sources; else None."""
@@ -87,6 +78,7 @@ def load_traffic(kernel: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_1907_09575_amd.rocprof_summary import source_digest
     if t.get("kernel") != kernel or t.get("source_digest") != source_digest():
         return None
     return t.get("hbm_bytes_per_launch")

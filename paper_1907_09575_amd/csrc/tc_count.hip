@@ -193,26 +193,31 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
   const int4* tab4 = reinterpret_cast<const int4*>(tr.tab);
 
   // window of tasks t .. t + 63, one per lane: end prefix and col start (the
-  // start prefix of a task is the end prefix of the previous one)
-  auto fetch = [&](int64_t tj, uint64_t& Pe, uint32_t& ts) {
-    Pe = A.tprefix[tj + 1 < T ? tj + 1 : T];
+  // start prefix of a task is the end prefix of the previous one). Prefixes
+  // are kept relative to the range start q0 in 32 bits: ends are clamped to
+  // len (a task ending past the range is cut there; the start of a task that
+  // begins past the range is never used), and a start before q0 wraps.
+  const uint64_t q0 = q;
+  auto fetch = [&](int64_t tj, uint32_t& Pe, uint32_t& ts) {
+    const uint64_t p = A.tprefix[tj + 1 < T ? tj + 1 : T] - q0;
+    Pe = p > (uint64_t)len ? len : (uint32_t)p;
     ts = A.tstart[tj < T ? tj : T - 1];
   };
-  uint64_t Pe;
+  uint32_t Pe;
   uint32_t tsj;
   fetch((int64_t)t + lane, Pe, tsj);
-  uint64_t P0 = A.tprefix[t];  // start prefix of the window's first task
+  uint32_t P0 = (uint32_t)(A.tprefix[t] - q0);  // start of the window's first task (may wrap)
 
   uint32_t done = 0;
   while (done < len) {
     const uint32_t rem = len - done;
-    // end of the lane's task relative to q, clamped to the remaining range
-    const uint64_t e64 = Pe - q;
-    const uint32_t e = e64 > (uint64_t)rem ? rem : (uint32_t)e64;
-    // start of the lane's task relative to q (wraps below q for lane 0 when the
-    // range begins inside its task), so cbase = col index of relative probe 0
-    const uint32_t e_prev = (uint32_t)__shfl_up((int)(uint32_t)e64, 1, 64);
-    const uint32_t s_rel = lane == 0 ? (uint32_t)(P0 - q) : e_prev;
+    // end of the lane's task relative to the current position, within the range
+    const uint32_t e = Pe - done;
+    // start of the lane's task relative to the current position (wraps below
+    // it for lane 0 when the range begins inside its task), so cbase = col
+    // index of relative probe 0
+    const uint32_t e_prev = (uint32_t)__shfl_up((int)e, 1, 64);
+    const uint32_t s_rel = lane == 0 ? P0 - done : e_prev;
     const uint32_t cbase = tsj - s_rel;
     const uint32_t lim = (uint32_t)__shfl((int)e, 63, 64);  // probes of this window
     if (lim == 0) break;  // unreachable when every task has a probe; guards progress
@@ -229,7 +234,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
       tdesc = tr.row_desc[lo];
     }
     const bool more = lim < rem;
-    uint64_t nPe = 0;
+    uint32_t nPe = 0;
     uint32_t ntsj = 0;
     if (more) fetch((int64_t)t + 64 + lane, nPe, ntsj);  // next window, in flight meanwhile
 
@@ -346,11 +351,10 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     }
     if (more) {
       t += 64;  // a window that is not the last covers exactly its 64 tasks
-      P0 = q + lim;
+      P0 = done + lim;
       Pe = nPe;
       tsj = ntsj;
     }
-    q += lim;
     done += lim;
   }
 }
@@ -536,11 +540,36 @@ __device__ __forceinline__ void items_body(const Args& A, const CountItem* __res
   block_flush<MODE>(hits, A);
 }
 
-template <int MODE, bool GLOBAL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 8 : 4)))
+// OCC: waves per SIMD the kernel's registers are budgeted for. A class whose
+// tables limit a CU to fewer work-groups gets the registers that would
+// otherwise go unused (fewer spills in the probe loop).
+template <int MODE, bool GLOBAL, int OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 void k_count_items(Args A, const CountItem* __restrict__ items) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
   items_body<MODE, GLOBAL>(A, items + (int64_t)blockIdx.x * kWaves, reinterpret_cast<int32_t*>(smem4));
+}
+
+// Count mode per class (chosen by timing at RMAT scale 24): wg_small and
+// wg_large tables (<= 4 / 16 KiB) would allow 8 or more work-groups per CU,
+// but 7 waves per SIMD with spill-free registers run faster; wg_huge tables
+// (>= 32 KiB) allow 4-5 work-groups per CU anyway. Support modes hold more
+// state per probe and run at 4.
+constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccSupport = 4;
+
+template <int MODE, bool GLOBAL>
+const void* items_kernel(int cls) {
+  if constexpr (MODE != MODE_COUNT) {
+    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport>;
+  } else if constexpr (GLOBAL) {
+    return (const void*)k_count_items<MODE, GLOBAL, kOccSmall>;  // no table: LDS does not limit
+  } else {
+    switch (cls) {
+      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge>;
+      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge>;
+      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall>;
+    }
+  }
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
@@ -579,17 +608,14 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (w.n_items[c] == 0) continue;
     const unsigned grid = (unsigned)(w.n_items[c] / kWaves);
-    if (c == CLS_GLOBAL) {
-      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, true>), dim3(grid), dim3(256), mark_bytes,
-                st, A, w.items[c]);
-    } else {
-      const size_t lds = items_lds_bytes(w.cls_log2S[c], VALS);
-      if (lds > 65536)
-        TC_HIP(hipFuncSetAttribute((const void*)k_count_items<MODE, false>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_items<MODE, false>), dim3(grid), dim3(256), lds, st, A,
-                w.items[c]);
-    }
+    const bool global = c == CLS_GLOBAL;
+    const void* f = global ? items_kernel<MODE, true>(c) : items_kernel<MODE, false>(c);
+    const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], VALS);
+    if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const CountItem* items = w.items[c];
+    void* kargs[] = {const_cast<Args*>(&A), &items};
+    LaunchScope ls(kLaunchNames[MODE][c], st);
+    TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(256), kargs, lds, st));
   }
   TC_HIP(hipGetLastError());
 }

@@ -5,8 +5,15 @@ Reads the CSV files rocprofv3 writes with ``--output-format csv``:
   <name>_counter_collection.csv    (from --pmc ...)
 and prints short text tables for ``profiles/``.
 
-    python -m paper_1907_09575_amd.rocprof_summary stats DIR/NAME_kernel_stats.csv
-    python -m paper_1907_09575_amd.rocprof_summary pmc DIR/NAME_counter_collection.csv COUNTER
+    python paper_1907_09575_amd/rocprof_summary.py stats DIR/NAME_kernel_stats.csv
+    python paper_1907_09575_amd/rocprof_summary.py pmc DIR/NAME_counter_collection.csv COUNTER
+    python paper_1907_09575_amd/rocprof_summary.py traffic FETCH.csv WRITE.csv BENCH.json LABEL OUT.json
+
+``traffic`` turns one FETCH_SIZE run and one WRITE_SIZE run of
+``bench.py --copy-calibration`` into HBM bytes per launch of the count class
+LABEL (e.g. count:wg_large): both counters are scaled by what they read for
+the 1 GiB calibration copy, and the launch is found by kernel name and grid
+size (the class's work-groups from the bench line, 256 threads each).
 
 The PMC summary also reports the counter for the largest plain copy kernel in
 the same run (a known-size calibration copy), so byte counts can be scaled.
@@ -14,8 +21,23 @@ the same run (a known-size calibration copy), so byte counts can be scaled.
 from __future__ import annotations
 
 import csv
+import hashlib
+import json
+import os
 import sys
 from collections import defaultdict
+
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+CALIBRATION_BYTES = 1 << 30
+
+
+def source_digest() -> str:
+    """Digest of the count-kernel sources a traffic measurement belongs to."""
+    h = hashlib.sha256()
+    for name in ("tc_count.hip", "tc_internal.h"):
+        with open(os.path.join(_CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
@@ -61,11 +83,52 @@ def pmc(path: str, counter: str):
     return "\n".join(lines)
 
 
+def _counter_rows(path, counter):
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", r.get("counter_name")) != counter:
+            continue
+        out.append((r.get("Kernel_Name", r.get("kernel_name")), int(float(r.get("Grid_Size", r.get("grid_size", 0)))),
+                    float(r.get("Counter_Value", r.get("counter_value", 0)))))
+    return out
+
+
+def traffic(fetch_csv, write_csv, bench_json, label, out_json, commands=()):
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    cls = label.split(":", 1)[1]
+    grid = bench["classes"][cls]["workgroups"] * 256
+    kname = "k_count_packs" if cls.startswith("pack") else "k_count_items"
+    res = {"kernel": label, "workload": bench["config"]["workload"] + " seed %d" % bench["config"]["seed"],
+           "source_digest": source_digest()}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        # calibration: the largest plain copy kernel of the run (1 GiB each way)
+        copies = [v for k, g, v in rows if "copy" in k.lower() and "count" not in k.lower()]
+        assert copies, "no calibration copy in %s" % path
+        cal = max(copies)
+        sel = [v for k, g, v in rows if short_name(k).startswith(kname) and "<0" in k and g == grid]
+        assert sel, "no launch of %s with grid %d in %s" % (kname, grid, path)
+        res[key + "_kib_per_launch"] = sum(sel) / len(sel)
+        res.setdefault("calibration", {"copy_bytes": CALIBRATION_BYTES})
+        res["calibration"][key + "_kib"] = cal
+        res["calibration"][key + "_scale"] = CALIBRATION_BYTES / 1024.0 / cal
+    hbm = sum(res[k + "_kib_per_launch"] * 1024.0 * res["calibration"][k + "_scale"] for k in ("fetch", "write"))
+    res["hbm_bytes_per_launch"] = hbm
+    res["algorithmic_bytes_per_launch"] = bench["roofline"]["algorithmic_bytes_per_launch"] \
+        if bench["roofline"].get("kernel") == label else None
+    res["commands"] = list(commands)
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats(argv[1]))
     elif len(argv) >= 3 and argv[0] == "pmc":
         print(pmc(argv[1], argv[2]))
+    elif len(argv) >= 6 and argv[0] == "traffic":
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], argv[5], argv[6:]), indent=1))
     else:
         print(__doc__)
         return 2
