@@ -7,7 +7,11 @@ and prints short text tables for ``profiles/``.
 
     python paper_1907_09575_amd/rocprof_summary.py stats DIR/NAME_kernel_stats.csv
     python paper_1907_09575_amd/rocprof_summary.py pmc DIR/NAME_counter_collection.csv COUNTER
+    python paper_1907_09575_amd/rocprof_summary.py launches DIR/NAME_kernel_trace.csv
     python paper_1907_09575_amd/rocprof_summary.py traffic FETCH.csv WRITE.csv BENCH.json LABEL OUT.json
+
+``launches`` groups the kernel trace by (kernel, grid size), which separates
+the launch classes that share one kernel instantiation.
 
 ``traffic`` turns one FETCH_SIZE run and one WRITE_SIZE run of
 ``bench.py --copy-calibration`` into HBM bytes per launch of the count class
@@ -83,6 +87,21 @@ def pmc(path: str, counter: str):
     return "\n".join(lines)
 
 
+def launches(path: str, top: int = 25):
+    per = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name", "")
+        grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
+        dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per[(name, grid)].append(dur)
+    items = sorted(per.items(), key=lambda kv: -sum(kv[1]))
+    lines = ["%-52s %11s %6s %12s %12s" % ("kernel", "grid", "calls", "total_ms", "avg_ms")]
+    for (name, grid), d in items[:top]:
+        lines.append("%-52s %11d %6d %12.3f %12.4f" % (short_name(name)[:52], grid, len(d), sum(d) / 1e6,
+                                                      sum(d) / len(d) / 1e6))
+    return "\n".join(lines)
+
+
 def _counter_rows(path, counter):
     out = []
     for r in csv.DictReader(open(path)):
@@ -125,6 +144,8 @@ def traffic(fetch_csv, write_csv, bench_json, label, out_json, commands=()):
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "launches":
+        print(launches(argv[1]))
     elif len(argv) >= 3 and argv[0] == "pmc":
         print(pmc(argv[1], argv[2]))
     elif len(argv) >= 6 and argv[0] == "traffic":
