@@ -129,6 +129,36 @@ def test_rmat_scale20(tc):
     check_full(tc, s, d, 1 << 20)
 
 
+def test_rmat_scale24_full_config(tc):
+    # the benchmark's graph and launch configuration (RMAT scale 24, edge
+    # factor 16, seed 1): the exported CSR and rank map equal the oracle's
+    # entry by entry, the total equals the oracle's Eq. 2, and the oriented
+    # support summed over sampled row ranges equals the oracle's row counts
+    n = 1 << 24
+    s, d = graphgen.rmat(24, seed=1, threads=16)
+    g = gpu_graph(tc, s, d, n)
+    T = gpu_count(tc, g)
+    print("gpu T=%d; oracle preprocessing ..." % T, flush=True)
+    U = oracle.preprocess(s, d, n)
+    del s, d
+    rp, col, perm = tc.tc_graph_export(g)
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), U.rank)
+    rp = rp.cpu().numpy()
+    assert np.array_equal(rp, U.row_ptr)
+    assert np.array_equal(col.cpu().numpy(), U.col)
+    del col
+    print("CSR equal; oracle count ...", flush=True)
+    assert T == oracle.count(U, threads=16)
+    Tg, sup = gpu_support(tc, g, tc.TC_SUPPORT_ORIENTED)
+    assert Tg == T
+    rng = np.random.default_rng(24)
+    for lo in list(rng.integers(0, n - 2048, 24)) + [0, n - 2048]:
+        hi = int(lo) + 2048
+        want = oracle.count_rows(U, int(lo), hi, threads=16)
+        assert int(sup[rp[lo]:rp[hi]].sum(dtype=np.int64)) == want, (lo, hi)
+
+
 def test_edge_cases(tc):
     # empty edge list
     g = gpu_graph(tc, np.zeros(0, np.int32), np.zeros(0, np.int32), 10)
