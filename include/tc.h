@@ -296,6 +296,18 @@ tc_status tc_timer_summary(tc_timer* t, char* buf, int64_t buf_bytes);
 tc_status tc_timer_reset(tc_timer* t);
 void tc_timer_free(tc_timer* t);
 
+/* ---- device memory --------------------------------------------------------- */
+
+/* The library keeps device blocks it has freed (graph arrays, temporaries)
+ * for reuse instead of returning them to the runtime: hipFree can block the
+ * host for milliseconds. Cached free bytes are bounded by a quarter of the
+ * device's memory and are released when an allocation runs out of memory.
+ * tc_release_cached_memory returns every cached block of every device to the
+ * runtime (waits for pending work on them). */
+void tc_release_cached_memory(void);
+/* Bytes handed out, cached free, and the peak handed out, on the current device. */
+tc_status tc_memory_stats(int64_t* in_use_bytes, int64_t* cached_bytes, int64_t* peak_bytes);
+
 /* ---- misc ----------------------------------------------------------------- */
 
 void tc_graph_free(tc_graph* g);

@@ -20,7 +20,8 @@ import torch
 __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
-    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "Server", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
+    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "Server", "tc_release_cached_memory",
+    "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
@@ -329,6 +330,22 @@ class _Result(ctypes.Structure):
 TC_REQ_COUNT, TC_REQ_SUPPORT_FULL, TC_REQ_SUPPORT_ORIENTED = 0, 1, 2
 _OPS = {"count": TC_REQ_COUNT, "support": TC_REQ_SUPPORT_FULL, "support_full": TC_REQ_SUPPORT_FULL,
         "support_oriented": TC_REQ_SUPPORT_ORIENTED}
+
+_sig("tc_release_cached_memory", [], None)
+_sig("tc_memory_stats", [ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)])
+
+
+def tc_release_cached_memory():
+    """Return the library's cached device blocks to the runtime."""
+    _lib.tc_release_cached_memory()
+
+
+def tc_memory_stats() -> dict:
+    """Device bytes the library has handed out, holds cached, and its peak."""
+    a, b, c = _I64(), _I64(), _I64()
+    _check(_lib.tc_memory_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "tc_memory_stats")
+    return {"in_use": a.value, "cached": b.value, "peak": c.value}
+
 
 _sig("tc_server_create", [_I64, _I32, ctypes.c_char_p, ctypes.POINTER(_P)])
 _sig("tc_server_submit", [_P, ctypes.POINTER(_Request), ctypes.POINTER(_I64)])

@@ -1,0 +1,198 @@
+// tc_alloc.cpp - caching device allocator for the library's temporaries and
+// graph arrays.
+//
+// hipFree (and hipFreeAsync of large blocks) can block the host for
+// milliseconds, and every preprocessing call allocates and frees several GB
+// of temporaries. Freed blocks are therefore kept per device and handed out
+// again: a block is reused for a request of at least 4/5 of its size (sizes
+// are rounded up to 2 MiB above 1 MiB, to powers of two below). When a block
+// is freed, an event is recorded on the stream of its last use; reusing it on
+// another stream first makes that stream wait for the event, on the same
+// stream ordering is implicit. Cached free bytes are bounded (a quarter of
+// the device's memory by default); beyond that, and whenever hipMalloc runs
+// out of memory, cached blocks are released (after their events complete).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+struct Block {
+  void* p = nullptr;
+  size_t size = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;  // null: no work pending on the block
+};
+
+struct DeviceCache {
+  std::multimap<size_t, Block> free;         // by size
+  std::unordered_map<void*, size_t> live;    // handed-out blocks
+  std::vector<hipEvent_t> events;            // recycled events
+  size_t cached = 0, cap = 0, in_use = 0, peak = 0;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceCache> g_dev;
+
+size_t round_size(size_t b) {
+  if (b <= ((size_t)1 << 20)) {
+    size_t r = 512;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = (size_t)2 << 20;
+  return (b + g - 1) / g * g;
+}
+
+DeviceCache& cache_for(int dev) {
+  DeviceCache& c = g_dev[dev];
+  if (c.cap == 0) {
+    size_t fr = 0, tot = 0;
+    c.cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 4 : ((size_t)16 << 30);
+  }
+  return c;
+}
+
+// Release cached blocks (waiting for their events) until at most `keep`
+// bytes stay cached. Called with g_mu held.
+void trim_locked(DeviceCache& c, size_t keep) {
+  while (c.cached > keep && !c.free.empty()) {
+    auto it = std::prev(c.free.end());  // largest first
+    Block b = it->second;
+    c.free.erase(it);
+    c.cached -= b.size;
+    if (b.ev) {
+      (void)hipEventSynchronize(b.ev);
+      c.events.push_back(b.ev);
+    }
+    (void)hipFree(b.p);
+  }
+}
+
+}  // namespace
+
+void* cache_alloc(size_t bytes, hipStream_t st) {
+  int dev = 0;
+  TC_HIP(hipGetDevice(&dev));
+  const size_t rb = round_size(bytes ? bytes : 1);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache& c = cache_for(dev);
+    auto it = c.free.lower_bound(rb);
+    if (it != c.free.end() && it->first <= rb + rb / 4) {
+      Block b = it->second;
+      c.free.erase(it);
+      c.cached -= b.size;
+      if (b.ev) {
+        if (b.st != st) {
+          hipError_t e = hipStreamWaitEvent(st, b.ev, 0);
+          if (e != hipSuccess) {
+            c.free.emplace(b.size, b);
+            c.cached += b.size;
+            throw Error(TC_EDEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
+          }
+        }
+        c.events.push_back(b.ev);
+      }
+      c.live[b.p] = b.size;
+      c.in_use += b.size;
+      c.peak = std::max(c.peak, c.in_use);
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, rb);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_mu);
+    trim_locked(cache_for(dev), 0);
+    e = hipMalloc(&p, rb);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? TC_ENOMEM : TC_EDEVICE,
+                std::string("hipMalloc(") + std::to_string(rb) + "): " + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCache& c = cache_for(dev);
+  c.live[p] = rb;
+  c.in_use += rb;
+  c.peak = std::max(c.peak, c.in_use);
+  return p;
+}
+
+void cache_free(void* p, hipStream_t st, bool idle) {
+  if (!p) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCache& c = cache_for(dev);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;  // not ours
+  Block b;
+  b.p = p;
+  b.size = it->second;
+  b.st = st;
+  c.live.erase(it);
+  c.in_use -= b.size;
+  if (!idle) {
+    if (c.events.empty()) {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) c.events.push_back(ev);
+    }
+    if (!c.events.empty() && hipEventRecord(c.events.back(), st) == hipSuccess) {
+      b.ev = c.events.back();
+      c.events.pop_back();
+    } else {
+      (void)hipStreamSynchronize(st);  // could not record: make the block idle
+    }
+  }
+  c.free.emplace(b.size, b);
+  c.cached += b.size;
+  if (c.cached > c.cap) trim_locked(c, c.cap / 2);
+}
+
+void cache_release_all() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_dev) {
+    (void)hipSetDevice(kv.first);
+    trim_locked(kv.second, 0);
+  }
+  (void)hipSetDevice(cur);
+}
+
+void cache_stats(int64_t* in_use, int64_t* cached, int64_t* peak) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCache& c = cache_for(dev);
+  if (in_use) *in_use = (int64_t)c.in_use;
+  if (cached) *cached = (int64_t)c.cached;
+  if (peak) *peak = (int64_t)c.peak;
+}
+
+}  // namespace tc
+
+extern "C" {
+
+void tc_release_cached_memory(void) { tc::cache_release_all(); }
+
+tc_status tc_memory_stats(int64_t* in_use_bytes, int64_t* cached_bytes, int64_t* peak_bytes) {
+  try {
+    tc::cache_stats(in_use_bytes, cached_bytes, peak_bytes);
+    return TC_OK;
+  } catch (...) {
+    return TC_EDEVICE;
+  }
+}
+
+}  // extern "C"

@@ -231,6 +231,7 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
              "batch plan: unsupported mode");
   TC_REQUIRE(num >= 0 && num < (1ll << 31), TC_EINVAL, "batch plan: bad number of graphs");
   std::unique_ptr<BatchPlan> P(new BatchPlan());
+  P->own.st = st;
   P->tun = parse_tuning(tuning_json);
   P->mode = mode;
   const bool vals = mode == MODE_SUPPORT_FULL;
@@ -330,7 +331,7 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
               raw.as<BatchUnit>(), order, n, P->d_units);
     TC_HIP(hipGetLastError());
   }
-  TC_HIP(hipStreamSynchronize(st));
+  check_sorts(st);
   return P.release();
 }
 
@@ -344,7 +345,18 @@ void plan_launch(BatchPlan& P, int64_t* d_counts, hipStream_t st, bool timed) {
 
 }  // namespace
 
-void free_plan(BatchPlan* P) { delete P; }
+void free_plan_idle(BatchPlan* P) {
+  if (!P) return;
+  P->own.release(true);
+  delete P;
+}
+
+void free_plan(BatchPlan* P) {
+  if (!P) return;
+  // launches of the plan may be queued on any stream: let the device drain
+  (void)hipDeviceSynchronize();
+  free_plan_idle(P);
+}
 
 int64_t plan_units(const BatchPlan& P) { return P.n_units; }
 
@@ -451,7 +463,7 @@ tc_status tc_batch_count(tc_batch* plan, int64_t* d_counts, void* stream) {
 
 void tc_batch_free(tc_batch* plan) {
   if (!plan) return;
-  delete plan->p;
+  tc::free_plan(plan->p);
   delete plan;
 }
 

@@ -130,6 +130,7 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
                  hipStream_t st) {
   TempStream temps(st);
   Owned own;
+  own.st = st;
   LocalRows H, P;
   gather_local(H, g, q, x, st);  // hash side: rows j == x
   gather_local(P, g, q, y, st);  // probe side: rows i == y
@@ -166,7 +167,7 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   CountView v{H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), P.col.as<int32_t>(), P.nnz, &w, q,
               (x + y) % q};
   launch_count(v, MODE_BLOCK, d_count, nullptr, d_per_shift, st);
-  TC_HIP(hipStreamSynchronize(st));
+  check_task_sorts(st);
 }
 
 }  // namespace tc

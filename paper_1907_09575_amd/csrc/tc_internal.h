@@ -105,24 +105,32 @@ __host__ __device__ inline int pack_table_log2(int64_t d) {
   return l;
 }
 
+// ---- device memory (tc_alloc.cpp) ------------------------------------------
+// Caching allocator: blocks are kept per device after they are freed and
+// reused (on another stream only after an event recorded at the free).
+// cache_free: `st` is the stream of the block's last use; idle = no work on
+// the block can be pending (no event needed).
+void* cache_alloc(size_t bytes, hipStream_t st);
+void cache_free(void* p, hipStream_t st, bool idle);
+void cache_release_all();
+
 // Allocations owned by a graph or a temporary work set (freed together).
+// `st` is the stream they are used on; release(idle) returns them to the
+// cache (idle: the caller knows no work on them is pending).
 struct Owned {
   std::vector<void*> ptrs;
   size_t bytes = 0;
+  hipStream_t st = nullptr;
   template <class T>
   T* alloc(int64_t count) {
-    void* p = nullptr;
-    size_t b = sizeof(T) * (size_t)(count > 0 ? count : 1);
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess)
-      throw Error(e == hipErrorOutOfMemory ? TC_ENOMEM : TC_EDEVICE,
-                  std::string("hipMalloc: ") + hipGetErrorString(e));
+    const size_t b = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    void* p = cache_alloc(b, st);
     ptrs.push_back(p);
     bytes += b;
     return static_cast<T*>(p);
   }
-  void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+  void release(bool idle = false) {
+    for (void* p : ptrs) cache_free(p, st, idle);
     ptrs.clear();
     bytes = 0;
   }
@@ -174,7 +182,11 @@ extern const char* const kClassNames[NUM_CLASSES];
 // Build a graph from a device edge list on `st` (tc_preprocess without the
 // argument checks; synchronises st) and free one.
 Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n, hipStream_t st);
+// destroy_graph waits for the device to drain (work using the graph may still
+// be queued on any stream); destroy_graph_idle is for callers that know no
+// such work is pending.
 void destroy_graph(Graph* g);
+void destroy_graph_idle(Graph* g);
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
@@ -259,7 +271,10 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
 // capture); per-entry counts go to d_counts[num].
 void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st);
 int64_t plan_units(const BatchPlan& P);
+// free_plan waits for the device to drain; free_plan_idle is for callers that
+// know no launch of the plan is pending.
 void free_plan(BatchPlan* P);
+void free_plan_idle(BatchPlan* P);
 
 // Clear an int32 device array by a kernel (timed: through TC_LAUNCH).
 void zero_i32(int32_t* p, int64_t n, hipStream_t st, bool timed);

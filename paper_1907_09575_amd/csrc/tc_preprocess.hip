@@ -408,11 +408,22 @@ struct GraphImpl : Graph {
   Owned owned;
 };
 
-void destroy_graph(Graph* g) { delete static_cast<GraphImpl*>(g); }
+void destroy_graph_idle(Graph* g) {
+  GraphImpl* gi = static_cast<GraphImpl*>(g);
+  gi->owned.release(true);
+  delete gi;
+}
+
+void destroy_graph(Graph* g) {
+  // work on the graph may be queued on any stream: let the device drain
+  (void)hipDeviceSynchronize();
+  destroy_graph_idle(g);
+}
 
 Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n,
                    hipStream_t st) {
   std::unique_ptr<GraphImpl> g(new GraphImpl());
+  g->owned.st = st;
   TC_HIP(hipGetDevice(&g->device));
   TempStream temps(st);  // temporaries are stream-ordered on st
   g->n = n;
@@ -548,10 +559,12 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   // ---- 6: work classes ------------------------------------------------------
   build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
              tl.start.as<uint32_t>(), tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), st);
-  TC_HIP(hipStreamSynchronize(st));
+  check_sorts(st);
   g->arena_bytes = g->owned.bytes;
   return g.release();
 }
+
+void check_task_sorts(hipStream_t st) { check_sorts(st); }
 
 void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
                 hipStream_t st, const char* name) {

@@ -162,7 +162,6 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipStream_t st = nullptr;
-  bool async = false;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   void alloc(size_t b) {
@@ -170,12 +169,10 @@ struct DevBuf {
     bytes = b;
     if (!b) return;
     st = temp_ctx().st;
-    async = temp_ctx().active;
-    if (async) TC_HIP(hipMallocAsync(&p, b, st));
-    else TC_HIP(hipMalloc(&p, b));
+    p = cache_alloc(b, st);
   }
   void release() {
-    if (p) (void)(async ? hipFreeAsync(p, st) : hipFree(p));
+    if (p) cache_free(p, st, false);
     p = nullptr;
     bytes = 0;
   }
@@ -212,121 +209,216 @@ void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits.
-// Per pass: (1) per-tile digit histograms, stored digit-major
-// hist[d * nblocks + tile]; (2) exclusive scan of hist gives every (digit,
-// tile) its global output offset; (3) each tile ranks its keys stably with
-// 8 wave ballots per key (peers = lanes with the same digit), stages them in
-// LDS in digit order and writes each digit's run contiguously.
+// Stable LSD radix sort, 8-bit digits, one kernel per digit.
+// (1) One read of the keys counts the digits of every pass; an exclusive scan
+//     of each pass's 256 counts gives the start of every digit's bucket.
+// (2) Per pass, work-groups take tiles in ticket order (an atomic counter, so
+//     a tile only ever waits for tiles that are already running), load the
+//     tile into registers and rank its keys stably by digit with wave ballots
+//     (peers = lanes with the same digit; counts carried across the tile's
+//     rows in LDS). Each digit's thread then publishes the tile's count,
+//     walks back over earlier tiles' published words until it meets an
+//     inclusive prefix (decoupled look-back), publishes its own inclusive
+//     prefix, and the tile writes each digit's run contiguously from LDS.
+//     A published word holds a 2-bit state and a 62-bit value in one 64-bit
+//     atomic. The wait is bounded: past the spin budget the kernel records a
+//     failure (sort_failed) and goes on, so every wave always finishes.
 // ---------------------------------------------------------------------------
 struct NoVal {};
 
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kPrimThreads * kSortItems;
+constexpr int kSortPassesMax = 8;
+constexpr uint64_t kLbAgg = 1ull << 62;   // word holds this tile's own count
+constexpr uint64_t kLbPre = 2ull << 62;   // word holds the inclusive prefix
+constexpr uint64_t kLbVal = (1ull << 62) - 1;
+constexpr uint32_t kLbSpinMax = 1u << 16;
+constexpr int kLbWin = 8;  // predecessors read per look-back step
+
+// Set by a sort whose look-back ran out of its spin budget (never expected;
+// checked by the host after the sorts of a call). One flag per source file
+// that instantiates the sort.
+static __device__ int g_sort_failed;
 
 template <class K>
-__global__ __launch_bounds__(256) void k_rs_hist(const K* __restrict__ kin, int64_t n, int shift,
-                                                 uint32_t dmask, uint32_t* __restrict__ hist,
-                                                 int64_t nblocks) {
-  __shared__ uint32_t h[4][256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) h[w][tid] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    int64_t idx = base + (int64_t)i * kPrimThreads + tid;
-    if (idx < n) {
-      uint32_t d = (uint32_t)(kin[idx] >> shift) & dmask;
-      atomicAdd(&h[wave][d], 1u);
-    }
-  }
-  __syncthreads();
-  hist[(int64_t)tid * nblocks + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+__device__ __forceinline__ uint32_t rs_digit(K k, int shift, uint32_t dmask) {
+  return (uint32_t)(k >> shift) & dmask;
 }
 
-template <class K, class V>
-__global__ __launch_bounds__(256) void k_rs_scatter(const K* __restrict__ kin, K* __restrict__ kout,
-                                                    const V* __restrict__ vin, V* __restrict__ vout,
-                                                    int64_t n, int shift, uint32_t dmask,
-                                                    const uint32_t* __restrict__ hist,
-                                                    const uint32_t* __restrict__ offs,
-                                                    int64_t nblocks) {
+// Lanes of a wave holding the same value d (8-bit): a mask of them.
+__device__ __forceinline__ uint64_t rs_peers(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int bb = 0; bb < 8; ++bb) {
+    const bool bit = (d >> bb) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+template <class K>
+__global__ __launch_bounds__(256) void k_rs_digits(const K* __restrict__ kin, int64_t n, int bit_lo,
+                                                   int bit_hi, uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[kSortPassesMax][256];
+  const int tid = threadIdx.x;
+  const int passes = (bit_hi - bit_lo + 7) / 8;
+  for (int p = 0; p < passes; ++p) h[p][tid] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    const K k = kin[i];
+    for (int p = 0; p < passes; ++p) {
+      const int shift = bit_lo + 8 * p;
+      const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+      atomicAdd(&h[p][rs_digit(k, shift, (1u << bits) - 1u)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][tid]) atomicAdd(&ghist[p * 256 + tid], h[p][tid]);
+}
+
+// In-place exclusive scan of each pass's 256 digit counts (one work-group).
+static __global__ __launch_bounds__(256) void k_rs_buckets(uint32_t* __restrict__ ghist, int passes) {
+  __shared__ uint32_t s_w[4];
+  for (int p = 0; p < passes; ++p) {
+    uint32_t tot;
+    const uint32_t v = ghist[p * 256 + threadIdx.x];
+    const uint32_t e = block_excl_scan(v, s_w, tot);
+    ghist[p * 256 + threadIdx.x] = e;
+    __syncthreads();
+  }
+}
+
+template <class K, class V, int KPT>
+__global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, K* __restrict__ kout,
+                                                     const V* __restrict__ vin, V* __restrict__ vout,
+                                                     int64_t n, int shift, uint32_t dmask,
+                                                     const uint32_t* __restrict__ bucket,
+                                                     uint64_t* __restrict__ status,
+                                                     uint32_t* __restrict__ ticket) {
+  constexpr int TILE = 256 * KPT;
+  constexpr int WCH = 64 * KPT;  // keys of the tile each wave ranks (a contiguous quarter)
   constexpr bool HV = !std::is_same<V, NoVal>::value;
   using VS = typename std::conditional<HV, V, char>::type;
-  __shared__ K s_k[kSortTile];
-  __shared__ VS s_v[HV ? kSortTile : 1];
-  __shared__ uint32_t s_goff[256], s_tstart[256], s_run[256];
-  __shared__ uint32_t s_wc[2][4][256];
+  __shared__ K s_k[TILE];
+  __shared__ VS s_v[HV ? TILE : 1];
+  __shared__ uint32_t s_cnt[4][256];  // per wave and digit: count, then the wave's offset
+  __shared__ uint32_t s_goff[256], s_tstart[256];
   __shared__ uint32_t s_tmp[4];
+  __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t blk = blockIdx.x;
-  const int64_t base = blk * kSortTile;
+  if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) s_cnt[w][tid] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const int64_t wbase = (int64_t)tile * TILE + (int64_t)wave * WCH;
 
-  uint32_t cnt = hist[(int64_t)tid * nblocks + blk];
-  s_goff[tid] = offs[(int64_t)tid * nblocks + blk];
-  uint32_t tot;
-  s_tstart[tid] = block_excl_scan(cnt, s_tmp, tot);
-  s_run[tid] = 0;
+  // the wave's quarter in registers: item i of lane l is key wbase + 64 i + l
+  K k[KPT];
+  VS v[KPT];
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const int64_t idx = wbase + 64 * i + lane;
+    k[i] = idx < n ? kin[idx] : K(0);
+    if constexpr (HV) v[i] = idx < n ? vin[idx] : V{};
+  }
+  // stable rank within the wave's quarter; the wave's own LDS counters carry
+  // the counts from item to item (a wave's LDS accesses complete in order)
+  uint32_t rank[KPT];
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint32_t* cnt_w = s_cnt[wave];
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const bool valid = wbase + 64 * i + lane < n;
+    const uint32_t d = rs_digit(k[i], shift, dmask);
+    const uint64_t peers = rs_peers(d, valid);
+    const uint32_t before = cnt_w[d];
+    rank[i] = before + (uint32_t)__popcll(peers & lt_mask);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && (peers & lt_mask) == 0) cnt_w[d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  // digit `tid`: offsets of the waves within the tile's run, the tile's count
+  uint32_t cnt = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    s_wc[0][w][tid] = 0;
-    s_wc[1][w][tid] = 0;
+    const uint32_t c = s_cnt[w][tid];
+    s_cnt[w][tid] = cnt;
+    cnt += c;
   }
-  __syncthreads();
-
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
-  for (int i = 0; i < kSortItems; ++i) {
-    const int64_t idx = base + (int64_t)i * kPrimThreads + tid;
-    const bool valid = idx < n;
-    K k = valid ? kin[idx] : K(0);
-    VS v{};
-    if constexpr (HV) {
-      if (valid) v = vin[idx];
-    }
-    const uint32_t d = (uint32_t)(k >> shift) & dmask;
-    uint64_t peers = __ballot(valid);
+  // publish the tile's count, look back for the earlier tiles' total,
+  // publish the inclusive prefix
+  uint64_t* my = status + (uint64_t)tile * 256 + tid;
+  if (tile == 0) {
+    __hip_atomic_store(my, kLbPre | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_goff[tid] = bucket[tid];
+  } else {
+    __hip_atomic_store(my, kLbAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // walk back kLbWin predecessors per step (their words are read together):
+    // add counts from the nearest one until an inclusive prefix; stop at a
+    // tile that has published nothing yet and read again from there
+    uint64_t excl = 0;
+    uint32_t spins = 0;
+    int64_t j = (int64_t)tile - 1;
+    while (j >= 0) {
+      uint64_t w[kLbWin];
 #pragma unroll
-    for (int bb = 0; bb < 8; ++bb) {
-      const bool bit = (d >> bb) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t wr = (uint32_t)__popcll(peers & lt_mask);
-    const int buf = i & 1;
-    if (valid && wr == 0) s_wc[buf][wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    {
-      uint32_t c = s_run[tid];
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        uint32_t t = s_wc[buf][w][tid];
-        s_wc[buf][w][tid] = c;
-        c += t;
+      for (int q = 0; q < kLbWin; ++q)
+        w[q] = j - q >= 0 ? __hip_atomic_load(status + (uint64_t)(j - q) * 256 + tid, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : kLbPre;  // before tile 0: an inclusive prefix of 0
+      int q = 0;
+      bool done = false;
+      for (; q < kLbWin; ++q) {
+        const uint64_t st = w[q] & ~kLbVal;
+        if (st == 0) break;
+        excl += w[q] & kLbVal;
+        if (st == kLbPre) {
+          done = true;
+          break;
+        }
       }
-      s_run[tid] = c;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) s_wc[buf ^ 1][w][tid] = 0;
+      if (done) break;
+      j -= q;
+      if (q < kLbWin) {  // tile j has not published yet
+        if (++spins > kLbSpinMax) {  // never expected: give up rather than hang
+          atomicExch(&g_sort_failed, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t lp = s_tstart[d] + s_wc[buf][wave][d] + wr;
-      s_k[lp] = k;
-      if constexpr (HV) s_v[lp] = v;
+    __hip_atomic_store(my, kLbPre | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_goff[tid] = bucket[tid] + (uint32_t)excl;
+  }
+  uint32_t tot;
+  s_tstart[tid] = block_excl_scan(cnt, s_tmp, tot);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    if (wbase + 64 * i + lane < n) {
+      const uint32_t d = rs_digit(k[i], shift, dmask);
+      const uint32_t lp = s_tstart[d] + s_cnt[wave][d] + rank[i];
+      s_k[lp] = k[i];
+      if constexpr (HV) s_v[lp] = v[i];
     }
   }
   __syncthreads();
-  const int64_t rem = n - base;
-  const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
+  const int64_t rem = n - (int64_t)tile * TILE;
+  const int tile_n = rem < TILE ? (int)rem : TILE;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const int lp = i * kPrimThreads + tid;
+  for (int i = 0; i < KPT; ++i) {
+    const int lp = i * 256 + tid;
     if (lp < tile_n) {
-      const K k = s_k[lp];
-      const uint32_t d = (uint32_t)(k >> shift) & dmask;
+      const K kk = s_k[lp];
+      const uint32_t d = rs_digit(kk, shift, dmask);
       const uint64_t gp = (uint64_t)s_goff[d] + (uint64_t)(lp - (int)s_tstart[d]);
-      kout[gp] = k;
+      kout[gp] = kk;
       if constexpr (HV) vout[gp] = s_v[lp];
     }
   }
@@ -338,39 +430,58 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const K* __restrict__ kin, K
 template <class K, class V>
 bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
                 hipStream_t st, const char* name) {
-  const char* n_hist = intern_name(std::string("rs_hist:") + name);
-  const char* n_scat = intern_name(std::string("rs_scatter:") + name);
+  constexpr int KPT = sizeof(K) + (std::is_same<V, NoVal>::value ? 0 : sizeof(V)) > 8 ? 8 : 16;
+  constexpr int TILE = 256 * KPT;
+  const char* n_digits = intern_name(std::string("rs_digits:") + name);
+  const char* n_pass = intern_name(std::string("rs_pass:") + name);
   if (n <= 1 || bit_hi <= bit_lo) return false;
   TC_REQUIRE(n < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW, "radix_sort: more than 2^32-1 keys");
-  const int64_t nb = div_up(n, kSortTile);
-  DevBuf hist(sizeof(uint32_t) * 256 * (size_t)nb), offs(sizeof(uint32_t) * 256 * (size_t)nb);
-  const int64_t hn = 256 * nb;
-  const int64_t pnb = div_up(hn, kScanTile);
-  DevBuf part(sizeof(uint32_t) * (size_t)pnb);
+  TC_REQUIRE(bit_hi - bit_lo <= 8 * kSortPassesMax, TC_EINVAL, "radix_sort: key range too wide");
+  const int passes = (bit_hi - bit_lo + 7) / 8;
+  const int64_t ntiles = div_up(n, TILE);
+  // per pass: ticket counter (padded to 64 words) + ntiles * 256 look-back words
+  const int64_t pass_words = 64 + ntiles * 256;
+  DevBuf ghist(sizeof(uint32_t) * 256 * kSortPassesMax);
+  DevBuf lb(sizeof(uint64_t) * (size_t)pass_words);
+  TC_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
+  const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
+  TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), 0, st, keys, n, bit_lo, bit_hi,
+            ghist.as<uint32_t>());
+  TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, ghist.as<uint32_t>(), passes);
   K* ka = keys;
   K* kb = keys_alt;
   V* va = vals;
   V* vb = vals_alt;
   bool alt = false;
-  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+  for (int p = 0; p < passes; ++p) {
+    const int shift = bit_lo + 8 * p;
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
-    TC_LAUNCH(n_hist, (k_rs_hist<K>), dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, dmask,
-                       hist.as<uint32_t>(), nb);
-    TC_LAUNCH("scan_reduce", (k_scan_reduce<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
-                       hist.as<uint32_t>(), hn, part.as<uint32_t>());
-    TC_LAUNCH("scan_partials", (k_scan_partials<uint32_t>), dim3(1), dim3(256), 0, st, part.as<uint32_t>(),
-                       pnb, (uint32_t*)nullptr);
-    TC_LAUNCH("scan_final", (k_scan_final<uint32_t, uint32_t>), dim3((unsigned)pnb), dim3(256), 0, st,
-                       hist.as<uint32_t>(), hn, part.as<uint32_t>(), offs.as<uint32_t>());
-    TC_LAUNCH(n_scat, (k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(256), 0, st, ka, kb, va, vb, n,
-                       shift, dmask, hist.as<uint32_t>(), offs.as<uint32_t>(), nb);
+    TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(uint64_t) * (size_t)pass_words, st));
+    uint64_t* words = lb.as<uint64_t>();
+    TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT>), dim3((unsigned)ntiles), dim3(256), 0, st, ka, kb, va, vb,
+              n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + 64,
+              reinterpret_cast<uint32_t*>(words));
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
     alt = !alt;
   }
   return alt;
+}
+
+// Throws TC_EDEVICE if a sort of this source file gave up waiting in its
+// look-back since the last check (and clears the flag). Synchronises st.
+static inline void check_sorts(hipStream_t st) {
+  int h = 0;
+  TC_HIP(hipMemcpyFromSymbolAsync(&h, HIP_SYMBOL(g_sort_failed), sizeof(int), 0, hipMemcpyDeviceToHost, st));
+  TC_HIP(hipStreamSynchronize(st));
+  if (h) {
+    const int z = 0;
+    TC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_sort_failed), &z, sizeof(int), 0, hipMemcpyHostToDevice, st));
+    TC_HIP(hipStreamSynchronize(st));
+    throw Error(TC_EDEVICE, "radix sort: a look-back wait exceeded its bound");
+  }
 }
 
 // Tasks in hashed-row order (the input of build_work).
@@ -388,5 +499,7 @@ struct TaskLists {
 // as sort buffers.
 void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
                 hipStream_t st, const char* name);
+// check_sorts for the task sorts of sort_tasks (synchronises st).
+void check_task_sorts(hipStream_t st);
 
 }  // namespace tc

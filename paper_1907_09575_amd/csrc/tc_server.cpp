@@ -234,7 +234,7 @@ struct Server {
       try {
         TC_REQUIRE(st != nullptr, TC_EDEVICE, "tc_server: worker stream");
         const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(e->m_raw, 1);
-        TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_edges), 2 * bytes, st));
+        d_edges = static_cast<int32_t*>(cache_alloc(2 * bytes, st));
         if (e->m_raw > 0) {
           TC_HIP(hipMemcpyAsync(d_edges, e->src, bytes, hipMemcpyHostToDevice, st));
           TC_HIP(hipMemcpyAsync(d_edges + e->m_raw, e->dst, bytes, hipMemcpyHostToDevice, st));
@@ -251,8 +251,8 @@ struct Server {
         err = x.what();
       }
       if (d_edges) {
-        (void)hipFreeAsync(d_edges, st);
         (void)hipStreamSynchronize(st);
+        cache_free(d_edges, st, true);
       }
       std::lock_guard<std::mutex> lk(mu);
       e->building = false;
@@ -321,8 +321,7 @@ struct Server {
         for (Req* q : v) {
           int32_t* sup = nullptr;
           if (op != TC_REQ_COUNT && q->ce->g->m > 0) {
-            TC_HIP(hipMallocAsync(reinterpret_cast<void**>(&q->d_support),
-                                  sizeof(int32_t) * (size_t)q->ce->g->m, tick_stream));
+            q->d_support = static_cast<int32_t*>(cache_alloc(sizeof(int32_t) * (size_t)q->ce->g->m, tick_stream));
             sup = q->d_support;
           }
           ents.push_back(PlanEntry{q->ce->g, sup});
@@ -377,14 +376,14 @@ struct Server {
             }
           }
         }
-        if (q->d_support) (void)hipFreeAsync(q->d_support, tick_stream);
+        if (q->d_support) cache_free(q->d_support, tick_stream, status == TC_OK);
         q->d_support = nullptr;
         if (q->ce) q->ce->last_use = ++use_clock;
         finish(q, s, e);
         release(q);
       }
       tk.reqs[op].clear();
-      if (tk.plans[op]) free_plan(tk.plans[op]);
+      if (tk.plans[op]) free_plan_idle(tk.plans[op]);
       tk.plans[op] = nullptr;
     }
     tk.running = false;
@@ -408,7 +407,7 @@ struct Server {
         if (!exit_now && !want_tick && !tk.running && to_free.empty())
           cv_sched.wait_for(lk, std::chrono::milliseconds(2));
       }
-      for (Graph* g : to_free) destroy_graph(g);
+      for (Graph* g : to_free) destroy_graph_idle(g);  // no request and no tick uses them
       if (exit_now) break;
       if (tk.running) {
         hipError_t q = hipEventQuery(tk.ev);
@@ -640,8 +639,9 @@ void tc_server_destroy(tc_server* srv) {
     }
     for (auto& t : s->workers)
       if (t.joinable()) t.join();
+    (void)hipDeviceSynchronize();
     for (auto& e : s->cache)
-      if (e->g) tc::destroy_graph(e->g);
+      if (e->g) tc::destroy_graph_idle(e->g);
     s->cache.clear();
     if (s->tick_stream) {
       (void)hipStreamSynchronize(s->tick_stream);

@@ -34,21 +34,6 @@ TempCtx& temp_ctx() {
 }
 
 TempStream::TempStream(hipStream_t st) : prev(temp_ctx()) {
-  // keep freed pool memory cached for the next preprocessing call (once per device)
-  static std::mutex mu;
-  static std::set<int> done;
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    std::lock_guard<std::mutex> lk(mu);
-    if (!done.count(dev)) {
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-      }
-      done.insert(dev);
-    }
-  }
   temp_ctx().active = true;
   temp_ctx().st = st;
 }
