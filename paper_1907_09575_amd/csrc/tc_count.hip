@@ -494,8 +494,13 @@ __device__ __forceinline__ void pack_body(const Args& A, const int32_t* __restri
   block_flush<MODE>(hits, A);
 }
 
+// Register budgets (waves per SIMD) of the pack kernel and of the persistent
+// batch kernel in count mode (their LDS use would allow about 6 work-groups per
+// CU; 5 with spill-free registers runs faster).
+constexpr int kOccPacks = 5, kOccBatch = 5;
+
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? kOccPacks : 4)))
 void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
                    uint32_t pack_slots) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
@@ -638,7 +643,7 @@ __global__ void k_batch_clear(unsigned long long* counts, int64_t n, unsigned in
 // were ordered when the plan was made (largest first by default). Each unit
 // runs the same body as its class's own kernel with its graph's arguments.
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? 6 : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? kOccBatch : 4)))
 void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__ units, uint32_t n_units,
                    unsigned int* __restrict__ queue, unsigned long long* __restrict__ counts) {
   extern __shared__ int4 smem4[];
