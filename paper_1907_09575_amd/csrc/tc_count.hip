@@ -467,8 +467,9 @@ __device__ __forceinline__ void pack_body(const Args& A, const int32_t* __restri
     if (VALS) val[slot] = (int32_t)p;
     md = disp > md ? disp : md;
   }
-  md = wave_max(md);
-  if (lane == 0) atomicMax(&s_D, md);
+  // (a plain LDS max per lane: a wave reduction here would share its lane
+  // addresses with the final one and keep them live across the probe loop)
+  if (md) atomicMax(&s_D, md);
   __syncthreads();
 
   TableRef tr{tab, val, 0, s_D, 0, 0, row_t0, row_desc, nr};
@@ -531,8 +532,7 @@ __device__ __forceinline__ void items_body(const Args& A, const CountItem* __res
     __syncthreads();
     const uint32_t bmask = S / kBucket - 1;
     int md = build_table<VALS>(tab, val, bmask, A.hcol, rs, d, tid, 256);
-    md = wave_max(md);
-    if (lane == 0) atomicMax(&s_D, md);
+    if (md) atomicMax(&s_D, md);  // per lane: see pack_body
     __syncthreads();
     tr.tab = tab;
     tr.val = val;
