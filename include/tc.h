@@ -258,11 +258,13 @@ void tc_server_destroy(tc_server* s);
 /* ---- work classes and phase timers (profiling) ------------------------------ */
 
 /* tc_count splits the hashed rows j into work classes, one kernel launch each:
- * 0 pack_small / 1 pack_large - light rows packed, one wave per pack;
- * 2 wg_small / 3 wg_large / 4 wg_huge - heavy rows, a work-group's four waves
- *   share one LDS table of the row; 5 global - rows whose table exceeds LDS,
+ * 0 pack_small / 1 pack_large - light rows packed, up to 256 per work-group,
+ *   their tables built together;
+ * 2 wg_small / 3 wg_large / 4 wg_huge / 5 wg_giant - heavy rows, a
+ *   work-group's four waves share one LDS table of the row (at most 1024 /
+ *   4096 / 8192 / 16384 slots); 6 global - rows of more than 8192 entries,
  *   looked up by binary search in HBM. */
-#define TC_NUM_CLASSES 6
+#define TC_NUM_CLASSES 7
 
 typedef struct {
   int64_t workgroups;   /* work-groups of the class's launch */

@@ -31,7 +31,7 @@ library_path = os.path.join(_HERE, "libtc.so")
 TC_OK, TC_EINVAL, TC_ENOMEM, TC_EDEVICE, TC_EOVERFLOW, TC_EBUSY, TC_ECANCELED = range(7)
 TC_SUPPORT_FULL = 0
 TC_SUPPORT_ORIENTED = 1
-TC_NUM_CLASSES = 6
+TC_NUM_CLASSES = 7
 
 if not os.path.exists(library_path):
     raise ImportError(

@@ -7,8 +7,8 @@
 
 namespace tc {
 
-const char* const kClassNames[NUM_CLASSES] = {"pack_small", "pack_large", "wg_small",
-                                              "wg_large",   "wg_huge",    "global"};
+const char* const kClassNames[NUM_CLASSES] = {"pack_small", "pack_large", "wg_small", "wg_large",
+                                              "wg_huge",    "wg_giant",   "global"};
 
 static thread_local std::string g_last_error;
 

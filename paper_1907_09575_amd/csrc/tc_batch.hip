@@ -125,19 +125,21 @@ Tuning parse_tuning(const char* js) {
   return t;
 }
 
+constexpr int kItemClasses = NUM_CLASSES - CLS_WG_SMALL;  // wg_small .. global
+
 // Per graph entry of the plan: where its units come from (device copy).
 struct BatchSrc {
   const int32_t* pack_rows[2];
   const uint32_t* pack_ptr[2];
-  const CountItem* items[4];  // classes wg_small, wg_large, wg_huge, global
+  const CountItem* items[kItemClasses];  // classes wg_small .. global
   const uint32_t* tbeg;
   const uint32_t* tend;
   const uint64_t* tprefix;
   const int64_t* row_ptr;
   uint32_t n_packs[2];
   uint32_t pack_slots[2];
-  uint32_t n_groups[4];
-  int32_t kind[4];  // BatchKind of each item class under the plan's LDS cap
+  uint32_t n_groups[kItemClasses];
+  int32_t kind[kItemClasses];  // BatchKind of each item class under the plan's LDS cap
   uint64_t unit_off;
 };
 
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(256) void k_batch_units(const BatchSrc* __restrict_
   const BatchSrc& s = src[blockIdx.x];
   const uint32_t np0 = s.n_packs[0], np1 = s.n_packs[1];
   uint32_t total = np0 + np1;
-  for (int c = 0; c < 4; ++c) total += s.n_groups[c];
+  for (int c = 0; c < kItemClasses; ++c) total += s.n_groups[c];
   for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) {
     BatchUnit u;
     uint64_t wgt = 0;
@@ -284,7 +286,7 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
       lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], vals));
       off += (uint64_t)w.n_packs[c];
     }
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kItemClasses; ++c) {
       const int cls = CLS_WG_SMALL + c;
       s.items[c] = w.items[cls];
       s.n_groups[c] = (uint32_t)(w.n_items[cls] / kWaves);
@@ -501,7 +503,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
     for (int32_t i = 0; i < num_graphs; ++i) {
       TC_REQUIRE(graphs[i] != nullptr, TC_EINVAL, "tc_batch_autotune: null graph handle");
       const tc::WorkSet& w = tc::G(graphs[i])->w;
-      for (int c = tc::CLS_WG_SMALL; c <= tc::CLS_WG_HUGE; ++c)
+      for (int c = tc::CLS_WG_SMALL; c <= tc::CLS_WG_GIANT; ++c)
         if (w.n_items[c]) max_log2 = std::max(max_log2, w.cls_log2S[c]);
     }
     std::vector<int> caps = {tc::kMaxLog2S};

@@ -10,12 +10,12 @@
 //
 // Hash table (Section 5.2, "Modifying the hashing routine"): U_b in LDS in
 // buckets of four 32-bit slots, bucket = k & (buckets - 1) (the direct bitwise
-// AND of the paper), at least 4 |U_b| slots. A key goes to the first free slot
-// of its bucket or, if the bucket is full, of the next ones; slots fill left
-// to right, so a lookup reads one bucket with a single 16-byte LDS read and
-// stops there unless the bucket is full. The build records the longest bucket
-// displacement D, which bounds every lookup; exactness never depends on the
-// absence of collisions.
+// AND of the paper), at least 4 |U_b| slots (2 |U_b| for rows of more than
+// 2048 keys). A key goes to the first free slot of its bucket or, if the
+// bucket is full, of the next ones; slots fill left to right, so a lookup
+// reads one bucket with a single 16-byte LDS read and stops there unless the
+// bucket is full. The build records the longest bucket displacement D, which
+// bounds every lookup; exactness never depends on the absence of collisions.
 //
 // Probe loop (one wave, flattened over tasks). A wave walks a range of
 // probes in batches of 64, lane l taking probe base + l, so every col[] read
@@ -33,11 +33,14 @@
 // U_b (every key exceeds b >= 0), so it needs no branch.
 //
 // Launch classes (decided in preprocessing from |U_b| and the row's probes):
-//   packs  - light rows b are packed (about 4K probes per pack); one wave per
-//            pack builds each row's table in its private LDS slice in turn.
+//   packs  - light rows b are packed (up to 256 rows per work-group); the
+//            work-group builds all their tables in LDS, then its waves probe
+//            the pack's task range, each task looking up its own row's table.
 //   heavy  - a row's probes are cut into per-wave ranges (16K probes); the 4
-//            waves of a work-group share one table of that row.
-//   global - a row whose table would not fit LDS (|U_b| > 4096): lookups are
+//            waves of a work-group share one table of that row. One launch per
+//            table size class (wg_small / wg_large / wg_huge / wg_giant), each
+//            compiled for the occupancy its LDS allows.
+//   global - a row whose table would not fit LDS (|U_b| > 8192): lookups are
 //            binary searches in the sorted U_b in HBM.
 // Reductions: per-lane 32-bit hit counters, wave reduction by xor shuffles,
 // one 64-bit atomic per work-group into the caller's counter (order-free and
@@ -558,9 +561,9 @@ void k_count_items(Args A, const CountItem* __restrict__ items) {
 // Count mode per class (chosen by timing at RMAT scale 24): wg_small and
 // wg_large tables (<= 4 / 16 KiB) would allow 8 or more work-groups per CU,
 // but 7 waves per SIMD with spill-free registers run faster; wg_huge tables
-// (>= 32 KiB) allow 4-5 work-groups per CU anyway. Support modes hold more
-// state per probe and run at 4.
-constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccSupport = 4;
+// (32 KiB) allow 4-5 work-groups per CU and wg_giant tables (64 KiB) 2.
+// Support modes hold more state per probe and run at 4.
+constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSupport = 4;
 
 template <int MODE, bool GLOBAL>
 const void* items_kernel(int cls) {
@@ -572,6 +575,7 @@ const void* items_kernel(int cls) {
     switch (cls) {
       case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge>;
       case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge>;
+      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant>;
       default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall>;
     }
   }
@@ -587,13 +591,14 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
 // launch names seen by the phase timer: "<mode>:<class>"
 const char* const kLaunchNames[4][NUM_CLASSES] = {
     {"count:pack_small", "count:pack_large", "count:wg_small", "count:wg_large", "count:wg_huge",
-     "count:global"},
+     "count:wg_giant", "count:global"},
     {"support_full:pack_small", "support_full:pack_large", "support_full:wg_small",
-     "support_full:wg_large", "support_full:wg_huge", "support_full:global"},
+     "support_full:wg_large", "support_full:wg_huge", "support_full:wg_giant", "support_full:global"},
     {"support_oriented:pack_small", "support_oriented:pack_large", "support_oriented:wg_small",
-     "support_oriented:wg_large", "support_oriented:wg_huge", "support_oriented:global"},
+     "support_oriented:wg_large", "support_oriented:wg_huge", "support_oriented:wg_giant",
+     "support_oriented:global"},
     {"block:pack_small", "block:pack_large", "block:wg_small", "block:wg_large", "block:wg_huge",
-     "block:global"}};
+     "block:wg_giant", "block:global"}};
 
 template <int MODE>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {

@@ -74,9 +74,10 @@ enum ItemClass : int {
   CLS_PACK_LARGE = 1,  // packs of light rows b, table <= 1024 slots
   CLS_WG_SMALL = 2,    // heavy rows, 4 waves share one table <= 1024 slots
   CLS_WG_LARGE = 3,    // heavy rows, table <= 4096 slots
-  CLS_WG_HUGE = 4,     // table <= 16384 slots (any row too large for the above)
-  CLS_GLOBAL = 5,      // table would not fit LDS: binary search in U_b in HBM
-  NUM_CLASSES = 6
+  CLS_WG_HUGE = 4,     // table <= 8192 slots
+  CLS_WG_GIANT = 5,    // table of 16384 slots (rows of 4097 .. 8192 keys)
+  CLS_GLOBAL = 6,      // table would not fit LDS: binary search in U_b in HBM
+  NUM_CLASSES = 7
 };
 
 constexpr int kWaves = 4;               // waves per work-group in every count launch
@@ -90,11 +91,15 @@ constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LD
 constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte offsets into U
 
 // Slots of the LDS hash table of a row with d keys: a power of two >= 4 d
-// (load factor <= 1/4, so almost every lookup ends in its first bucket), at
-// least 64.
+// (load factor <= 1/4, so almost every lookup ends in its first bucket) for
+// rows of up to 2048 keys (tables of up to 8192 slots, 32 KiB), >= 2 d above
+// (load <= 1/2: an absent key needs a second bucket read about once in seven,
+// but such rows take half the LDS, so twice as many work-groups fit a CU and
+// rows of up to 8192 keys stay in LDS); at least 64.
 __host__ __device__ inline int table_log2(int64_t d) {
+  const int64_t want = d <= 2048 ? 4 * d : 2 * d;
   int l = 6;
-  while ((1ll << l) < 4 * d) ++l;
+  while ((1ll << l) < want) ++l;
   return l;
 }
 

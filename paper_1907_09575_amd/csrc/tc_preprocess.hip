@@ -207,6 +207,7 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
     if (W > 0) {
       l = table_log2(row_ptr[b + 1] - row_ptr[b]);
       if (l > kMaxLog2S) c = CLS_GLOBAL;
+      else if (l > 13) c = CLS_WG_GIANT;
       else if (l > 12) c = CLS_WG_HUGE;
       else if (W < kHeavyMin && l <= 10) c = l <= 8 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
       else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
