@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=1000)
     p.add_argument("--serve-warmup", type=int, default=100)
     p.add_argument("--serve-slots", type=int, default=64)
+    p.add_argument("--serve-prep-threads", type=int, default=8)
     return p.parse_args()
 
 
@@ -257,7 +258,7 @@ def bench_served(tc, args):
     edges = dict(zip(keys, graphgen.generate_many([distinct[k] for k in keys], args.gen_threads)))
     warm, meas = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
     budget = 96 << 30
-    opts = {"prep_threads": 4}
+    opts = {"prep_threads": args.serve_prep_threads}
 
     def submit_all(srv, rs, arrivals=None):
         t0 = time.perf_counter()

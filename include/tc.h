@@ -235,7 +235,8 @@ typedef struct {
   double t_done;
 } tc_result;
 
-/* options_json (nullable), flat object: "prep_threads" (default 4),
+/* options_json (nullable), flat object: "prep_threads" (default: half the
+ * host's threads, 1 .. 8),
  * "lds_cap_log2" and "blocks_per_cu" (the batch schedule of every tick). */
 tc_status tc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const char* options_json,
                            tc_server** out);

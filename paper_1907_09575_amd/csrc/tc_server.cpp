@@ -75,11 +75,18 @@ size_t prep_estimate(int64_t m_raw, int64_t n) {
   return (size_t)(56 * m_raw + 40 * n) + ((size_t)1 << 20);
 }
 
+// Preprocessing workers by default: half the host's threads, 1 .. 8 (each
+// worker spends much of its time waiting for its stream).
+int default_prep_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(8u, hc / 2));
+}
+
 struct Server {
   int device = 0;
   int64_t budget = 0;
   int max_slots = 1;
-  int prep_threads = 4;
+  int prep_threads = default_prep_threads();
   std::string tuning;  // batch schedule of every tick
 
   std::mutex mu;
