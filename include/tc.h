@@ -153,9 +153,10 @@ typedef struct tc_batch tc_batch;
  *   "blocks_per_cu" (int, 0 = as many as LDS allows), "lds_cap_log2" (int in
  *   [6, 14]: item rows whose table exceeds 2^cap slots are looked up in HBM
  *   instead of LDS), "order" ("lpt" | "input"), "graph" (1 = launch through a
- *   captured HIP graph, 0 = plain launches); tc_batch_autotune's output is
- *   accepted as is. Unknown keys: TC_EINVAL. The handles must outlive the
- *   plan. Synchronises `stream`.
+ *   captured HIP graph, 0 = plain launches), "chunk" (int, units taken per
+ *   queue atomic, default 1, 0 = about 16 atomics per work-group);
+ *   tc_batch_autotune's output is accepted as is. Unknown keys: TC_EINVAL.
+ *   The handles must outlive the plan. Synchronises `stream`.
  */
 tc_status tc_batch_create(const tc_graph* const* graphs, int32_t num_graphs,
                           const char* tuning_json, void* stream, tc_batch** out);

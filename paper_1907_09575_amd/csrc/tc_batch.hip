@@ -33,6 +33,7 @@ struct Tuning {
   int lds_cap_log2 = kMaxLog2S;
   bool lpt = true;
   bool graph = true;
+  int chunk = 1;  // units per queue atomic (0: about 16 atomics per work-group)
 };
 
 constexpr int kMaxBlocksPerCU = 8;
@@ -114,6 +115,9 @@ Tuning parse_tuning(const char* js) {
       t.lpt = v == "lpt";
     } else if (k == "graph") {
       t.graph = to_int(k, v) != 0;
+    } else if (k == "chunk") {
+      t.chunk = to_int(k, v);
+      TC_REQUIRE(t.chunk >= 0 && t.chunk <= 4096, TC_EINVAL, "tuning json: chunk outside [0, 4096]");
     } else if (k == "waves_per_block") {
       TC_REQUIRE(to_int(k, v) == kWaves, TC_EINVAL, "tuning json: waves_per_block must be 4");
     } else if (k == "ms" || k == "units" || k == "hbm_units" || k == "grid" || k == "lds_bytes") {
@@ -201,6 +205,7 @@ struct BatchPlan {
   std::vector<std::pair<int32_t*, int64_t>> support;  // arrays cleared before each launch
   int64_t n_graphs = 0, n_units = 0, hbm_units = 0;
   int bpc = 0;  // resident work-groups per compute unit the grid was sized for
+  uint32_t chunk = 1;  // units per queue atomic
   unsigned grid = 0;
   size_t lds = 0;
   int cus = 0;
@@ -306,6 +311,8 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
   if (bpc == 0) bpc = (int)std::max<size_t>(1, std::min<size_t>(kMaxBlocksPerCU, kLdsPerCU / P->lds));
   P->bpc = bpc;
   P->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(P->n_units, (int64_t)bpc * P->cus));
+  P->chunk = t.chunk > 0 ? (uint32_t)t.chunk
+                         : (uint32_t)std::max<int64_t>(1, std::min<int64_t>(64, P->n_units / ((int64_t)P->grid * 16)));
   batch_kernel_lds(mode, P->lds);
 
   P->d_args = P->own.alloc<CountArgs>(std::max<int64_t>(num, 1));
@@ -341,7 +348,7 @@ namespace {
 
 void plan_launch(BatchPlan& P, int64_t* d_counts, hipStream_t st, bool timed) {
   for (const auto& z : P.support) zero_i32(z.first, z.second, st, timed);
-  launch_batch(P.mode, P.d_args, P.d_units, P.n_units, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st,
+  launch_batch(P.mode, P.d_args, P.d_units, P.n_units, P.chunk, P.n_graphs, P.d_queue, d_counts, P.grid, P.lds, st,
                timed);
 }
 
@@ -400,8 +407,9 @@ std::string plan_json(const BatchPlan& P, double ms) {
   char buf[512];
   std::snprintf(buf, sizeof(buf),
                 "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\", \"graph\": %d, "
-                "\"units\": %lld, \"hbm_units\": %lld, \"grid\": %u, \"lds_bytes\": %zu, \"ms\": %.4f}",
-                P.bpc, P.tun.lds_cap_log2, P.tun.lpt ? "lpt" : "input", P.tun.graph ? 1 : 0,
+                "\"chunk\": %u, \"units\": %lld, \"hbm_units\": %lld, \"grid\": %u, \"lds_bytes\": %zu, "
+                "\"ms\": %.4f}",
+                P.bpc, P.tun.lds_cap_log2, P.tun.lpt ? "lpt" : "input", P.tun.graph ? 1 : 0, P.chunk,
                 (long long)P.n_units, (long long)P.hbm_units, P.grid, P.lds, ms);
   return buf;
 }

@@ -362,22 +362,25 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
   }
 }
 
+// Work-group total of the hits (returned to thread 0, which also adds it to
+// A.count when that is set).
 template <int MODE>
-__device__ __forceinline__ void block_flush(uint32_t hits, const Args& A) {
+__device__ __forceinline__ unsigned long long block_flush(uint32_t hits, const Args& A) {
   __shared__ unsigned long long s_sum[kWaves];
   unsigned long long h = wave_sum((unsigned long long)hits);
   if (lane_id() == 0) s_sum[threadIdx.x >> 6] = h;
   __syncthreads();
-  if (threadIdx.x == 0 && A.count) {
-    unsigned long long tot = 0;
+  unsigned long long tot = 0;
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) tot += s_sum[w];
-    if (tot) atomicAdd(A.count, tot);
+    if (A.count && tot) atomicAdd(A.count, tot);
   }
   if (MODE == MODE_BLOCK && A.per_shift && (int)threadIdx.x < A.q) {
     const unsigned int c = shift_counters()[threadIdx.x];
     if (c) atomicAdd(&A.per_shift[threadIdx.x], (unsigned long long)c);
   }
+  return tot;
 }
 
 // Clear the work-group's shift counters (MODE_BLOCK); a barrier follows in
@@ -395,7 +398,7 @@ __device__ __forceinline__ void block_init() {
 constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
 
 template <int MODE>
-__device__ __forceinline__ void pack_body(const Args& A, const int32_t* __restrict__ rows,
+__device__ __forceinline__ unsigned long long pack_body(const Args& A, const int32_t* __restrict__ rows,
                                           const uint32_t* __restrict__ pack_ptr, uint32_t pack,
                                           uint32_t pack_slots, int32_t* smem) {
   __shared__ int s_D;
@@ -495,7 +498,7 @@ __device__ __forceinline__ void pack_body(const Args& A, const int32_t* __restri
     }
     wave_probe<MODE, TK_MULTI>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
   }
-  block_flush<MODE>(hits, A);
+  return block_flush<MODE>(hits, A);
 }
 
 // Register budgets (waves per SIMD) of the pack kernel and of the persistent
@@ -513,7 +516,8 @@ void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __r
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
 template <int MODE, bool GLOBAL>
-__device__ __forceinline__ void items_body(const Args& A, const CountItem* __restrict__ grp, int32_t* smem) {
+__device__ __forceinline__ unsigned long long items_body(const Args& A, const CountItem* __restrict__ grp,
+                                                         int32_t* smem) {
   __shared__ int s_D;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -545,7 +549,7 @@ __device__ __forceinline__ void items_body(const Args& A, const CountItem* __res
   wave_sync_lds();
   const CountItem it = grp[wave];
   if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE>(A, tr, it.t0, it.q0, it.len, bm, hits);
-  block_flush<MODE>(hits, A);
+  return block_flush<MODE>(hits, A);
 }
 
 // OCC: waves per SIMD the kernel's registers are budgeted for. A class whose
@@ -644,46 +648,54 @@ __global__ void k_batch_clear(unsigned long long* counts, int64_t n, unsigned in
 }
 
 // Persistent work-groups pull units from one queue until it is empty (every
-// work-group reaches the exit once the counter passes n_units); the units
-// were ordered when the plan was made (largest first by default). Each unit
-// runs the same body as its class's own kernel with its graph's arguments.
+// work-group reaches the exit once the counter passes the last chunk); the
+// units were ordered when the plan was made (largest first by default). One
+// atomic takes `chunk` consecutive units (a tuning choice: fewer atomics on
+// the one counter against coarser balance). Each unit runs the same body as
+// its class's own kernel with its graph's arguments.
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? kOccBatch : 4)))
 void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__ units, uint32_t n_units,
-                   unsigned int* __restrict__ queue, unsigned long long* __restrict__ counts) {
+                   uint32_t chunk, unsigned int* __restrict__ queue, unsigned long long* __restrict__ counts) {
   extern __shared__ int4 smem4[];
   int32_t* smem = reinterpret_cast<int32_t*>(smem4);
-  __shared__ uint32_t s_unit;
+  __shared__ uint32_t s_chunk;
+  const uint32_t n_chunks = (n_units + chunk - 1) / chunk;
   for (;;) {
-    __syncthreads();  // the previous unit is done with LDS and s_unit
-    if (threadIdx.x == 0) s_unit = atomicAdd(queue, 1u);
+    __syncthreads();  // the previous chunk is done with s_chunk
+    if (threadIdx.x == 0) s_chunk = atomicAdd(queue, 1u);
     __syncthreads();
-    const uint32_t u = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: unit loads go scalar
-    if (u >= n_units) break;
-    const BatchUnit bu = units[u];
-    Args A = gargs[bu.graph];
-    A.count = counts + bu.graph;
-    if (bu.kind == BK_PACK) {
-      pack_body<MODE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
-    } else if (bu.kind == BK_ITEMS) {
-      items_body<MODE, false>(A, static_cast<const CountItem*>(bu.p0), smem);
-    } else {
-      items_body<MODE, true>(A, static_cast<const CountItem*>(bu.p0), smem);
+    const uint32_t ci = __builtin_amdgcn_readfirstlane(s_chunk);  // uniform: unit loads go scalar
+    if (ci >= n_chunks) break;
+    const uint32_t u_end = ci * chunk + chunk < n_units ? ci * chunk + chunk : n_units;
+    for (uint32_t u = ci * chunk; u < u_end; ++u) {
+      __syncthreads();  // the previous unit is done with LDS
+      const BatchUnit bu = units[u];
+      Args A = gargs[bu.graph];
+      A.count = counts + bu.graph;
+      if (bu.kind == BK_PACK) {
+        pack_body<MODE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+      } else if (bu.kind == BK_ITEMS) {
+        items_body<MODE, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+      } else {
+        items_body<MODE, true>(A, static_cast<const CountItem*>(bu.p0), smem);
+      }
     }
   }
 }
 
 template <int MODE>
-void launch_batch_mode(const Args* d_args, const BatchUnit* d_units, int64_t n_units, unsigned int* d_queue,
-                       unsigned long long* counts, unsigned grid, size_t lds, hipStream_t st, bool timed) {
+void launch_batch_mode(const Args* d_args, const BatchUnit* d_units, int64_t n_units, uint32_t chunk,
+                       unsigned int* d_queue, unsigned long long* counts, unsigned grid, size_t lds,
+                       hipStream_t st, bool timed) {
   static const char* const kNames[3] = {"count:batch", "support_full:batch", "support_oriented:batch"};
   if (n_units == 0) return;
   if (timed)
     TC_LAUNCH(kNames[MODE], k_count_batch<MODE>, dim3(grid), dim3(256), lds, st, d_args, d_units,
-              (uint32_t)n_units, d_queue, counts);
+              (uint32_t)n_units, chunk, d_queue, counts);
   else
     hipLaunchKernelGGL(k_count_batch<MODE>, dim3(grid), dim3(256), lds, st, d_args, d_units,
-                       (uint32_t)n_units, d_queue, counts);
+                       (uint32_t)n_units, chunk, d_queue, counts);
 }
 
 }  // namespace
@@ -697,8 +709,9 @@ size_t items_lds_bytes(int log2S, bool vals) {
 }
 
 void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,
-                  int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds,
-                  hipStream_t st, bool timed) {
+                  uint32_t chunk, int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid,
+                  size_t lds, hipStream_t st, bool timed) {
+  TC_REQUIRE(chunk >= 1, TC_EINVAL, "launch_batch: chunk must be >= 1");
   TC_REQUIRE(mode == MODE_COUNT || mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED, TC_EINVAL,
              "launch_batch: unsupported mode");
   auto* counts = reinterpret_cast<unsigned long long*>(d_counts);
@@ -707,13 +720,13 @@ void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_un
   else hipLaunchKernelGGL(k_batch_clear, dim3(cg), dim3(256), 0, st, counts, n_out, d_queue);
   switch (mode) {
     case MODE_COUNT:
-      launch_batch_mode<MODE_COUNT>(d_args, d_units, n_units, d_queue, counts, grid, lds, st, timed);
+      launch_batch_mode<MODE_COUNT>(d_args, d_units, n_units, chunk, d_queue, counts, grid, lds, st, timed);
       break;
     case MODE_SUPPORT_FULL:
-      launch_batch_mode<MODE_SUPPORT_FULL>(d_args, d_units, n_units, d_queue, counts, grid, lds, st, timed);
+      launch_batch_mode<MODE_SUPPORT_FULL>(d_args, d_units, n_units, chunk, d_queue, counts, grid, lds, st, timed);
       break;
     default:
-      launch_batch_mode<MODE_SUPPORT_ORIENTED>(d_args, d_units, n_units, d_queue, counts, grid, lds, st,
+      launch_batch_mode<MODE_SUPPORT_ORIENTED>(d_args, d_units, n_units, chunk, d_queue, counts, grid, lds, st,
                                                timed);
       break;
   }

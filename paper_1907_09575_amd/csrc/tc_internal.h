@@ -257,8 +257,8 @@ static_assert(sizeof(BatchUnit) == 32, "BatchUnit layout");
 // and must be cleared by the caller). timed: through TC_LAUNCH (not inside a
 // capture).
 void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,
-                  int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid, size_t lds,
-                  hipStream_t st, bool timed);
+                  uint32_t chunk, int64_t n_out, unsigned int* d_queue, int64_t* d_counts, unsigned grid,
+                  size_t lds, hipStream_t st, bool timed);
 // Allow the persistent kernel of `mode` `lds` bytes of dynamic LDS (call
 // outside any capture).
 void batch_kernel_lds(CountMode mode, size_t lds);

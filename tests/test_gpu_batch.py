@@ -81,6 +81,8 @@ def test_batch_default_schedule(tc, mixed):
     {"lds_cap_log2": 10, "order": "input"},
     {"lds_cap_log2": 6},          # every item group looks its row up in HBM
     {"graph": 0},                 # plain launches instead of the plan's HIP graph
+    {"chunk": 1},                 # one unit per queue atomic
+    {"chunk": 64, "order": "input"},
 ])
 def test_batch_schedules(tc, mixed, tuning):
     graphs, want = mixed
