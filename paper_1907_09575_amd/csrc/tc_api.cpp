@@ -95,7 +95,7 @@ tc_status tc_graph_class_stats(const tc_graph* gh, tc_class_stats* out) {
     for (int c = 0; c < tc::NUM_CLASSES; ++c) {
       tc_class_stats& o = out[c];
       const bool pack = c == tc::CLS_PACK_SMALL || c == tc::CLS_PACK_LARGE;
-      o.workgroups = pack ? g.w.n_packs[c] : g.w.n_items[c] / tc::kWaves;
+      o.workgroups = pack ? g.w.n_packs[c] : g.w.n_items[c] / tc::class_waves(c);
       o.rows = g.w.cls_stats[c][0];
       o.table_keys = g.w.cls_stats[c][1];
       o.tasks = g.w.cls_stats[c][2];

@@ -55,7 +55,8 @@ using Args = CountArgs;
 
 constexpr int kU = 8;                   // 64-probe batches per super-batch
 constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bits)
-constexpr int kMarkInts = kWaves * kBmWords;
+constexpr int kMarkInts = kWaves * kBmWords;          // packs
+constexpr int kItemMarkInts = kWavesBig * kBmWords;   // item work-groups (up to 8 waves)
 constexpr int32_t kEmpty = -1;
 constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // byte offset past any col buffer
 
@@ -366,14 +367,14 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
 // A.count when that is set).
 template <int MODE>
 __device__ __forceinline__ unsigned long long block_flush(uint32_t hits, const Args& A) {
-  __shared__ unsigned long long s_sum[kWaves];
+  __shared__ unsigned long long s_sum[kWavesBig];
   unsigned long long h = wave_sum((unsigned long long)hits);
   if (lane_id() == 0) s_sum[threadIdx.x >> 6] = h;
   __syncthreads();
   unsigned long long tot = 0;
   if (threadIdx.x == 0) {
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) tot += s_sum[w];
+    const int nw = (int)(blockDim.x >> 6);
+    for (int w = 0; w < nw; ++w) tot += s_sum[w];
     if (A.count && tot) atomicAdd(A.count, tot);
   }
   if (MODE == MODE_BLOCK && A.per_shift && (int)threadIdx.x < A.q) {
@@ -532,13 +533,13 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
     __syncthreads();  // shift counters cleared before any credit
   } else {
     const uint32_t S = 1u << grp[0].log2S;
-    int32_t* tab = smem + kMarkInts;
+    int32_t* tab = smem + kItemMarkInts;
     int32_t* val = tab + S;
-    for (uint32_t i = tid; i < S; i += 256) tab[i] = kEmpty;
+    for (uint32_t i = tid; i < S; i += blockDim.x) tab[i] = kEmpty;
     if (tid == 0) s_D = 0;
     __syncthreads();
     const uint32_t bmask = S / kBucket - 1;
-    int md = build_table<VALS>(tab, val, bmask, A.hcol, rs, d, tid, 256);
+    int md = build_table<VALS>(tab, val, bmask, A.hcol, rs, d, tid, (int)blockDim.x);
     if (md) atomicMax(&s_D, md);  // per lane: see pack_body
     __syncthreads();
     tr.tab = tab;
@@ -555,11 +556,11 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
 // OCC: waves per SIMD the kernel's registers are budgeted for. A class whose
 // tables limit a CU to fewer work-groups gets the registers that would
 // otherwise go unused (fewer spills in the probe loop).
-template <int MODE, bool GLOBAL, int OCC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
+template <int MODE, bool GLOBAL, int OCC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(OCC)))
 void k_count_items(Args A, const CountItem* __restrict__ items) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  items_body<MODE, GLOBAL>(A, items + (int64_t)blockIdx.x * kWaves, reinterpret_cast<int32_t*>(smem4));
+  items_body<MODE, GLOBAL>(A, items + (int64_t)blockIdx.x * WAVES, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Count mode per class (chosen by timing at RMAT scale 24): wg_small and
@@ -571,16 +572,20 @@ constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSup
 
 template <int MODE, bool GLOBAL>
 const void* items_kernel(int cls) {
-  if constexpr (MODE != MODE_COUNT) {
-    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport>;
-  } else if constexpr (GLOBAL) {
-    return (const void*)k_count_items<MODE, GLOBAL, kOccSmall>;  // no table: LDS does not limit
+  static_assert(class_waves(CLS_WG_HUGE) == kWavesBig && class_waves(CLS_WG_GIANT) == kWavesBig &&
+                    class_waves(CLS_WG_LARGE) == kWaves && class_waves(CLS_GLOBAL) == kWaves,
+                "work-group shapes of the item classes");
+  if constexpr (GLOBAL) {  // no table: LDS does not limit
+    return (const void*)k_count_items<MODE, GLOBAL, MODE == MODE_COUNT ? kOccSmall : kOccSupport, kWaves>;
+  } else if constexpr (MODE != MODE_COUNT) {
+    if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig>;
+    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves>;
   } else {
     switch (cls) {
-      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge>;
-      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge>;
-      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant>;
-      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall>;
+      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge, kWaves>;
+      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge, kWavesBig>;
+      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant, kWavesBig>;
+      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall, kWaves>;
     }
   }
 }
@@ -621,7 +626,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (w.n_items[c] == 0) continue;
-    const unsigned grid = (unsigned)(w.n_items[c] / kWaves);
+    const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
     const bool global = c == CLS_GLOBAL;
     const void* f = global ? items_kernel<MODE, true>(c) : items_kernel<MODE, false>(c);
     const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], VALS);
@@ -629,7 +634,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const CountItem* items = w.items[c];
     void* kargs[] = {const_cast<Args*>(&A), &items};
     LaunchScope ls(kLaunchNames[MODE][c], st);
-    TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(256), kargs, lds, st));
+    TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(64 * class_waves(c)), kargs, lds, st));
   }
   TC_HIP(hipGetLastError());
 }
@@ -705,7 +710,7 @@ size_t pack_lds_bytes(uint32_t slots, bool vals) {
 }
 
 size_t items_lds_bytes(int log2S, bool vals) {
-  return sizeof(int32_t) * ((size_t)kMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * (vals ? 2 : 1)));
+  return sizeof(int32_t) * ((size_t)kItemMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * (vals ? 2 : 1)));
 }
 
 void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,

@@ -80,7 +80,8 @@ enum ItemClass : int {
   NUM_CLASSES = 7
 };
 
-constexpr int kWaves = 4;               // waves per work-group in every count launch
+constexpr int kWaves = 4;               // waves per work-group of packs, small item classes, batch units
+constexpr int kWavesBig = 8;            // waves per work-group of wg_huge / wg_giant items
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
 constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
 constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
@@ -89,6 +90,12 @@ constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + o
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
 constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte offsets into U
+
+// Waves sharing one table in a work-group of item class c: the classes whose
+// tables allow only a few work-groups per CU get twice the waves per table.
+__host__ __device__ constexpr int class_waves(int c) {
+  return (c == CLS_WG_HUGE || c == CLS_WG_GIANT) ? kWavesBig : kWaves;
+}
 
 // Slots of the LDS hash table of a row with d keys: a power of two >= 4 d
 // (load factor <= 1/4, so almost every lookup ends in its first bucket) for

@@ -261,9 +261,11 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const unsigned long long* _
   if (threadIdx.x == 0) out[c] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-__device__ __forceinline__ uint32_t wg_parts(uint64_t W) {
-  const uint64_t per = (uint64_t)kWaves * kWaveChunk;
-  return (uint32_t)(kWaves * ((W + per - 1) / per));
+// Wave items of a heavy row with W probes: a multiple of the class's waves
+// per work-group (each group of `waves` consecutive items shares one table).
+__device__ __forceinline__ uint32_t wg_parts(uint64_t W, int waves) {
+  const uint64_t per = (uint64_t)waves * kWaveChunk;
+  return (uint32_t)(waves * ((W + per - 1) / per));
 }
 
 __global__ void k_class_count(const int8_t* __restrict__ cls, int64_t n, int c,
@@ -274,7 +276,7 @@ __global__ void k_class_count(const int8_t* __restrict__ cls, int64_t n, int c,
   uint32_t v = 0;
   if (cls[b] == c) {
     if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) v = 1;
-    else v = wg_parts(tprefix[tend[b]] - tprefix[tbeg[b]]);
+    else v = wg_parts(tprefix[tend[b]] - tprefix[tbeg[b]], class_waves(c));
   }
   cnt[b] = v;
 }
