@@ -84,8 +84,8 @@ constexpr int kWaves = 4;               // waves per work-group of packs, small 
 constexpr int kWavesBig = 8;            // waves per work-group of wg_huge / wg_giant items
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
 constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
-constexpr uint64_t kHeavyMin = 4096;    // rows with fewer probes than this are packed
-constexpr uint64_t kPackTarget = 16384; // target probes per pack of light rows (one work-group)
+constexpr uint64_t kHeavyMin = 32768;   // rows with fewer probes than this are packed
+constexpr uint64_t kPackTarget = 65536; // target probes per pack of light rows (one work-group)
 constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + one row's table)
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
