@@ -220,18 +220,22 @@ void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStrea
 //     walks back over earlier tiles' published words until it meets an
 //     inclusive prefix (decoupled look-back), publishes its own inclusive
 //     prefix, and the tile writes each digit's run contiguously from LDS.
-//     A published word holds a 2-bit state and a 62-bit value in one 64-bit
-//     atomic. The wait is bounded: past the spin budget the kernel records a
-//     failure (sort_failed) and goes on, so every wave always finishes.
+//     A published word is 0 (nothing yet), an aggregate (count + 1) or an
+//     inclusive prefix (value with the top bit set), in one 32-bit atomic
+//     when the sort holds fewer than 2^31 keys, else one 64-bit atomic. The
+//     wait is bounded: past the spin budget the kernel records a failure
+//     (sort_failed) and goes on, so every wave always finishes.
 // ---------------------------------------------------------------------------
 struct NoVal {};
 
 constexpr int kSortPassesMax = 8;
-constexpr uint64_t kLbAgg = 1ull << 62;   // word holds this tile's own count
-constexpr uint64_t kLbPre = 2ull << 62;   // word holds the inclusive prefix
-constexpr uint64_t kLbVal = (1ull << 62) - 1;
 constexpr uint32_t kLbSpinMax = 1u << 16;
-constexpr int kLbWin = 8;  // predecessors read per look-back step
+constexpr int kLbWin = 4;  // predecessors read per look-back step
+
+template <class W>
+__host__ __device__ constexpr W lb_top() {
+  return (W)1 << (8 * sizeof(W) - 1);
+}
 
 // Set by a sort whose look-back ran out of its spin budget (never expected;
 // checked by the host after the sorts of a call). One flag per source file
@@ -288,16 +292,17 @@ static __global__ __launch_bounds__(256) void k_rs_buckets(uint32_t* __restrict_
   }
 }
 
-template <class K, class V, int KPT>
+template <class K, class V, int KPT, class W, int WIN>
 __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                      const V* __restrict__ vin, V* __restrict__ vout,
                                                      int64_t n, int shift, uint32_t dmask,
                                                      const uint32_t* __restrict__ bucket,
-                                                     uint64_t* __restrict__ status,
+                                                     W* __restrict__ status,
                                                      uint32_t* __restrict__ ticket) {
   constexpr int TILE = 256 * KPT;
   constexpr int WCH = 64 * KPT;  // keys of the tile each wave ranks (a contiguous quarter)
   constexpr bool HV = !std::is_same<V, NoVal>::value;
+  constexpr W TOP = lb_top<W>();
   using VS = typename std::conditional<HV, V, char>::type;
   __shared__ K s_k[TILE];
   __shared__ VS s_v[HV ? TILE : 1];
@@ -353,39 +358,39 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
   }
   // publish the tile's count, look back for the earlier tiles' total,
   // publish the inclusive prefix
-  uint64_t* my = status + (uint64_t)tile * 256 + tid;
+  W* my = status + (uint64_t)tile * 256 + tid;
   if (tile == 0) {
-    __hip_atomic_store(my, kLbPre | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(my, TOP | (W)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_goff[tid] = bucket[tid];
   } else {
-    __hip_atomic_store(my, kLbAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // walk back kLbWin predecessors per step (their words are read together):
+    __hip_atomic_store(my, (W)cnt + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // walk back WIN predecessors per step (their words are read together):
     // add counts from the nearest one until an inclusive prefix; stop at a
     // tile that has published nothing yet and read again from there
     uint64_t excl = 0;
     uint32_t spins = 0;
     int64_t j = (int64_t)tile - 1;
     while (j >= 0) {
-      uint64_t w[kLbWin];
+      W w[WIN];
 #pragma unroll
-      for (int q = 0; q < kLbWin; ++q)
+      for (int q = 0; q < WIN; ++q)
         w[q] = j - q >= 0 ? __hip_atomic_load(status + (uint64_t)(j - q) * 256 + tid, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT)
-                          : kLbPre;  // before tile 0: an inclusive prefix of 0
+                          : TOP;  // before tile 0: an inclusive prefix of 0
       int q = 0;
       bool done = false;
-      for (; q < kLbWin; ++q) {
-        const uint64_t st = w[q] & ~kLbVal;
-        if (st == 0) break;
-        excl += w[q] & kLbVal;
-        if (st == kLbPre) {
+      for (; q < WIN; ++q) {
+        if (w[q] == 0) break;
+        if (w[q] & TOP) {
+          excl += w[q] & ~TOP;
           done = true;
           break;
         }
+        excl += w[q] - 1;
       }
       if (done) break;
       j -= q;
-      if (q < kLbWin) {  // tile j has not published yet
+      if (q < WIN) {  // tile j has not published yet
         if (++spins > kLbSpinMax) {  // never expected: give up rather than hang
           atomicExch(&g_sort_failed, 1);
           break;
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    __hip_atomic_store(my, kLbPre | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(my, TOP | (W)(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_goff[tid] = bucket[tid] + (uint32_t)excl;
   }
   uint32_t tot;
@@ -424,25 +429,39 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
   }
 }
 
-// Sorts keys[0..n) by bits [bit_lo, bit_hi) (stable), carrying vals if V is
-// not NoVal. keys/vals and keys_alt/vals_alt are ping-pong buffers of n
-// elements; returns true if the sorted data ended in the *_alt buffers.
+// Default keys per thread of a sort tile for key type K and value type V:
+// tiles of 6144 4-byte, 8192 8-byte and 6144 12-byte elements (48-72 KiB of
+// LDS), the fastest measured that keep the registers of a tile without
+// spills (larger tiles halve the look-back words per key, but past these
+// sizes a wave runs out of registers).
 template <class K, class V>
-bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                hipStream_t st, const char* name) {
-  constexpr int KPT = sizeof(K) + (std::is_same<V, NoVal>::value ? 0 : sizeof(V)) > 8 ? 8 : 16;
+constexpr int rs_default_kpt() {
+  constexpr int e = (int)sizeof(K) + (std::is_same<V, NoVal>::value ? 0 : (int)sizeof(V));
+  return e <= 4 ? 24 : e <= 8 ? 32 : e <= 12 ? 24 : 16;
+}
+
+// Sorts keys[0..n) by bits [bit_lo, bit_hi) (stable), carrying vals if V is
+// not NoVal, with KPT keys per thread per tile and look-back words of type W
+// (uint32_t needs n < 2^31). keys/vals and keys_alt/vals_alt are ping-pong
+// buffers of n elements; returns true if the sorted data ended in the *_alt
+// buffers.
+template <class K, class V, int KPT, class W, int WIN = kLbWin>
+bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
+                    hipStream_t st, const char* name) {
   constexpr int TILE = 256 * KPT;
   const char* n_digits = intern_name(std::string("rs_digits:") + name);
   const char* n_pass = intern_name(std::string("rs_pass:") + name);
   if (n <= 1 || bit_hi <= bit_lo) return false;
   TC_REQUIRE(n < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW, "radix_sort: more than 2^32-1 keys");
+  TC_REQUIRE(sizeof(W) == 8 || n < ((int64_t)1 << 31), TC_EINVAL, "radix_sort: 32-bit look-back words");
   TC_REQUIRE(bit_hi - bit_lo <= 8 * kSortPassesMax, TC_EINVAL, "radix_sort: key range too wide");
   const int passes = (bit_hi - bit_lo + 7) / 8;
   const int64_t ntiles = div_up(n, TILE);
-  // per pass: ticket counter (padded to 64 words) + ntiles * 256 look-back words
-  const int64_t pass_words = 64 + ntiles * 256;
+  // per pass: ticket counter (padded to 256 bytes) + ntiles * 256 look-back words
+  const int64_t pad = 256 / (int64_t)sizeof(W);
+  const int64_t pass_words = pad + ntiles * 256;
   DevBuf ghist(sizeof(uint32_t) * 256 * kSortPassesMax);
-  DevBuf lb(sizeof(uint64_t) * (size_t)pass_words);
+  DevBuf lb(sizeof(W) * (size_t)pass_words);
   TC_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
   const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
   TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), 0, st, keys, n, bit_lo, bit_hi,
@@ -457,10 +476,10 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
     const int shift = bit_lo + 8 * p;
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
-    TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(uint64_t) * (size_t)pass_words, st));
-    uint64_t* words = lb.as<uint64_t>();
-    TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT>), dim3((unsigned)ntiles), dim3(256), 0, st, ka, kb, va, vb,
-              n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + 64,
+    TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(W) * (size_t)pass_words, st));
+    W* words = lb.as<W>();
+    TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN>), dim3((unsigned)ntiles), dim3(256), 0, st, ka, kb,
+              va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
               reinterpret_cast<uint32_t*>(words));
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
@@ -468,6 +487,15 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
     alt = !alt;
   }
   return alt;
+}
+
+template <class K, class V>
+bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
+                hipStream_t st, const char* name) {
+  constexpr int KPT = rs_default_kpt<K, V>();
+  if (n < ((int64_t)1 << 31))
+    return radix_sort_cfg<K, V, KPT, uint32_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
+  return radix_sort_cfg<K, V, KPT, uint64_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
 }
 
 // Throws TC_EDEVICE if a sort of this source file gave up waiting in its
