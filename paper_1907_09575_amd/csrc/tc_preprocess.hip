@@ -49,20 +49,54 @@ __global__ void k_canon(const int32_t* __restrict__ src, const int32_t* __restri
   keys[i] = key;
 }
 
-__global__ void k_unique_flags(const uint64_t* __restrict__ keys, int64_t m, uint64_t sent,
-                               uint32_t* __restrict__ flags) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  uint64_t k = keys[i];
-  flags[i] = (k != sent && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
-}
+// Distinct keys of a sorted key array (the sentinel marks dropped self loops).
+struct UniquePred {
+  const uint64_t* keys;
+  uint64_t sent;
+  uint64_t* out;
+  struct Item {
+    uint64_t k;
+  };
+  __device__ bool operator()(int64_t i, Item& it) const {
+    const uint64_t k = keys[i];
+    it.k = k;
+    return k != sent && (i == 0 || keys[i - 1] != k);
+  }
+  __device__ void emit(int64_t, const Item& it, uint32_t pos) const { out[pos] = it.k; }
+};
 
-template <class T>
-__global__ void k_compact(const T* __restrict__ in, const uint32_t* __restrict__ flags,
-                          const uint32_t* __restrict__ pos, int64_t m, T* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  if (flags[i]) out[pos[i]] = in[i];
+// Entry i of U (row a, column b) starts a task iff U_a has entries after i
+// and U_b is not empty (one bit per row); the task's key is b and its value
+// the probe range [i + 1, row end of a).
+struct TaskPred {
+  const uint64_t* okey;
+  int s;
+  const int64_t* row_ptr;
+  const uint64_t* nonempty;
+  uint32_t* tkey;
+  uint64_t* tval;
+  struct Item {
+    uint32_t b, end;
+  };
+  __device__ bool operator()(int64_t i, Item& it) const {
+    const uint64_t k = okey[i];
+    const int64_t a = (int64_t)(k >> s);
+    it.b = (uint32_t)(k & ((1ull << s) - 1));
+    it.end = (uint32_t)row_ptr[a + 1];
+    return (int64_t)it.end - i - 1 > 0 && ((nonempty[it.b >> 6] >> (it.b & 63)) & 1ull);
+  }
+  __device__ void emit(int64_t i, const Item& it, uint32_t pos) const {
+    tkey[pos] = it.b;
+    tval[pos] = (uint64_t)(i + 1) | ((uint64_t)it.end << 32);
+  }
+};
+
+// Bit r of the bitmap: row r of a CSR is not empty.
+__global__ __launch_bounds__(256) void k_nonempty_bits(const int64_t* __restrict__ row_ptr, int64_t n,
+                                                       uint64_t* __restrict__ bits) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t b = __ballot(r < n && row_ptr[r + 1] > row_ptr[r]);
+  if (lane_id() == 0 && r < n) bits[r >> 6] = b;
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
@@ -128,31 +162,6 @@ __global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n
 __global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32_t* __restrict__ col) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) col[i] = (int32_t)(okey[i] & ((1ull << s) - 1));
-}
-
-__global__ void k_task_flags(const uint64_t* __restrict__ okey, int64_t m, int s,
-                             const int64_t* __restrict__ row_ptr, uint32_t* __restrict__ flags) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  uint64_t k = okey[i];
-  int64_t a = (int64_t)(k >> s), b = (int64_t)(k & ((1ull << s) - 1));
-  int64_t after = row_ptr[a + 1] - i - 1;
-  int64_t db = row_ptr[b + 1] - row_ptr[b];
-  flags[i] = (after > 0 && db > 0) ? 1u : 0u;
-}
-
-__global__ void k_task_emit(const uint64_t* __restrict__ okey, int64_t m, int s,
-                            const int64_t* __restrict__ row_ptr, const uint32_t* __restrict__ flags,
-                            const uint32_t* __restrict__ pos, uint32_t* __restrict__ tkey,
-                            uint64_t* __restrict__ tval) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m || !flags[i]) return;
-  uint64_t k = okey[i];
-  int64_t a = (int64_t)(k >> s);
-  uint32_t b = (uint32_t)(k & ((1ull << s) - 1));
-  uint32_t t = pos[i];
-  tkey[t] = b;
-  tval[t] = (uint64_t)(i + 1) | ((uint64_t)row_ptr[a + 1] << 32);
 }
 
 __global__ void k_task_split(const uint64_t* __restrict__ tval, int64_t T,
@@ -435,10 +444,9 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   g->sbits = s;
   const uint64_t sent = (2 * s >= 64) ? ~0ull : ((1ull << (2 * s)) - 1);
 
-  DevBuf dscal(64);  // device scalars: [0] err (int), [8] m (u32 total), [16] wplus, [24] maxd
+  DevBuf dscal(64);  // device scalars: [0] err (int), [16] wplus, [24] maxd
   TC_HIP(hipMemsetAsync(dscal.p, 0, 64, st));
   int* d_err = reinterpret_cast<int*>(dscal.as<char>());
-  uint32_t* d_tot32 = reinterpret_cast<uint32_t*>(dscal.as<char>() + 8);
   unsigned long long* d_wplus = reinterpret_cast<unsigned long long*>(dscal.as<char>() + 16);
   unsigned int* d_maxd = reinterpret_cast<unsigned int*>(dscal.as<char>() + 24);
   uint64_t* d_tot64 = reinterpret_cast<uint64_t*>(dscal.as<char>() + 32);
@@ -458,20 +466,13 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
                                            m_raw, 0, 2 * s, st, "dedup");
     const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
-    DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
-    DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m_raw, 1));
-    if (m_raw > 0) {
-      TC_LAUNCH("unique_flags", k_unique_flags, dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted, m_raw, sent,
-                         flags.as<uint32_t>());
-      device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, d_tot32, st);
-      m = read_scalar(d_tot32, st);
-    }
-    TC_REQUIRE(m <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
-    E.alloc(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
-    if (m > 0)
-      TC_LAUNCH("compact", (k_compact<uint64_t>), dim3(grid_for(m_raw)), dim3(kT), 0, st, sorted,
-                         flags.as<uint32_t>(), pos.as<uint32_t>(), m_raw, E.as<uint64_t>());
-    TC_HIP(hipGetLastError());
+    UniquePred up{sorted, sent, nullptr};
+    m = compact("dedup", m_raw, up, [&](int64_t total, UniquePred& p) {
+      TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
+      E.alloc(sizeof(uint64_t) * (size_t)total);
+      p.out = E.as<uint64_t>();
+    }, st);
+    if (m == 0) E.alloc(sizeof(uint64_t));
   }
   g->m = m;
 
@@ -537,22 +538,21 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   // ---- 5: tasks grouped by hashed row b -----------------------------------
   TaskLists tl;
   {
-    DevBuf flags(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
-    DevBuf pos(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1));
     int64_t T = 0;
+    DevBuf tk, tv;
     if (m > 0) {
-      TC_LAUNCH("task_flags", k_task_flags, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
-                flags.as<uint32_t>());
-      device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), m, d_tot32, st);
-      T = read_scalar(d_tot32, st);
+      DevBuf ne(sizeof(uint64_t) * (size_t)div_up(n, 64));
+      TC_LAUNCH("nonempty_bits", k_nonempty_bits, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n,
+                ne.as<uint64_t>());
+      TaskPred tp{okey, s, g->row_ptr, ne.as<uint64_t>(), nullptr, nullptr};
+      T = compact("tasks", m, tp, [&](int64_t total, TaskPred& p) {
+        tk.alloc(sizeof(uint32_t) * (size_t)total);
+        tv.alloc(sizeof(uint64_t) * (size_t)total);
+        p.tkey = tk.as<uint32_t>();
+        p.tval = tv.as<uint64_t>();
+      }, st);
     }
-    if (T > 0) {
-      DevBuf tk(sizeof(uint32_t) * (size_t)T), tv(sizeof(uint64_t) * (size_t)T);
-      TC_LAUNCH("task_emit", k_task_emit, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->row_ptr,
-                flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
-      TC_HIP(hipGetLastError());
-      sort_tasks(tl, tk.as<uint32_t>(), tv.as<uint64_t>(), T, n, s, st, "tasks");
-    }
+    if (T > 0) sort_tasks(tl, tk.as<uint32_t>(), tv.as<uint64_t>(), T, n, s, st, "tasks");
     g->wedges_plus = (int64_t)read_scalar(reinterpret_cast<uint64_t*>(d_wplus), st);
     g->max_dplus = (int64_t)read_scalar(reinterpret_cast<uint32_t*>(d_maxd), st);
   }

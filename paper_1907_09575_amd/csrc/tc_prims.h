@@ -209,6 +209,94 @@ void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStrea
 }
 
 // ---------------------------------------------------------------------------
+// Stable stream compaction in two reads of the input and no per-element
+// flag or position arrays: k_compact_count counts the selected elements of
+// each tile (4096 elements: each wave a contiguous quarter, 16 rows of 64),
+// an exclusive scan of the tile counts gives every tile's output base, and
+// k_compact_emit evaluates the predicate again and hands each selected
+// element its output position (tile base + earlier waves + running count +
+// ballot rank), so the output keeps the input order.
+//
+// P is a functor with
+//   __device__ bool operator()(int64_t i, Item& it) const  (select i; fill it)
+//   __device__ void emit(int64_t i, const Item& it, uint32_t pos) const
+// and a nested type Item (data the emit needs, loaded with the predicate).
+// ---------------------------------------------------------------------------
+constexpr int kCompactRows = 16;
+constexpr int kCompactTile = 256 * kCompactRows;
+
+template <class P>
+__global__ __launch_bounds__(256) void k_compact_count(int64_t m, P pred, uint32_t* __restrict__ tile_cnt) {
+  __shared__ uint32_t s_w[4];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t wbase = (int64_t)blockIdx.x * kCompactTile + (int64_t)wave * (64 * kCompactRows);
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kCompactRows; ++j) {
+    const int64_t i = wbase + 64 * j + lane;
+    typename P::Item it;
+    const bool sel = i < m && pred(i, it);
+    c += (uint32_t)__popcll(__ballot(sel));
+  }
+  if (lane == 0) s_w[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_compact_emit(int64_t m, P pred, const uint32_t* __restrict__ tile_off) {
+  __shared__ uint32_t s_w[4];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t wbase = (int64_t)blockIdx.x * kCompactTile + (int64_t)wave * (64 * kCompactRows);
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  typename P::Item it[kCompactRows];
+  uint64_t bal[kCompactRows];
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kCompactRows; ++j) {
+    const int64_t i = wbase + 64 * j + lane;
+    const bool sel = i < m && pred(i, it[j]);
+    bal[j] = __ballot(sel);
+    c += (uint32_t)__popcll(bal[j]);
+  }
+  if (lane == 0) s_w[wave] = c;
+  __syncthreads();
+  uint32_t base = tile_off[blockIdx.x];
+  for (int w = 0; w < wave; ++w) base += s_w[w];
+#pragma unroll
+  for (int j = 0; j < kCompactRows; ++j) {
+    if ((bal[j] >> lane) & 1ull) pred.emit(wbase + 64 * j + lane, it[j], base + (uint32_t)__popcll(bal[j] & lt_mask));
+    base += (uint32_t)__popcll(bal[j]);
+  }
+}
+
+// Compacts [0, m) under predicate `pred` (see above) and returns the number
+// of selected elements. `prepare(total, pred)` runs on the host between the
+// count and the emit (to allocate the output and point pred at it); nothing
+// is emitted when total is 0. Synchronises st once. m < 2^32.
+template <class P, class F>
+int64_t compact(const char* name, int64_t m, P pred, F&& prepare, hipStream_t st) {
+  if (m <= 0) return 0;
+  const int64_t tiles = div_up(m, kCompactTile);
+  DevBuf cnt(sizeof(uint32_t) * (size_t)tiles), off(sizeof(uint32_t) * (size_t)tiles);
+  DevBuf tot(sizeof(uint32_t));
+  const char* n_count = intern_name(std::string("compact_count:") + name);
+  const char* n_emit = intern_name(std::string("compact_emit:") + name);
+  TC_LAUNCH(n_count, (k_compact_count<P>), dim3((unsigned)tiles), dim3(256), 0, st, m, pred,
+            cnt.as<uint32_t>());
+  device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), off.as<uint32_t>(), tiles, tot.as<uint32_t>(), st);
+  uint32_t total = 0;
+  TC_HIP(hipMemcpyAsync(&total, tot.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipStreamSynchronize(st));
+  if (total == 0) return 0;
+  prepare((int64_t)total, pred);
+  TC_LAUNCH(n_emit, (k_compact_emit<P>), dim3((unsigned)tiles), dim3(256), 0, st, m, pred,
+            off.as<uint32_t>());
+  TC_HIP(hipGetLastError());
+  return (int64_t)total;
+}
+
+// ---------------------------------------------------------------------------
 // Stable LSD radix sort, 8-bit digits, one kernel per digit.
 // (1) One read of the keys counts the digits of every pass; an exclusive scan
 //     of each pass's 256 counts gives the start of every digit's bucket.
@@ -259,25 +347,48 @@ __device__ __forceinline__ uint64_t rs_peers(uint32_t d, bool valid) {
   return peers;
 }
 
+// Digit counts of every pass in one read of the keys. Each thread loads 8
+// keys before counting them (memory parallelism), and the work-group keeps 8
+// copies of each histogram, lane l counting into copy l % 8, so that the many
+// equal digits of skewed keys (the high bits of power-law vertex ids) do not
+// serialise on one LDS word. Dynamic LDS: passes * 256 * 8 words.
+constexpr int kDigitCopies = 8;
+constexpr int kDigitBatch = 8;
+
 template <class K>
 __global__ __launch_bounds__(256) void k_rs_digits(const K* __restrict__ kin, int64_t n, int bit_lo,
                                                    int bit_hi, uint32_t* __restrict__ ghist) {
-  __shared__ uint32_t h[kSortPassesMax][256];
+  extern __shared__ uint32_t h_dyn[];  // [pass][digit][copy]
   const int tid = threadIdx.x;
   const int passes = (bit_hi - bit_lo + 7) / 8;
-  for (int p = 0; p < passes; ++p) h[p][tid] = 0;
+  for (int x = tid; x < passes * 256 * kDigitCopies; x += 256) h_dyn[x] = 0;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
-    const K k = kin[i];
-    for (int p = 0; p < passes; ++p) {
-      const int shift = bit_lo + 8 * p;
-      const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
-      atomicAdd(&h[p][rs_digit(k, shift, (1u << bits) - 1u)], 1u);
+  const int cp = tid & (kDigitCopies - 1);
+  const int64_t stride = (int64_t)gridDim.x * 256 * kDigitBatch;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * kDigitBatch + tid; base < n; base += stride) {
+    K k[kDigitBatch];
+#pragma unroll
+    for (int b = 0; b < kDigitBatch; ++b) {
+      const int64_t i = base + (int64_t)b * 256;
+      k[b] = i < n ? kin[i] : K(0);
+    }
+#pragma unroll
+    for (int b = 0; b < kDigitBatch; ++b) {
+      if (base + (int64_t)b * 256 >= n) break;
+      for (int p = 0; p < passes; ++p) {
+        const int shift = bit_lo + 8 * p;
+        const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+        atomicAdd(&h_dyn[(p * 256 + rs_digit(k[b], shift, (1u << bits) - 1u)) * kDigitCopies + cp], 1u);
+      }
     }
   }
   __syncthreads();
-  for (int p = 0; p < passes; ++p)
-    if (h[p][tid]) atomicAdd(&ghist[p * 256 + tid], h[p][tid]);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int c = 0; c < kDigitCopies; ++c) t += h_dyn[(p * 256 + tid) * kDigitCopies + c];
+    if (t) atomicAdd(&ghist[p * 256 + tid], t);
+  }
 }
 
 // In-place exclusive scan of each pass's 256 digit counts (one work-group).
@@ -464,7 +575,8 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
   DevBuf lb(sizeof(W) * (size_t)pass_words);
   TC_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
   const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
-  TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), 0, st, keys, n, bit_lo, bit_hi,
+  TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256),
+            sizeof(uint32_t) * 256 * kDigitCopies * (size_t)passes, st, keys, n, bit_lo, bit_hi,
             ghist.as<uint32_t>());
   TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, ghist.as<uint32_t>(), passes);
   K* ka = keys;
