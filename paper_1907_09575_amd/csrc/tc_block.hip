@@ -158,12 +158,12 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
                 flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
       TC_HIP(hipGetLastError());
       const int bits = std::max(1, ceil_log2_u64((uint64_t)H.nloc));
-      sort_tasks(tl, tk.as<uint32_t>(), tv.as<uint64_t>(), T, H.nloc, bits, st, "block_tasks");
+      sort_tasks(tl, tk, tv, T, H.nloc, bits, st, "block_tasks");
     }
   }
   WorkSet w;
   build_work(w, own, H.nloc, H.row_ptr.as<int64_t>(), T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
-             tl.start.as<uint32_t>(), tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), st);
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st);
   CountView v{H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), P.col.as<int32_t>(), P.nnz, &w, q,
               (x + y) % q};
   launch_count(v, MODE_BLOCK, d_count, nullptr, d_per_shift, st);

@@ -303,12 +303,12 @@ inline CountView graph_view(const Graph& g) {
 
 // ---- work-set construction (tc_preprocess.hip) --------------------------------
 // From T tasks in hashed-row order (tb_row = row of each task, tb_ptr = row
-// bounds, tb_start / tb_len = first probe and probe count, tb_prefix = their
-// exclusive prefix with the total at [T]): classes, class-major order, packs
-// and items. hrow_ptr gives |U_b| of every hashed row.
+// bounds, tb_val = first probe | end << 32 of each task, tb_prefix = the
+// exclusive prefix of their probe counts with the total at [T]): classes,
+// class-major order, packs and items. hrow_ptr gives |U_b| of every hashed row.
 void build_work(WorkSet& w, Owned& own, int64_t nrows, const int64_t* hrow_ptr, int64_t T,
-                const uint32_t* tb_row, const int64_t* tb_ptr, const uint32_t* tb_start,
-                const uint32_t* tb_len, const uint64_t* tb_prefix, hipStream_t st);
+                const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
+                const uint64_t* tb_prefix, hipStream_t st);
 
 
 inline int ceil_log2_u64(uint64_t x) {

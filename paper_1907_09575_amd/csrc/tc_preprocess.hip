@@ -164,16 +164,6 @@ __global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32
   if (i < m) col[i] = (int32_t)(okey[i] & ((1ull << s) - 1));
 }
 
-__global__ void k_task_split(const uint64_t* __restrict__ tval, int64_t T,
-                             uint32_t* __restrict__ tstart, uint32_t* __restrict__ tlen) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T) return;
-  uint64_t v = tval[t];
-  uint32_t st = (uint32_t)v, en = (uint32_t)(v >> 32);
-  tstart[t] = st;
-  tlen[t] = en - st;
-}
-
 // W+ = sum_a C(d+(a), 2) and max d+(a).
 __global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ row_ptr, int64_t n,
                                                    unsigned long long* __restrict__ wplus,
@@ -277,60 +267,91 @@ __device__ __forceinline__ uint32_t wg_parts(uint64_t W, int waves) {
   return (uint32_t)(waves * ((W + per - 1) / per));
 }
 
-__global__ void k_class_count(const int8_t* __restrict__ cls, int64_t n, int c,
-                              const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
-                              const uint64_t* __restrict__ tprefix, uint32_t* __restrict__ cnt) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  uint32_t v = 0;
-  if (cls[b] == c) {
-    if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) v = 1;
-    else v = wg_parts(tprefix[tend[b]] - tprefix[tbeg[b]], class_waves(c));
+// Rows with work (class >= 0): key = class, value = row (compacted in row
+// order, then stably sorted by class: the class-major row order).
+struct WorkRowPred {
+  const int8_t* cls;
+  uint32_t* key;
+  uint32_t* row;
+  struct Item {
+    int8_t c;
+  };
+  __device__ bool operator()(int64_t b, Item& it) const {
+    it.c = cls[b];
+    return it.c >= 0;
   }
-  cnt[b] = v;
-}
-
-// Tasks of row b if it is in class c, else 0 (b-order task bounds).
-__global__ void k_class_tasks(const int8_t* __restrict__ cls, int64_t n, int c,
-                              const int64_t* __restrict__ tb_ptr, uint32_t* __restrict__ cnt) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < n) cnt[b] = cls[b] == c ? (uint32_t)(tb_ptr[b + 1] - tb_ptr[b]) : 0u;
-}
-
-// Class-major task range of each row of class c: base + its class-local offset.
-__global__ void k_row_begin(const int8_t* __restrict__ cls, int64_t n, int c,
-                            const uint32_t* __restrict__ offs, uint32_t base,
-                            const int64_t* __restrict__ tb_ptr, uint32_t* __restrict__ tbeg,
-                            uint32_t* __restrict__ tend) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
-  const int cb = cls[b];
-  if (cb == c) {
-    tbeg[b] = base + offs[b];
-    tend[b] = base + offs[b] + (uint32_t)(tb_ptr[b + 1] - tb_ptr[b]);
-  } else if (cb < 0 && c == 0) {
-    tbeg[b] = 0;  // no tasks
-    tend[b] = 0;
+  __device__ void emit(int64_t b, const Item& it, uint32_t pos) const {
+    key[pos] = (uint32_t)it.c;
+    row[pos] = (uint32_t)b;
   }
+};
+
+// Per class-major row i (row b = crow[i]): its number of tasks, its probes
+// W_b, and its wave items (item classes only).
+struct CmTasks {
+  const uint32_t* crow;
+  const int64_t* tptr;
+  __device__ uint32_t operator()(int64_t i) const {
+    const uint32_t b = crow[i];
+    return (uint32_t)(tptr[b + 1] - tptr[b]);
+  }
+};
+struct CmProbes {
+  const uint32_t* crow;
+  const int64_t* tptr;
+  const uint64_t* tprefix;
+  __device__ uint64_t operator()(int64_t i) const {
+    const uint32_t b = crow[i];
+    return tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+  }
+};
+struct CmItems {
+  const uint32_t* crow;
+  const int8_t* cls;
+  const int64_t* tptr;
+  const uint64_t* tprefix;
+  __device__ uint32_t operator()(int64_t i) const {
+    const uint32_t b = crow[i];
+    const int c = cls[b];
+    if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) return 0;
+    return wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]], class_waves(c));
+  }
+};
+
+// Task range of every row with work in the class-major task order, and the
+// row's class-major position.
+__global__ void k_cm_place(const uint32_t* __restrict__ crow, int64_t R, const uint32_t* __restrict__ tsc,
+                           uint32_t* __restrict__ tbeg, uint32_t* __restrict__ tend,
+                           uint32_t* __restrict__ cm_pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  const uint32_t b = crow[i];
+  tbeg[b] = tsc[i];
+  tend[b] = tsc[i + 1];
+  cm_pos[b] = (uint32_t)i;
 }
 
-// Move task t (b order) to its class-major position.
+// Task t (hashed-row order) to its class-major slot: first probe and the
+// class-major exclusive prefix (the row's base plus the prefix within the
+// row, which keeps its order).
 __global__ void k_task_permute(int64_t T, const uint32_t* __restrict__ tb_row,
-                               const int64_t* __restrict__ tb_ptr, const uint32_t* __restrict__ tbeg,
-                               const uint32_t* __restrict__ tb_start, const uint32_t* __restrict__ tb_len,
-                               uint32_t* __restrict__ tstart, uint32_t* __restrict__ tlen) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                               const int64_t* __restrict__ tb_ptr, const uint64_t* __restrict__ tb_val,
+                               const uint64_t* __restrict__ tb_prefix, const uint32_t* __restrict__ tbeg,
+                               const uint32_t* __restrict__ cm_pos, const uint64_t* __restrict__ wsc,
+                               uint32_t* __restrict__ tstart, uint64_t* __restrict__ tprefix) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const uint32_t b = tb_row[t];
-  const int64_t nt = (int64_t)tbeg[b] + (t - tb_ptr[b]);
-  tstart[nt] = tb_start[t];
-  tlen[nt] = tb_len[t];
+  const int64_t p0 = tb_ptr[b];
+  const int64_t nt = (int64_t)tbeg[b] + (t - p0);
+  tstart[nt] = (uint32_t)tb_val[t];
+  tprefix[nt] = wsc[cm_pos[b]] + (tb_prefix[t] - tb_prefix[p0]);
 }
 
-__global__ void k_class_rows(const int8_t* __restrict__ cls, int64_t n, int c,
-                             const uint32_t* __restrict__ offs, int32_t* __restrict__ rows) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < n && cls[b] == c) rows[offs[b]] = (int32_t)b;
+// Values of a device array at NUM_CLASSES + 1 positions (class boundaries).
+template <class T>
+__global__ void k_gather_at(const T* __restrict__ a, const int64_t* __restrict__ at, int k, T* __restrict__ out) {
+  if ((int)threadIdx.x < k) out[threadIdx.x] = a[at[threadIdx.x]];
 }
 
 __global__ void k_rows_work(const int32_t* __restrict__ rows, int64_t nr,
@@ -368,22 +389,26 @@ __global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* 
 // One thread per wave item of a work-group class: find its row b (upper bound
 // in the per-row item offsets), cut the row's probe range evenly and find the
 // task holding the first probe.
-__global__ void k_emit_items(const uint32_t* __restrict__ offs, int64_t n, int64_t total,
-                             const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
-                             const uint64_t* __restrict__ tprefix,
+// Wave items of the nr class-major rows crow[0..nr) of one class: offs
+// (nr + 1 entries, absolute) is the exclusive prefix of their item counts;
+// item j (0 <= j < total) is part idx of the row whose range holds offs[0] + j.
+__global__ void k_emit_items(const uint32_t* __restrict__ offs, const uint32_t* __restrict__ crow, int64_t nr,
+                             int64_t total, const uint32_t* __restrict__ tbeg,
+                             const uint32_t* __restrict__ tend, const uint64_t* __restrict__ tprefix,
                              const int64_t* __restrict__ row_ptr, CountItem* __restrict__ items) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= total) return;
-  // largest b with offs[b] <= j (offs has n + 1 entries, non-decreasing)
-  int64_t lo = 0, hi = n;  // invariant offs[lo] <= j < offs[hi]
+  const int64_t target = (int64_t)offs[0] + j;
+  // largest r with offs[r] <= target (every row has at least one item)
+  int64_t lo = 0, hi = nr;  // invariant offs[lo] <= target < offs[hi]
   while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)offs[mid] <= j) lo = mid;
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)offs[mid] <= target) lo = mid;
     else hi = mid;
   }
-  const int64_t b = lo;
-  const uint64_t parts = offs[b + 1] - offs[b];
-  const uint64_t idx = (uint64_t)(j - (int64_t)offs[b]);
+  const int64_t b = crow[lo];
+  const uint64_t parts = offs[lo + 1] - offs[lo];
+  const uint64_t idx = (uint64_t)(target - (int64_t)offs[lo]);
   const int64_t t_lo = tbeg[b], t_hi = tend[b];
   const uint64_t P0 = tprefix[t_lo];
   const uint64_t W = tprefix[t_hi] - P0;
@@ -552,7 +577,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
         p.tval = tv.as<uint64_t>();
       }, st);
     }
-    if (T > 0) sort_tasks(tl, tk.as<uint32_t>(), tv.as<uint64_t>(), T, n, s, st, "tasks");
+    if (T > 0) sort_tasks(tl, tk, tv, T, n, s, st, "tasks");
     g->wedges_plus = (int64_t)read_scalar(reinterpret_cast<uint64_t*>(d_wplus), st);
     g->max_dplus = (int64_t)read_scalar(reinterpret_cast<uint32_t*>(d_maxd), st);
   }
@@ -561,7 +586,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
   // ---- 6: work classes ------------------------------------------------------
   build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
-             tl.start.as<uint32_t>(), tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), st);
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st);
   check_sorts(st);
   g->arena_bytes = g->owned.bytes;
   return g.release();
@@ -569,7 +594,16 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
 void check_task_sorts(hipStream_t st) { check_sorts(st); }
 
-void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
+// Probes of a task from its (first probe | end << 32) value.
+struct TaskLenLoad {
+  const uint64_t* val;
+  __device__ uint64_t operator()(int64_t t) const {
+    const uint64_t v = val[t];
+    return (uint64_t)((uint32_t)(v >> 32) - (uint32_t)v);
+  }
+};
+
+void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows, int key_bits,
                 hipStream_t st, const char* name) {
   tl.T = T;
   tl.ptr.alloc(sizeof(int64_t) * (size_t)(nrows + 1));
@@ -579,28 +613,24 @@ void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nr
     return;
   }
   tl.row.alloc(sizeof(uint32_t) * (size_t)T);
-  tl.start.alloc(sizeof(uint32_t) * (size_t)T);
-  tl.len.alloc(sizeof(uint32_t) * (size_t)T);
+  tl.val.alloc(sizeof(uint64_t) * (size_t)T);
   tl.prefix.alloc(sizeof(uint64_t) * (size_t)(T + 1));
-  DevBuf tv2(sizeof(uint64_t) * (size_t)T);
-  // the row array doubles as the key ping-pong buffer
-  bool alt = radix_sort<uint32_t, uint64_t>(tk, tl.row.as<uint32_t>(), tv, tv2.as<uint64_t>(), T, 0,
-                                            key_bits, st, name);
-  const uint64_t* sval = alt ? tv2.as<uint64_t>() : tv;
-  if (!alt)
-    TC_HIP(hipMemcpyAsync(tl.row.p, tk, sizeof(uint32_t) * (size_t)T, hipMemcpyDeviceToDevice, st));
-  TC_LAUNCH("task_split", k_task_split, dim3(grid_for(T)), dim3(kT), 0, st, sval, T,
-            tl.start.as<uint32_t>(), tl.len.as<uint32_t>());
-  device_excl_scan<uint32_t, uint64_t>(tl.len.as<uint32_t>(), tl.prefix.as<uint64_t>(), T,
-                                       tl.prefix.as<uint64_t>() + T, st);
+  const bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tl.row.as<uint32_t>(), tv.as<uint64_t>(),
+                                                  tl.val.as<uint64_t>(), T, 0, key_bits, st, name);
+  if (!alt) {  // sorted data ended in the input buffers: take them over
+    tl.row.swap(tk);
+    tl.val.swap(tv);
+  }
+  device_excl_scan_f<uint64_t>(TaskLenLoad{tl.val.as<uint64_t>()}, tl.prefix.as<uint64_t>(), T,
+                               tl.prefix.as<uint64_t>() + T, st);
   TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nrows + 1)), dim3(kT), 0, st,
             tl.row.as<uint32_t>(), T, 0, nrows, tl.ptr.as<int64_t>());
   TC_HIP(hipGetLastError());
 }
 
 void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int64_t T,
-                const uint32_t* tb_row, const int64_t* tb_ptr, const uint32_t* tb_start,
-                const uint32_t* tb_len, const uint64_t* tb_prefix, hipStream_t st) {
+                const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
+                const uint64_t* tb_prefix, hipStream_t st) {
   w.nrows = n;
   w.n_tasks = T;
   w.tbeg = own.alloc<uint32_t>(n);
@@ -610,9 +640,10 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   DevBuf dscal(64);
   uint32_t* d_tot32 = dscal.as<uint32_t>();
   uint64_t* d_tot64 = reinterpret_cast<uint64_t*>(dscal.as<char>() + 32);
+  // rows without tasks keep the empty range [0, 0)
+  TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tbeg, n, 0u);
+  TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tend, n, 0u);
   if (T == 0) {
-    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tbeg, n, 0u);
-    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, w.tend, n, 0u);
     TC_HIP(hipMemsetAsync(w.tprefix, 0, sizeof(uint64_t), st));
     w.probes = 0;
     return;
@@ -626,27 +657,95 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   TC_HIP(hipGetLastError());
   int h_cl[NUM_CLASSES];
   TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
-  // class-major task order: the rows of class 0 (ascending b), then class 1,
+
+  // class-major row order: the rows of class 0 (ascending b), then class 1,
   // ...; each row keeps its tasks in b order, so every class - and every pack
   // of consecutive rows of a class - owns one contiguous task range
+  DevBuf ckey, crow_in;
+  WorkRowPred wp{cls.as<int8_t>(), nullptr, nullptr};
+  const int64_t R = compact("work_rows", n, wp, [&](int64_t total, WorkRowPred& p) {
+    ckey.alloc(sizeof(uint32_t) * (size_t)total);
+    crow_in.alloc(sizeof(uint32_t) * (size_t)total);
+    p.key = ckey.as<uint32_t>();
+    p.row = crow_in.as<uint32_t>();
+  }, st);
+  TC_REQUIRE(R > 0, TC_EDEVICE, "build_work: tasks but no row with work");
+  uint32_t* crow = reinterpret_cast<uint32_t*>(own.alloc<int32_t>(R));  // pack classes keep their rows
   {
-    DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
-    uint32_t base = 0;
-    for (int c = 0; c < NUM_CLASSES; ++c) {
-      TC_LAUNCH("class_tasks", k_class_tasks, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                tb_ptr, cnt.as<uint32_t>());
-      device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
-                                           offs.as<uint32_t>() + n, st);
-      TC_LAUNCH("row_begin", k_row_begin, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                offs.as<uint32_t>(), base, tb_ptr, w.tbeg, w.tend);
-      base += read_scalar(offs.as<uint32_t>() + n, st);
-    }
-    TC_REQUIRE((int64_t)base == T, TC_EDEVICE, "build_work: class-major task order lost tasks");
-    DevBuf tlen(sizeof(uint32_t) * (size_t)T);
-    TC_LAUNCH("task_permute", k_task_permute, dim3(grid_for(T)), dim3(kT), 0, st, T, tb_row, tb_ptr,
-              w.tbeg, tb_start, tb_len, w.tstart, tlen.as<uint32_t>());
-    device_excl_scan<uint32_t, uint64_t>(tlen.as<uint32_t>(), w.tprefix, T, w.tprefix + T, st);
+    DevBuf ckey2(sizeof(uint32_t) * (size_t)R);
+    const bool alt = radix_sort<uint32_t, uint32_t>(ckey.as<uint32_t>(), ckey2.as<uint32_t>(),
+                                                    crow_in.as<uint32_t>(), crow, R, 0, 3, st, "classes");
+    if (!alt) TC_HIP(hipMemcpyAsync(crow, crow_in.p, sizeof(uint32_t) * (size_t)R, hipMemcpyDeviceToDevice, st));
+    const uint32_t* skey = alt ? ckey2.as<uint32_t>() : ckey.as<uint32_t>();
+    DevBuf cptr(sizeof(int64_t) * (NUM_CLASSES + 1));
+    TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(1), dim3(kT), 0, st, skey, R, 0, (int64_t)NUM_CLASSES,
+              cptr.as<int64_t>());
+    // per class-major row: exclusive prefixes of tasks, probes and items
+    DevBuf tsc(sizeof(uint32_t) * (size_t)(R + 1)), wsc(sizeof(uint64_t) * (size_t)(R + 1));
+    DevBuf usc(sizeof(uint32_t) * (size_t)(R + 1));
+    device_excl_scan_f<uint32_t>(CmTasks{crow, tb_ptr}, tsc.as<uint32_t>(), R, tsc.as<uint32_t>() + R, st);
+    device_excl_scan_f<uint64_t>(CmProbes{crow, tb_ptr, tb_prefix}, wsc.as<uint64_t>(), R,
+                                 wsc.as<uint64_t>() + R, st);
+    device_excl_scan_f<uint32_t>(CmItems{crow, cls.as<int8_t>(), tb_ptr, tb_prefix}, usc.as<uint32_t>(), R,
+                                 usc.as<uint32_t>() + R, st);
+    DevBuf cm_pos(sizeof(uint32_t) * (size_t)n);
+    TC_LAUNCH("cm_place", k_cm_place, dim3(grid_for(R)), dim3(kT), 0, st, crow, R, tsc.as<uint32_t>(), w.tbeg,
+              w.tend, cm_pos.as<uint32_t>());
+    TC_LAUNCH("task_permute", k_task_permute, dim3(grid_for(T)), dim3(kT), 0, st, T, tb_row, tb_ptr, tb_val,
+              tb_prefix, w.tbeg, cm_pos.as<uint32_t>(), wsc.as<uint64_t>(), w.tstart, w.tprefix);
+    TC_HIP(hipMemcpyAsync(w.tprefix + T, tb_prefix + T, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    // class boundaries and the item offsets there
+    DevBuf ub(sizeof(uint32_t) * (NUM_CLASSES + 1));
+    TC_LAUNCH("gather_at", (k_gather_at<uint32_t>), dim3(1), dim3(64), 0, st, usc.as<uint32_t>(),
+              cptr.as<int64_t>(), NUM_CLASSES + 1, ub.as<uint32_t>());
+    int64_t h_cp[NUM_CLASSES + 1];
+    uint32_t h_ub[NUM_CLASSES + 1], h_tt = 0;
+    TC_HIP(hipMemcpyAsync(h_cp, cptr.p, sizeof(h_cp), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipMemcpyAsync(h_ub, ub.p, sizeof(h_ub), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipMemcpyAsync(&h_tt, tsc.as<uint32_t>() + R, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipStreamSynchronize(st));
+    TC_REQUIRE((int64_t)h_tt == T && h_cp[NUM_CLASSES] == R, TC_EDEVICE,
+               "build_work: class-major task order lost tasks");
     TC_HIP(hipGetLastError());
+
+    for (int c = 0; c < NUM_CLASSES; ++c) {
+      w.cls_log2S[c] = h_cl[c];
+      const int64_t r0 = h_cp[c], nr = h_cp[c + 1] - h_cp[c];
+      if (nr == 0) continue;
+      if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
+        int32_t* rows = reinterpret_cast<int32_t*>(crow + r0);
+        const int64_t total = nr;
+        DevBuf wk(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
+        DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
+        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, w.tbeg,
+                  w.tend, w.tprefix, hrow_ptr, wk.as<uint64_t>(), sl.as<uint32_t>());
+        device_excl_scan<uint64_t, uint64_t>(wk.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
+        device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
+        DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
+        TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
+                  psl.as<uint32_t>(), total, pf.as<uint32_t>());
+        device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
+        const int64_t np = read_scalar(d_tot32, st);
+        uint32_t* pack_ptr = own.alloc<uint32_t>(np + 1);
+        TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
+                  pp.as<uint32_t>(), total, pack_ptr, np);
+        TC_HIP(hipGetLastError());
+        w.pack_rows[c] = rows;
+        w.pack_ptr[c] = pack_ptr;
+        w.n_pack_rows[c] = total;
+        w.n_packs[c] = np;
+        w.pack_log2S[c] = h_cl[c];
+      } else {
+        const int64_t total = (int64_t)h_ub[c + 1] - (int64_t)h_ub[c];
+        if (total == 0) continue;
+        CountItem* items = own.alloc<CountItem>(total);
+        TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, usc.as<uint32_t>() + r0,
+                  crow + r0, nr, total, w.tbeg, w.tend, w.tprefix, hrow_ptr, items);
+        TC_HIP(hipGetLastError());
+        w.items[c] = items;
+        w.n_items[c] = total;
+      }
+    }
   }
   {
     const int64_t nb = (int64_t)grid_for(n);
@@ -659,48 +758,6 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     TC_HIP(hipGetLastError());
     TC_HIP(hipMemcpyAsync(&w.cls_stats[0][0], sums.p, sizeof(w.cls_stats), hipMemcpyDeviceToHost, st));
     TC_HIP(hipStreamSynchronize(st));
-  }
-  DevBuf cnt(sizeof(uint32_t) * (size_t)n), offs(sizeof(uint32_t) * (size_t)(n + 1));
-  for (int c = 0; c < NUM_CLASSES; ++c) {
-    w.cls_log2S[c] = h_cl[c];
-    TC_LAUNCH("class_count", k_class_count, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-              w.tbeg, w.tend, w.tprefix, cnt.as<uint32_t>());
-    device_excl_scan<uint32_t, uint32_t>(cnt.as<uint32_t>(), offs.as<uint32_t>(), n,
-                                         offs.as<uint32_t>() + n, st);
-    const int64_t total = read_scalar(offs.as<uint32_t>() + n, st);
-    if (total == 0) continue;
-    if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
-      int32_t* rows = own.alloc<int32_t>(total);
-      TC_LAUNCH("class_rows", k_class_rows, dim3(grid_for(n)), dim3(kT), 0, st, cls.as<int8_t>(), n, c,
-                offs.as<uint32_t>(), rows);
-      DevBuf wk(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
-      DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
-      TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, w.tbeg,
-                w.tend, w.tprefix, hrow_ptr, wk.as<uint64_t>(), sl.as<uint32_t>());
-      device_excl_scan<uint64_t, uint64_t>(wk.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
-      device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
-      DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
-      TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
-                psl.as<uint32_t>(), total, pf.as<uint32_t>());
-      device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
-      const int64_t np = read_scalar(d_tot32, st);
-      uint32_t* pack_ptr = own.alloc<uint32_t>(np + 1);
-      TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
-                pp.as<uint32_t>(), total, pack_ptr, np);
-      TC_HIP(hipGetLastError());
-      w.pack_rows[c] = rows;
-      w.pack_ptr[c] = pack_ptr;
-      w.n_pack_rows[c] = total;
-      w.n_packs[c] = np;
-      w.pack_log2S[c] = h_cl[c];
-    } else {
-      CountItem* items = own.alloc<CountItem>(total);
-      TC_LAUNCH("emit_items", k_emit_items, dim3(grid_for(total)), dim3(kT), 0, st, offs.as<uint32_t>(),
-                n, total, w.tbeg, w.tend, w.tprefix, hrow_ptr, items);
-      TC_HIP(hipGetLastError());
-      w.items[c] = items;
-      w.n_items[c] = total;
-    }
   }
 }
 

@@ -7,6 +7,7 @@
 
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "tc_internal.h"
@@ -73,16 +74,23 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kPrimThreads * kScanItems;
 
+// Element i of the scanned sequence as L::operator()(i) (an array read or a
+// value computed from other arrays).
 template <class Tin, class Tout>
-__global__ __launch_bounds__(256) void k_scan_reduce(const Tin* __restrict__ in, int64_t n,
-                                                     Tout* __restrict__ partial) {
+struct ArrayLoad {
+  const Tin* in;
+  __device__ Tout operator()(int64_t i) const { return (Tout)in[i]; }
+};
+
+template <class L, class Tout>
+__global__ __launch_bounds__(256) void k_scan_reduce(L load, int64_t n, Tout* __restrict__ partial) {
   __shared__ Tout s_w[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   Tout acc = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     int64_t idx = base + (int64_t)i * kPrimThreads + threadIdx.x;
-    if (idx < n) acc += (Tout)in[idx];
+    if (idx < n) acc += load(idx);
   }
   acc = wave_sum(acc);
   if (lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
@@ -117,9 +125,8 @@ __global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ partial, 
   if (total && threadIdx.x == 0) *total = carry;
 }
 
-template <class Tin, class Tout>
-__global__ __launch_bounds__(256) void k_scan_final(const Tin* __restrict__ in, int64_t n,
-                                                    const Tout* __restrict__ partial,
+template <class L, class Tout>
+__global__ __launch_bounds__(256) void k_scan_final(L load, int64_t n, const Tout* __restrict__ partial,
                                                     Tout* __restrict__ out) {
   __shared__ Tout s_w[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(256) void k_scan_final(const Tin* __restrict__ in, 
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-    v[i] = idx < n ? (Tout)in[idx] : Tout(0);
+    v[i] = idx < n ? load(idx) : Tout(0);
     local += v[i];
   }
   Tout tot;
@@ -177,6 +184,11 @@ struct DevBuf {
     bytes = 0;
   }
   ~DevBuf() { release(); }
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+    std::swap(st, o.st);
+  }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   template <class T>
@@ -190,22 +202,29 @@ const char* intern_name(const std::string& s);
 
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Exclusive scan of n elements; out may alias in. If total != nullptr, the
-// grand total is written there (device pointer).
-template <class Tin, class Tout>
-void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStream_t st) {
+// Exclusive scan of the n elements load(0..n-1) into out; if total !=
+// nullptr, the grand total is written there (device pointer). out may alias
+// what load reads only if element i depends on position i alone.
+template <class Tout, class L>
+void device_excl_scan_f(L load, Tout* out, int64_t n, Tout* total, hipStream_t st) {
   if (n <= 0) {
     if (total) TC_HIP(hipMemsetAsync(total, 0, sizeof(Tout), st));
     return;
   }
   int64_t nb = div_up(n, kScanTile);
   DevBuf part(sizeof(Tout) * (size_t)nb);
-  TC_LAUNCH("scan_reduce", (k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
-                     part.as<Tout>());
+  TC_LAUNCH("scan_reduce", (k_scan_reduce<L, Tout>), dim3((unsigned)nb), dim3(256), 0, st, load, n,
+            part.as<Tout>());
   TC_LAUNCH("scan_partials", (k_scan_partials<Tout>), dim3(1), dim3(256), 0, st, part.as<Tout>(), nb, total);
-  TC_LAUNCH("scan_final", (k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(256), 0, st, in, n,
-                     part.as<Tout>(), out);
+  TC_LAUNCH("scan_final", (k_scan_final<L, Tout>), dim3((unsigned)nb), dim3(256), 0, st, load, n,
+            part.as<Tout>(), out);
   TC_HIP(hipGetLastError());
+}
+
+// Exclusive scan of n array elements; out may alias in.
+template <class Tin, class Tout>
+void device_excl_scan(const Tin* in, Tout* out, int64_t n, Tout* total, hipStream_t st) {
+  device_excl_scan_f<Tout>(ArrayLoad<Tin, Tout>{in}, out, n, total, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,16 +647,15 @@ static inline void check_sorts(hipStream_t st) {
 struct TaskLists {
   int64_t T = 0;
   DevBuf row;     // uint32 [T]: hashed row of each task
-  DevBuf start;   // uint32 [T]: first probe (probe-side index)
-  DevBuf len;     // uint32 [T]: probes
-  DevBuf prefix;  // uint64 [T + 1]: exclusive prefix of len, total at [T]
+  DevBuf val;     // uint64 [T]: first probe | (end of the probe range) << 32
+  DevBuf prefix;  // uint64 [T + 1]: exclusive prefix of the probe counts, total at [T]
   DevBuf ptr;     // int64 [nrows + 1]: tasks of row b are [ptr[b], ptr[b + 1])
 };
 
-// Sort T emitted tasks (keys = hashed row in [0, 2^key_bits), values =
-// first probe | end << 32) stably by row and fill `tl`. tk / tv are consumed
-// as sort buffers.
-void sort_tasks(TaskLists& tl, uint32_t* tk, uint64_t* tv, int64_t T, int64_t nrows, int key_bits,
+// Sort T emitted tasks (tk = hashed row in [0, 2^key_bits), tv = first
+// probe | end << 32) stably by row and fill `tl`. tk / tv are consumed as
+// sort buffers (tl may take them over).
+void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows, int key_bits,
                 hipStream_t st, const char* name);
 // check_sorts for the task sorts of sort_tasks (synchronises st).
 void check_task_sorts(hipStream_t st);
