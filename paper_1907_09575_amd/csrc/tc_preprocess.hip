@@ -33,20 +33,38 @@ namespace {
 constexpr int kT = 256;
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, div_up(n, kT)); }
 
-__global__ void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m,
-                        int64_t n, int s, uint64_t sent, uint64_t* __restrict__ keys,
-                        int* __restrict__ err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  int64_t u = src[i], v = dst[i];
-  uint64_t key = sent;
-  if (u < 0 || u >= n || v < 0 || v >= n) {
-    atomicOr(err, 1);
-  } else if (u != v) {
-    uint64_t lo = (uint64_t)(u < v ? u : v), hi = (uint64_t)(u < v ? v : u);
-    key = (lo << s) | hi;
+// Elementwise kernels over m elements take kEw consecutive-stride elements
+// per thread (i = block * 256 * kEw + j * 256 + thread): their loads are
+// issued together, which keeps more bytes in flight per wave.
+constexpr int kEw = 4;
+inline unsigned grid_ew(int64_t m) { return (unsigned)std::max<int64_t>(1, div_up(m, (int64_t)kT * kEw)); }
+
+__global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                               int64_t m, int64_t n, int s, uint64_t sent,
+                                               uint64_t* __restrict__ keys, int* __restrict__ err) {
+  const int64_t i0 = (int64_t)blockIdx.x * (kT * kEw) + threadIdx.x;
+  int64_t u[kEw], v[kEw];
+#pragma unroll
+  for (int j = 0; j < kEw; ++j) {
+    const int64_t i = i0 + (int64_t)j * kT;
+    u[j] = i < m ? src[i] : 0;
+    v[j] = i < m ? dst[i] : 0;
   }
-  keys[i] = key;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kEw; ++j) {
+    const int64_t i = i0 + (int64_t)j * kT;
+    if (i >= m) break;
+    uint64_t key = sent;
+    if (u[j] < 0 || u[j] >= n || v[j] < 0 || v[j] >= n) {
+      bad = true;
+    } else if (u[j] != v[j]) {
+      const uint64_t lo = (uint64_t)(u[j] < v[j] ? u[j] : v[j]), hi = (uint64_t)(u[j] < v[j] ? v[j] : u[j]);
+      key = (lo << s) | hi;
+    }
+    keys[i] = key;
+  }
+  if (bad) atomicOr(err, 1);
 }
 
 // Distinct keys of a sorted key array (the sentinel marks dropped self loops).
@@ -133,14 +151,32 @@ __global__ void k_perm(const uint64_t* __restrict__ rk, int64_t n, int s, int32_
   if (r < n) perm[rk[r] & ((1ull << s) - 1)] = (int32_t)r;
 }
 
-__global__ void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
-                         const int32_t* __restrict__ perm, uint64_t* __restrict__ okey) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+__global__ __launch_bounds__(256) void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
+                                                const int32_t* __restrict__ perm, uint64_t* __restrict__ okey) {
+  constexpr int kI = 2 * kEw;  // gathers: more in flight
+  const int64_t i0 = (int64_t)blockIdx.x * (kT * kI) + threadIdx.x;
   const uint64_t mask = (1ull << s) - 1;
-  uint64_t e = E[i];
-  uint64_t ru = (uint64_t)perm[e >> s], rv = (uint64_t)perm[e & mask];
-  okey[i] = ru < rv ? ((ru << s) | rv) : ((rv << s) | ru);
+  uint64_t e[kI];
+#pragma unroll
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = i0 + (int64_t)j * kT;
+    e[j] = i < m ? E[i] : 0;
+  }
+  uint32_t ru[kI], rv[kI];
+#pragma unroll
+  for (int j = 0; j < kI; ++j) {
+    const bool in = i0 + (int64_t)j * kT < m;
+    ru[j] = in ? (uint32_t)perm[e[j] >> s] : 0u;
+    rv[j] = in ? (uint32_t)perm[e[j] & mask] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kI; ++j) {
+    const int64_t i = i0 + (int64_t)j * kT;
+    if (i < m) {
+      const uint64_t a = ru[j], b = rv[j];
+      okey[i] = a < b ? ((a << s) | b) : ((b << s) | a);
+    }
+  }
 }
 
 // Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
@@ -165,18 +201,22 @@ __global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32
 }
 
 // W+ = sum_a C(d+(a), 2) and max d+(a).
+// Grids of the reducing kernels below: a few blocks per CU, each looping
+// over its rows, so that the per-block global atomics stay few.
+constexpr unsigned kReduceBlocks = 1024;
+inline unsigned grid_reduce(int64_t n) { return (unsigned)std::min<int64_t>(kReduceBlocks, grid_for(n)); }
+
 __global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ row_ptr, int64_t n,
                                                    unsigned long long* __restrict__ wplus,
                                                    unsigned int* __restrict__ maxd) {
   __shared__ uint64_t s_w[4];
   __shared__ uint32_t s_m[4];
-  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t w = 0;
   uint32_t md = 0;
-  if (a < n) {
-    uint64_t d = (uint64_t)(row_ptr[a + 1] - row_ptr[a]);
-    w = d * (d - (d > 0)) / 2;
-    md = (uint32_t)d;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t d = (uint64_t)(row_ptr[a + 1] - row_ptr[a]);
+    w += d * (d - (d > 0)) / 2;
+    md = max(md, (uint32_t)d);
   }
   w = wave_sum(w);
   md = wave_max(md);
@@ -199,10 +239,15 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
                                                   const uint64_t* __restrict__ tprefix,
                                                   const int64_t* __restrict__ row_ptr, int64_t n,
                                                   int8_t* __restrict__ cls, int* __restrict__ cls_log2S) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int c = -1, l = 0;
-  if (b < n) {
-    uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
+  __shared__ int s_max[NUM_CLASSES];
+  if (threadIdx.x < NUM_CLASSES) s_max[threadIdx.x] = 0;
+  __syncthreads();
+  int lmax[NUM_CLASSES];
+#pragma unroll
+  for (int k = 0; k < NUM_CLASSES; ++k) lmax[k] = 0;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+    int c = -1, l = 0;
+    const uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
     if (W > 0) {
       l = table_log2(row_ptr[b + 1] - row_ptr[b]);
       if (l > kMaxLog2S) c = CLS_GLOBAL;
@@ -212,12 +257,16 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
       else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
     }
     cls[b] = (int8_t)c;
+#pragma unroll
+    for (int k = 0; k < NUM_CLASSES; ++k) lmax[k] = c == k && l > lmax[k] ? l : lmax[k];
   }
 #pragma unroll
   for (int k = 0; k < NUM_CLASSES; ++k) {
-    int mk = wave_max(c == k ? l : 0);
-    if (lane_id() == 0 && mk > 0) atomicMax(&cls_log2S[k], mk);
+    const int mk = wave_max(lmax[k]);
+    if (lane_id() == 0 && mk > 0) atomicMax(&s_max[k], mk);
   }
+  __syncthreads();
+  if (threadIdx.x < NUM_CLASSES && s_max[threadIdx.x] > 0) atomicMax(&cls_log2S[threadIdx.x], s_max[threadIdx.x]);
 }
 
 // Per-class sums (rows, table keys, tasks, probes): LDS accumulation per
@@ -483,7 +532,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     if (m_raw > 0) {
-      TC_LAUNCH("canon", k_canon, dim3(grid_for(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
+      TC_LAUNCH("canon", k_canon, dim3(grid_ew(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
                          sent, ka.as<uint64_t>(), d_err);
       TC_HIP(hipGetLastError());
     }
@@ -542,7 +591,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   const uint64_t* okey = ok.as<uint64_t>();
   {
     if (m > 0) {
-      TC_LAUNCH("orient", k_orient, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
+      TC_LAUNCH("orient", k_orient, dim3((unsigned)std::max<int64_t>(1, div_up(m, kT * 2 * kEw))), dim3(kT), 0,
+                st, E.as<uint64_t>(), m, s,
                          g->perm, ok.as<uint64_t>());
       TC_HIP(hipGetLastError());
       // E's buffer is the ping-pong partner
@@ -556,7 +606,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->row_ptr, n + 1,
                          (int64_t)0);
     }
-    TC_LAUNCH("row_stats", k_row_stats, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n, d_wplus, d_maxd);
+    TC_LAUNCH("row_stats", k_row_stats, dim3(grid_reduce(n)), dim3(kT), 0, st, g->row_ptr, n, d_wplus,
+              d_maxd);
     TC_HIP(hipGetLastError());
   }
 
@@ -652,7 +703,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   DevBuf cls(sizeof(int8_t) * (size_t)n);
   DevBuf clsl(sizeof(int) * NUM_CLASSES);
   TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
-  TC_LAUNCH("classify", k_classify, dim3(grid_for(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
+  TC_LAUNCH("classify", k_classify, dim3(grid_reduce(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
             cls.as<int8_t>(), clsl.as<int>());
   TC_HIP(hipGetLastError());
   int h_cl[NUM_CLASSES];
