@@ -323,10 +323,11 @@ int64_t compact(const char* name, int64_t m, P pred, F&& prepare, hipStream_t st
 //     a tile only ever waits for tiles that are already running), load the
 //     tile into registers and rank its keys stably by digit with wave ballots
 //     (peers = lanes with the same digit; counts carried across the tile's
-//     rows in LDS). Each digit's thread then publishes the tile's count,
-//     walks back over earlier tiles' published words until it meets an
-//     inclusive prefix (decoupled look-back), publishes its own inclusive
-//     prefix, and the tile writes each digit's run contiguously from LDS.
+//     rows in LDS). Each digit's thread then publishes the tile's count, the
+//     tile is put in digit order in LDS (giving the predecessors time to
+//     publish), each digit's thread walks back over earlier tiles' published
+//     words until it meets an inclusive prefix (decoupled look-back) and
+//     publishes its own, and the tile writes each digit's run contiguously.
 //     A published word is 0 (nothing yet), an aggregate (count + 1) or an
 //     inclusive prefix (value with the top bit set), in one 32-bit atomic
 //     when the sort holds fewer than 2^31 keys, else one 64-bit atomic. The
@@ -486,14 +487,26 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
     s_cnt[w][tid] = cnt;
     cnt += c;
   }
-  // publish the tile's count, look back for the earlier tiles' total,
-  // publish the inclusive prefix
+  // publish the tile's count; put the tile in digit order in LDS (while the
+  // predecessors publish theirs); then look back for the earlier tiles'
+  // total and publish the inclusive prefix
   W* my = status + (uint64_t)tile * 256 + tid;
+  __hip_atomic_store(my, tile == 0 ? (TOP | (W)cnt) : (W)cnt + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t tot;
+  s_tstart[tid] = block_excl_scan(cnt, s_tmp, tot);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    if (wbase + 64 * i + lane < n) {
+      const uint32_t d = rs_digit(k[i], shift, dmask);
+      const uint32_t lp = s_tstart[d] + s_cnt[wave][d] + rank[i];
+      s_k[lp] = k[i];
+      if constexpr (HV) s_v[lp] = v[i];
+    }
+  }
   if (tile == 0) {
-    __hip_atomic_store(my, TOP | (W)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_goff[tid] = bucket[tid];
   } else {
-    __hip_atomic_store(my, (W)cnt + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // walk back WIN predecessors per step (their words are read together):
     // add counts from the nearest one until an inclusive prefix; stop at a
     // tile that has published nothing yet and read again from there
@@ -530,18 +543,6 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
     }
     __hip_atomic_store(my, TOP | (W)(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_goff[tid] = bucket[tid] + (uint32_t)excl;
-  }
-  uint32_t tot;
-  s_tstart[tid] = block_excl_scan(cnt, s_tmp, tot);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < KPT; ++i) {
-    if (wbase + 64 * i + lane < n) {
-      const uint32_t d = rs_digit(k[i], shift, dmask);
-      const uint32_t lp = s_tstart[d] + s_cnt[wave][d] + rank[i];
-      s_k[lp] = k[i];
-      if constexpr (HV) s_v[lp] = v[i];
-    }
   }
   __syncthreads();
   const int64_t rem = n - (int64_t)tile * TILE;
