@@ -621,11 +621,16 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
   return alt;
 }
 
+// True when the environment variable TC_SORT_WIDE_WORDS is set to a non-zero
+// value: sorts then use 64-bit look-back words at every size (the path that
+// sorts of 2^31 keys or more take), so that tests reach it at small sizes.
+bool sort_wide_words_forced();
+
 template <class K, class V>
 bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
                 hipStream_t st, const char* name) {
   constexpr int KPT = rs_default_kpt<K, V>();
-  if (n < ((int64_t)1 << 31))
+  if (n < ((int64_t)1 << 31) && !sort_wide_words_forced())
     return radix_sort_cfg<K, V, KPT, uint32_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
   return radix_sort_cfg<K, V, KPT, uint64_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
 }

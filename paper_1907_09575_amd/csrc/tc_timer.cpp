@@ -1,5 +1,6 @@
 // tc_timer.cpp - phase timers: HIP events around every library launch made
 // while a timer is attached to the calling host thread.
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <set>
@@ -26,6 +27,11 @@ const char* intern_name(const std::string& s) {
   static std::set<std::string> names;
   std::lock_guard<std::mutex> lk(mu);
   return names.insert(s).first->c_str();
+}
+
+bool sort_wide_words_forced() {
+  const char* v = std::getenv("TC_SORT_WIDE_WORDS");
+  return v != nullptr && v[0] != '\0' && !(v[0] == '0' && v[1] == '\0');
 }
 
 TempCtx& temp_ctx() {

@@ -303,3 +303,14 @@ def test_block_tiny_grid_larger_than_graph(tc):
     check_blocks(tc, g, U, 13)
     b, sh = gpu_block(tc, g, 64, 63, 63)
     assert b == 0 and not sh.any()
+
+
+def test_sort_wide_lookback_words(tc, monkeypatch):
+    # sorts of 2^31 keys or more publish their look-back state in 64-bit
+    # words; the environment switch forces that path at small sizes, where
+    # the whole preprocessing (five sorts) and the count must still match
+    monkeypatch.setenv("TC_SORT_WIDE_WORDS", "1")
+    s, d = graphgen.rmat(16, seed=21)
+    check_full(tc, s, d, 1 << 16, support=False)
+    s, d, n = sg.random_graph(300, 0.05, 77)
+    check_full(tc, *sg.messy(s, d, n, seed=3), support=False)
