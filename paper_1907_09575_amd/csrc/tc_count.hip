@@ -187,6 +187,12 @@ __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
 template <int MODE, int KIND>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
                            uint32_t* bm, uint32_t& hits) {
+  // the range is the wave's own (uniform across its lanes): scalar registers
+  // (readfirstlane returns int: widen through uint32_t, never sign-extend)
+  t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+  len = (uint32_t)__builtin_amdgcn_readfirstlane((int)len);
+  q = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(q >> 32)) << 32) |
+      (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)q);
   constexpr bool GLOBAL = KIND == TK_GLOBAL;
   constexpr bool MULTI = KIND == TK_MULTI;
   constexpr bool kNeedTs = MODE == MODE_SUPPORT_FULL || MODE == MODE_SUPPORT_ORIENTED;
@@ -223,7 +229,8 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     const uint32_t e_prev = (uint32_t)__shfl_up((int)e, 1, 64);
     const uint32_t s_rel = lane == 0 ? P0 - done : e_prev;
     const uint32_t cbase = tsj - s_rel;
-    const uint32_t lim = (uint32_t)__shfl((int)e, 63, 64);  // probes of this window
+    // probes of this window (wave-uniform: kept in a scalar register)
+    const uint32_t lim = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)e, 63, 64));
     if (lim == 0) break;  // unreachable when every task has a probe; guards progress
     // packs: the table of the lane's task (last row whose first task <= it)
     uint32_t tdesc = 0;
