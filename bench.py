@@ -71,6 +71,30 @@ def count_kernel_bytes(stats: dict, cls: str) -> int:
     return 4 * s["probes"] + 4 * s["table_keys"] + 12 * s["tasks"] + 32 * s["rows"]
 
 
+def measure_copy_gbs(dev, nbytes=1 << 31, reps=5):
+    """On-box reference bandwidth: a plain device-to-device copy of nbytes
+    (read + write bytes per second, GB/s, best of reps), reported beside the
+    published peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.synchronize()
+    return round(2 * nbytes / (best / 1e3) / 1e9, 1)
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed PMC summary, if it
     was taken on the current count-kernel sources; else None."""
@@ -370,6 +394,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # (not in calibration runs: their one 1 GiB copy scales the PMC byte counters)
+    copy_gbs = None if args.copy_calibration else measure_copy_gbs(dev)
+
     def step():
         g = tc.tc_preprocess(src, dst, n)
         tc.tc_count(g, out)
@@ -425,10 +452,12 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": load_traffic(dom), "algorithmic_bytes_per_launch": bytes_per_launch,
-                    "avg_launch_ms": round(launches[dom]["avg_ms"], 4)}
+                    "avg_launch_ms": round(launches[dom]["avg_ms"], 4),
+                    "copy_GBps": copy_gbs,
+                    "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": None, "traffic": None,
+                    "unit": "GB/s", "frac": None, "traffic": None, "copy_GBps": copy_gbs,
                     "note": "dominant kernel is not a count kernel"}
 
     # whole count phase against the same roofline

@@ -9,6 +9,12 @@ and prints short text tables for ``profiles/``.
     python paper_1907_09575_amd/rocprof_summary.py pmc DIR/NAME_counter_collection.csv COUNTER
     python paper_1907_09575_amd/rocprof_summary.py launches DIR/NAME_kernel_trace.csv
     python paper_1907_09575_amd/rocprof_summary.py traffic FETCH.csv WRITE.csv BENCH.json LABEL OUT.json
+    python paper_1907_09575_amd/rocprof_summary.py ratios DIR/NAME_counter_collection.csv
+
+``ratios`` averages every counter of a run per (kernel, grid) and prints the
+LDS bank-conflict rate (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: the share of
+LDS-active cycles stalled by bank conflicts) and the L2 hit rate
+(TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)) where those counters are present.
 
 ``launches`` groups the kernel trace by (kernel, grid size), which separates
 the launch classes that share one kernel instantiation.
@@ -102,6 +108,33 @@ def launches(path: str, top: int = 25):
     return "\n".join(lines)
 
 
+def ratios(path: str, top: int = 20):
+    per = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name", r.get("kernel_name"))
+        grid = int(float(r.get("Grid_Size", r.get("grid_size", 0)) or 0))
+        cn = r.get("Counter_Name", r.get("counter_name"))
+        per[(name, grid)][cn].append(float(r.get("Counter_Value", r.get("counter_value", 0))))
+    def avg(d, k):
+        v = d.get(k)
+        return sum(v) / len(v) if v else None
+    rows = []
+    for (name, grid), d in per.items():
+        bc, act = avg(d, "SQ_LDS_BANK_CONFLICT"), avg(d, "SQ_LDS_IDX_ACTIVE")
+        hit, miss = avg(d, "TCC_HIT_sum"), avg(d, "TCC_MISS_sum")
+        weight = act if act is not None else (hit or 0) + (miss or 0)
+        rows.append((weight, name, grid, len(next(iter(d.values()))),
+                     None if not act else bc / act,
+                     None if hit is None or miss is None or hit + miss == 0 else hit / (hit + miss)))
+    rows.sort(key=lambda r: -r[0])
+    lines = ["%-52s %11s %5s %16s %10s" % ("kernel", "grid", "n", "lds_conflict", "l2_hit")]
+    for _, name, grid, n, lc, l2 in rows[:top]:
+        lines.append("%-52s %11d %5d %16s %10s" % (short_name(name)[:52], grid, n,
+                                                   "-" if lc is None else "%.4f" % lc,
+                                                   "-" if l2 is None else "%.4f" % l2))
+    return "\n".join(lines)
+
+
 def _counter_rows(path, counter):
     out = []
     for r in csv.DictReader(open(path)):
@@ -146,6 +179,8 @@ def main(argv):
         print(kernel_stats(argv[1]))
     elif len(argv) >= 2 and argv[0] == "launches":
         print(launches(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "ratios":
+        print(ratios(argv[1]))
     elif len(argv) >= 3 and argv[0] == "pmc":
         print(pmc(argv[1], argv[2]))
     elif len(argv) >= 6 and argv[0] == "traffic":
