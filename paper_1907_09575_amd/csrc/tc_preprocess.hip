@@ -67,11 +67,15 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ src, 
   if (bad) atomicOr(err, 1);
 }
 
-// Distinct keys of a sorted key array (the sentinel marks dropped self loops).
+// Distinct keys of a sorted key array (the sentinel marks dropped self loops);
+// each is written out with its upper endpoint (low s bits) beside it, the
+// input of the upper-endpoint degree count.
 struct UniquePred {
   const uint64_t* keys;
   uint64_t sent;
+  int s;
   uint64_t* out;
+  uint32_t* out_hi;
   struct Item {
     uint64_t k;
   };
@@ -80,7 +84,10 @@ struct UniquePred {
     it.k = k;
     return k != sent && (i == 0 || keys[i - 1] != k);
   }
-  __device__ void emit(int64_t, const Item& it, uint32_t pos) const { out[pos] = it.k; }
+  __device__ void emit(int64_t, const Item& it, uint32_t pos) const {
+    out[pos] = it.k;
+    out_hi[pos] = (uint32_t)(it.k & ((1ull << s) - 1));
+  }
 };
 
 // Entry i of U (row a, column b) starts a task iff U_a has entries after i
@@ -125,11 +132,6 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-__global__ void k_hi_keys(const uint64_t* __restrict__ E, int64_t m, int s, uint32_t* __restrict__ hk) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) hk[i] = (uint32_t)(E[i] & ((1ull << s) - 1));
 }
 
 // deg(v) = (edges whose lower endpoint is v) + (edges whose upper endpoint is v),
@@ -194,6 +196,15 @@ __global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n
   }
   row_ptr[r] = lo;
 }
+
+// Column of a sorted orient key, written by the orient sort's last pass.
+struct ColEpi {
+  int32_t* col;
+  int s;
+  __device__ void operator()(uint64_t pos, uint64_t key) const {
+    col[pos] = (int32_t)(key & ((1ull << s) - 1));
+  }
+};
 
 __global__ void k_col(const uint64_t* __restrict__ okey, int64_t m, int s, int32_t* __restrict__ col) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -527,7 +538,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
   // ---- 1-2: simple graph -------------------------------------------------
   int64_t m = 0;
-  DevBuf E;
+  DevBuf E, Ehi;  // distinct keys (lo << s | hi) and their upper endpoints
   {
     DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
@@ -540,11 +551,13 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
                                            m_raw, 0, 2 * s, st, "dedup");
     const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
-    UniquePred up{sorted, sent, nullptr};
+    UniquePred up{sorted, sent, s, nullptr, nullptr};
     m = compact("dedup", m_raw, up, [&](int64_t total, UniquePred& p) {
       TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
       E.alloc(sizeof(uint64_t) * (size_t)total);
+      Ehi.alloc(sizeof(uint32_t) * (size_t)total);
       p.out = E.as<uint64_t>();
+      p.out_hi = Ehi.as<uint32_t>();
     }, st);
     if (m == 0) E.alloc(sizeof(uint64_t));
   }
@@ -561,14 +574,11 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       DevBuf lo_ptr(sizeof(int64_t) * (size_t)(n + 1)), hi_ptr(sizeof(int64_t) * (size_t)(n + 1));
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, E.as<uint64_t>(),
                          m, s, n, lo_ptr.as<int64_t>());
-      DevBuf ha(sizeof(uint32_t) * (size_t)m), hb(sizeof(uint32_t) * (size_t)m);
-      TC_LAUNCH("hi_keys", k_hi_keys, dim3(grid_for(m)), dim3(kT), 0, st, E.as<uint64_t>(), m, s,
-                         ha.as<uint32_t>());
-      TC_HIP(hipGetLastError());
-      bool halt = radix_sort<uint32_t, NoVal>(ha.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
+      DevBuf hb(sizeof(uint32_t) * (size_t)m);
+      bool halt = radix_sort<uint32_t, NoVal>(Ehi.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
                                               0, s, st, "degree");
       TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st,
-                         halt ? hb.as<uint32_t>() : ha.as<uint32_t>(), m, 0, n, hi_ptr.as<int64_t>());
+                         halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), m, 0, n, hi_ptr.as<int64_t>());
       TC_LAUNCH("deg_from_bounds", k_deg_from_bounds, dim3(grid_for(n)), dim3(kT), 0, st, lo_ptr.as<int64_t>(),
                          hi_ptr.as<int64_t>(), n, deg.as<uint32_t>());
       TC_HIP(hipGetLastError());
@@ -584,6 +594,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     TC_HIP(hipGetLastError());
   }
 
+  Ehi.release();
+
   // ---- 4: orient, U in CSR -------------------------------------------------
   g->row_ptr = g->owned.alloc<int64_t>(n + 1);
   g->col = g->owned.alloc<int32_t>(m);
@@ -596,12 +608,14 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
                          g->perm, ok.as<uint64_t>());
       TC_HIP(hipGetLastError());
       // E's buffer is the ping-pong partner
-      bool alt = radix_sort<uint64_t, NoVal>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
-                                             0, 2 * s, st, "orient");
+      // (the last pass also writes each key's column: U's col array)
+      bool alt = radix_sort<uint64_t, NoVal, ColEpi>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
+                                                     0, 2 * s, st, "orient", ColEpi{g->col, s});
       if (alt) okey = E.as<uint64_t>();
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
-      TC_LAUNCH("col", k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
+      if (m == 1)  // no sort pass ran
+        TC_LAUNCH("col", k_col, dim3(grid_for(m)), dim3(kT), 0, st, okey, m, s, g->col);
     } else {
       TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(n + 1)), dim3(kT), 0, st, g->row_ptr, n + 1,
                          (int64_t)0);

@@ -336,6 +336,13 @@ int64_t compact(const char* name, int64_t m, P pred, F&& prepare, hipStream_t st
 // ---------------------------------------------------------------------------
 struct NoVal {};
 
+// Epilogue of a sort's last pass: called with every key and its final
+// position as it is written (NoEpi: nothing).
+struct NoEpi {
+  template <class K>
+  __device__ void operator()(uint64_t, K) const {}
+};
+
 constexpr int kSortPassesMax = 8;
 constexpr uint32_t kLbSpinMax = 1u << 16;
 constexpr int kLbWin = 4;  // predecessors read per look-back step
@@ -423,13 +430,13 @@ static __global__ __launch_bounds__(256) void k_rs_buckets(uint32_t* __restrict_
   }
 }
 
-template <class K, class V, int KPT, class W, int WIN>
+template <class K, class V, int KPT, class W, int WIN, class Epi>
 __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                      const V* __restrict__ vin, V* __restrict__ vout,
                                                      int64_t n, int shift, uint32_t dmask,
                                                      const uint32_t* __restrict__ bucket,
                                                      W* __restrict__ status,
-                                                     uint32_t* __restrict__ ticket) {
+                                                     uint32_t* __restrict__ ticket, Epi epi) {
   constexpr int TILE = 256 * KPT;
   constexpr int WCH = 64 * KPT;  // keys of the tile each wave ranks (a contiguous quarter)
   constexpr bool HV = !std::is_same<V, NoVal>::value;
@@ -556,6 +563,7 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
       const uint64_t gp = (uint64_t)s_goff[d] + (uint64_t)(lp - (int)s_tstart[d]);
       kout[gp] = kk;
       if constexpr (HV) vout[gp] = s_v[lp];
+      epi(gp, kk);
     }
   }
 }
@@ -575,10 +583,11 @@ constexpr int rs_default_kpt() {
 // not NoVal, with KPT keys per thread per tile and look-back words of type W
 // (uint32_t needs n < 2^31). keys/vals and keys_alt/vals_alt are ping-pong
 // buffers of n elements; returns true if the sorted data ended in the *_alt
-// buffers.
-template <class K, class V, int KPT, class W, int WIN = kLbWin>
+// buffers. The last pass calls epi(final position, key) for every key (no
+// pass runs, and epi is not called, when n <= 1).
+template <class K, class V, int KPT, class W, int WIN = kLbWin, class Epi = NoEpi>
 bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                    hipStream_t st, const char* name) {
+                    hipStream_t st, const char* name, Epi epi = Epi{}) {
   constexpr int TILE = 256 * KPT;
   const char* n_digits = intern_name(std::string("rs_digits:") + name);
   const char* n_pass = intern_name(std::string("rs_pass:") + name);
@@ -610,9 +619,14 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     const uint32_t dmask = (1u << bits) - 1u;
     TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(W) * (size_t)pass_words, st));
     W* words = lb.as<W>();
-    TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN>), dim3((unsigned)ntiles), dim3(256), 0, st, ka, kb,
-              va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
-              reinterpret_cast<uint32_t*>(words));
+    if (p + 1 < passes)
+      TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, NoEpi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
+                kb, va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
+                reinterpret_cast<uint32_t*>(words), NoEpi{});
+    else
+      TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, Epi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
+                kb, va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
+                reinterpret_cast<uint32_t*>(words), epi);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
@@ -626,13 +640,15 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
 // sorts of 2^31 keys or more take), so that tests reach it at small sizes.
 bool sort_wide_words_forced();
 
-template <class K, class V>
+template <class K, class V, class Epi = NoEpi>
 bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                hipStream_t st, const char* name) {
+                hipStream_t st, const char* name, Epi epi = Epi{}) {
   constexpr int KPT = rs_default_kpt<K, V>();
   if (n < ((int64_t)1 << 31) && !sort_wide_words_forced())
-    return radix_sort_cfg<K, V, KPT, uint32_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
-  return radix_sort_cfg<K, V, KPT, uint64_t>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st, name);
+    return radix_sort_cfg<K, V, KPT, uint32_t, kLbWin, Epi>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi,
+                                                            st, name, epi);
+  return radix_sort_cfg<K, V, KPT, uint64_t, kLbWin, Epi>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st,
+                                                          name, epi);
 }
 
 // Throws TC_EDEVICE if a sort of this source file gave up waiting in its
