@@ -38,6 +38,9 @@ inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, div_
 // issued together, which keeps more bytes in flight per wave.
 constexpr int kEw = 4;
 inline unsigned grid_ew(int64_t m) { return (unsigned)std::max<int64_t>(1, div_up(m, (int64_t)kT * kEw)); }
+// Grid of a key producer that also counts digits (grid-stride loop; one LDS
+// histogram flush per work-group).
+constexpr unsigned kProducerBlocks = 2048;
 
 __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                                                int64_t m, int64_t n, int s, uint64_t sent,
@@ -153,32 +156,43 @@ __global__ void k_perm(const uint64_t* __restrict__ rk, int64_t n, int s, int32_
   if (r < n) perm[rk[r] & ((1ull << s) - 1)] = (int32_t)r;
 }
 
+// Orient keys (rank_lo << s | rank_hi) and, for the orient sort, the digit
+// counts of every key written.
 __global__ __launch_bounds__(256) void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
-                                                const int32_t* __restrict__ perm, uint64_t* __restrict__ okey) {
+                                                const int32_t* __restrict__ perm, uint64_t* __restrict__ okey,
+                                                uint32_t* __restrict__ hist) {
+  extern __shared__ uint32_t h_dyn[];
   constexpr int kI = 2 * kEw;  // gathers: more in flight
-  const int64_t i0 = (int64_t)blockIdx.x * (kT * kI) + threadIdx.x;
+  DigitCounter dc;
+  dc.init(h_dyn, 0, 2 * s);
   const uint64_t mask = (1ull << s) - 1;
-  uint64_t e[kI];
+  for (int64_t base = (int64_t)blockIdx.x * (kT * kI); base < m; base += (int64_t)gridDim.x * (kT * kI)) {
+    const int64_t i0 = base + threadIdx.x;
+    uint64_t e[kI];
 #pragma unroll
-  for (int j = 0; j < kI; ++j) {
-    const int64_t i = i0 + (int64_t)j * kT;
-    e[j] = i < m ? E[i] : 0;
-  }
-  uint32_t ru[kI], rv[kI];
+    for (int j = 0; j < kI; ++j) {
+      const int64_t i = i0 + (int64_t)j * kT;
+      e[j] = i < m ? E[i] : 0;
+    }
+    uint32_t ru[kI], rv[kI];
 #pragma unroll
-  for (int j = 0; j < kI; ++j) {
-    const bool in = i0 + (int64_t)j * kT < m;
-    ru[j] = in ? (uint32_t)perm[e[j] >> s] : 0u;
-    rv[j] = in ? (uint32_t)perm[e[j] & mask] : 0u;
-  }
+    for (int j = 0; j < kI; ++j) {
+      const bool in = i0 + (int64_t)j * kT < m;
+      ru[j] = in ? (uint32_t)perm[e[j] >> s] : 0u;
+      rv[j] = in ? (uint32_t)perm[e[j] & mask] : 0u;
+    }
 #pragma unroll
-  for (int j = 0; j < kI; ++j) {
-    const int64_t i = i0 + (int64_t)j * kT;
-    if (i < m) {
-      const uint64_t a = ru[j], b = rv[j];
-      okey[i] = a < b ? ((a << s) | b) : ((b << s) | a);
+    for (int j = 0; j < kI; ++j) {
+      const int64_t i = i0 + (int64_t)j * kT;
+      if (i < m) {
+        const uint64_t a = ru[j], b = rv[j];
+        const uint64_t k = a < b ? ((a << s) | b) : ((b << s) | a);
+        okey[i] = k;
+        dc.add(k);
+      }
     }
   }
+  dc.flush(hist);
 }
 
 // Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
@@ -603,14 +617,18 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   const uint64_t* okey = ok.as<uint64_t>();
   {
     if (m > 0) {
-      TC_LAUNCH("orient", k_orient, dim3((unsigned)std::max<int64_t>(1, div_up(m, kT * 2 * kEw))), dim3(kT), 0,
-                st, E.as<uint64_t>(), m, s,
-                         g->perm, ok.as<uint64_t>());
+      DevBuf ohist(sizeof(uint32_t) * 256 * kSortPassesMax);  // digit counts, from k_orient
+      TC_HIP(hipMemsetAsync(ohist.p, 0, ohist.bytes, st));
+      TC_LAUNCH("orient", k_orient,
+                dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw))), dim3(kT),
+                digit_lds_bytes(0, 2 * s), st, E.as<uint64_t>(), m, s, g->perm, ok.as<uint64_t>(),
+                ohist.as<uint32_t>());
       TC_HIP(hipGetLastError());
       // E's buffer is the ping-pong partner
       // (the last pass also writes each key's column: U's col array)
       bool alt = radix_sort<uint64_t, NoVal, ColEpi>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
-                                                     0, 2 * s, st, "orient", ColEpi{g->col, s});
+                                                     0, 2 * s, st, "orient", ColEpi{g->col, s},
+                                                     ohist.as<uint32_t>());
       if (alt) okey = E.as<uint64_t>();
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);

@@ -418,6 +418,49 @@ __global__ __launch_bounds__(256) void k_rs_digits(const K* __restrict__ kin, in
   }
 }
 
+// Digit counts taken by the kernel that produces a sort's keys, so that the
+// sort needs no read of its own: every work-group counts the keys it writes
+// into LDS (layout and copies as in k_rs_digits; dynamic LDS of
+// digit_lds_bytes) and adds its counts to a [passes][256] global histogram
+// once, at the end. Pass the histogram to radix_sort (zeroed before the
+// producer runs).
+__host__ __device__ constexpr int digit_passes(int bit_lo, int bit_hi) { return (bit_hi - bit_lo + 7) / 8; }
+inline size_t digit_lds_bytes(int bit_lo, int bit_hi) {
+  return sizeof(uint32_t) * 256 * kDigitCopies * (size_t)digit_passes(bit_lo, bit_hi);
+}
+
+struct DigitCounter {
+  uint32_t* h;  // LDS
+  int bit_lo, bit_hi, passes, cp;
+  __device__ void init(uint32_t* lds, int lo, int hi) {
+    h = lds;
+    bit_lo = lo;
+    bit_hi = hi;
+    passes = digit_passes(lo, hi);
+    cp = threadIdx.x & (kDigitCopies - 1);
+    for (int x = threadIdx.x; x < passes * 256 * kDigitCopies; x += blockDim.x) h[x] = 0;
+    __syncthreads();
+  }
+  template <class K>
+  __device__ void add(K k) const {
+    for (int p = 0; p < passes; ++p) {
+      const int shift = bit_lo + 8 * p;
+      const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+      atomicAdd(&h[(p * 256 + rs_digit(k, shift, (1u << bits) - 1u)) * kDigitCopies + cp], 1u);
+    }
+  }
+  // all threads, after the block's last add
+  __device__ void flush(uint32_t* __restrict__ ghist) const {
+    __syncthreads();
+    for (int x = threadIdx.x; x < passes * 256; x += blockDim.x) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int c = 0; c < kDigitCopies; ++c) t += h[x * kDigitCopies + c];
+      if (t) atomicAdd(&ghist[x], t);
+    }
+  }
+};
+
 // In-place exclusive scan of each pass's 256 digit counts (one work-group).
 static __global__ __launch_bounds__(256) void k_rs_buckets(uint32_t* __restrict__ ghist, int passes) {
   __shared__ uint32_t s_w[4];
@@ -584,10 +627,12 @@ constexpr int rs_default_kpt() {
 // (uint32_t needs n < 2^31). keys/vals and keys_alt/vals_alt are ping-pong
 // buffers of n elements; returns true if the sorted data ended in the *_alt
 // buffers. The last pass calls epi(final position, key) for every key (no
-// pass runs, and epi is not called, when n <= 1).
+// pass runs, and epi is not called, when n <= 1). hist: the keys' digit
+// counts ([passes][256], from a DigitCounter in the producing kernel; it is
+// scanned in place), or nullptr to count them here.
 template <class K, class V, int KPT, class W, int WIN = kLbWin, class Epi = NoEpi>
 bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                    hipStream_t st, const char* name, Epi epi = Epi{}) {
+                    hipStream_t st, const char* name, Epi epi = Epi{}, uint32_t* hist = nullptr) {
   constexpr int TILE = 256 * KPT;
   const char* n_digits = intern_name(std::string("rs_digits:") + name);
   const char* n_pass = intern_name(std::string("rs_pass:") + name);
@@ -600,14 +645,18 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
   // per pass: ticket counter (padded to 256 bytes) + ntiles * 256 look-back words
   const int64_t pad = 256 / (int64_t)sizeof(W);
   const int64_t pass_words = pad + ntiles * 256;
-  DevBuf ghist(sizeof(uint32_t) * 256 * kSortPassesMax);
+  DevBuf own_hist;
   DevBuf lb(sizeof(W) * (size_t)pass_words);
-  TC_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
-  const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
-  TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256),
-            sizeof(uint32_t) * 256 * kDigitCopies * (size_t)passes, st, keys, n, bit_lo, bit_hi,
-            ghist.as<uint32_t>());
-  TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, ghist.as<uint32_t>(), passes);
+  uint32_t* gh = hist;
+  if (!gh) {
+    own_hist.alloc(sizeof(uint32_t) * 256 * kSortPassesMax);
+    gh = own_hist.as<uint32_t>();
+    TC_HIP(hipMemsetAsync(gh, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
+    const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
+    TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), digit_lds_bytes(bit_lo, bit_hi), st, keys,
+              n, bit_lo, bit_hi, gh);
+  }
+  TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, gh, passes);
   K* ka = keys;
   K* kb = keys_alt;
   V* va = vals;
@@ -621,11 +670,11 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     W* words = lb.as<W>();
     if (p + 1 < passes)
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, NoEpi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
-                kb, va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
+                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
                 reinterpret_cast<uint32_t*>(words), NoEpi{});
     else
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, Epi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
-                kb, va, vb, n, shift, dmask, ghist.as<uint32_t>() + 256 * p, words + pad,
+                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
                 reinterpret_cast<uint32_t*>(words), epi);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
@@ -642,13 +691,13 @@ bool sort_wide_words_forced();
 
 template <class K, class V, class Epi = NoEpi>
 bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                hipStream_t st, const char* name, Epi epi = Epi{}) {
+                hipStream_t st, const char* name, Epi epi = Epi{}, uint32_t* hist = nullptr) {
   constexpr int KPT = rs_default_kpt<K, V>();
   if (n < ((int64_t)1 << 31) && !sort_wide_words_forced())
     return radix_sort_cfg<K, V, KPT, uint32_t, kLbWin, Epi>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi,
-                                                            st, name, epi);
+                                                            st, name, epi, hist);
   return radix_sort_cfg<K, V, KPT, uint64_t, kLbWin, Epi>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st,
-                                                          name, epi);
+                                                          name, epi, hist);
 }
 
 // Throws TC_EDEVICE if a sort of this source file gave up waiting in its
