@@ -67,33 +67,34 @@ __global__ __launch_bounds__(256) void k_entry_rows(const int64_t* __restrict__ 
 }
 
 // Entry p of local probe row a (= erow[p]) holding b starts a task iff
-// b % q == x, the row has entries after p, and U_b is not empty.
-__global__ void k_block_task_flags(const int32_t* __restrict__ pcol, const uint32_t* __restrict__ erow,
-                                   const int64_t* __restrict__ prow_ptr, int64_t pm,
-                                   const int64_t* __restrict__ hrow_ptr, int64_t nh, int32_t q,
-                                   int32_t x, uint32_t* __restrict__ flags) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pm) return;
-  const int32_t b = pcol[p];
-  uint32_t f = 0;
-  if (b % q == x) {
+// b % q == x, the row has entries after p, and U_b is not empty; the task's
+// key is the local hashed row b / q and its value the probe range
+// [p + 1, end of row a).
+struct BlockTaskPred {
+  const int32_t* pcol;
+  const uint32_t* erow;
+  const int64_t* prow_ptr;
+  const int64_t* hrow_ptr;
+  int64_t nh;
+  int32_t q, x;
+  uint32_t* tkey;
+  uint64_t* tval;
+  struct Item {
+    uint32_t lb, end;
+  };
+  __device__ bool operator()(int64_t p, Item& it) const {
+    const int32_t b = pcol[p];
+    if (b % q != x) return false;
     const int64_t lb = b / q;
-    const int64_t after = prow_ptr[erow[p] + 1] - p - 1;
-    f = (lb < nh && after > 0 && hrow_ptr[lb + 1] > hrow_ptr[lb]) ? 1u : 0u;
+    it.lb = (uint32_t)lb;
+    it.end = (uint32_t)prow_ptr[erow[p] + 1];
+    return lb < nh && (int64_t)it.end - p - 1 > 0 && hrow_ptr[lb + 1] > hrow_ptr[lb];
   }
-  flags[p] = f;
-}
-
-__global__ void k_block_task_emit(const int32_t* __restrict__ pcol, const uint32_t* __restrict__ erow,
-                                  const int64_t* __restrict__ prow_ptr, int64_t pm, int32_t q,
-                                  const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
-                                  uint32_t* __restrict__ tkey, uint64_t* __restrict__ tval) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pm || !flags[p]) return;
-  const uint32_t t = pos[p];
-  tkey[t] = (uint32_t)(pcol[p] / q);
-  tval[t] = (uint64_t)(p + 1) | ((uint64_t)prow_ptr[erow[p] + 1] << 32);
-}
+  __device__ void emit(int64_t p, const Item& it, uint32_t pos) const {
+    tkey[pos] = it.lb;
+    tval[pos] = (uint64_t)(p + 1) | ((uint64_t)it.end << 32);
+  }
+};
 
 // Local CSR of the rows v == r (mod q).
 struct LocalRows {
@@ -142,21 +143,16 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
     DevBuf erow(sizeof(uint32_t) * (size_t)P.nnz);
     TC_LAUNCH("block_entry_rows", k_entry_rows, dim3((unsigned)div_up(P.nloc, kBT / 64)), dim3(kBT), 0,
               st, P.row_ptr.as<int64_t>(), P.nloc, erow.as<uint32_t>());
-    DevBuf flags(sizeof(uint32_t) * (size_t)P.nnz), pos(sizeof(uint32_t) * (size_t)P.nnz);
-    DevBuf tot(sizeof(uint32_t));
-    TC_LAUNCH("block_task_flags", k_block_task_flags, dim3(blocks_for(P.nnz)), dim3(kBT), 0, st,
-              P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), P.nnz,
-              H.row_ptr.as<int64_t>(), H.nloc, q, x, flags.as<uint32_t>());
-    device_excl_scan<uint32_t, uint32_t>(flags.as<uint32_t>(), pos.as<uint32_t>(), P.nnz,
-                                         tot.as<uint32_t>(), st);
-    TC_HIP(hipGetLastError());
-    T = read_dev(tot.as<uint32_t>(), st);
+    DevBuf tk, tv;
+    BlockTaskPred bp{P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), H.row_ptr.as<int64_t>(),
+                     H.nloc, q, x, nullptr, nullptr};
+    T = compact("block_tasks", P.nnz, bp, [&](int64_t total, BlockTaskPred& pr) {
+      tk.alloc(sizeof(uint32_t) * (size_t)total);
+      tv.alloc(sizeof(uint64_t) * (size_t)total);
+      pr.tkey = tk.as<uint32_t>();
+      pr.tval = tv.as<uint64_t>();
+    }, st);
     if (T > 0) {
-      DevBuf tk(sizeof(uint32_t) * (size_t)T), tv(sizeof(uint64_t) * (size_t)T);
-      TC_LAUNCH("block_task_emit", k_block_task_emit, dim3(blocks_for(P.nnz)), dim3(kBT), 0, st,
-                P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), P.nnz, q,
-                flags.as<uint32_t>(), pos.as<uint32_t>(), tk.as<uint32_t>(), tv.as<uint64_t>());
-      TC_HIP(hipGetLastError());
       const int bits = std::max(1, ceil_log2_u64((uint64_t)H.nloc));
       sort_tasks(tl, tk, tv, T, H.nloc, bits, st, "block_tasks");
     }
