@@ -307,8 +307,7 @@ __global__ __launch_bounds__(256) void k_class_stats(const int8_t* __restrict__ 
   __shared__ unsigned long long acc[kStatCols];
   if (threadIdx.x < kStatCols) acc[threadIdx.x] = 0;
   __syncthreads();
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < n) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
     const int c = cls[b];
     if (c >= 0) {
       atomicAdd(&acc[c * 4 + 0], 1ull);
@@ -831,7 +830,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     }
   }
   {
-    const int64_t nb = (int64_t)grid_for(n);
+    const int64_t nb = (int64_t)grid_reduce(n);
     DevBuf part(sizeof(unsigned long long) * (size_t)nb * kStatCols);
     DevBuf sums(sizeof(unsigned long long) * kStatCols);
     TC_LAUNCH("class_stats", k_class_stats, dim3((unsigned)nb), dim3(kT), 0, st, cls.as<int8_t>(), n,

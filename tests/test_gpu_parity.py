@@ -314,3 +314,35 @@ def test_sort_wide_lookback_words(tc, monkeypatch):
     check_full(tc, s, d, 1 << 16, support=False)
     s, d, n = sg.random_graph(300, 0.05, 77)
     check_full(tc, *sg.messy(s, d, n, seed=3), support=False)
+
+
+def test_largest_vertex_id_space(tc):
+    # n = 2^31 - 1, the largest vertex count the ABI takes: 62-bit sort keys
+    # (8 radix passes), 64 KiB digit histograms and n-sized rank, row and
+    # work arrays. K6 + a wheel + a friendship graph (with duplicates and
+    # self loops) are placed on ids spread over [0, n), the largest id
+    # included; the oracle runs on the same graph with its ids compacted in
+    # order, which keeps the degree order and therefore U's order, W+ and
+    # both support arrays
+    n = 2 ** 31 - 1
+    s, d, k = sg.disjoint_union(sg.disjoint_union(sg.complete(6), sg.wheel(8)), sg.friendship(3))
+    s, d, k = sg.messy(s, d, k, seed=9)
+    rng = np.random.default_rng(5)
+    ids = np.concatenate([[0], np.sort(rng.choice(n - 2, size=k - 2, replace=False) + 1), [n - 1]])
+    ids = ids.astype(np.int64)
+    assert len(ids) == k and np.all(np.diff(ids) > 0)
+    U = oracle.preprocess(s, d, k)
+    T = oracle.count(U)
+    assert T == comb(6, 3) + 8 + 3
+    g = gpu_graph(tc, ids[s].astype(np.int32), ids[d].astype(np.int32), n)
+    info = g.info()
+    w = oracle.wedges(U)
+    assert info["n"] == n and info["m"] == U.m
+    assert (info["wedges_plus"], info["probes"], info["tasks"]) == (w["wedges_plus"], w["probes"], w["tasks"])
+    assert gpu_count(tc, g) == T
+    for mode in (oracle.MODE_FULL, oracle.MODE_ORIENTED):
+        Tr, s_ref = oracle.support(U, mode)
+        Tg, sup = gpu_support(tc, g, mode)
+        assert Tg == Tr == T
+        assert np.array_equal(sup, s_ref), "support mode %d differs" % mode
+    g.free()
