@@ -346,3 +346,25 @@ def test_largest_vertex_id_space(tc):
         assert Tg == Tr == T
         assert np.array_equal(sup, s_ref), "support mode %d differs" % mode
     g.free()
+
+
+def test_raw_edge_list_past_2_pow_31(tc):
+    # m_raw = 2^31 + 12345 raw pairs (a sort of 2^31 keys or more publishes
+    # its look-back state in 64-bit words): seeded random pairs over 40
+    # vertices are K40 with self loops and ~1.3 million duplicates of every
+    # pair, so T = C(40, 3), m = 780 and every edge has full support 38
+    m_raw = 2 ** 31 + 12345
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(31)
+    src = torch.randint(0, 40, (m_raw,), dtype=torch.int32, device="cuda", generator=gen)
+    dst = torch.randint(0, 40, (m_raw,), dtype=torch.int32, device="cuda", generator=gen)
+    print("case n=40 m_raw=%d" % m_raw, flush=True)
+    g = tc.tc_preprocess(src, dst, 40)
+    del src, dst
+    info = g.info()
+    assert info["m_raw"] == m_raw and info["m"] == comb(40, 2)
+    assert gpu_count(tc, g) == comb(40, 3)
+    Tg, sup = gpu_support(tc, g, tc.TC_SUPPORT_FULL)
+    assert Tg == comb(40, 3) and np.all(sup == 38)
+    g.free()
+    torch.cuda.empty_cache()
