@@ -11,8 +11,10 @@ preprocessing (ppt) are reported beside it.
 
 Roofline: every library launch in the timed steps is bracketed by HIP events
 (tc_timer_attach); the kernel with the largest total time is the dominant one
-and its algorithmic bytes per launch over its average event
-time give `achieved`.
+and its algorithmic bytes per launch (4 per probe + 4 per hashed-row key +
+12 per task + 32 per row of its class) over its average event time give
+`achieved`. `count_median_ms` times tc_count alone on the resident graph
+(2 warm-ups, median of 11).
 
 cpu_baseline: the CPU oracle (plain C, list-based intersection) timed end to
 end (its own preprocessing + count) on a bounded sample: the RMAT graph of the
@@ -365,8 +367,8 @@ def bench_served(tc, args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the count would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the count "
+              "would shard by replicating U on every GPU and splitting the tasks)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -438,6 +440,23 @@ def main():
 
     step_s = (t1 - t0) / args.steps
     count_ms = sum(v["total_ms"] for k, v in kern.items() if k.startswith("count:")) / args.steps
+    # count alone on the resident graph: 2 warm-ups, median of 11 (HIP events
+    # around tc_count on the current stream)
+    count_runs = []
+    if not args.copy_calibration:
+        g = tc.tc_preprocess(src, dst, n)
+        for r in range(13):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tc.tc_count(g, out)
+            e1.record()
+            e1.synchronize()
+            assert int(out.item()) == T
+            if r >= 2:
+                count_runs.append(e0.elapsed_time(e1))
+        g.free()
+    count_median_ms = float(np.median(count_runs)) if count_runs else None
     pre_kernel_ms = sum(v["total_ms"] for k, v in kern.items()
                         if not k.startswith("count:") and not k.startswith("_") and k != "zero_i64") / args.steps
     pre_ms = step_s * 1e3 - count_ms  # wall time of the step outside the count kernels
@@ -484,6 +503,8 @@ def main():
         "wedges_plus": info["wedges_plus"],
         "probes": info["probes"],
         "count_ms": count_ms,
+        "count_median_ms": round(count_median_ms, 4) if count_median_ms else None,
+        "count_median_edges_per_s": info["m"] / (count_median_ms / 1e3) if count_median_ms else None,
         "preprocess_ms": pre_ms,
         "preprocess_kernel_ms": pre_kernel_ms,
         "count_edges_per_s": info["m"] / (count_ms / 1e3) if count_ms > 0 else None,
