@@ -560,18 +560,23 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
                          sent, ka.as<uint64_t>(), d_err);
       TC_HIP(hipGetLastError());
     }
-    TC_REQUIRE(read_scalar(d_err, st) == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
+    // the id check is read back with the dedup count (one host sync for both)
+    int h_err = 0;
+    TC_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
     bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
                                            m_raw, 0, 2 * s, st, "dedup");
     const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
     UniquePred up{sorted, sent, s, nullptr, nullptr};
+    if (m_raw == 0) TC_HIP(hipStreamSynchronize(st));  // (compact has no sync then)
     m = compact("dedup", m_raw, up, [&](int64_t total, UniquePred& p) {
+      TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
       TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
       E.alloc(sizeof(uint64_t) * (size_t)total);
       Ehi.alloc(sizeof(uint32_t) * (size_t)total);
       p.out = E.as<uint64_t>();
       p.out_hi = Ehi.as<uint32_t>();
     }, st);
+    TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
     if (m == 0) E.alloc(sizeof(uint64_t));
   }
   g->m = m;
@@ -641,6 +646,11 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
               d_maxd);
     TC_HIP(hipGetLastError());
   }
+  // read back with the task count below (one host sync)
+  unsigned long long h_wplus = 0;
+  unsigned int h_maxd = 0;
+  TC_HIP(hipMemcpyAsync(&h_wplus, d_wplus, sizeof(h_wplus), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipMemcpyAsync(&h_maxd, d_maxd, sizeof(h_maxd), hipMemcpyDeviceToHost, st));
 
   // ---- 5: tasks grouped by hashed row b -----------------------------------
   TaskLists tl;
@@ -659,9 +669,10 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
         p.tval = tv.as<uint64_t>();
       }, st);
     }
+    if (m == 0) TC_HIP(hipStreamSynchronize(st));  // (no task count then)
     if (T > 0) sort_tasks(tl, tk, tv, T, n, s, st, "tasks");
-    g->wedges_plus = (int64_t)read_scalar(reinterpret_cast<uint64_t*>(d_wplus), st);
-    g->max_dplus = (int64_t)read_scalar(reinterpret_cast<uint32_t*>(d_maxd), st);
+    g->wedges_plus = (int64_t)h_wplus;
+    g->max_dplus = (int64_t)h_maxd;
   }
   E.release();
   ok.release();
@@ -730,7 +741,9 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     w.probes = 0;
     return;
   }
-  w.probes = (int64_t)read_scalar(tb_prefix + T, st);
+  // the probe total is read back with the row count below (one host sync)
+  uint64_t h_probes = 0;
+  TC_HIP(hipMemcpyAsync(&h_probes, tb_prefix + T, sizeof(h_probes), hipMemcpyDeviceToHost, st));
   DevBuf cls(sizeof(int8_t) * (size_t)n);
   DevBuf clsl(sizeof(int) * NUM_CLASSES);
   TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
@@ -751,6 +764,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     p.key = ckey.as<uint32_t>();
     p.row = crow_in.as<uint32_t>();
   }, st);
+  w.probes = (int64_t)h_probes;
   TC_REQUIRE(R > 0, TC_EDEVICE, "build_work: tasks but no row with work");
   uint32_t* crow = reinterpret_cast<uint32_t*>(own.alloc<int32_t>(R));  // pack classes keep their rows
   {
@@ -790,31 +804,45 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
                "build_work: class-major task order lost tasks");
     TC_HIP(hipGetLastError());
 
+    // packs of the two pack classes: flags for both, one host sync for both
+    // pack counts, then the pack pointers
+    DevBuf pf[2], pp[2];
+    DevBuf ptot(sizeof(uint32_t) * 2);
+    for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
+      const int64_t r0 = h_cp[c], total = h_cp[c + 1] - h_cp[c];
+      if (total == 0) continue;
+      int32_t* rows = reinterpret_cast<int32_t*>(crow + r0);
+      DevBuf wk(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
+      DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
+      TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, w.tbeg,
+                w.tend, w.tprefix, hrow_ptr, wk.as<uint64_t>(), sl.as<uint32_t>());
+      device_excl_scan<uint64_t, uint64_t>(wk.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
+      device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
+      pf[c].alloc(sizeof(uint32_t) * (size_t)total);
+      pp[c].alloc(sizeof(uint32_t) * (size_t)total);
+      TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
+                psl.as<uint32_t>(), total, pf[c].as<uint32_t>());
+      device_excl_scan<uint32_t, uint32_t>(pf[c].as<uint32_t>(), pp[c].as<uint32_t>(), total,
+                                           ptot.as<uint32_t>() + c, st);
+    }
+    uint32_t h_np[2] = {0, 0};
+    if (h_cp[CLS_PACK_LARGE + 1] > h_cp[CLS_PACK_SMALL]) {
+      TC_HIP(hipMemcpyAsync(h_np, ptot.p, sizeof(h_np), hipMemcpyDeviceToHost, st));
+      TC_HIP(hipStreamSynchronize(st));
+    }
     for (int c = 0; c < NUM_CLASSES; ++c) {
       w.cls_log2S[c] = h_cl[c];
       const int64_t r0 = h_cp[c], nr = h_cp[c + 1] - h_cp[c];
       if (nr == 0) continue;
       if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) {
-        int32_t* rows = reinterpret_cast<int32_t*>(crow + r0);
-        const int64_t total = nr;
-        DevBuf wk(sizeof(uint64_t) * (size_t)total), pw(sizeof(uint64_t) * (size_t)total);
-        DevBuf sl(sizeof(uint32_t) * (size_t)total), psl(sizeof(uint32_t) * (size_t)total);
-        TC_LAUNCH("rows_work", k_rows_work, dim3(grid_for(total)), dim3(kT), 0, st, rows, total, w.tbeg,
-                  w.tend, w.tprefix, hrow_ptr, wk.as<uint64_t>(), sl.as<uint32_t>());
-        device_excl_scan<uint64_t, uint64_t>(wk.as<uint64_t>(), pw.as<uint64_t>(), total, d_tot64, st);
-        device_excl_scan<uint32_t, uint32_t>(sl.as<uint32_t>(), psl.as<uint32_t>(), total, d_tot32, st);
-        DevBuf pf(sizeof(uint32_t) * (size_t)total), pp(sizeof(uint32_t) * (size_t)total);
-        TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
-                  psl.as<uint32_t>(), total, pf.as<uint32_t>());
-        device_excl_scan<uint32_t, uint32_t>(pf.as<uint32_t>(), pp.as<uint32_t>(), total, d_tot32, st);
-        const int64_t np = read_scalar(d_tot32, st);
+        const int64_t np = h_np[c];
         uint32_t* pack_ptr = own.alloc<uint32_t>(np + 1);
-        TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(total)), dim3(kT), 0, st, pf.as<uint32_t>(),
-                  pp.as<uint32_t>(), total, pack_ptr, np);
+        TC_LAUNCH("pack_emit", k_pack_emit, dim3(grid_for(nr)), dim3(kT), 0, st, pf[c].as<uint32_t>(),
+                  pp[c].as<uint32_t>(), nr, pack_ptr, np);
         TC_HIP(hipGetLastError());
-        w.pack_rows[c] = rows;
+        w.pack_rows[c] = reinterpret_cast<int32_t*>(crow + r0);
         w.pack_ptr[c] = pack_ptr;
-        w.n_pack_rows[c] = total;
+        w.n_pack_rows[c] = nr;
         w.n_packs[c] = np;
         w.pack_log2S[c] = h_cl[c];
       } else {
@@ -838,8 +866,8 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     TC_LAUNCH("reduce_cols", k_reduce_cols, dim3(kStatCols), dim3(kT), 0, st,
               part.as<unsigned long long>(), nb, kStatCols, sums.as<unsigned long long>());
     TC_HIP(hipGetLastError());
+    // (valid once st is synchronised: both callers check their sorts next)
     TC_HIP(hipMemcpyAsync(&w.cls_stats[0][0], sums.p, sizeof(w.cls_stats), hipMemcpyDeviceToHost, st));
-    TC_HIP(hipStreamSynchronize(st));
   }
 }
 
