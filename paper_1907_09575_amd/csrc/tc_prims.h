@@ -149,9 +149,9 @@ __global__ __launch_bounds__(256) void k_scan_final(L load, int64_t n, const Tou
 }
 
 // Stream that preprocessing temporaries are ordered on (set by TempStream).
-// While one is set, DevBuf allocates with hipMallocAsync and frees with
-// hipFreeAsync on it, from the device's default memory pool (which keeps
-// freed blocks for reuse), so freeing a temporary needs no synchronisation.
+// DevBuf allocates from the caching allocator on it and returns blocks to
+// the cache with an event recorded on it, so freeing a temporary needs no
+// synchronisation and the block is reused only after the work queued so far.
 struct TempCtx {
   bool active = false;
   hipStream_t st = nullptr;
