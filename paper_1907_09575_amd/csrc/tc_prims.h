@@ -125,26 +125,42 @@ __global__ __launch_bounds__(256) void k_scan_partials(T* __restrict__ partial, 
   if (total && threadIdx.x == 0) *total = carry;
 }
 
+// Tile scan with carry-in. Element j of the tile is item j / 256 of thread
+// j % 256 (striped: every load and store of a wave is one contiguous run);
+// each item row is scanned within its wave by shuffles, and one LDS exchange
+// of the 8 x 4 wave totals gives every element its offset.
 template <class L, class Tout>
 __global__ __launch_bounds__(256) void k_scan_final(L load, int64_t n, const Tout* __restrict__ partial,
                                                     Tout* __restrict__ out) {
-  __shared__ Tout s_w[4];
+  __shared__ Tout s_w[kScanItems][4];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   Tout v[kScanItems];
-  Tout local = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
+    const int64_t idx = base + (int64_t)i * kPrimThreads + threadIdx.x;
     v[i] = idx < n ? load(idx) : Tout(0);
-    local += v[i];
   }
-  Tout tot;
-  Tout ex = block_excl_scan(local, s_w, tot) + partial[blockIdx.x];
+  Tout inc[kScanItems];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-    if (idx < n) out[idx] = ex;
-    ex += v[i];
+    inc[i] = wave_incl_scan(v[i]);
+    if (lane == 63) s_w[i][wave] = inc[i];
+  }
+  __syncthreads();
+  Tout off = partial[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    Tout before = 0, row = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const Tout x = s_w[i][w];
+      if (w < wave) before += x;
+      row += x;
+    }
+    const int64_t idx = base + (int64_t)i * kPrimThreads + threadIdx.x;
+    if (idx < n) out[idx] = off + before + inc[i] - v[i];
+    off += row;
   }
 }
 
