@@ -60,16 +60,20 @@ DeviceCache& cache_for(int dev) {
   return c;
 }
 
-// Release cached blocks (waiting for their events) until at most `keep`
-// bytes stay cached. Called with g_mu held.
+// Release cached blocks until at most `keep` bytes stay cached. Called with
+// g_mu held. Blocks with pending work are waited for by one device
+// synchronisation (not through their events: the stream an event was
+// recorded on may have been destroyed since).
 void trim_locked(DeviceCache& c, size_t keep) {
+  bool synced = false;
   while (c.cached > keep && !c.free.empty()) {
     auto it = std::prev(c.free.end());  // largest first
     Block b = it->second;
     c.free.erase(it);
     c.cached -= b.size;
     if (b.ev) {
-      (void)hipEventSynchronize(b.ev);
+      if (!synced) (void)hipDeviceSynchronize();
+      synced = true;
       c.events.push_back(b.ev);
     }
     (void)hipFree(b.p);
@@ -157,6 +161,22 @@ void cache_free(void* p, hipStream_t st, bool idle) {
   c.free.emplace(b.size, b);
   c.cached += b.size;
   if (c.cached > c.cap) trim_locked(c, c.cap / 2);
+}
+
+void cache_retire_stream(hipStream_t st) {
+  if (!st) return;
+  (void)hipStreamSynchronize(st);
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_dev) {
+    DeviceCache& c = kv.second;
+    for (auto& fb : c.free) {
+      Block& b = fb.second;
+      if (b.st != st) continue;
+      if (b.ev) c.events.push_back(b.ev);  // its record has completed: the event is free again
+      b.ev = nullptr;
+      b.st = nullptr;
+    }
+  }
 }
 
 void cache_release_all() {

@@ -228,7 +228,10 @@ struct BatchPlan {
   }
   ~BatchPlan() {
     drop_graph();
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (cap_stream) {
+      cache_retire_stream(cap_stream);
+      (void)hipStreamDestroy(cap_stream);
+    }
   }
 };
 

@@ -125,6 +125,9 @@ __host__ __device__ inline int pack_table_log2(int64_t d) {
 void* cache_alloc(size_t bytes, hipStream_t st);
 void cache_free(void* p, hipStream_t st, bool idle);
 void cache_release_all();
+// Call before destroying a stream that blocks were freed on: synchronises it
+// and makes its cached blocks idle, so that no cached event refers to it.
+void cache_retire_stream(hipStream_t st);
 
 // Allocations owned by a graph or a temporary work set (freed together).
 // `st` is the stream they are used on; release(idle) returns them to the

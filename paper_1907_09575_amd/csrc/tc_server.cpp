@@ -288,7 +288,10 @@ struct Server {
       for (Req* q : failed) release(q);
       cv_sched.notify_all();
     }
-    if (st) (void)hipStreamDestroy(st);
+    if (st) {
+      cache_retire_stream(st);
+      (void)hipStreamDestroy(st);
+    }
   }
 
   // One tick: plans and launches over the ready requests, then (after the
@@ -651,7 +654,7 @@ void tc_server_destroy(tc_server* srv) {
       if (e->g) tc::destroy_graph_idle(e->g);
     s->cache.clear();
     if (s->tick_stream) {
-      (void)hipStreamSynchronize(s->tick_stream);
+      tc::cache_retire_stream(s->tick_stream);
       (void)hipStreamDestroy(s->tick_stream);
     }
     if (s->d_counts) (void)hipFree(s->d_counts);
