@@ -22,6 +22,12 @@
  *    host thread).
  *  - A tc_graph is immutable after tc_preprocess, so calls on one graph from
  *    several streams or threads may run concurrently.
+ *  - Device temporaries come from a per-device cache inside the library
+ *    (tc_release_cached_memory returns it); running out of device memory in
+ *    any call is TC_ENOMEM and leaves the library usable.
+ *  - Environment: TC_SORT_WIDE_WORDS=1 makes every internal radix sort use
+ *    the 64-bit look-back words that sorts of 2^31 keys or more take (a test
+ *    switch; results are identical).
  */
 #ifndef TC_H
 #define TC_H
