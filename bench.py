@@ -122,16 +122,21 @@ def cpu_baseline(scale: int, edge_factor: int, seed: int, threads: int, bench_sc
     t1 = time.perf_counter()
     T = oracle.count(U, threads=threads)
     t2 = time.perf_counter()
+    T1 = oracle.count(U, threads=1)  # the same count on one host thread
+    t3 = time.perf_counter()
+    assert T1 == T
     return {
         "value": len(src) / (t2 - t0),
         "unit": "edges/s",
         "cores": threads,
         "kind": "oracle",
+        "value_1thread": len(src) / ((t1 - t0) + (t3 - t2)),
         "sample": "RMAT scale %d (same generator and parameters, %d raw pairs = 1/%d of the benchmark "
-                  "input), oracle preprocessing + count end to end; count phase alone %.3g edges/s "
-                  "(m=%d, T=%d, %.2f s + %.2f s)" % (
-                      scale, len(src), 1 << max(0, bench_scale - scale), U.m / (t2 - t1), U.m, T,
-                      t1 - t0, t2 - t1),
+                  "input), oracle preprocessing (one thread) + count end to end; count phase alone "
+                  "%.3g edges/s on %d threads, %.3g on 1 (m=%d, T=%d, %.2f s + %.2f s; 1 thread: "
+                  "%.2f s)" % (
+                      scale, len(src), 1 << max(0, bench_scale - scale), U.m / (t2 - t1), threads,
+                      U.m / (t3 - t2), U.m, T, t1 - t0, t2 - t1, t3 - t2),
     }
 
 
