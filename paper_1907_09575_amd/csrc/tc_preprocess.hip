@@ -504,14 +504,6 @@ __global__ void k_emit_items(const uint32_t* __restrict__ offs, const uint32_t* 
   items[j] = it;
 }
 
-template <class T>
-T read_scalar(const T* d, hipStream_t st) {
-  T h{};
-  TC_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, st));
-  TC_HIP(hipStreamSynchronize(st));
-  return h;
-}
-
 }  // namespace
 
 struct GraphImpl : Graph {
