@@ -16,6 +16,11 @@ and its algorithmic bytes per launch (4 per probe + 4 per hashed-row key +
 `achieved`. `count_median_ms` times tc_count alone on the resident graph
 (2 warm-ups, median of 11).
 
+Beside the step: one rank's block of the 13 x 13 grid (`block`), per-edge
+support in both modes on a resident RMAT scale-20 graph (`support`), the
+batched form against the plain launch loop (`batched`) and the served form
+against a plain FIFO (`served`); each is skipped with its --no-* flag.
+
 cpu_baseline: the CPU oracle (plain C, list-based intersection) timed end to
 end (its own preprocessing + count) on a bounded sample: the RMAT graph of the
 same generator at a smaller scale (default 20, 1/16 of the pairs).
@@ -54,6 +59,8 @@ def parse():
     p.add_argument("--kernels-json", default=None, help="write the full per-kernel timer summary here")
     p.add_argument("--no-block", action="store_true", help="skip the 13x13 block grid of the graph")
     p.add_argument("--block-q", type=int, default=13)
+    p.add_argument("--no-support", action="store_true", help="skip the per-edge support leg")
+    p.add_argument("--support-scale", type=int, default=20)
     p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     p.add_argument("--batch-graphs", type=int, default=4096)
     p.add_argument("--no-serve", action="store_true", help="skip served vs plain FIFO")
@@ -181,6 +188,84 @@ def bench_block(tc, g, T, q):
         count_ms = sum(v["total_ms"] for kk, v in k.items() if kk.startswith("block:")) / reps
         out[name] = {"x": x, "y": y, "count": int(cnt.item()), "per_shift": ps.cpu().tolist(),
                      "ms_total": round(wall * 1e3, 3), "count_kernel_ms": round(count_ms, 3)}
+    return out
+
+
+def bench_support(tc, args):
+    """Per-edge support (Eq. 1) on a resident RMAT graph (default scale 20,
+    the support workload): tc_count, then tc_edge_support in FULL and ORIENTED
+    mode, each 2 warm-ups and the median of 5 (HIP events around the call on
+    the current stream). Every run is checked: sum of FULL = 3T, sum of
+    ORIENTED = T. Algorithmic bytes: the count's (count_kernel_bytes over the
+    classes), plus 4m to clear the support array and 4m to write it back, plus
+    for FULL the H_b edge ids read from the tables (4m) and two remote int32
+    read-modify-writes per triangle (16 T)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    dev = torch.device("cuda", 0)
+    scale = args.support_scale
+    src_h, dst_h = graphgen.rmat(scale, edge_factor=args.edge_factor, seed=args.seed,
+                                 threads=args.gen_threads)
+    m_raw = len(src_h)
+    src = torch.from_numpy(src_h).to(dev)
+    dst = torch.from_numpy(dst_h).to(dev)
+    del src_h, dst_h
+    g = tc.tc_preprocess(src, dst, 1 << scale)
+    del src, dst
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    tc.tc_count(g, cnt)
+    torch.cuda.synchronize()
+    T = int(cnt.item())
+    m = g.info()["m"]
+    cstats = tc.tc_graph_class_stats(g)
+    b_count = sum(count_kernel_bytes(cstats, c) for c in cstats if cstats[c]["rows"])
+    sup = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    out = {"workload": "rmat%d_ef%d_support" % (scale, args.edge_factor), "n": 1 << scale,
+           "m_raw": m_raw, "m": m, "triangles": T}
+    for name, mode, total, extra in (("full", tc.TC_SUPPORT_FULL, 3 * T, 12 * m + 16 * T),
+                                     ("oriented", tc.TC_SUPPORT_ORIENTED, T, 8 * m)):
+        runs = []
+        timer = tc.Timer(capacity=4096)
+        with timer:
+            for r in range(7):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                tc.tc_edge_support(g, mode, support=sup)
+                e1.record()
+                e1.synchronize()
+                s = int(sup[:m].sum(dtype=torch.int64).item())
+                assert s == total, "%s support sums to %d, not %d" % (name, s, total)
+                if r >= 2:
+                    runs.append(e0.elapsed_time(e1))
+        k = timer.summary()
+        timer.free()
+        kern_ms = sum(v["total_ms"] for kk, v in k.items() if kk.startswith("support_")) / 7
+        med = float(np.median(runs))
+        alg = b_count + extra
+        out[name] = {"median_ms": round(med, 4), "kernel_ms": round(kern_ms, 4),
+                     "edges_per_s": m / (med / 1e3), "raw_edges_per_s": m_raw / (med / 1e3),
+                     "alg_bytes": alg, "alg_GBps": round(alg / (med / 1e3) / 1e9, 1),
+                     "frac": round(alg / (med / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "sum_check": "3T" if name == "full" else "T"}
+    # the plain count on the same resident graph, for comparison
+    runs = []
+    for r in range(7):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tc.tc_count(g, cnt)
+        e1.record()
+        e1.synchronize()
+        assert int(cnt.item()) == T
+        if r >= 2:
+            runs.append(e0.elapsed_time(e1))
+    out["count_median_ms"] = round(float(np.median(runs)), 4)
+    g.free()
+    del sup
+    torch.cuda.empty_cache()
     return out
 
 
@@ -530,6 +615,9 @@ def main():
         g.free()
     del src, dst
     torch.cuda.empty_cache()
+    if not args.no_support:
+        print("support (RMAT scale %d) ..." % args.support_scale, file=sys.stderr, flush=True)
+        result["support"] = bench_support(tc, args)
     if not args.no_batch:
         result["batched"] = bench_batch(tc, args)
         torch.cuda.empty_cache()

@@ -153,7 +153,9 @@ __device__ unsigned int* shift_counters() {
   return s_shift;
 }
 
-template <int MODE, bool GLOBAL>
+// TASK_EDGE: also credit the task's own edge (a, b) here, one atomic per hit;
+// the main probe paths leave it to credit_task instead.
+template <int MODE, bool GLOBAL, bool TASK_EDGE>
 __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos,
                                        uint32_t ts, int32_t k) {
   // indices are checked against m so that no credit can leave the array
@@ -164,11 +166,34 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
     atomicAdd(&shift_counters()[z], 1u);
   } else if (MODE == MODE_SUPPORT_FULL) {
     const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
-    if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
-    if (pos < A.m) atomicAdd(&A.support[pos], 1);          // edge (a, k): probed entry of U_a
-    if (other < A.m) atomicAdd(&A.support[other], 1);      // edge (b, k): k's entry in U_b
+    if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
+    if (pos < A.m) atomicAdd(&A.support[pos], 1);      // edge (a, k): probed entry of U_a
+    if (other < A.m) atomicAdd(&A.support[other], 1);  // edge (b, k): k's entry in U_b
   } else if (MODE == MODE_SUPPORT_ORIENTED) {
-    if (ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
+    if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
+  }
+}
+
+// The task-edge credit of one row of 64 probes (support modes; every lane of
+// the wave calls it). Probes are laid out in task order, so the lanes of one
+// task are contiguous and share ts (the task's own U position + 1, distinct
+// per task): the first lane of each run adds the run's hits with one atomic
+// instead of one atomic per hit, which would serialise on one address.
+template <int MODE>
+__device__ __forceinline__ void credit_task(const Args& A, bool found, uint32_t ts) {
+  if (MODE != MODE_SUPPORT_FULL && MODE != MODE_SUPPORT_ORIENTED) return;
+  const uint64_t hitm = __ballot(found);
+  if (hitm == 0) return;
+  const int lane = lane_id();
+  const uint32_t prev = (uint32_t)__shfl_up((int)ts, 1, 64);
+  const bool head = lane == 0 || prev != ts;
+  const uint64_t headm = __ballot(head);
+  if (head) {
+    const uint64_t from = ~((1ull << lane) - 1ull);     // lanes >= this one
+    const uint64_t above = headm & ~((2ull << lane) - 1ull);  // later heads (none past lane 63)
+    const uint64_t upto = above ? (above & (0ull - above)) - 1ull : ~0ull;  // lanes before the next head
+    const uint32_t c = (uint32_t)__popcll(hitm & from & upto);
+    if (c && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], (int)c);
   }
 }
 
@@ -321,8 +346,9 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               found = j >= 0;
               if (found) {
                 ++hits;
-                credit<MODE, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
+                credit<MODE, false, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
               }
+              credit_task<MODE>(A, found, ts[u]);
             }
             unres[u] = ok[u] & !found & (v[u - g0].w != kEmpty);
             any_unres |= unres[u];
@@ -342,7 +368,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               } else {
                 const int j = match_slot(w, k[u]);
                 found = j >= 0;
-                if (found) credit<MODE, false>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
+                if (found) credit<MODE, false, true>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
               }
               hits += found ? 1u : 0u;
               unres[u] = !found & (w.w != kEmpty);
@@ -355,8 +381,9 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
           const int64_t where = ok[u] ? hbm_find(A.hcol, tr.rs, tr.d, k[u]) : -1;
           if (where >= 0) {
             ++hits;
-            if (MODE != MODE_COUNT) credit<MODE, true>(A, tr, (int)where, pos[u], ts[u], k[u]);
+            if (MODE != MODE_COUNT) credit<MODE, true, false>(A, tr, (int)where, pos[u], ts[u], k[u]);
           }
+          credit_task<MODE>(A, where >= 0, ts[u]);
         }
       }
     }
