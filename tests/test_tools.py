@@ -1,6 +1,6 @@
 """Host logic of the measurement tools (CPU): the PMC traffic scaling, the
 LDS / L2 ratio and launch-class summaries of rocprof_summary, and bench.py's
-algorithmic-bytes formula."""
+algorithmic-bytes formula, defaults and single-GPU refusal."""
 import csv
 import json
 import os
@@ -79,3 +79,28 @@ def test_count_kernel_bytes_formula():
     import bench
     stats = {"wg_large": {"probes": 10, "table_keys": 3, "tasks": 2, "rows": 1}}
     assert bench.count_kernel_bytes(stats, "wg_large") == 4 * 10 + 4 * 3 + 12 * 2 + 32 * 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # exits with status 2 and a message before any device work
+    import subprocess
+    for argv, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        e = dict(os.environ, **env)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True,
+                           text=True, env=e, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
+
+
+def test_bench_defaults():
+    import bench
+    saved = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        a = bench.parse()
+    finally:
+        sys.argv = saved
+    assert (a.gpus, a.steps, a.warmup, a.scale, a.edge_factor) == (1, 5, 2, 24, 16)
+    assert a.support_scale == 20 and a.block_q == 13 and a.batch_graphs == 4096
+    assert not (a.no_block or a.no_support or a.no_batch or a.no_serve or a.no_cpu_baseline)
