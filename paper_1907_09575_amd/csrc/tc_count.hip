@@ -58,6 +58,11 @@ constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bit
 constexpr int kMarkInts = kWaves * kBmWords;          // packs
 constexpr int kItemMarkInts = kWavesBig * kBmWords;   // item work-groups (up to 8 waves)
 constexpr int32_t kEmpty = -1;
+// FULL support, single-row LDS tables: a slot's value word is the key's index
+// in its row (< 2^13: such rows have at most 8192 keys) plus its hits in this
+// work-group times 2^13 (at most one per task, and a work-group holds at most
+// 8 wave items of 16384 probes: < 2^18, so the word stays below 2^31).
+constexpr int kValBits = 13;
 constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // byte offset past any col buffer
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -93,7 +98,8 @@ __device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int
 
 // Insert U_b = col[rs, rs + d) into a cleared bucketed table of (bmask + 1)
 // buckets; threads tid, tid + nt, ... share the work. Returns this thread's
-// longest bucket displacement. VALS: also store every key's U position.
+// longest bucket displacement. VALS: also store every key's index in the row
+// (its U position is rs + index), with a zero hit count above it.
 template <bool VALS>
 __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int32_t* __restrict__ col,
                            int64_t rs, int64_t d, int tid, int nt) {
@@ -122,7 +128,7 @@ __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int
         bk = (bk + 1) & bmask;
         ++disp;
       }
-      if (VALS) val[slot] = (int32_t)(rs + i0 + (int64_t)j * nt);
+      if (VALS) val[slot] = (int32_t)(i0 + (int64_t)j * nt);
       md = disp > md ? disp : md;
     }
   }
@@ -131,7 +137,8 @@ __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int
 
 struct TableRef {
   const int32_t* tab;  // (bmask + 1) * kBucket slots (a pack: all its rows' tables)
-  const int32_t* val;  // U positions (support mode)
+  int32_t* val;        // FULL support: packs hold U positions; single-row tables
+                       // hold row index | hits << kValBits (summed in LDS)
   uint32_t bmask;
   int D;
   int64_t rs, d;  // the row itself (HBM fallback)
@@ -155,7 +162,7 @@ __device__ unsigned int* shift_counters() {
 
 // TASK_EDGE: also credit the task's own edge (a, b) here, one atomic per hit;
 // the main probe paths leave it to credit_task instead.
-template <int MODE, bool GLOBAL, bool TASK_EDGE>
+template <int MODE, int KIND, bool TASK_EDGE>
 __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos,
                                        uint32_t ts, int32_t k) {
   // indices are checked against m so that no credit can leave the array
@@ -165,10 +172,16 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
     if (z < 0) z += A.q;
     atomicAdd(&shift_counters()[z], 1u);
   } else if (MODE == MODE_SUPPORT_FULL) {
-    const uint32_t other = (uint32_t)(GLOBAL ? where : t.val[where]);
     if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
-    if (pos < A.m) atomicAdd(&A.support[pos], 1);      // edge (a, k): probed entry of U_a
-    if (other < A.m) atomicAdd(&A.support[other], 1);  // edge (b, k): k's entry in U_b
+    if (pos < A.m) atomicAdd(&A.support[pos], 1);  // edge (a, k): probed entry of U_a
+    // edge (b, k): k's entry in U_b. A single-row table counts it in the
+    // slot's LDS word (flushed once per work-group by flush_row_hits).
+    if (KIND == TK_SINGLE) {
+      atomicAdd(&t.val[where], 1 << kValBits);
+    } else {
+      const uint32_t other = (uint32_t)(KIND == TK_GLOBAL ? where : t.val[where]);
+      if (other < A.m) atomicAdd(&A.support[other], 1);
+    }
   } else if (MODE == MODE_SUPPORT_ORIENTED) {
     if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
   }
@@ -346,7 +359,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               found = j >= 0;
               if (found) {
                 ++hits;
-                credit<MODE, false, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
+                credit<MODE, KIND, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
               }
               credit_task<MODE>(A, found, ts[u]);
             }
@@ -368,7 +381,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               } else {
                 const int j = match_slot(w, k[u]);
                 found = j >= 0;
-                if (found) credit<MODE, false, true>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
+                if (found) credit<MODE, KIND, true>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
               }
               hits += found ? 1u : 0u;
               unres[u] = !found & (w.w != kEmpty);
@@ -381,7 +394,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
           const int64_t where = ok[u] ? hbm_find(A.hcol, tr.rs, tr.d, k[u]) : -1;
           if (where >= 0) {
             ++hits;
-            if (MODE != MODE_COUNT) credit<MODE, true, false>(A, tr, (int)where, pos[u], ts[u], k[u]);
+            if (MODE != MODE_COUNT) credit<MODE, TK_GLOBAL, false>(A, tr, (int)where, pos[u], ts[u], k[u]);
           }
           credit_task<MODE>(A, where >= 0, ts[u]);
         }
@@ -505,7 +518,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
       bk = (bk + 1) & bmask;
       ++disp;
     }
-    if (VALS) val[slot] = (int32_t)p;
+    if (VALS) val[slot] = (int32_t)p;  // absolute U position (packs credit (b, k) directly)
     md = disp > md ? disp : md;
   }
   // (a plain LDS max per lane: a wave reduction here would share its lane
@@ -584,6 +597,18 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
   wave_sync_lds();
   const CountItem it = grp[wave];
   if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  if constexpr (VALS && !GLOBAL) {
+    // the (b, k) credits of the work-group: one atomic per slot that was hit
+    __syncthreads();
+    const uint32_t S = 1u << grp[0].log2S;
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+      if (tr.tab[i] == kEmpty) continue;
+      const uint32_t w = (uint32_t)tr.val[i];
+      const uint32_t c = w >> kValBits;
+      const int64_t p = rs + (int64_t)(w & ((1u << kValBits) - 1u));
+      if (c && p < (int64_t)A.m) atomicAdd(&A.support[p], (int)c);
+    }
+  }
   return block_flush<MODE>(hits, A);
 }
 
