@@ -175,7 +175,8 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
     if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
     if (pos < A.m) atomicAdd(&A.support[pos], 1);  // edge (a, k): probed entry of U_a
     // edge (b, k): k's entry in U_b. A single-row table counts it in the
-    // slot's LDS word (flushed once per work-group by flush_row_hits).
+    // slot's LDS word (added to the array once per work-group, after the
+    // probe loop of items_body).
     if (KIND == TK_SINGLE) {
       atomicAdd(&t.val[where], 1 << kValBits);
     } else {
