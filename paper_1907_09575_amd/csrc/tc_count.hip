@@ -63,6 +63,9 @@ constexpr int32_t kEmpty = -1;
 // work-group times 2^13 (at most one per task, and a work-group holds at most
 // 8 wave items of 16384 probes: < 2^18, so the word stays below 2^31).
 constexpr int kValBits = 13;
+static_assert((1 << kValBits) >= (1 << kMaxLog2S) / 2, "row index of an LDS table below the hit count");
+static_assert((uint64_t)kWavesBig * kWaveChunk < (1ull << (31 - kValBits)),
+              "hits of one slot in one work-group keep the value word below 2^31");
 constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // byte offset past any col buffer
 
 __device__ __forceinline__ void wave_sync_lds() {
