@@ -10,6 +10,7 @@ import pytest
 
 import graphgen
 import oracle
+import sampled_support
 import smallgraphs as sg
 
 torch = pytest.importorskip("torch")
@@ -132,8 +133,10 @@ def test_rmat_scale20(tc):
 def test_rmat_scale24_full_config(tc):
     # the benchmark's graph and launch configuration (RMAT scale 24, edge
     # factor 16, seed 1): the exported CSR and rank map equal the oracle's
-    # entry by entry, the total equals the oracle's Eq. 2, and the oriented
-    # support summed over sampled row ranges equals the oracle's row counts
+    # entry by entry, the total equals the oracle's Eq. 2, the oriented
+    # support summed over sampled row ranges equals the oracle's row counts,
+    # and full support sums to 3T and equals |Adj(a) & Adj(b)| on sampled
+    # edges (uniform ones and the longest rows, whose tables are the largest)
     n = 1 << 24
     s, d = graphgen.rmat(24, seed=1, threads=16)
     g = gpu_graph(tc, s, d, n)
@@ -157,6 +160,14 @@ def test_rmat_scale24_full_config(tc):
         hi = int(lo) + 2048
         want = oracle.count_rows(U, int(lo), hi, threads=16)
         assert int(sup[rp[lo]:rp[hi]].sum(dtype=np.int64)) == want, (lo, hi)
+    del sup
+    print("oriented support equal; full support ...", flush=True)
+    Tf, full = gpu_support(tc, g, tc.TC_SUPPORT_FULL)
+    assert Tf == T
+    assert int(full.sum(dtype=np.int64)) == 3 * T
+    pos = sampled_support.sample_positions(U.row_ptr, seed=24)
+    want = sampled_support.sampled_full_support(U.row_ptr, U.col, pos)
+    assert np.array_equal(full[pos].astype(np.int64), want)
 
 
 def test_edge_cases(tc):

@@ -286,3 +286,18 @@ def test_er_simple():
     assert np.all(s != d)
     keys = np.minimum(s, d).astype(np.int64) * 500 + np.maximum(s, d)
     assert len(np.unique(keys)) == 4000
+
+
+# -------------------------------------------- sampled full support helper --
+
+def test_sampled_full_support_helper():
+    # the large-graph spot check of full support equals the oracle's full
+    # support on every edge of a small graph and on the sampled ones of a
+    # larger graph
+    import sampled_support as ss
+    for scale, seed in ((10, 3), (14, 7)):
+        s, d = graphgen.rmat(scale, seed=seed)
+        U = oracle.preprocess(s, d, 1 << scale)
+        _, full = oracle.support(U, oracle.MODE_FULL)
+        pos = np.arange(U.m) if scale == 10 else ss.sample_positions(U.row_ptr, seed=scale)
+        assert np.array_equal(ss.sampled_full_support(U.row_ptr, U.col, pos), full[pos].astype(np.int64))
