@@ -14,13 +14,17 @@ Two layers:
   vertices) - the definitions of Section 2 written out with no ordering at
   all, used to pin the C layer.
 
-Parity status: every function here is pinned by closed forms, brute force or
-invariants in ``tests/test_oracle.py``; none is "parity unpinned".
+Parity status: each function is pinned in ``tests/test_oracle.py`` (and the
+property tests in ``tests/test_oracle_properties.py``) by something other
+than itself: closed forms, brute force over vertex triples or edge subsets,
+trace(A^3), or identities between independent functions (row-range sums
+against the total, per-rank work against the whole graph's). The pins of
+each function are listed in ``PINS`` below; a function missing from it would
+be "parity unpinned".
 """
 from __future__ import annotations
 
 import ctypes
-import itertools
 import os
 import subprocess
 from dataclasses import dataclass
@@ -59,9 +63,9 @@ def _load():
     lib.oc_simple_edges.argtypes = [P, P, I64, I64, P, P]
     lib.oc_simple_edges.restype = I64
     lib.oc_degree_order.argtypes = [P, P, I64, I64, P, P]
-    lib.oc_degree_order.restype = None
+    lib.oc_degree_order.restype = ctypes.c_int
     lib.oc_build_upper.argtypes = [P, P, I64, I64, P, P, P]
-    lib.oc_build_upper.restype = None
+    lib.oc_build_upper.restype = ctypes.c_int
     lib.oc_count.argtypes = [P, P, I64, ctypes.c_int]
     lib.oc_count.restype = I64
     lib.oc_count_rows.argtypes = [P, P, I64, I64, ctypes.c_int]
@@ -77,7 +81,13 @@ def _load():
     lib.oc_pair_common.argtypes = [P, P, I64, I64]
     lib.oc_pair_common.restype = I64
     lib.oc_build_adjacency.argtypes = [P, P, I64, I64, P, P]
-    lib.oc_build_adjacency.restype = None
+    lib.oc_build_adjacency.restype = ctypes.c_int
+    lib.oc_block_work.argtypes = [P, P, I64, I64, I64, I64, P]
+    lib.oc_block_work.restype = ctypes.c_int
+    lib.oc_vertex_triangles.argtypes = [P, P, I64, P]
+    lib.oc_vertex_triangles.restype = I64
+    lib.oc_truss.argtypes = [P, P, I64, P]
+    lib.oc_truss.restype = I64
     lib.oc_max_threads.argtypes = []
     lib.oc_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -86,6 +96,12 @@ def _load():
 
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ok(rc):
+    if rc == -2:
+        raise MemoryError("oracle allocation failed")
+    return rc
 
 
 def max_threads() -> int:
@@ -132,11 +148,12 @@ def preprocess(src, dst, n) -> Upper:
     m = len(lo)
     deg = np.empty(max(n, 1), np.int32)
     rank = np.empty(max(n, 1), np.int32)
-    lib.oc_degree_order(lo.ctypes.data, hi.ctypes.data, m, int(n), deg.ctypes.data, rank.ctypes.data)
+    _ok(lib.oc_degree_order(lo.ctypes.data, hi.ctypes.data, m, int(n), deg.ctypes.data,
+                            rank.ctypes.data))
     row_ptr = np.empty(n + 1, np.int64)
     col = np.empty(max(m, 1), np.int32)
-    lib.oc_build_upper(lo.ctypes.data, hi.ctypes.data, m, int(n), rank.ctypes.data,
-                       row_ptr.ctypes.data, col.ctypes.data)
+    _ok(lib.oc_build_upper(lo.ctypes.data, hi.ctypes.data, m, int(n), rank.ctypes.data,
+                           row_ptr.ctypes.data, col.ctypes.data))
     return Upper(int(n), lo, hi, deg[:n], rank[:n], row_ptr, col[:m])
 
 
@@ -147,6 +164,7 @@ def count(U: Upper, threads: int | None = None) -> int:
 
 
 def count_rows(U: Upper, a_lo: int, a_hi: int, threads: int | None = None) -> int:
+    """Eq. 2's sum over the rows a of U in [a_lo, a_hi) only."""
     return int(_load().oc_count_rows(U.row_ptr.ctypes.data, U.col.ctypes.data, int(a_lo),
                                      int(a_hi), int(threads or max_threads())))
 
@@ -199,9 +217,53 @@ def adjacency(lo, hi, n) -> Adjacency:
     m = len(lo)
     ptr = np.empty(n + 1, np.int64)
     adj = np.empty(max(2 * m, 1), np.int32)
-    _load().oc_build_adjacency(lo.ctypes.data, hi.ctypes.data, m, int(n), ptr.ctypes.data,
-                               adj.ctypes.data)
+    _ok(_load().oc_build_adjacency(lo.ctypes.data, hi.ctypes.data, m, int(n), ptr.ctypes.data,
+                                   adj.ctypes.data))
     return Adjacency(int(n), ptr, adj[:2 * m])
+
+
+def block_work(U: Upper, q: int, x: int, y: int) -> dict:
+    """Work of rank (x, y) of the q x q grid (Section 5.1; Section 7.2's
+    balance and intersection-count tables): tasks, probes, probes per shift
+    (closing vertex in the shift's residue class, Eq. 5) and the tasks each
+    shift would intersect (probe list and hashed list both hold an entry of
+    that class)."""
+    out = np.zeros(2 + 2 * q, np.int64)
+    _ok(_load().oc_block_work(U.row_ptr.ctypes.data, U.col.ctypes.data, U.n, int(q), int(x), int(y),
+                              out.ctypes.data))
+    return {"tasks": int(out[0]), "probes": int(out[1]), "shift_probes": out[2:2 + q].copy(),
+            "shift_tasks": out[2 + q:].copy()}
+
+
+def vertex_triangles(U: Upper) -> np.ndarray:
+    """t[v] = triangles containing original vertex v (int64[n])."""
+    t = np.zeros(max(U.n, 1), np.int64)
+    _load().oc_vertex_triangles(U.row_ptr.ctypes.data, U.col.ctypes.data, U.n, t.ctypes.data)
+    return t[U.rank]
+
+
+def clustering(U: Upper):
+    """Local clustering coefficients and transitivity from per-vertex
+    triangle counts (Section 1's application): cc[v] = t(v) / C(d(v), 2) in
+    float64 (0 where d(v) < 2), transitivity = 3 T / sum_v C(d(v), 2) (0 if
+    there is no pair of adjacent edges). Both are one division of two exact
+    integers, so they are correctly rounded."""
+    t = vertex_triangles(U)
+    d = U.deg.astype(np.int64)
+    pairs = d * (d - 1) // 2
+    cc = np.zeros(U.n, np.float64)
+    nz = pairs > 0
+    cc[nz] = t[nz].astype(np.float64) / pairs[nz].astype(np.float64)
+    W = int(pairs.sum())
+    T3 = int(t.sum())  # = 3 T
+    return cc, (float(T3) / float(W) if W else 0.0), t, W
+
+
+def truss(U: Upper):
+    """(largest trussness, int32 trussness of every edge in U order)."""
+    tau = np.zeros(max(U.m, 1), np.int32)
+    kmax = _ok(_load().oc_truss(U.row_ptr.ctypes.data, U.col.ctypes.data, U.n, tau.ctypes.data))
+    return int(kmax), tau[:U.m]
 
 
 # ---------------------------------------------------------------------------
@@ -243,11 +305,29 @@ def brute_edge_support(src, dst, n) -> dict:
     return {e: sum(1 for w in range(n) if all(w in adj[x] for x in e)) for e in E}
 
 
-def brute_triangles(src, dst, n):
-    """All triangles as sorted vertex triples (original ids)."""
-    E = brute_edge_set(src, dst)
-    out = []
-    for i, j, k in itertools.combinations(range(n), 3):
-        if frozenset((i, j)) in E and frozenset((i, k)) in E and frozenset((j, k)) in E:
-            out.append((i, j, k))
-    return out
+# The CPU tests that pin each function against something other than itself
+# (closed forms, brute force, independent identities).
+PINS = {
+    "simple_edges": ["test_preprocess_structure", "test_count_is_the_triple_definition"],
+    "preprocess": ["test_preprocess_structure", "test_preprocess_idempotent_on_simple_input",
+                   "test_out_of_range_rejected", "test_oriented_support_is_eq1"],
+    "count": ["test_closed_forms", "test_brute_force_random", "test_trace_a_cubed",
+              "test_count_is_the_triple_definition", "test_relabel_duplicate_and_loop_invariance"],
+    "count_rows": ["test_count_rows_partition_sums_to_total", "test_count_rows_single_row_is_eq1_by_sets",
+                   "test_count_rows_empty_and_closed_form", "test_count_rows_equals_oriented_support_row_sums"],
+    "support": ["test_support_complete", "test_support_wheel_and_friendship", "test_support_tripartite",
+                "test_support_brute", "test_full_support_is_triangles_per_edge", "test_oriented_support_is_eq1"],
+    "wedges": ["test_wedges_brute"],
+    "block_counts": ["test_block_counts", "test_blocks_and_shifts_decompose_T"],
+    "block_count_one": ["test_block_counts", "test_blocks_and_shifts_decompose_T"],
+    "block_work": ["test_block_work_sums_over_ranks", "test_block_work_by_sets"],
+    "adjacency": ["test_pair_common_matches_support"],
+    "vertex_triangles": ["test_vertex_triangles_closed_forms", "test_vertex_triangles_diagonal_of_a_cubed",
+                         "test_vertex_triangles_are_triangles_through_each_vertex"],
+    "clustering": ["test_clustering_closed_forms", "test_transitivity_matches_counts"],
+    "truss": ["test_truss_closed_forms", "test_truss_brute_force_over_subsets", "test_truss_invariants_rmat",
+              "test_truss_is_the_subset_definition"],
+    "brute_edge_set": ["test_er_simple", "test_preprocess_structure"],
+    "brute_count": ["test_closed_forms_brute"],
+    "brute_edge_support": ["test_support_brute_closed_forms"],
+}

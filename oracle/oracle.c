@@ -41,12 +41,32 @@
  *                     Eq. 5 contributes the triangles whose closing vertex k has
  *                     k % q == (x + y + z) % q.
  *   oc_block_count_one  the same for one rank (x, y) only.
+ *   oc_count_rows     Eq. 2's sum restricted to the rows a of U in [a_lo, a_hi).
+ *   oc_block_work     the work of one rank (x, y) of the same decomposition:
+ *                     its tasks and probes under the <j,i,k> rule, the probes
+ *                     whose closing vertex falls in each shift's residue class,
+ *                     and per shift the intersections a rank would perform
+ *                     (both the probe list and the hashed list hold an entry
+ *                     of that residue class).
  *   oc_pair_common    |Adj(u) & Adj(v)| for one pair by joint traversal of the
  *                     two full sorted adjacency lists (the definition of a
  *                     triangle in Section 2), for spot checks on large graphs.
+ *   oc_vertex_triangles  per-vertex triangle counts t(v) (Section 1 names local
+ *                     clustering coefficients as a use of triangle counts):
+ *                     each triangle a<b<k found by Eq. 1 adds one to each of
+ *                     its three vertices.
+ *   oc_truss          trussness of every edge (Section 1 names the k-truss as
+ *                     a use of per-edge triangle counts): the k-truss is the
+ *                     largest subgraph whose every edge lies in at least k - 2
+ *                     of its triangles; computed level by level from that
+ *                     definition, recounting every edge's triangles inside the
+ *                     remaining subgraph after each round of deletions.
  *
  * Integer widths: counts are int64 (Table "datasets" has counts near 5e11);
  * per-edge values int32.
+ *
+ * Errors: functions that allocate return a negative value (-2) when malloc
+ * fails; the Python layer turns it into MemoryError.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -99,18 +119,20 @@ int64_t oc_simple_edges(const int32_t* src, const int32_t* dst, int64_t m_raw, i
  * deg[v] = |Adj(v)| in the simple graph. rank[v] = position of v after
  * sorting all vertices by (deg, v) ascending.
  * ------------------------------------------------------------------------- */
-void oc_degree_order(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, int32_t* deg,
-                     int32_t* rank) {
+int oc_degree_order(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, int32_t* deg,
+                    int32_t* rank) {
+  uint64_t* key = (uint64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
+  if (!key) return -2;
   for (int64_t v = 0; v < n; ++v) deg[v] = 0;
   for (int64_t e = 0; e < m; ++e) {
     deg[lo[e]]++;
     deg[hi[e]]++;
   }
-  uint64_t* key = (uint64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
   for (int64_t v = 0; v < n; ++v) key[v] = ((uint64_t)(uint32_t)deg[v] << 32) | (uint64_t)v;
   qsort(key, (size_t)n, sizeof(uint64_t), cmp_u64);
   for (int64_t r = 0; r < n; ++r) rank[key[r] & 0xFFFFFFFFu] = (int32_t)r;
   free(key);
+  return 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -118,9 +140,10 @@ void oc_degree_order(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n,
  * Row a holds Adj>(a) = {rank(w) : {v, w} in E, rank(v) = a, rank(w) > a},
  * sorted ascending. row_ptr has n + 1 entries.
  * ------------------------------------------------------------------------- */
-void oc_build_upper(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, const int32_t* rank,
-                    int64_t* row_ptr, int32_t* col) {
+int oc_build_upper(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, const int32_t* rank,
+                   int64_t* row_ptr, int32_t* col) {
   uint64_t* key = (uint64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint64_t));
+  if (!key) return -2;
   for (int64_t e = 0; e < m; ++e) {
     uint64_t ru = (uint64_t)rank[lo[e]], rv = (uint64_t)rank[hi[e]];
     uint64_t a = ru < rv ? ru : rv, b = ru < rv ? rv : ru;
@@ -132,6 +155,7 @@ void oc_build_upper(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, 
   for (int64_t a = 0; a < n; ++a) row_ptr[a + 1] += row_ptr[a];
   for (int64_t e = 0; e < m; ++e) col[e] = (int32_t)(key[e] & 0xFFFFFFFFu);
   free(key);
+  return 0;
 }
 
 /* |U_a & U_b| restricted to k > b, by joint traversal of the two sorted lists
@@ -164,8 +188,9 @@ int64_t oc_count(const int64_t* row_ptr, const int32_t* col, int64_t n, int nthr
   return total;
 }
 
-/* Count restricted to the rows a in [a_lo, a_hi) (a bounded sample of Eq. 2's
- * sum, used to time the oracle). */
+/* Eq. 2's sum restricted to the rows a in [a_lo, a_hi): the triangles whose
+ * lowest-ranked vertex lies in that range (a bounded sample of the sum, used
+ * to time the oracle and to check per-row sums of oriented support). */
 int64_t oc_count_rows(const int64_t* row_ptr, const int32_t* col, int64_t a_lo, int64_t a_hi,
                       int nthreads) {
   int64_t total = 0;
@@ -323,9 +348,10 @@ int64_t oc_pair_common(const int64_t* adj_ptr, const int32_t* adj, int64_t u, in
 
 /* Full symmetric adjacency of the simple graph, lists sorted (for
  * oc_pair_common). adj has 2m entries, adj_ptr n + 1. */
-void oc_build_adjacency(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, int64_t* adj_ptr,
-                        int32_t* adj) {
+int oc_build_adjacency(const int32_t* lo, const int32_t* hi, int64_t m, int64_t n, int64_t* adj_ptr,
+                       int32_t* adj) {
   uint64_t* key = (uint64_t*)malloc((size_t)(2 * m > 0 ? 2 * m : 1) * sizeof(uint64_t));
+  if (!key) return -2;
   for (int64_t e = 0; e < m; ++e) {
     key[2 * e] = ((uint64_t)(uint32_t)lo[e] << 32) | (uint32_t)hi[e];
     key[2 * e + 1] = ((uint64_t)(uint32_t)hi[e] << 32) | (uint32_t)lo[e];
@@ -336,6 +362,164 @@ void oc_build_adjacency(const int32_t* lo, const int32_t* hi, int64_t m, int64_t
   for (int64_t v = 0; v < n; ++v) adj_ptr[v + 1] += adj_ptr[v];
   for (int64_t e = 0; e < 2 * m; ++e) adj[e] = (int32_t)(key[e] & 0xFFFFFFFFu);
   free(key);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Work of one rank (x, y) of the q x q cyclic decomposition (Section 5.1,
+ * C[L] convention; Section 7.2 reports its per-shift balance and how the
+ * number of intersections grows with the number of ranks).
+ * The rank's tasks are the nonzeros (i, j) of U with j % q == x, i % q == y
+ * whose row i has entries after j and whose row j is not empty (the <j,i,k>
+ * rule of Section 3.1 with empty hashed lists skipped); each such task probes
+ * the entries k of U_i after j.
+ * out[0]        tasks
+ * out[1]        probes
+ * out[2 + z]    probes whose k has k % q == (x + y + z) % q (shift z of Eq. 5)
+ * out[2 + q + z] tasks that shift z would intersect: both the task's probe
+ *               list and U_j hold an entry of that residue class.
+ * Returns 0, or -2 if malloc fails.
+ * ------------------------------------------------------------------------- */
+int oc_block_work(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t q, int64_t x, int64_t y,
+                  int64_t* out) {
+  char* in_probe = (char*)malloc((size_t)q);
+  char* in_hash = (char*)malloc((size_t)q);
+  if (!in_probe || !in_hash) {
+    free(in_probe);
+    free(in_hash);
+    return -2;
+  }
+  for (int64_t c = 0; c < 2 + 2 * q; ++c) out[c] = 0;
+  for (int64_t i = y; i < n; i += q) {
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int64_t j = col[p];
+      if (j % q != x) continue;
+      int64_t after = row_ptr[i + 1] - p - 1;
+      int64_t dj = row_ptr[j + 1] - row_ptr[j];
+      if (after <= 0 || dj <= 0) continue;
+      out[0] += 1;
+      out[1] += after;
+      memset(in_probe, 0, (size_t)q);
+      memset(in_hash, 0, (size_t)q);
+      for (int64_t a = p + 1; a < row_ptr[i + 1]; ++a) {
+        int64_t z = ((col[a] % q) - x - y) % q;
+        if (z < 0) z += q;
+        out[2 + z] += 1;
+        in_probe[z] = 1;
+      }
+      for (int64_t b = row_ptr[j]; b < row_ptr[j + 1]; ++b) {
+        int64_t z = ((col[b] % q) - x - y) % q;
+        if (z < 0) z += q;
+        in_hash[z] = 1;
+      }
+      for (int64_t z = 0; z < q; ++z) out[2 + q + z] += in_probe[z] && in_hash[z];
+    }
+  }
+  free(in_probe);
+  free(in_hash);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Per-vertex triangle counts in rank space: t[v] = number of triangles that
+ * contain v. Every triangle a < b < k is found once, by Eq. 1's intersection
+ * for the nonzero (a, b), and adds one to t[a], t[b] and t[k].
+ * Returns T.
+ * ------------------------------------------------------------------------- */
+int64_t oc_vertex_triangles(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t* t) {
+  int64_t total = 0;
+  for (int64_t v = 0; v < n; ++v) t[v] = 0;
+  for (int64_t a = 0; a < n; ++a) {
+    for (int64_t p = row_ptr[a]; p < row_ptr[a + 1]; ++p) {
+      int64_t b = col[p];
+      int64_t i = row_ptr[a], ie = row_ptr[a + 1], j = row_ptr[b], je = row_ptr[b + 1];
+      while (i < ie && j < je) {
+        if (col[i] < col[j]) ++i;
+        else if (col[i] > col[j]) ++j;
+        else {
+          t[a]++;
+          t[b]++;
+          t[col[i]]++;
+          ++total;
+          ++i;
+          ++j;
+        }
+      }
+    }
+  }
+  return total;
+}
+
+/* ---------------------------------------------------------------------------
+ * Trussness of every edge, indexed by U position. The k-truss (k >= 2) is the
+ * largest subgraph in which every edge lies in at least k - 2 triangles of
+ * that subgraph; the trussness of an edge is the largest k whose k-truss
+ * holds it (every edge is in the 2-truss).
+ * Level by level from the definition: H starts as the whole graph (the
+ * 2-truss). For k = 3, 4, ...: count every edge's triangles inside H, delete
+ * from H every edge with fewer than k - 2 of them (their trussness is k - 1),
+ * and count again, until a round deletes nothing; H is then the k-truss.
+ * (Deleting only lowers the counts of other edges, and an edge of any
+ * subgraph that meets the k-truss condition keeps at least k - 2 triangles in
+ * every H containing that subgraph, so no such edge is ever deleted.)
+ * Triangles inside H are found by the joint traversal of Eq. 1 over the
+ * entries of U still in H. Returns the largest trussness (0 for a graph
+ * without edges), or -2 if malloc fails.
+ * ------------------------------------------------------------------------- */
+int64_t oc_truss(const int64_t* row_ptr, const int32_t* col, int64_t n, int32_t* tau) {
+  const int64_t m = row_ptr[n];
+  char* alive = (char*)malloc((size_t)(m > 0 ? m : 1));
+  int64_t* sup = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+  if (!alive || !sup) {
+    free(alive);
+    free(sup);
+    return -2;
+  }
+  for (int64_t p = 0; p < m; ++p) {
+    alive[p] = 1;
+    tau[p] = 0;
+  }
+  int64_t left = m, kmax = 0;
+  for (int64_t k = 3; left > 0; ++k) {
+    for (;;) {
+      /* triangles of every edge of H */
+      for (int64_t p = 0; p < m; ++p) sup[p] = 0;
+      for (int64_t a = 0; a < n; ++a) {
+        for (int64_t p = row_ptr[a]; p < row_ptr[a + 1]; ++p) {
+          if (!alive[p]) continue;
+          int64_t b = col[p];
+          int64_t i = row_ptr[a], ie = row_ptr[a + 1], j = row_ptr[b], je = row_ptr[b + 1];
+          while (i < ie && j < je) {
+            if (col[i] < col[j]) ++i;
+            else if (col[i] > col[j]) ++j;
+            else {
+              if (alive[i] && alive[j]) { /* edges (a, k) and (b, k) also in H */
+                sup[p]++;
+                sup[i]++;
+                sup[j]++;
+              }
+              ++i;
+              ++j;
+            }
+          }
+        }
+      }
+      int64_t deleted = 0;
+      for (int64_t p = 0; p < m; ++p) {
+        if (alive[p] && sup[p] < k - 2) {
+          alive[p] = 0;
+          tau[p] = (int32_t)(k - 1);
+          ++deleted;
+        }
+      }
+      left -= deleted;
+      if (deleted) kmax = k - 1;
+      if (deleted == 0 || left == 0) break;
+    }
+  }
+  free(alive);
+  free(sup);
+  return kmax;
 }
 
 int oc_max_threads(void) {

@@ -141,3 +141,19 @@ CLOSED_FORMS = [
     ("tree200", lambda: random_tree(200, 3), 0),
     ("grid9x11", lambda: grid(9, 11), 0),
 ]
+
+
+def cliques_sharing_vertex(p, q):
+    """K_p and K_q with one common vertex (0): trussness p inside the first
+    clique, q inside the second."""
+    a = list(range(p))
+    b = [0] + list(range(p, p + q - 1))
+    pairs = list(itertools.combinations(a, 2)) + list(itertools.combinations(b, 2))
+    return _arr(pairs, p + q - 1)
+
+
+def clique_with_pendants(p, k):
+    """K_p plus k pendant vertices hung on vertex 0: trussness p on the
+    clique's edges, 2 on the pendant edges."""
+    pairs = list(itertools.combinations(range(p), 2)) + [(0, p + i) for i in range(k)]
+    return _arr(pairs, p + k)

@@ -1,5 +1,7 @@
 """Pins for the CPU oracle (no GPU): closed forms, brute force, trace(A^3)/6,
 invariants and the paper's decomposition identities (Eq. 2, Eq. 5)."""
+import importlib.util
+import os
 from math import comb
 
 import numpy as np
@@ -301,3 +303,91 @@ def test_sampled_full_support_helper():
         _, full = oracle.support(U, oracle.MODE_FULL)
         pos = np.arange(U.m) if scale == 10 else ss.sample_positions(U.row_ptr, seed=scale)
         assert np.array_equal(ss.sampled_full_support(U.row_ptr, U.col, pos), full[pos].astype(np.int64))
+
+
+# ------------------------------------------------------- row-range sums ---
+
+def test_count_rows_partition_sums_to_total():
+    # Eq. 2's sum split at random row boundaries adds up to the whole sum
+    s, d = graphgen.rmat(12, seed=31)
+    U = oracle.preprocess(s, d, 1 << 12)
+    T = oracle.count(U)
+    rng = np.random.default_rng(31)
+    cuts = np.unique(np.concatenate([[0, U.n], rng.integers(0, U.n, 17)]))
+    parts = [oracle.count_rows(U, int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    assert sum(parts) == T
+    assert oracle.count_rows(U, 0, U.n, threads=1) == T
+
+
+def test_count_rows_single_row_is_eq1_by_sets():
+    # one row a: sum over b in U_a of |U_a & U_b| (Eq. 1), by Python sets
+    s, d = graphgen.rmat(10, seed=32)
+    U = oracle.preprocess(s, d, 1 << 10)
+    rows = [set(U.col[U.row_ptr[a]:U.row_ptr[a + 1]].tolist()) for a in range(U.n)]
+    for a in range(U.n):
+        want = sum(len(rows[a] & rows[b]) for b in rows[a])
+        assert oracle.count_rows(U, a, a + 1, threads=1) == want, a
+
+
+def test_count_rows_empty_and_closed_form():
+    n = 30
+    U = oracle.preprocess(*sg.complete(n))
+    # K_n: every degree is n - 1, so rank = id and U_a = {a + 1, ..., n - 1};
+    # row a closes C(n - 1 - a, 2) triangles (its lowest vertex is a)
+    for a in range(n):
+        assert oracle.count_rows(U, a, a + 1) == comb(n - 1 - a, 2)
+        assert oracle.count_rows(U, a, a) == 0
+    assert oracle.count_rows(U, 7, 3) == 0
+
+
+def test_count_rows_equals_oriented_support_row_sums():
+    s, d = graphgen.rmat(11, seed=33)
+    U = oracle.preprocess(s, d, 1 << 11)
+    _, so = oracle.support(U, oracle.MODE_ORIENTED)
+    for lo, hi in [(0, 1), (0, 100), (517, 1203), (2000, 2048), (1500, 1501)]:
+        assert oracle.count_rows(U, lo, hi) == int(so[U.row_ptr[lo]:U.row_ptr[hi]].sum())
+
+
+# ---------------------------------------------------------- registry ------
+
+def test_every_oracle_function_is_pinned():
+    # every public oracle function names the tests that pin it, and they exist
+    import inspect
+    import sys
+    public = {name for name, f in inspect.getmembers(oracle, inspect.isfunction)
+              if not name.startswith("_") and f.__module__ == "oracle"}
+    public -= {"build", "max_threads"}
+    assert public <= set(oracle.PINS), sorted(public - set(oracle.PINS))
+    here = os.path.dirname(os.path.abspath(__file__))
+    known = {}
+    for fn in ("test_oracle.py", "test_oracle_apps.py", "test_oracle_properties.py"):
+        mod = os.path.splitext(fn)[0]
+        if mod not in sys.modules:
+            spec = importlib.util.spec_from_file_location(mod, os.path.join(here, fn))
+            m = importlib.util.module_from_spec(spec)
+            spec.loader.exec_module(m)
+        else:
+            m = sys.modules[mod]
+        known.update({k: fn for k in dir(m) if k.startswith("test_")})
+    for name, tests in oracle.PINS.items():
+        assert tests, name
+        for t in tests:
+            assert t in known, (name, t)
+
+
+# ---------------------------------------------- the brute-force layer -----
+
+@pytest.mark.parametrize("name,make,expected", [c for c in sg.CLOSED_FORMS if c[0] not in ("K40", "wheel100")],
+                         ids=[c[0] for c in sg.CLOSED_FORMS if c[0] not in ("K40", "wheel100")])
+def test_closed_forms_brute(name, make, expected):
+    # the pure-Python triple count agrees with the textbook values too
+    assert oracle.brute_count(*make()) == expected
+
+
+def test_support_brute_closed_forms():
+    sup = oracle.brute_edge_support(*sg.complete(9))
+    assert len(sup) == comb(9, 2) and set(sup.values()) == {7}
+    sup = oracle.brute_edge_support(*sg.wheel(8))
+    assert all(v == (2 if 0 in e else 1) for e, v in sup.items())
+    sup = oracle.brute_edge_support(*sg.complete_bipartite(3, 4))
+    assert set(sup.values()) == {0}

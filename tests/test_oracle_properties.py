@@ -12,7 +12,11 @@ invariants rather than against itself:
 - oriented support of U's edge (a, b) is Eq. 1, the number of k > b adjacent
   to both (rank space), and sums to T;
 - the q x q blocks of Section 5.1 sum to T, their shifts (Eq. 5) to each
-  block, and one rank computed alone equals its entry of the grid.
+  block, and one rank computed alone equals its entry of the grid;
+- per-vertex triangle counts equal the number of triangles through each
+  vertex (brute force over triples);
+- trussness of every edge equals its definition over all edge subsets
+  (graphs of at most 11 edges).
 """
 import numpy as np
 import pytest
@@ -130,6 +134,46 @@ def test_blocks_and_shifts_decompose_T(g, q, data):
     b, s = oracle.block_count_one(U, q, x, y)
     assert b == int(B[x, y])
     assert np.array_equal(s, S[x, y])
+
+
+@SETTINGS
+@given(raw_graphs(max_n=18, max_pairs=90))
+def test_vertex_triangles_are_triangles_through_each_vertex(g):
+    src, dst, n = g
+    E = oracle.brute_edge_set(src, dst)
+    t = np.zeros(n, np.int64)
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                if {frozenset((i, j)), frozenset((i, k)), frozenset((j, k))} <= E:
+                    t[[i, j, k]] += 1
+    assert np.array_equal(oracle.vertex_triangles(oracle.preprocess(src, dst, n)), t)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(raw_graphs(max_n=7, max_pairs=14))
+def test_truss_is_the_subset_definition(g):
+    src, dst, n = g
+    E = sorted(tuple(sorted(e)) for e in oracle.brute_edge_set(src, dst))
+    if len(E) > 11:
+        E = E[:11]
+        src = np.array([e[0] for e in E], np.int32)
+        dst = np.array([e[1] for e in E], np.int32)
+    want = {e: 2 for e in E}
+    for mask in range(1, 1 << len(E)):
+        H = [E[i] for i in range(len(E)) if mask >> i & 1]
+        adj = {}
+        for u, v in H:
+            adj.setdefault(u, set()).add(v)
+            adj.setdefault(v, set()).add(u)
+        low = min(len(adj[u] & adj[v]) for u, v in H)
+        for e in H:
+            want[e] = max(want[e], low + 2)
+    U = oracle.preprocess(src, dst, n)
+    _, tau = oracle.truss(U)
+    edges = [tuple(sorted(e)) for e in original_edges(U)]
+    assert dict(zip(edges, tau.tolist())) == want
 
 
 if __name__ == "__main__":
