@@ -28,26 +28,12 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import graphgen  # noqa: E402
 import oracle  # noqa: E402
 
+sys.path.insert(0, os.path.dirname(HERE))
+from grid_tasks import rank_tasks  # noqa: E402
+
 
 def digest(a, dtype):
     return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
-
-
-def rank_tasks(U, q):
-    """Tasks of every rank (x, y) of the q x q grid (j % q == x, i % q == y,
-    U_i has entries after j, U_j not empty), as a q x q array."""
-    deg = np.diff(U.row_ptr)
-    out = np.zeros(q * q, np.int64)
-    step = 1 << 24
-    for r0 in range(0, U.n, step):
-        r1 = min(U.n, r0 + step)
-        p0, p1 = int(U.row_ptr[r0]), int(U.row_ptr[r1])
-        rows = np.repeat(np.arange(r0, r1, dtype=np.int64), deg[r0:r1])
-        pos = np.arange(p0, p1, dtype=np.int64)
-        j = U.col[p0:p1].astype(np.int64)
-        ok = (U.row_ptr[rows + 1] - pos - 1 > 0) & (deg[j] > 0)
-        out += np.bincount((j % q) * q + rows % q, weights=ok, minlength=q * q).astype(np.int64)
-    return out.reshape(q, q)
 
 
 def main():
@@ -71,7 +57,7 @@ def main():
     print("T = %d (%.0f s)" % (T, time.time() - t0), flush=True)
     w = oracle.wedges(U)
     q = a.q
-    tasks = rank_tasks(U, q)
+    tasks = rank_tasks(U.row_ptr, U.col, q)
     x, y = (int(v) for v in np.unravel_index(int(np.argmax(tasks)), tasks.shape))
     blocks = []
     for bx, by in ((0, 0), (x, y)):

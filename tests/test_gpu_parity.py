@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import graphgen
+import grid_tasks
 import oracle
 import sampled_support
 import smallgraphs as sg
@@ -168,6 +169,20 @@ def test_rmat_scale24_full_config(tc):
     pos = sampled_support.sample_positions(U.row_ptr, seed=24)
     want = sampled_support.sampled_full_support(U.row_ptr, U.col, pos)
     assert np.array_equal(full[pos].astype(np.int64), want)
+    del full
+    # one rank's block of the 13 x 13 grid at its real shape (Section 5.1):
+    # rank (0, 0) and the rank with the most tasks, count and per-shift
+    # counts (Eq. 5) against the oracle's
+    q = 13
+    xm, ym = grid_tasks.max_task_rank(U.row_ptr, U.col, q)
+    ps = torch.empty(q, dtype=torch.int64, device="cuda")
+    for x, y in ((0, 0), (xm, ym)):
+        print("block (%d, %d) of %d x %d" % (x, y, q, q), flush=True)
+        cnt, _ = tc.tc_block_count(g, q, x, y, per_shift=ps)
+        torch.cuda.synchronize()
+        b, shifts = oracle.block_count_one(U, q, x, y)
+        assert int(cnt.item()) == b
+        assert np.array_equal(ps.cpu().numpy(), shifts)
 
 
 def test_edge_cases(tc):
