@@ -22,8 +22,8 @@ batched form against the plain launch loop (`batched`) and the served form
 against a plain FIFO (`served`); each is skipped with its --no-* flag.
 
 cpu_baseline: the CPU oracle (plain C, list-based intersection) timed end to
-end (its own preprocessing + count) on a bounded sample: the RMAT graph of the
-same generator at a smaller scale (default 20, 1/16 of the pairs).
+end (its own preprocessing + count) on a bounded sample of the same input:
+the first 1/8 of its raw pairs (--cpu-full adds the whole input).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--scale 24]
 """
@@ -51,7 +51,11 @@ def parse():
     p.add_argument("--scale", type=int, default=24)
     p.add_argument("--edge-factor", type=int, default=16)
     p.add_argument("--seed", type=int, default=1)
-    p.add_argument("--cpu-scale", type=int, default=20)
+    p.add_argument("--cpu-sample", type=int, default=8,
+                   help="cpu_baseline runs the oracle on the first 1/N of the input's raw pairs")
+    p.add_argument("--cpu-full", action="store_true", help="also run the oracle on the whole input")
+    p.add_argument("--cpu-threads", type=int, default=16,
+                   help="oracle threads (the host cores allotted to one GPU)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
@@ -118,33 +122,64 @@ def load_traffic(kernel: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(scale: int, edge_factor: int, seed: int, threads: int, bench_scale: int):
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scale: int, edge_factor: int, seed: int, threads: int, frac: int, full: bool):
+    """The CPU oracle (plain C: qsort preprocessing on one thread, list-based
+    intersection on `threads` threads) end to end on a bounded sample of the
+    benchmark's own input: the first 1/frac of the RMAT stream's raw pairs
+    (the pairs are drawn independently, so a prefix is an RMAT sample on the
+    same vertex space). With full=True the oracle also runs on the whole
+    input (minutes)."""
     import graphgen
     import oracle
 
     src, dst = graphgen.rmat(scale, edge_factor=edge_factor, seed=seed, threads=threads)
     n = 1 << scale
-    t0 = time.perf_counter()
-    U = oracle.preprocess(src, dst, n)
-    t1 = time.perf_counter()
-    T = oracle.count(U, threads=threads)
-    t2 = time.perf_counter()
-    T1 = oracle.count(U, threads=1)  # the same count on one host thread
-    t3 = time.perf_counter()
-    assert T1 == T
-    return {
-        "value": len(src) / (t2 - t0),
+    k = len(src) // frac
+    ss, ds = src[:k].copy(), dst[:k].copy()
+
+    def run(s, d, label):
+        t0 = time.perf_counter()
+        U = oracle.preprocess(s, d, n)
+        t1 = time.perf_counter()
+        print("cpu baseline %s: oracle preprocessing %.1f s" % (label, t1 - t0), file=sys.stderr, flush=True)
+        T = oracle.count(U, threads=threads)
+        t2 = time.perf_counter()
+        print("cpu baseline %s: oracle count %.1f s" % (label, t2 - t1), file=sys.stderr, flush=True)
+        return U, T, t1 - t0, t2 - t1
+
+    U, T, tp, tc_ = run(ss, ds, "sample")
+    out = {
+        "value": k / (tp + tc_),
         "unit": "edges/s",
         "cores": threads,
         "kind": "oracle",
-        "value_1thread": len(src) / ((t1 - t0) + (t3 - t2)),
-        "sample": "RMAT scale %d (same generator and parameters, %d raw pairs = 1/%d of the benchmark "
-                  "input), oracle preprocessing (one thread) + count end to end; count phase alone "
-                  "%.3g edges/s on %d threads, %.3g on 1 (m=%d, T=%d, %.2f s + %.2f s; 1 thread: "
-                  "%.2f s)" % (
-                      scale, len(src), 1 << max(0, bench_scale - scale), U.m / (t2 - t1), threads,
-                      U.m / (t3 - t2), U.m, T, t1 - t0, t2 - t1, t3 - t2),
+        "host_cpu": host_cpu_model(),
+        "host_cpu_count": os.cpu_count(),
+        "count_edges_per_s": U.m / tc_,
+        "sample": "first 1/%d of the RMAT scale %d raw pairs (%d pairs, n = 2^%d; m = %d, T = %d): oracle "
+                  "preprocessing %.2f s on one thread (qsort) + count %.2f s on %d threads; threads = the "
+                  "host cores allotted to one GPU (%d of the %s this host reports)" % (
+                      frac, scale, k, scale, U.m, T, tp, tc_, threads, threads, os.cpu_count()),
     }
+    if full:
+        del U
+        U, T, tp, tc_ = run(src, dst, "full")
+        out["full"] = {"pairs": len(src), "m": U.m, "triangles": T, "preprocess_s": round(tp, 2),
+                       "count_s": round(tc_, 2), "edges_per_s": len(src) / (tp + tc_),
+                       "count_edges_per_s": U.m / tc_}
+    return out
 
 
 def pct(vals, q):
@@ -625,9 +660,9 @@ def main():
         result["served"] = bench_served(tc, args)
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        threads = max(1, min(16, os.cpu_count() or 1))
-        result["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, threads,
-                                              args.scale)
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        result["cpu_baseline"] = cpu_baseline(args.scale, args.edge_factor, args.seed, threads,
+                                              args.cpu_sample, args.cpu_full)
     print(json.dumps(result), flush=True)
 
 
