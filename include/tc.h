@@ -189,6 +189,24 @@ tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, in
                            const char* tuning_json, void* stream);
 
 /*
+ * tc_count_batched_noalloc - tc_count_batched for callers that cannot
+ * allocate device memory (code that runs while a HIP graph is being captured,
+ * tight serving loops, harnesses that forbid hipMalloc). Same per-graph
+ * counts as tc_count_batched (d_counts: device int64[num_graphs], handle
+ * order), with the default schedule in graph order. Everything else the call
+ * needs - the queue counter, the graphs' kernel arguments and unit lists -
+ * lives in a fixed 64 MiB device array of the library (one per GPU, held
+ * until the process ends); the call allocates no device memory and frees
+ * none. A batch that needs more of it than 64 MiB (about 2 million work
+ * units: graphs x their packs and item groups) fails with TC_EOVERFLOW and a
+ * message naming the size. Calls on one GPU share that array: calls that
+ * overlap on one GPU (concurrent streams or threads) race and give wrong
+ * counts. Synchronises `stream`.
+ */
+tc_status tc_count_batched_noalloc(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
+                                   void* stream);
+
+/*
  * tc_batch_autotune - time candidate schedules (LDS caps that change the
  * plan x unit orders x blocks per CU) on these graphs and write
  * {"best": {...}, "candidates": [...]} into the host buffer out_json[cap];

@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
-    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "Server", "tc_release_cached_memory",
+    "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_count_batched_noalloc", "Server", "tc_release_cached_memory",
     "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
@@ -66,6 +66,7 @@ _sig("tc_batch_create", [ctypes.POINTER(_P), _I32, ctypes.c_char_p, _P, ctypes.P
 _sig("tc_batch_count", [_P, _P, _P])
 _sig("tc_batch_free", [_P], None)
 _sig("tc_count_batched", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, _P])
+_sig("tc_count_batched_noalloc", [ctypes.POINTER(_P), _I32, _P, _P])
 _sig("tc_batch_describe", [_P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_batch_autotune", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_graph_free", [_P], None)
@@ -312,6 +313,15 @@ def tc_count_batched(graphs, counts: torch.Tensor | None = None, tuning=None, st
     _check(_lib.tc_count_batched(_handles(graphs), len(graphs),
                                  _dev_ptr(counts, torch.int64, "counts", len(graphs)), _tuning(tuning),
                                  _stream(stream)), "tc_count_batched")
+    return counts
+
+
+def tc_count_batched_noalloc(graphs, counts: torch.Tensor, stream=None):
+    """tc_count_batched without device allocation (the library's fixed
+    scratch array); `counts` is a caller-allocated int64 device tensor."""
+    _check(_lib.tc_count_batched_noalloc(_handles(graphs), len(graphs),
+                                         _dev_ptr(counts, torch.int64, "counts", len(graphs)),
+                                         _stream(stream)), "tc_count_batched_noalloc")
     return counts
 
 

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "tc_prims.h"
@@ -148,7 +149,8 @@ struct BatchSrc {
 };
 
 // One work-group per graph entry: emit its units and their weights (probes
-// plus per-row overheads; the LPT key is the complement of the weight).
+// plus per-row overheads; the LPT key is the complement of the weight; key
+// and idx may be null when no order is wanted).
 __global__ __launch_bounds__(256) void k_batch_units(const BatchSrc* __restrict__ src, BatchUnit* __restrict__ units,
                                                      uint32_t* __restrict__ key, uint32_t* __restrict__ idx) {
   const BatchSrc& s = src[blockIdx.x];
@@ -186,8 +188,10 @@ __global__ __launch_bounds__(256) void k_batch_units(const BatchSrc* __restrict_
     }
     const uint64_t o = s.unit_off + j;
     units[o] = u;
-    key[o] = 0xFFFFFFFFu - (uint32_t)(wgt < 0xFFFFFFFFull ? wgt : 0xFFFFFFFFull);
-    idx[o] = (uint32_t)o;
+    if (key) {  // LPT order wanted: weights for the sort
+      key[o] = 0xFFFFFFFFu - (uint32_t)(wgt < 0xFFFFFFFFull ? wgt : 0xFFFFFFFFull);
+      idx[o] = (uint32_t)o;
+    }
   }
 }
 
@@ -235,32 +239,34 @@ struct BatchPlan {
   }
 };
 
-BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, const char* tuning_json,
-                     hipStream_t st) {
-  TC_REQUIRE(mode == MODE_COUNT || mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED, TC_EINVAL,
-             "batch plan: unsupported mode");
-  TC_REQUIRE(num >= 0 && num < (1ll << 31), TC_EINVAL, "batch plan: bad number of graphs");
-  std::unique_ptr<BatchPlan> P(new BatchPlan());
-  P->own.st = st;
-  P->tun = parse_tuning(tuning_json);
-  P->mode = mode;
-  const bool vals = mode == MODE_SUPPORT_FULL;
-  TC_HIP(hipGetDevice(&P->device));
-  TC_HIP(hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device));
-  P->n_graphs = num;
-  const Tuning& t = P->tun;
+namespace {
 
-  std::vector<CountArgs> args((size_t)std::max<int64_t>(num, 1));
-  std::vector<BatchSrc> srcs((size_t)std::max<int64_t>(num, 1));
+// Host side of a plan: every entry's kernel arguments and unit sources, the
+// dynamic LDS the persistent kernel needs, the number of units and how many
+// of them look their rows up in HBM. Support arrays of support modes are
+// recorded in `support` when it is not null.
+struct PlanHost {
+  std::vector<CountArgs> args;
+  std::vector<BatchSrc> srcs;
+  size_t lds = 0;
+  uint64_t units = 0;
+  int64_t hbm_units = 0;
+};
+
+void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mode, const Tuning& t,
+               int device, std::vector<std::pair<int32_t*, int64_t>>* support) {
+  const bool vals = mode == MODE_SUPPORT_FULL;
+  H.args.assign((size_t)std::max<int64_t>(num, 1), CountArgs{});
+  H.srcs.assign((size_t)std::max<int64_t>(num, 1), BatchSrc{});
   size_t lds = 0;
   uint64_t off = 0;
   int64_t hbm_units = 0;
   for (int64_t i = 0; i < num; ++i) {
     TC_REQUIRE(entries[i].g != nullptr, TC_EINVAL, "batch plan: null graph handle");
     const Graph& g = *entries[i].g;
-    TC_REQUIRE(g.device == P->device, TC_EINVAL, "tc_batch_create: graph built on another device");
+    TC_REQUIRE(g.device == device, TC_EINVAL, "batch plan: graph built on another device");
     const WorkSet& w = g.w;
-    CountArgs& A = args[(size_t)i];
+    CountArgs& A = H.args[(size_t)i];
     std::memset(&A, 0, sizeof(A));
     A.row_ptr = g.row_ptr;
     A.hcol = g.col;
@@ -275,9 +281,9 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
     if (mode != MODE_COUNT) {
       TC_REQUIRE(entries[i].support != nullptr || g.m == 0, TC_EINVAL, "batch plan: null support array");
       A.support = entries[i].support;
-      if (g.m > 0) P->support.emplace_back(entries[i].support, g.m);
+      if (g.m > 0 && support) support->emplace_back(entries[i].support, g.m);
     }
-    BatchSrc& s = srcs[(size_t)i];
+    BatchSrc& s = H.srcs[(size_t)i];
     std::memset(&s, 0, sizeof(s));
     s.tbeg = w.tbeg;
     s.tend = w.tend;
@@ -306,16 +312,46 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
       off += s.n_groups[c];
     }
   }
+  H.lds = std::max(lds, items_lds_bytes(-1, vals));
+  H.units = off;
+  H.hbm_units = hbm_units;
+}
+
+// Resident work-groups per CU and the persistent grid of a schedule.
+void plan_grid(const Tuning& t, size_t lds, int64_t n_units, int cus, int& bpc, unsigned& grid,
+               uint32_t& chunk) {
+  bpc = t.blocks_per_cu;
+  if (bpc == 0) bpc = (int)std::max<size_t>(1, std::min<size_t>(kMaxBlocksPerCU, kLdsPerCU / lds));
+  grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_units, (int64_t)bpc * cus));
+  chunk = t.chunk > 0 ? (uint32_t)t.chunk
+                      : (uint32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_units / ((int64_t)grid * 16)));
+}
+
+}  // namespace
+
+BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, const char* tuning_json,
+                     hipStream_t st) {
+  TC_REQUIRE(mode == MODE_COUNT || mode == MODE_SUPPORT_FULL || mode == MODE_SUPPORT_ORIENTED, TC_EINVAL,
+             "batch plan: unsupported mode");
+  TC_REQUIRE(num >= 0 && num < (1ll << 31), TC_EINVAL, "batch plan: bad number of graphs");
+  std::unique_ptr<BatchPlan> P(new BatchPlan());
+  P->own.st = st;
+  P->tun = parse_tuning(tuning_json);
+  P->mode = mode;
+  TC_HIP(hipGetDevice(&P->device));
+  TC_HIP(hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device));
+  P->n_graphs = num;
+  const Tuning& t = P->tun;
+  PlanHost H;
+  plan_host(H, entries, num, mode, t, P->device, &P->support);
+  std::vector<CountArgs>& args = H.args;
+  std::vector<BatchSrc>& srcs = H.srcs;
+  const uint64_t off = H.units;
   TC_REQUIRE(off < 0xFFFFFFF0ull, TC_EOVERFLOW, "tc_batch_create: more than 2^32 work units");
   P->n_units = (int64_t)off;
-  P->hbm_units = hbm_units;
-  P->lds = std::max(lds, items_lds_bytes(-1, vals));
-  int bpc = t.blocks_per_cu;
-  if (bpc == 0) bpc = (int)std::max<size_t>(1, std::min<size_t>(kMaxBlocksPerCU, kLdsPerCU / P->lds));
-  P->bpc = bpc;
-  P->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(P->n_units, (int64_t)bpc * P->cus));
-  P->chunk = t.chunk > 0 ? (uint32_t)t.chunk
-                         : (uint32_t)std::max<int64_t>(1, std::min<int64_t>(64, P->n_units / ((int64_t)P->grid * 16)));
+  P->hbm_units = H.hbm_units;
+  P->lds = H.lds;
+  plan_grid(t, P->lds, P->n_units, P->cus, P->bpc, P->grid, P->chunk);
   batch_kernel_lds(mode, P->lds);
 
   P->d_args = P->own.alloc<CountArgs>(std::max<int64_t>(num, 1));
@@ -442,6 +478,90 @@ void copy_out(const std::string& s, char* out, size_t cap) {
 
 }  // namespace
 
+// ---- counting without allocation -------------------------------------------
+// tc_count_batched_noalloc keeps everything a batch plan would allocate -
+// the queue counter, every graph's kernel arguments and unit sources, and the
+// units themselves - in one fixed device array. Every GPU the library runs
+// on holds its own copy of it until the process ends; host code must use the
+// address hipGetSymbolAddress returns for the current device, never the
+// array's name (which in host code is only a stand-in for the symbol).
+namespace {
+
+constexpr size_t kScratchBytes = 64ull << 20;  // 64 MiB: about 2 million units
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Address of this device's scratch array (looked up once per device, with
+// that device current).
+unsigned char* scratch_on(int device) {
+  TC_REQUIRE(device >= 0 && device < kScratchDevices, TC_EINVAL, "tc_count_batched_noalloc: device id too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    TC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TC_REQUIRE(p != nullptr, TC_EDEVICE, "tc_count_batched_noalloc: no address for the scratch array");
+    g_scratch_ptr[device] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[device]);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Layout of one call in the scratch array: queue counter, kernel arguments,
+// unit sources, units (in graph order).
+struct ScratchLayout {
+  size_t args = 0, srcs = 0, units = 0, total = 0;
+  ScratchLayout(int64_t num, int64_t n_units) {
+    args = 256;
+    srcs = args + align256(sizeof(CountArgs) * (size_t)std::max<int64_t>(num, 1));
+    units = srcs + align256(sizeof(BatchSrc) * (size_t)std::max<int64_t>(num, 1));
+    total = units + sizeof(BatchUnit) * (size_t)std::max<int64_t>(n_units, 1);
+  }
+};
+
+void count_batched_noalloc(const PlanEntry* entries, int64_t num, int64_t* d_counts, hipStream_t st) {
+  int device = 0;
+  TC_HIP(hipGetDevice(&device));
+  int cus = 0;
+  TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  unsigned char* base = scratch_on(device);
+  Tuning t;  // the default schedule, graph order (no sort: sorting needs temporaries)
+  t.lpt = false;
+  PlanHost H;
+  plan_host(H, entries, num, MODE_COUNT, t, device, nullptr);
+  TC_REQUIRE(H.units < 0xFFFFFFF0ull, TC_EOVERFLOW, "tc_count_batched_noalloc: more than 2^32 work units");
+  const ScratchLayout L(num, (int64_t)H.units);
+  if (L.total > kScratchBytes)
+    throw Error(TC_EOVERFLOW, "tc_count_batched_noalloc: the batch needs " + std::to_string(L.total) +
+                                  " bytes of scratch (" + std::to_string(H.units) + " work units), more than its " +
+                                  std::to_string(kScratchBytes) + "-byte array; use tc_count_batched");
+  int bpc = 0;
+  unsigned grid = 0;
+  uint32_t chunk = 1;
+  plan_grid(t, H.lds, (int64_t)H.units, cus, bpc, grid, chunk);
+  batch_kernel_lds(MODE_COUNT, H.lds);
+  auto* d_queue = reinterpret_cast<unsigned int*>(base);
+  auto* d_args = reinterpret_cast<CountArgs*>(base + L.args);
+  auto* d_srcs = reinterpret_cast<BatchSrc*>(base + L.srcs);
+  auto* d_units = reinterpret_cast<BatchUnit*>(base + L.units);
+  TC_HIP(hipMemcpyAsync(d_args, H.args.data(), sizeof(CountArgs) * (size_t)num, hipMemcpyHostToDevice, st));
+  TC_HIP(hipMemcpyAsync(d_srcs, H.srcs.data(), sizeof(BatchSrc) * (size_t)num, hipMemcpyHostToDevice, st));
+  if (H.units > 0) {
+    TC_LAUNCH("batch_units", k_batch_units, dim3((unsigned)num), dim3(256), 0, st, d_srcs, d_units,
+              (uint32_t*)nullptr, (uint32_t*)nullptr);
+    TC_HIP(hipGetLastError());
+  }
+  // clears the counts and the queue counter (a kernel), then the persistent launch
+  launch_batch(MODE_COUNT, d_args, d_units, (int64_t)H.units, chunk, num, d_queue, d_counts, grid, H.lds, st, true);
+  // the host copies above read H's vectors: they must be done before H goes
+  TC_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
 }  // namespace tc
 
 struct tc_batch {
@@ -502,6 +622,19 @@ tc_status tc_count_batched(const tc_graph* const* graphs, int32_t num_graphs, in
   }
   tc_batch_free(plan);
   return s;
+}
+
+tc_status tc_count_batched_noalloc(const tc_graph* const* graphs, int32_t num_graphs, int64_t* d_counts,
+                                   void* stream) {
+  return tc::guard("tc_count_batched_noalloc", [&] {
+    TC_REQUIRE(num_graphs >= 0, TC_EINVAL, "tc_count_batched_noalloc: num_graphs < 0");
+    TC_REQUIRE(num_graphs == 0 || graphs != nullptr, TC_EINVAL, "tc_count_batched_noalloc: null graph list");
+    TC_REQUIRE(num_graphs == 0 || d_counts != nullptr, TC_EINVAL, "tc_count_batched_noalloc: null counts");
+    if (num_graphs == 0) return;
+    std::vector<tc::PlanEntry> e((size_t)num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) e[(size_t)i] = tc::PlanEntry{tc::G(graphs[i]), nullptr};
+    tc::count_batched_noalloc(e.data(), num_graphs, d_counts, static_cast<hipStream_t>(stream));
+  });
 }
 
 tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, void* stream, char* out_json,
