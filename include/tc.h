@@ -145,6 +145,53 @@ tc_status tc_edge_support(const tc_graph* g, int mode, int32_t* d_support, int64
 tc_status tc_block_count(const tc_graph* g, int32_t q, int32_t x, int32_t y, int64_t* d_count,
                          int64_t* d_per_shift, void* stream);
 
+/* ---- uses of the counts (Section 1: clustering coefficients, k-truss) ------- */
+
+/*
+ * tc_vertex_triangles - number of triangles through every vertex, indexed by
+ * original vertex id: d_tri is device int64[n] (caller-owned, overwritten).
+ * Computed from the per-edge support of TC_SUPPORT_FULL: the two edges a
+ * triangle has at v each count it once, so t(v) is half their sum. The sum
+ * over all vertices is 3T. Asynchronous on `stream` except for one
+ * synchronisation after the internal column sort; allocates temporaries
+ * (the support array and U's column lists: about 16 m + 8 n bytes).
+ */
+tc_status tc_vertex_triangles(const tc_graph* g, int64_t* d_tri, void* stream);
+
+/*
+ * tc_clustering - local clustering coefficients (Section 1 names them as a
+ * use of triangle counts): d_cc[u] = t(u) / C(d(u), 2) as a double (0 when
+ * the degree d(u) < 2), indexed by original vertex id; each is one correctly
+ * rounded division of two exact integers. d_tri (nullable) receives t(u) as
+ * tc_vertex_triangles does; d_sums (nullable, device int64[2]) receives
+ * sum_u t(u) = 3T and sum_u C(d(u), 2), the numerator and denominator of the
+ * transitivity. At least one output is required (TC_EINVAL otherwise).
+ * Same synchronisation and temporaries as tc_vertex_triangles.
+ */
+tc_status tc_clustering(const tc_graph* g, double* d_cc, int64_t* d_tri, int64_t* d_sums, void* stream);
+
+/*
+ * tc_transitivity - global clustering coefficient 3T / sum_u C(d(u), 2)
+ * (0 if no vertex has two neighbours) into the host double *out.
+ * Synchronises `stream`.
+ */
+tc_status tc_transitivity(const tc_graph* g, double* out, void* stream);
+
+/*
+ * tc_truss - trussness of every edge (Section 1 names the k-truss as a use
+ * of per-edge triangle counts). The k-truss is the largest subgraph in which
+ * every edge lies in at least k - 2 of the subgraph's triangles; an edge's
+ * trussness is the largest k whose k-truss contains it (>= 2). d_tau is
+ * device int32[m] in U order (the order of tc_graph_export's d_col);
+ * *kmax (host, nullable) receives the largest trussness (0 without edges).
+ * Computed by peeling from the TC_SUPPORT_FULL support: each round removes
+ * the edges whose support in the remaining graph is below k - 2 and takes
+ * the triangles they close out of their other edges' support. Synchronises
+ * `stream` once per round; allocates temporaries (about 28 m + 8 n bytes).
+ * TC_EOVERFLOW for 2^31 or more edges.
+ */
+tc_status tc_truss(const tc_graph* g, int32_t* d_tau, int32_t* kmax, void* stream);
+
 /* ---- batched counting ---------------------------------------------------- */
 
 /* Opaque plan for counting a fixed set of graphs in one persistent launch. */

@@ -21,7 +21,8 @@ __all__ = [
     "TCError", "Graph", "Batch", "tc_preprocess", "tc_graph_info", "tc_graph_export", "tc_count",
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
     "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_count_batched_noalloc", "Server", "tc_release_cached_memory",
-    "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "Timer", "TC_SUPPORT_FULL",
+    "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "tc_vertex_triangles", "tc_clustering",
+    "tc_transitivity", "tc_truss", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
@@ -70,6 +71,10 @@ _sig("tc_count_batched_noalloc", [ctypes.POINTER(_P), _I32, _P, _P])
 _sig("tc_batch_describe", [_P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_batch_autotune", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_graph_free", [_P], None)
+_sig("tc_vertex_triangles", [_P, _P, _P])
+_sig("tc_clustering", [_P, _P, _P, _P, _P])
+_sig("tc_transitivity", [_P, ctypes.POINTER(ctypes.c_double), _P])
+_sig("tc_truss", [_P, _P, ctypes.POINTER(_I32), _P])
 _sig("tc_graph_class_stats", [_P, _P])
 _sig("tc_class_name", [_I32], ctypes.c_char_p)
 _sig("tc_timer_create", [_I32, ctypes.POINTER(_P)])
@@ -226,6 +231,49 @@ def tc_block_count(g: Graph, q: int, x: int, y: int, count: torch.Tensor | None 
                                _dev_ptr(per_shift, torch.int64, "per_shift", int(q)), _stream(stream)),
            "tc_block_count")
     return count, per_shift
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def tc_vertex_triangles(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Triangles through every vertex (int64, original ids)."""
+    n = g.info()["n"]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=_dev())
+    _check(_lib.tc_vertex_triangles(g.handle, _dev_ptr(out, torch.int64, "tri", n), _stream(stream)),
+           "tc_vertex_triangles")
+    return out
+
+
+def tc_clustering(g: Graph, cc: torch.Tensor | None = None, tri: torch.Tensor | None = None,
+                  sums: torch.Tensor | None = None, stream=None):
+    """Local clustering coefficients (float64, original ids); optionally the
+    per-vertex triangles and [3T, sum C(d, 2)]."""
+    n = g.info()["n"]
+    if cc is None:
+        cc = torch.empty(n, dtype=torch.float64, device=_dev())
+    _check(_lib.tc_clustering(g.handle, _dev_ptr(cc, torch.float64, "cc", n), _dev_ptr(tri, torch.int64, "tri", n),
+                              _dev_ptr(sums, torch.int64, "sums", 2), _stream(stream)), "tc_clustering")
+    return cc, tri, sums
+
+
+def tc_transitivity(g: Graph, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(_lib.tc_transitivity(g.handle, ctypes.byref(out), _stream(stream)), "tc_transitivity")
+    return out.value
+
+
+def tc_truss(g: Graph, tau: torch.Tensor | None = None, stream=None):
+    """(trussness int32 in U order, largest trussness)."""
+    m = g.info()["m"]
+    if tau is None:
+        tau = torch.empty(max(m, 1), dtype=torch.int32, device=_dev())
+    k = _I32()
+    _check(_lib.tc_truss(g.handle, _dev_ptr(tau, torch.int32, "tau", m), ctypes.byref(k), _stream(stream)),
+           "tc_truss")
+    return tau[:m], k.value
 
 
 class Batch:

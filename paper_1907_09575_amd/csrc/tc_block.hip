@@ -57,15 +57,6 @@ __global__ __launch_bounds__(256) void k_gather_rows(const int64_t* __restrict__
   for (int64_t i = threadIdx.x & 63; i < d; i += 64) lcol[o + i] = col[s + i];
 }
 
-// Local probe row of every probe-side entry (for the task kernels).
-__global__ __launch_bounds__(256) void k_entry_rows(const int64_t* __restrict__ lrow_ptr, int64_t nloc,
-                                                    uint32_t* __restrict__ erow) {
-  const int64_t lv = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (lv >= nloc) return;
-  const int64_t s = lrow_ptr[lv], e = lrow_ptr[lv + 1];
-  for (int64_t i = s + (threadIdx.x & 63); i < e; i += 64) erow[i] = (uint32_t)lv;
-}
-
 // Entry p of local probe row a (= erow[p]) holding b starts a task iff
 // b % q == x, the row has entries after p, and U_b is not empty; the task's
 // key is the local hashed row b / q and its value the probe range

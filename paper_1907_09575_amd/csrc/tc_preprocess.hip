@@ -195,22 +195,6 @@ __global__ __launch_bounds__(256) void k_orient(const uint64_t* __restrict__ E, 
   dc.flush(hist);
 }
 
-// Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
-// with row(i) >= r (binary search per row), so row_ptr[n] = m.
-template <class K>
-__global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n,
-                         int64_t* __restrict__ row_ptr) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r > n) return;
-  int64_t lo = 0, hi = m;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)(keys[mid] >> s) < r) lo = mid + 1;
-    else hi = mid;
-  }
-  row_ptr[r] = lo;
-}
-
 // Column of a sorted orient key, written by the orient sort's last pass.
 struct ColEpi {
   int32_t* col;

@@ -730,6 +730,32 @@ static inline void check_sorts(hipStream_t st) {
   }
 }
 
+// Row pointers from keys sorted by row (row = key >> s): row_ptr[r] = first i
+// with row(i) >= r (binary search per row), so row_ptr[n] = m.
+template <class K>
+__global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n,
+                         int64_t* __restrict__ row_ptr) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)(keys[mid] >> s) < r) lo = mid + 1;
+    else hi = mid;
+  }
+  row_ptr[r] = lo;
+}
+
+// Row of every entry of a CSR: erow[i] = r for row_ptr[r] <= i < row_ptr[r + 1]
+// (one wave per row, coalesced writes; grid: div_up(nrows, 4) x 256).
+static __global__ __launch_bounds__(256) void k_entry_rows(const int64_t* __restrict__ row_ptr, int64_t nrows,
+                                                           uint32_t* __restrict__ erow) {
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (r >= nrows) return;
+  const int64_t s = row_ptr[r], e = row_ptr[r + 1];
+  for (int64_t i = s + (threadIdx.x & 63); i < e; i += 64) erow[i] = (uint32_t)r;
+}
+
 // Tasks in hashed-row order (the input of build_work).
 struct TaskLists {
   int64_t T = 0;
