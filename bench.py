@@ -16,7 +16,9 @@ and its algorithmic bytes per launch (4 per probe + 4 per hashed-row key +
 `achieved`. `count_median_ms` times tc_count alone on the resident graph
 (2 warm-ups, median of 11).
 
-Beside the step: one rank's block of the 13 x 13 grid (`block`), per-edge
+Beside the step: one rank's block of the 13 x 13 grid (`block`), the
+ablations of Section 7.3 and the per-rank tables of Section 7.2
+(`ablation`), per-edge
 support in both modes on a resident RMAT scale-20 graph (`support`), the
 batched form against the plain launch loop (`batched`) and the served form
 against a plain FIFO (`served`); each is skipped with its --no-* flag.
@@ -63,6 +65,8 @@ def parse():
     p.add_argument("--kernels-json", default=None, help="write the full per-kernel timer summary here")
     p.add_argument("--no-block", action="store_true", help="skip the 13x13 block grid of the graph")
     p.add_argument("--block-q", type=int, default=13)
+    p.add_argument("--no-ablation", action="store_true", help="skip the ablations and per-rank tables")
+    p.add_argument("--ablation-q", default="4,5,6,13", help="grid sizes of the per-rank tables")
     p.add_argument("--no-support", action="store_true", help="skip the per-edge support leg")
     p.add_argument("--support-scale", type=int, default=20)
     p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
@@ -223,6 +227,69 @@ def bench_block(tc, g, T, q):
         count_ms = sum(v["total_ms"] for kk, v in k.items() if kk.startswith("block:")) / reps
         out[name] = {"x": x, "y": y, "count": int(cnt.item()), "per_shift": ps.cpu().tolist(),
                      "ms_total": round(wall * 1e3, 3), "count_kernel_ms": round(count_ms, 3)}
+    return out
+
+
+def bench_ablation(tc, g, T, qs):
+    """Section 7.3 and Section 7.2 on one GPU, on the benchmark's graph.
+    Ablations: tc_count on the graph and on its variants without each of
+    Section 5.2's optimizations (<i,j,k> enumeration instead of <j,i,k>, no
+    doubly sparse traversal, multiplicative hashing instead of the direct
+    AND), each one warm-up and the median of 5 (HIP events), with its probes,
+    tasks and the count checked against T. Per-rank tables for every q: all
+    q x q ranks' work (tc_block_stats): task imbalance (max / average over
+    ranks, Section 7.2's task-count imbalance), per-shift imbalance (max /
+    average of the probes of a (rank, shift) pair, the work behind Table
+    "r_l_imb"), and the intersections performed when the shifts run one by
+    one, summed over ranks and shifts (Table "opcount"), with its growth
+    from the previous q."""
+    import numpy as np
+    import torch
+    out = {}
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    base_ms = None
+    for name, flags in (("jik", 0), ("ijk", tc.TC_VARIANT_IJK), ("no_dcsr", tc.TC_VARIANT_NO_DCSR),
+                        ("mul_hash", tc.TC_VARIANT_MUL_HASH)):
+        print("ablation %s ..." % name, file=sys.stderr, flush=True)
+        V = g if flags == 0 else tc.tc_graph_variant(g, flags)
+        runs = []
+        for r in range(6):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tc.tc_count(V, cnt)
+            e1.record()
+            e1.synchronize()
+            assert int(cnt.item()) == T, "%s counts %d, not T = %d" % (name, int(cnt.item()), T)
+            if r:
+                runs.append(e0.elapsed_time(e1))
+        info = V.info()
+        med = float(np.median(runs))
+        base_ms = med if base_ms is None else base_ms
+        out[name] = {"count_ms": round(med, 3), "probes": info["probes"], "tasks": info["tasks"],
+                     "time_vs_jik": round(med / base_ms, 3)}
+        if flags:
+            V.free()
+    grid = {}
+    prev = None
+    for q in qs:
+        print("rank tables q=%d ..." % q, file=sys.stderr, flush=True)
+        rows = []
+        for x in range(q):
+            for y in range(q):
+                rows.append(tc.tc_block_stats(g, q, x, y).cpu().numpy())
+        a = np.stack(rows)
+        tasks, probes = a[:, 0], a[:, 1]
+        sp, stsk = a[:, 2:2 + q], a[:, 2 + q:]
+        inter = int(stsk.sum())
+        grid[str(q)] = {"ranks": q * q, "tasks_total": int(tasks.sum()), "probes_total": int(probes.sum()),
+                        "task_imbalance": round(float(tasks.max() / tasks.mean()), 4),
+                        "probe_imbalance": round(float(probes.max() / probes.mean()), 4),
+                        "shift_probe_imbalance": round(float(sp.max() / sp.mean()), 4),
+                        "intersections": inter,
+                        "intersection_growth": round(inter / prev - 1, 4) if prev else None}
+        prev = inter
+    out["rank_tables"] = grid
     return out
 
 
@@ -647,6 +714,11 @@ def main():
         g = step()
         torch.cuda.synchronize()
         result["block"] = bench_block(tc, g, T, args.block_q)
+        g.free()
+    if not args.no_ablation:
+        g = step()
+        torch.cuda.synchronize()
+        result["ablation"] = bench_ablation(tc, g, T, [int(v) for v in args.ablation_q.split(",") if v])
         g.free()
     del src, dst
     torch.cuda.empty_cache()

@@ -145,6 +145,34 @@ tc_status tc_edge_support(const tc_graph* g, int mode, int32_t* d_support, int64
 tc_status tc_block_count(const tc_graph* g, int32_t q, int32_t x, int32_t y, int64_t* d_count,
                          int64_t* d_per_shift, void* stream);
 
+/* ---- ablations of the paper's optimizations (Section 7.3) ------------------ */
+
+/* Flags of tc_graph_variant (combinable). */
+enum {
+  TC_VARIANT_IJK = 1,      /* <i,j,k> enumeration: for every nonzero (i, j) of U, U_i is hashed and
+                              all of U_j is looked up (instead of hashing U_j and looking up
+                              U_i's entries after j) */
+  TC_VARIANT_NO_DCSR = 2,  /* no doubly sparse traversal (Section 5.2): every hashed row is
+                              visited, also rows without work, and intersections whose hashed
+                              list is empty are kept */
+  TC_VARIANT_MUL_HASH = 4  /* no direct-AND addressing (Section 5.2, "Modifying the hashing
+                              routine"): every table is addressed by a multiplicative hash
+                              (top bits of k * 0x9E3779B1) with linear probing */
+};
+
+/*
+ * tc_graph_variant - a graph handle that counts g's triangles with some of
+ * the optimizations of Section 5.2 undone, for the measurements of Section
+ * 7.3 (runtime gained by each). The new handle shares g's U (g must outlive
+ * it; free it with tc_graph_free) and has a work set of its own: tc_count on
+ * it gives the same T; tc_graph_info reports its probes and tasks (with
+ * TC_VARIANT_IJK, probes = the sum of |U_j| over the nonzeros (i, j)).
+ * Only tc_count, tc_graph_info, tc_graph_class_stats, tc_graph_export and
+ * tc_graph_free accept a variant (others: TC_EINVAL). Synchronises
+ * `stream`. TC_EINVAL for unknown flags.
+ */
+tc_status tc_graph_variant(const tc_graph* g, int32_t flags, void* stream, tc_graph** out);
+
 /* ---- uses of the counts (Section 1: clustering coefficients, k-truss) ------- */
 
 /*
@@ -191,6 +219,24 @@ tc_status tc_transitivity(const tc_graph* g, double* out, void* stream);
  * TC_EOVERFLOW for 2^31 or more edges.
  */
 tc_status tc_truss(const tc_graph* g, int32_t* d_tau, int32_t* kmax, void* stream);
+
+/*
+ * tc_block_stats - the work of rank (x, y) of the q x q grid of tc_block_count
+ * (Section 7.2 measures its balance across ranks and shifts, Table
+ * "r_l_imb", and how the number of intersections grows with the number of
+ * ranks, Table "opcount"). d_out is device int64[2 + 2 q]:
+ *   [0]         tasks: nonzeros (i, j) of the rank whose row i has entries
+ *               after j and whose U_j is not empty;
+ *   [1]         probes: lookups of those tasks (entries of U_i after j);
+ *   [2 + z]     the probes whose closing vertex k falls in shift z's class,
+ *               (k - x - y) mod q == z (Eq. 5);
+ *   [2 + q + z] the intersections shift z performs when the shifts run one
+ *               by one: tasks whose probe list and U_j both hold an entry of
+ *               that class.
+ * Same argument rules as tc_block_count; allocates temporaries; synchronises
+ * `stream` (rank extraction).
+ */
+tc_status tc_block_stats(const tc_graph* g, int32_t q, int32_t x, int32_t y, int64_t* d_out, void* stream);
 
 /* ---- batched counting ---------------------------------------------------- */
 

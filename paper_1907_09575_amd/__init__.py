@@ -22,7 +22,8 @@ __all__ = [
     "tc_edge_support", "tc_block_count", "tc_batch_create", "tc_batch_count", "tc_batch_free",
     "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_count_batched_noalloc", "Server", "tc_release_cached_memory",
     "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "tc_vertex_triangles", "tc_clustering",
-    "tc_transitivity", "tc_truss", "Timer", "TC_SUPPORT_FULL",
+    "tc_transitivity", "tc_truss", "tc_graph_variant", "tc_block_stats", "TC_VARIANT_IJK", "TC_VARIANT_NO_DCSR",
+    "TC_VARIANT_MUL_HASH", "Timer", "TC_SUPPORT_FULL",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
@@ -72,6 +73,8 @@ _sig("tc_batch_describe", [_P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_batch_autotune", [ctypes.POINTER(_P), _I32, _P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_graph_free", [_P], None)
 _sig("tc_vertex_triangles", [_P, _P, _P])
+_sig("tc_graph_variant", [_P, _I32, _P, ctypes.POINTER(_P)])
+_sig("tc_block_stats", [_P, _I32, _I32, _I32, _P, _P])
 _sig("tc_clustering", [_P, _P, _P, _P, _P])
 _sig("tc_transitivity", [_P, ctypes.POINTER(ctypes.c_double), _P])
 _sig("tc_truss", [_P, _P, ctypes.POINTER(_I32), _P])
@@ -237,6 +240,19 @@ def _dev():
     return torch.device("cuda", torch.cuda.current_device())
 
 
+TC_VARIANT_IJK, TC_VARIANT_NO_DCSR, TC_VARIANT_MUL_HASH = 1, 2, 4
+
+
+def tc_graph_variant(g: Graph, flags: int, stream=None) -> Graph:
+    """A handle counting g's triangles with Section 5.2's optimizations
+    undone (TC_VARIANT_* flags); it shares g's U, so keep g alive."""
+    out = ctypes.c_void_p()
+    _check(_lib.tc_graph_variant(g.handle, int(flags), _stream(stream), ctypes.byref(out)), "tc_graph_variant")
+    v = Graph(out.value)
+    v.base = g  # keeps the shared arrays' owner alive
+    return v
+
+
 def tc_vertex_triangles(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Triangles through every vertex (int64, original ids)."""
     n = g.info()["n"]
@@ -274,6 +290,16 @@ def tc_truss(g: Graph, tau: torch.Tensor | None = None, stream=None):
     _check(_lib.tc_truss(g.handle, _dev_ptr(tau, torch.int32, "tau", m), ctypes.byref(k), _stream(stream)),
            "tc_truss")
     return tau[:m], k.value
+
+
+def tc_block_stats(g: Graph, q: int, x: int, y: int, out: torch.Tensor | None = None, stream=None):
+    """Work of rank (x, y) of the q x q grid: int64 device tensor
+    [tasks, probes, shift_probes[q], shift_tasks[q]]."""
+    if out is None:
+        out = torch.empty(2 + 2 * int(q), dtype=torch.int64, device=_dev())
+    _check(_lib.tc_block_stats(g.handle, int(q), int(x), int(y), _dev_ptr(out, torch.int64, "out", 2 + 2 * int(q)),
+                               _stream(stream)), "tc_block_stats")
+    return out
 
 
 class Batch:

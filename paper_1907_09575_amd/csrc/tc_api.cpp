@@ -80,6 +80,7 @@ tc_status tc_edge_support(const tc_graph* gh, int mode, int32_t* d_support, int6
     TC_REQUIRE(mode == TC_SUPPORT_FULL || mode == TC_SUPPORT_ORIENTED, TC_EINVAL,
                "tc_edge_support: unknown mode");
     const tc::Graph& g = *tc::G(gh);
+    tc::require_plain(g, "tc_edge_support");
     TC_REQUIRE(d_support || g.m == 0, TC_EINVAL, "tc_edge_support: null support array");
     hipStream_t st = static_cast<hipStream_t>(stream);
     tc::launch_count(tc::graph_view(g),

@@ -150,6 +150,7 @@ __global__ void k_zero_u64x2(unsigned long long* p) {
 }
 
 void vertex_counts(const Graph& g, int64_t* d_tri, double* d_cc, int64_t* d_sums, hipStream_t st) {
+  require_plain(g, "per-vertex triangle counts");
   TempStream temps(st);
   const int64_t n = g.n;
   auto* sums = reinterpret_cast<unsigned long long*>(d_sums);
@@ -281,6 +282,7 @@ T read_scalar(const T* d, hipStream_t st) {
 }
 
 int32_t truss(const Graph& g, int32_t* d_tau, hipStream_t st) {
+  require_plain(g, "tc_truss");
   TempStream temps(st);
   const int64_t m = g.m;
   if (m == 0) return 0;

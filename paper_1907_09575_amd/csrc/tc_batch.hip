@@ -265,6 +265,7 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
     TC_REQUIRE(entries[i].g != nullptr, TC_EINVAL, "batch plan: null graph handle");
     const Graph& g = *entries[i].g;
     TC_REQUIRE(g.device == device, TC_EINVAL, "batch plan: graph built on another device");
+    require_plain(g, "batch plan");
     const WorkSet& w = g.w;
     CountArgs& A = H.args[(size_t)i];
     std::memset(&A, 0, sizeof(A));

@@ -157,6 +157,113 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   check_task_sorts(st);
 }
 
+namespace {
+
+// Shift classes present in every local hashed row: bit z of mask[lb] is set
+// when U_b (b = lb * q + x) holds an entry k with (k - x - y) mod q == z
+// (one wave per row).
+__global__ __launch_bounds__(256) void k_row_shift_mask(const int64_t* __restrict__ hrow_ptr,
+                                                        const int32_t* __restrict__ hcol, int64_t nloc,
+                                                        int32_t q, int32_t xy, uint64_t* __restrict__ mask) {
+  const int64_t lb = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (lb >= nloc) return;
+  uint64_t mk = 0;
+  for (int64_t i = hrow_ptr[lb] + lane_id(); i < hrow_ptr[lb + 1]; i += 64) {
+    int z = (int)((uint32_t)hcol[i] % (uint32_t)q) - xy;
+    if (z < 0) z += q;
+    mk |= 1ull << z;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) mk |= (uint64_t)__shfl_xor((unsigned long long)mk, d, 64);
+  if (lane_id() == 0) mask[lb] = mk;
+}
+
+// Work of the rank's tasks (tkey = local hashed row, tval = first probe | end
+// << 32 in the local probe CSR), one wave per task, tasks strided over the
+// grid: out[0] tasks, out[1] probes, out[2 + z] probes of shift z, out[2 + q
+// + z] tasks whose probe list and hashed list both hold shift z's class.
+__global__ __launch_bounds__(256) void k_block_work(const uint32_t* __restrict__ tkey,
+                                                    const uint64_t* __restrict__ tval, int64_t T,
+                                                    const int32_t* __restrict__ pcol,
+                                                    const uint64_t* __restrict__ hmask, int32_t q, int32_t xy,
+                                                    unsigned long long* __restrict__ out) {
+  __shared__ unsigned int s_probe[64], s_task[64];
+  __shared__ unsigned long long s_tot[2];
+  if (threadIdx.x < 64) {
+    s_probe[threadIdx.x] = 0;
+    s_task[threadIdx.x] = 0;
+  }
+  if (threadIdx.x < 2) s_tot[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  uint64_t tasks = 0, probes = 0;
+  for (int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); t < T; t += waves) {
+    const uint64_t v = tval[t];
+    const uint32_t first = (uint32_t)v, end = (uint32_t)(v >> 32);
+    uint64_t pm = 0;
+    for (uint32_t i = first + (uint32_t)lane; i < end; i += 64) {
+      int z = (int)((uint32_t)pcol[i] % (uint32_t)q) - xy;
+      if (z < 0) z += q;
+      pm |= 1ull << z;
+      atomicAdd(&s_probe[z], 1u);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pm |= (uint64_t)__shfl_xor((unsigned long long)pm, d, 64);
+    const uint64_t both = pm & hmask[tkey[t]];
+    if (lane < q && ((both >> lane) & 1ull)) atomicAdd(&s_task[lane], 1u);
+    tasks += 1;
+    probes += end - first;
+  }
+  if (lane == 0 && tasks) {
+    atomicAdd(&s_tot[0], (unsigned long long)tasks);
+    atomicAdd(&s_tot[1], (unsigned long long)probes);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 && s_tot[threadIdx.x]) atomicAdd(&out[threadIdx.x], s_tot[threadIdx.x]);
+  if ((int)threadIdx.x < q) {
+    if (s_probe[threadIdx.x]) atomicAdd(&out[2 + threadIdx.x], (unsigned long long)s_probe[threadIdx.x]);
+    if (s_task[threadIdx.x]) atomicAdd(&out[2 + q + threadIdx.x], (unsigned long long)s_task[threadIdx.x]);
+  }
+}
+
+__global__ void k_zero_n(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+void block_stats(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_out, hipStream_t st) {
+  TempStream temps(st);
+  auto* out = reinterpret_cast<unsigned long long*>(d_out);
+  TC_LAUNCH("zero_stats", k_zero_n, dim3(1), dim3(192), 0, st, out, 2 + 2 * q);
+  LocalRows H, P;
+  gather_local(H, g, q, x, st);
+  gather_local(P, g, q, y, st);
+  if (P.nnz == 0 || H.nnz == 0) return;
+  DevBuf erow(sizeof(uint32_t) * (size_t)P.nnz);
+  TC_LAUNCH("block_entry_rows", k_entry_rows, dim3((unsigned)div_up(P.nloc, kBT / 64)), dim3(kBT), 0, st,
+            P.row_ptr.as<int64_t>(), P.nloc, erow.as<uint32_t>());
+  DevBuf tk, tv;
+  BlockTaskPred bp{P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), H.row_ptr.as<int64_t>(),
+                   H.nloc, q, x, nullptr, nullptr};
+  const int64_t T = compact("block_stats_tasks", P.nnz, bp, [&](int64_t total, BlockTaskPred& pr) {
+    tk.alloc(sizeof(uint32_t) * (size_t)total);
+    tv.alloc(sizeof(uint64_t) * (size_t)total);
+    pr.tkey = tk.as<uint32_t>();
+    pr.tval = tv.as<uint64_t>();
+  }, st);
+  if (T == 0) return;
+  DevBuf hmask(sizeof(uint64_t) * (size_t)H.nloc);
+  const int32_t xy = (x + y) % q;
+  TC_LAUNCH("block_row_mask", k_row_shift_mask, dim3((unsigned)div_up(H.nloc, kBT / 64)), dim3(kBT), 0, st,
+            H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), H.nloc, q, xy, hmask.as<uint64_t>());
+  const unsigned grid = (unsigned)std::min<int64_t>(4096, div_up(T, kBT / 64));
+  TC_LAUNCH("block_work", k_block_work, dim3(grid), dim3(kBT), 0, st, tk.as<uint32_t>(), tv.as<uint64_t>(), T,
+            P.col.as<int32_t>(), hmask.as<uint64_t>(), q, xy, out);
+  TC_HIP(hipGetLastError());
+}
+
 }  // namespace tc
 
 extern "C" tc_status tc_block_count(const tc_graph* gh, int32_t q, int32_t x, int32_t y, int64_t* d_count,
@@ -167,6 +274,7 @@ extern "C" tc_status tc_block_count(const tc_graph* gh, int32_t q, int32_t x, in
     TC_REQUIRE(x >= 0 && x < q && y >= 0 && y < q, TC_EINVAL, "tc_block_count: (x, y) outside the grid");
     TC_REQUIRE(d_count != nullptr || d_per_shift != nullptr, TC_EINVAL,
                "tc_block_count: no output array");
+    tc::require_plain(*tc::G(gh), "tc_block_count");
     tc::block_count(*tc::G(gh), q, x, y, d_count, d_per_shift, static_cast<hipStream_t>(stream));
     tc::set_last_error("");
     return TC_OK;
@@ -175,6 +283,28 @@ extern "C" tc_status tc_block_count(const tc_graph* gh, int32_t q, int32_t x, in
     return e.status;
   } catch (const std::bad_alloc&) {
     tc::set_last_error("tc_block_count: host allocation failed");
+    return TC_ENOMEM;
+  } catch (const std::exception& e) {
+    tc::set_last_error(e.what());
+    return TC_EDEVICE;
+  }
+}
+
+extern "C" tc_status tc_block_stats(const tc_graph* gh, int32_t q, int32_t x, int32_t y, int64_t* d_out,
+                                    void* stream) {
+  try {
+    TC_REQUIRE(gh != nullptr && d_out != nullptr, TC_EINVAL, "tc_block_stats: null argument");
+    TC_REQUIRE(q >= 1 && q <= 64, TC_EINVAL, "tc_block_stats: q must be in [1, 64]");
+    TC_REQUIRE(x >= 0 && x < q && y >= 0 && y < q, TC_EINVAL, "tc_block_stats: (x, y) outside the grid");
+    tc::require_plain(*tc::G(gh), "tc_block_stats");
+    tc::block_stats(*tc::G(gh), q, x, y, d_out, static_cast<hipStream_t>(stream));
+    tc::set_last_error("");
+    return TC_OK;
+  } catch (const tc::Error& e) {
+    tc::set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    tc::set_last_error("tc_block_stats: host allocation failed");
     return TC_ENOMEM;
   } catch (const std::exception& e) {
     tc::set_last_error(e.what());

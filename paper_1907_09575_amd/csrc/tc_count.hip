@@ -85,6 +85,20 @@ __device__ __forceinline__ int32_t col_load(__amdgpu_buffer_rsrc_t r, uint32_t b
   return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
 }
 
+// Bucket of key k in a table of bmask + 1 buckets: the direct bitwise AND of
+// Section 5.2 (the key's low bits), or, MH (the ablation of that choice,
+// tc_graph_variant), a multiplicative hash: the top log2(buckets) bits of
+// k times 2^32 / golden ratio.
+template <bool MH>
+__device__ __forceinline__ uint32_t bucket_of(int32_t k, uint32_t bmask) {
+  if constexpr (!MH) {
+    return (uint32_t)k & bmask;
+  } else {
+    const uint32_t B = (uint32_t)__popc(bmask);
+    return (uint32_t)(((uint64_t)((uint32_t)k * 0x9E3779B1u) << B) >> 32);
+  }
+}
+
 // Lookup by binary search in the sorted row col[rs, rs + d); returns the
 // position of k or -1.
 __device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int64_t rs, int64_t d,
@@ -103,7 +117,7 @@ __device__ __forceinline__ int64_t hbm_find(const int32_t* __restrict__ col, int
 // buckets; threads tid, tid + nt, ... share the work. Returns this thread's
 // longest bucket displacement. VALS: also store every key's index in the row
 // (its U position is rs + index), with a zero hit count above it.
-template <bool VALS>
+template <bool VALS, bool MH>
 __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int32_t* __restrict__ col,
                            int64_t rs, int64_t d, int tid, int nt) {
   constexpr int kB = 8;  // keys fetched at once so that their loads overlap
@@ -118,7 +132,7 @@ __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       if (key[j] == kEmpty) continue;
-      uint32_t bk = (uint32_t)key[j] & bmask;
+      uint32_t bk = bucket_of<MH>(key[j], bmask);
       int disp = 0;
       int slot = -1;
       while (true) {
@@ -226,7 +240,7 @@ __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
 
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
 // task t contains probe q.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool MH>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
                            uint32_t* bm, uint32_t& hits) {
   // the range is the wave's own (uniform across its lanes): scalar registers
@@ -349,7 +363,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
           int4 v[kG];
 #pragma unroll
           for (int u = g0; u < g0 + kG; ++u) {
-            bk[u] = bbase[u] + ((uint32_t)k[u] & bmask[u]);
+            bk[u] = bbase[u] + bucket_of<MH>(k[u], bmask[u]);
             v[u - g0] = tab4[bk[u]];
           }
 #pragma unroll
@@ -449,7 +463,7 @@ __device__ __forceinline__ void block_init() {
 // each task looking up its own row's table.
 constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
 
-template <int MODE>
+template <int MODE, bool MH>
 __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int32_t* __restrict__ rows,
                                           const uint32_t* __restrict__ pack_ptr, uint32_t pack,
                                           uint32_t pack_slots, int32_t* smem) {
@@ -473,11 +487,14 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
   if (tid < nr) {
     const int32_t b = rows[r0 + tid];
     const int64_t rs64 = A.row_ptr[b];
+    const uint32_t tb = A.tbeg[b], te = A.tend[b];
     rs = (uint32_t)rs64;
-    d = (uint32_t)(A.row_ptr[b + 1] - rs64);
+    // a row without tasks (a pack member only without the doubly sparse
+    // traversal, tc_graph_variant) gets no table
+    d = te > tb ? (uint32_t)(A.row_ptr[b + 1] - rs64) : 0u;
     S = 1u << pack_table_log2(d);
-    row_t0[tid] = A.tbeg[b];
-    if (tid == nr - 1) s_tend = A.tend[b];
+    row_t0[tid] = tb;
+    if (tid == nr - 1) s_tend = te;
   }
   uint32_t S_tot, K_tot;
   const uint32_t off = block_excl_scan(S, s_w, S_tot);
@@ -510,7 +527,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
     const int32_t key = A.hcol[p];
     const uint32_t dsc = row_desc[lo];
     const uint32_t base = dsc & 0xFFFFu, bmask = dsc >> 16;
-    uint32_t bk = (uint32_t)key & bmask;
+    uint32_t bk = bucket_of<MH>(key, bmask);
     int disp = 0, slot = -1;
     while (true) {
 #pragma unroll
@@ -548,7 +565,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
       lo = lo + (c - 1) * step;
       hi = lo + step < hi ? lo + step : hi;
     }
-    wave_probe<MODE, TK_MULTI>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
+    wave_probe<MODE, TK_MULTI, MH>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
   }
   return block_flush<MODE>(hits, A);
 }
@@ -558,16 +575,16 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
 // CU; 5 with spill-free registers runs faster).
 constexpr int kOccPacks = 5, kOccBatch = 5;
 
-template <int MODE>
+template <int MODE, bool MH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? kOccPacks : 4)))
 void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
                    uint32_t pack_slots) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  pack_body<MODE>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
+  pack_body<MODE, MH>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
-template <int MODE, bool GLOBAL>
+template <int MODE, bool GLOBAL, bool MH>
 __device__ __forceinline__ unsigned long long items_body(const Args& A, const CountItem* __restrict__ grp,
                                                          int32_t* smem) {
   __shared__ int s_D;
@@ -590,7 +607,7 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
     if (tid == 0) s_D = 0;
     __syncthreads();
     const uint32_t bmask = S / kBucket - 1;
-    int md = build_table<VALS>(tab, val, bmask, A.hcol, rs, d, tid, (int)blockDim.x);
+    int md = build_table<VALS, MH>(tab, val, bmask, A.hcol, rs, d, tid, (int)blockDim.x);
     if (md) atomicMax(&s_D, md);  // per lane: see pack_body
     __syncthreads();
     tr.tab = tab;
@@ -600,7 +617,7 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
   }
   wave_sync_lds();
   const CountItem it = grp[wave];
-  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE, MH>(A, tr, it.t0, it.q0, it.len, bm, hits);
   if constexpr (VALS && !GLOBAL) {
     // the (b, k) credits of the work-group: one atomic per slot that was hit
     __syncthreads();
@@ -619,11 +636,11 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
 // OCC: waves per SIMD the kernel's registers are budgeted for. A class whose
 // tables limit a CU to fewer work-groups gets the registers that would
 // otherwise go unused (fewer spills in the probe loop).
-template <int MODE, bool GLOBAL, int OCC, int WAVES>
+template <int MODE, bool GLOBAL, int OCC, int WAVES, bool MH>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(OCC)))
 void k_count_items(Args A, const CountItem* __restrict__ items) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  items_body<MODE, GLOBAL>(A, items + (int64_t)blockIdx.x * WAVES, reinterpret_cast<int32_t*>(smem4));
+  items_body<MODE, GLOBAL, MH>(A, items + (int64_t)blockIdx.x * WAVES, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Count mode per class (chosen by timing at RMAT scale 24): wg_small and
@@ -633,22 +650,22 @@ void k_count_items(Args A, const CountItem* __restrict__ items) {
 // Support modes hold more state per probe and run at 4.
 constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSupport = 4;
 
-template <int MODE, bool GLOBAL>
+template <int MODE, bool GLOBAL, bool MH>
 const void* items_kernel(int cls) {
   static_assert(class_waves(CLS_WG_HUGE) == kWavesBig && class_waves(CLS_WG_GIANT) == kWavesBig &&
                     class_waves(CLS_WG_LARGE) == kWaves && class_waves(CLS_GLOBAL) == kWaves,
                 "work-group shapes of the item classes");
   if constexpr (GLOBAL) {  // no table: LDS does not limit
-    return (const void*)k_count_items<MODE, GLOBAL, MODE == MODE_COUNT ? kOccSmall : kOccSupport, kWaves>;
+    return (const void*)k_count_items<MODE, GLOBAL, MODE == MODE_COUNT ? kOccSmall : kOccSupport, kWaves, MH>;
   } else if constexpr (MODE != MODE_COUNT) {
-    if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig>;
-    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves>;
+    if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig, MH>;
+    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves, MH>;
   } else {
     switch (cls) {
-      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge, kWaves>;
-      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge, kWavesBig>;
-      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant, kWavesBig>;
-      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall, kWaves>;
+      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge, kWaves, MH>;
+      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge, kWavesBig, MH>;
+      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant, kWavesBig, MH>;
+      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall, kWaves, MH>;
     }
   }
 }
@@ -672,7 +689,7 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
     {"block:pack_small", "block:pack_large", "block:wg_small", "block:wg_large", "block:wg_huge",
      "block:wg_giant", "block:global"}};
 
-template <int MODE>
+template <int MODE, bool MH>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const size_t mark_bytes = items_lds_bytes(-1, VALS);
@@ -682,16 +699,16 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
     const size_t lds = pack_lds_bytes(slots, VALS);
     if (lds > 65536)
-      TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE>,
+      TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, MH>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], k_count_packs<MODE>, dim3((unsigned)w.n_packs[c]), dim3(256), lds,
+    TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, MH>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
               st, A, w.pack_rows[c], w.pack_ptr[c], slots);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (w.n_items[c] == 0) continue;
     const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
     const bool global = c == CLS_GLOBAL;
-    const void* f = global ? items_kernel<MODE, true>(c) : items_kernel<MODE, false>(c);
+    const void* f = global ? items_kernel<MODE, true, MH>(c) : items_kernel<MODE, false, MH>(c);
     const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], VALS);
     if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const CountItem* items = w.items[c];
@@ -742,11 +759,11 @@ void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__
       Args A = gargs[bu.graph];
       A.count = counts + bu.graph;
       if (bu.kind == BK_PACK) {
-        pack_body<MODE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+        pack_body<MODE, false>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
       } else if (bu.kind == BK_ITEMS) {
-        items_body<MODE, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+        items_body<MODE, false, false>(A, static_cast<const CountItem*>(bu.p0), smem);
       } else {
-        items_body<MODE, true>(A, static_cast<const CountItem*>(bu.p0), smem);
+        items_body<MODE, true, false>(A, static_cast<const CountItem*>(bu.p0), smem);
       }
     }
   }
@@ -817,11 +834,15 @@ void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t*
   Args A{v.hrow_ptr, v.hcol, v.pcol, w.tstart, w.tprefix, w.tbeg, w.tend, w.n_tasks, (uint32_t)v.pm,
          reinterpret_cast<unsigned long long*>(d_count), d_support,
          reinterpret_cast<unsigned long long*>(d_per_shift), v.q, v.xy};
+  TC_REQUIRE(v.hash == 0 || mode == MODE_COUNT, TC_EINVAL, "launch_count: multiplicative hashing counts only");
   switch (mode) {
-    case MODE_COUNT: launch_mode<MODE_COUNT>(w, A, st); break;
-    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL>(w, A, st); break;
-    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED>(w, A, st); break;
-    case MODE_BLOCK: launch_mode<MODE_BLOCK>(w, A, st); break;
+    case MODE_COUNT:
+      if (v.hash) launch_mode<MODE_COUNT, true>(w, A, st);
+      else launch_mode<MODE_COUNT, false>(w, A, st);
+      break;
+    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL, false>(w, A, st); break;
+    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED, false>(w, A, st); break;
+    case MODE_BLOCK: launch_mode<MODE_BLOCK, false>(w, A, st); break;
   }
 }
 

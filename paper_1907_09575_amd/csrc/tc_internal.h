@@ -179,12 +179,17 @@ struct WorkSet {
 };
 
 // Device-resident graph: U in CSR (rank space) and its work set.
+// A variant (tc_graph_variant) shares U with the graph it was made from and
+// has a work set of its own: variant holds its TC_VARIANT_* flags and hash
+// the table addressing (0: the direct AND, 1: multiplicative hashing).
 struct Graph {
   int device = 0;
   int64_t n = 0, m_raw = 0, m = 0;
   int64_t wedges_plus = 0, max_dplus = 0;
   int sbits = 1;  // ceil(log2(n)), >= 1
   size_t arena_bytes = 0;
+  int variant = 0;
+  int hash = 0;
 
   int64_t* row_ptr = nullptr;  // n + 1, U rows
   int32_t* col = nullptr;      // m, rows sorted ascending
@@ -202,6 +207,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 // such work is pending.
 void destroy_graph(Graph* g);
 void destroy_graph_idle(Graph* g);
+// A variant of `base` (TC_VARIANT_* flags) sharing its U (tc_graph_variant).
+Graph* build_variant(const Graph& base, int flags, hipStream_t st);
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
@@ -222,6 +229,7 @@ struct CountView {
   int64_t pm;  // entries of pcol
   const WorkSet* w;
   int32_t q = 1, xy = 0;  // MODE_BLOCK: grid size and (x + y) % q
+  int hash = 0;           // 1: multiplicative hashing (MODE_COUNT only)
 };
 
 void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t* d_support,
@@ -301,7 +309,15 @@ size_t pack_lds_bytes(uint32_t slots, bool vals);
 size_t items_lds_bytes(int log2S, bool vals);
 
 inline CountView graph_view(const Graph& g) {
-  return CountView{g.row_ptr, g.col, g.col, g.m, &g.w, 1, 0};
+  return CountView{g.row_ptr, g.col, g.col, g.m, &g.w, 1, 0, g.hash};
+}
+
+// Entry points that rely on the <j,i,k> task layout of a graph's own work
+// set (support, blocks, batches, the uses of support) refuse variants.
+inline void require_plain(const Graph& g, const char* where) {
+  if (g.variant != 0)
+    throw Error(TC_EINVAL, std::string(where) + ": not defined for a variant graph (tc_graph_variant); "
+                                                "use the graph it was made from");
 }
 
 // ---- work-set construction (tc_preprocess.hip) --------------------------------
@@ -309,9 +325,11 @@ inline CountView graph_view(const Graph& g) {
 // bounds, tb_val = first probe | end << 32 of each task, tb_prefix = the
 // exclusive prefix of their probe counts with the total at [T]): classes,
 // class-major order, packs and items. hrow_ptr gives |U_b| of every hashed row.
+// all_rows: every hashed row gets a work unit, also rows without tasks (the
+// ablation of the doubly sparse traversal; they go to pack_small).
 void build_work(WorkSet& w, Owned& own, int64_t nrows, const int64_t* hrow_ptr, int64_t T,
                 const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
-                const uint64_t* tb_prefix, hipStream_t st);
+                const uint64_t* tb_prefix, hipStream_t st, bool all_rows = false);
 
 
 inline int ceil_log2_u64(uint64_t x) {

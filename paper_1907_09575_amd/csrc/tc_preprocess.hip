@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ r
 // (maxima reduced per wave before one atomic per wave and class).
 __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tptr,
                                                   const uint64_t* __restrict__ tprefix,
-                                                  const int64_t* __restrict__ row_ptr, int64_t n,
+                                                  const int64_t* __restrict__ row_ptr, int64_t n, bool all_rows,
                                                   int8_t* __restrict__ cls, int* __restrict__ cls_log2S) {
   __shared__ int s_max[NUM_CLASSES];
   if (threadIdx.x < NUM_CLASSES) s_max[threadIdx.x] = 0;
@@ -264,6 +264,11 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
       else if (l > 12) c = CLS_WG_HUGE;
       else if (W < kHeavyMin && l <= 10) c = l <= 8 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
       else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
+    } else if (all_rows) {
+      // no doubly sparse traversal: a row without work is still visited (a
+      // pack member whose table stays empty: it has no task to look up)
+      c = CLS_PACK_SMALL;
+      l = table_log2(0);
     }
     cls[b] = (int8_t)c;
 #pragma unroll
@@ -419,7 +424,9 @@ __global__ void k_rows_work(const int32_t* __restrict__ rows, int64_t nr,
   if (i >= nr) return;
   int64_t b = rows[i];
   w[i] = tprefix[tend[b]] - tprefix[tbeg[b]];
-  slots[i] = 1u << pack_table_log2(row_ptr[b + 1] - row_ptr[b]);
+  // a row without tasks (visited only without the doubly sparse traversal)
+  // needs no table
+  slots[i] = 1u << pack_table_log2(tend[b] > tbeg[b] ? row_ptr[b + 1] - row_ptr[b] : 0);
 }
 
 // A pack starts at row i when the running probe total, the running table
@@ -663,6 +670,87 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
 void check_task_sorts(hipStream_t st) { check_sorts(st); }
 
+namespace {
+
+// Tasks of a variant work set, one test per nonzero p = (a, b) of U (a from
+// erow). <j,i,k> (the default): hashed row b, probes = U_a's entries after b,
+// skipped when there are none, and also when U_b is empty unless keep_empty.
+// <i,j,k>: hashed row a, probes = all of U_b (skipped when U_b is empty: such
+// a task has nothing to look up).
+struct VariantTaskPred {
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const uint32_t* erow;
+  bool ijk, keep_empty;
+  uint32_t* tkey;
+  uint64_t* tval;
+  struct Item {
+    uint32_t key;
+    uint64_t val;
+  };
+  __device__ bool operator()(int64_t p, Item& it) const {
+    const uint32_t a = erow[p];
+    const int32_t b = col[p];
+    const int64_t bs = row_ptr[b], be = row_ptr[b + 1];
+    if (ijk) {
+      it.key = a;
+      it.val = (uint64_t)bs | ((uint64_t)be << 32);
+      return be > bs;
+    }
+    const int64_t end = row_ptr[a + 1];
+    it.key = (uint32_t)b;
+    it.val = (uint64_t)(p + 1) | ((uint64_t)end << 32);
+    return end - p - 1 > 0 && (keep_empty || be > bs);
+  }
+  __device__ void emit(int64_t, const Item& it, uint32_t pos) const {
+    tkey[pos] = it.key;
+    tval[pos] = it.val;
+  }
+};
+
+}  // namespace
+
+Graph* build_variant(const Graph& base, int flags, hipStream_t st) {
+  std::unique_ptr<GraphImpl> g(new GraphImpl());
+  g->owned.st = st;
+  TC_HIP(hipGetDevice(&g->device));
+  TC_REQUIRE(g->device == base.device, TC_EINVAL, "tc_graph_variant: graph built on another device");
+  TempStream temps(st);
+  g->n = base.n;
+  g->m_raw = base.m_raw;
+  g->m = base.m;
+  g->wedges_plus = base.wedges_plus;
+  g->max_dplus = base.max_dplus;
+  g->sbits = base.sbits;
+  g->row_ptr = base.row_ptr;  // U is shared, not owned
+  g->col = base.col;
+  g->perm = base.perm;
+  g->variant = flags;
+  g->hash = (flags & TC_VARIANT_MUL_HASH) ? 1 : 0;
+  const bool ijk = (flags & TC_VARIANT_IJK) != 0, no_dcsr = (flags & TC_VARIANT_NO_DCSR) != 0;
+  const int64_t n = g->n, m = g->m;
+  TaskLists tl;
+  if (m > 0) {
+    DevBuf erow(sizeof(uint32_t) * (size_t)m);
+    TC_LAUNCH("entry_rows", k_entry_rows, dim3((unsigned)std::max<int64_t>(1, div_up(n, kT / 64))), dim3(kT), 0,
+              st, g->row_ptr, n, erow.as<uint32_t>());
+    DevBuf tk, tv;
+    VariantTaskPred vp{g->row_ptr, g->col, erow.as<uint32_t>(), ijk, no_dcsr, nullptr, nullptr};
+    const int64_t T = compact("variant_tasks", m, vp, [&](int64_t total, VariantTaskPred& pr) {
+      tk.alloc(sizeof(uint32_t) * (size_t)total);
+      tv.alloc(sizeof(uint64_t) * (size_t)total);
+      pr.tkey = tk.as<uint32_t>();
+      pr.tval = tv.as<uint64_t>();
+    }, st);
+    if (T > 0) sort_tasks(tl, tk, tv, T, n, g->sbits, st, "variant_tasks");
+  }
+  build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st, no_dcsr);
+  check_sorts(st);
+  g->arena_bytes = g->owned.bytes;
+  return g.release();
+}
+
 // Probes of a task from its (first probe | end << 32) value.
 struct TaskLenLoad {
   const uint64_t* val;
@@ -699,7 +787,7 @@ void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows,
 
 void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int64_t T,
                 const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
-                const uint64_t* tb_prefix, hipStream_t st) {
+                const uint64_t* tb_prefix, hipStream_t st, bool all_rows) {
   w.nrows = n;
   w.n_tasks = T;
   w.tbeg = own.alloc<uint32_t>(n);
@@ -724,7 +812,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   DevBuf clsl(sizeof(int) * NUM_CLASSES);
   TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
   TC_LAUNCH("classify", k_classify, dim3(grid_reduce(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
-            cls.as<int8_t>(), clsl.as<int>());
+            all_rows, cls.as<int8_t>(), clsl.as<int>());
   TC_HIP(hipGetLastError());
   int h_cl[NUM_CLASSES];
   TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
@@ -848,6 +936,31 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
 }
 
 }  // namespace tc
+
+extern "C" tc_status tc_graph_variant(const tc_graph* gh, int32_t flags, void* stream, tc_graph** out) {
+  try {
+    TC_REQUIRE(out != nullptr, TC_EINVAL, "tc_graph_variant: out is NULL");
+    *out = nullptr;
+    TC_REQUIRE(gh != nullptr, TC_EINVAL, "tc_graph_variant: null graph");
+    TC_REQUIRE((flags & ~(TC_VARIANT_IJK | TC_VARIANT_NO_DCSR | TC_VARIANT_MUL_HASH)) == 0, TC_EINVAL,
+               "tc_graph_variant: unknown flags");
+    const tc::Graph& base = *tc::G(gh);
+    tc::require_plain(base, "tc_graph_variant");
+    tc::Graph* g = tc::build_variant(base, flags, static_cast<hipStream_t>(stream));
+    *out = reinterpret_cast<tc_graph*>(g);
+    tc::set_last_error("");
+    return TC_OK;
+  } catch (const tc::Error& e) {
+    tc::set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    tc::set_last_error("tc_graph_variant: host allocation failed");
+    return TC_ENOMEM;
+  } catch (const std::exception& e) {
+    tc::set_last_error(e.what());
+    return TC_EDEVICE;
+  }
+}
 
 extern "C" tc_status tc_preprocess(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw,
                                    int32_t n, void* stream, tc_graph** out) {
