@@ -365,6 +365,23 @@ def bench_support(tc, args):
         if r >= 2:
             runs.append(e0.elapsed_time(e1))
     out["count_median_ms"] = round(float(np.median(runs)), 4)
+    # the uses of the counts (Section 1) on the same graph: per-vertex counts
+    # and clustering coefficients (checked: sum of t = 3T), trussness
+    t0 = time.perf_counter()
+    sums = torch.empty(2, dtype=torch.int64, device=dev)
+    cc, _, _ = tc.tc_clustering(g, sums=sums)
+    torch.cuda.synchronize()
+    t_cc = time.perf_counter() - t0
+    assert int(sums[0].item()) == 3 * T
+    t0 = time.perf_counter()
+    tau, kmax = tc.tc_truss(g)
+    torch.cuda.synchronize()
+    t_truss = time.perf_counter() - t0
+    out["clustering"] = {"ms": round(t_cc * 1e3, 3), "transitivity": int(sums[0].item()) / int(sums[1].item()),
+                         "avg_local": float(cc.mean().item())}
+    out["truss"] = {"ms": round(t_truss * 1e3, 3), "kmax": kmax,
+                    "edges_in_kmax_truss": int((tau == kmax).sum().item())}
+    del cc, tau
     g.free()
     del sup
     torch.cuda.empty_cache()

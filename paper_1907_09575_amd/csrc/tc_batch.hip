@@ -379,8 +379,8 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
     TC_LAUNCH("batch_gather", k_gather_units, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st,
               raw.as<BatchUnit>(), order, n, P->d_units);
     TC_HIP(hipGetLastError());
+    if (t.lpt) check_sorts(st);  // (synchronises st; a plan in input order needs no check)
   }
-  check_sorts(st);
   return P.release();
 }
 

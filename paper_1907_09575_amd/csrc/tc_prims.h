@@ -168,16 +168,23 @@ __global__ __launch_bounds__(256) void k_scan_final(L load, int64_t n, const Tou
 // DevBuf allocates from the caching allocator on it and returns blocks to
 // the cache with an event recorded on it, so freeing a temporary needs no
 // synchronisation and the block is reused only after the work queued so far.
+// Each TempStream also owns a device word that the radix sorts of its scope
+// set when a look-back wait gives up (check_sorts reads it): a failure is
+// reported to the call whose sort failed, never to a concurrent one.
 struct TempCtx {
   bool active = false;
   hipStream_t st = nullptr;
+  int* fail = nullptr;
 };
 TempCtx& temp_ctx();
 
 struct TempStream {
   TempCtx prev;
+  void* fail_word = nullptr;
   explicit TempStream(hipStream_t st);
-  ~TempStream() { temp_ctx() = prev; }
+  ~TempStream();
+  TempStream(const TempStream&) = delete;
+  TempStream& operator=(const TempStream&) = delete;
 };
 
 // Device buffer owned by one scope.
@@ -368,10 +375,6 @@ __host__ __device__ constexpr W lb_top() {
   return (W)1 << (8 * sizeof(W) - 1);
 }
 
-// Set by a sort whose look-back ran out of its spin budget (never expected;
-// checked by the host after the sorts of a call). One flag per source file
-// that instantiates the sort.
-static __device__ int g_sort_failed;
 
 template <class K>
 __device__ __forceinline__ uint32_t rs_digit(K k, int shift, uint32_t dmask) {
@@ -495,7 +498,8 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
                                                      int64_t n, int shift, uint32_t dmask,
                                                      const uint32_t* __restrict__ bucket,
                                                      W* __restrict__ status,
-                                                     uint32_t* __restrict__ ticket, Epi epi) {
+                                                     uint32_t* __restrict__ ticket, int* __restrict__ fail,
+                                                     Epi epi) {
   constexpr int TILE = 256 * KPT;
   constexpr int WCH = 64 * KPT;  // keys of the tile each wave ranks (a contiguous quarter)
   constexpr bool HV = !std::is_same<V, NoVal>::value;
@@ -601,7 +605,7 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
       j -= q;
       if (q < WIN) {  // tile j has not published yet
         if (++spins > kLbSpinMax) {  // never expected: give up rather than hang
-          atomicExch(&g_sort_failed, 1);
+          atomicExch(fail, 1);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -658,6 +662,8 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
   TC_REQUIRE(bit_hi - bit_lo <= 8 * kSortPassesMax, TC_EINVAL, "radix_sort: key range too wide");
   const int passes = (bit_hi - bit_lo + 7) / 8;
   const int64_t ntiles = div_up(n, TILE);
+  int* fail = temp_ctx().fail;
+  TC_REQUIRE(fail != nullptr, TC_EDEVICE, "radix_sort: called outside a TempStream scope");
   // per pass: ticket counter (padded to 256 bytes) + ntiles * 256 look-back words
   const int64_t pad = 256 / (int64_t)sizeof(W);
   const int64_t pass_words = pad + ntiles * 256;
@@ -687,11 +693,11 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     if (p + 1 < passes)
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, NoEpi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
                 kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
-                reinterpret_cast<uint32_t*>(words), NoEpi{});
+                reinterpret_cast<uint32_t*>(words), fail, NoEpi{});
     else
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, Epi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
                 kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
-                reinterpret_cast<uint32_t*>(words), epi);
+                reinterpret_cast<uint32_t*>(words), fail, epi);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
@@ -716,15 +722,16 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
                                                           name, epi, hist);
 }
 
-// Throws TC_EDEVICE if a sort of this source file gave up waiting in its
-// look-back since the last check (and clears the flag). Synchronises st.
+// Throws TC_EDEVICE if a sort of the current TempStream scope gave up waiting
+// in its look-back (and clears the word). Synchronises st.
 static inline void check_sorts(hipStream_t st) {
+  int* fail = temp_ctx().fail;
+  TC_REQUIRE(fail != nullptr, TC_EDEVICE, "check_sorts: called outside a TempStream scope");
   int h = 0;
-  TC_HIP(hipMemcpyFromSymbolAsync(&h, HIP_SYMBOL(g_sort_failed), sizeof(int), 0, hipMemcpyDeviceToHost, st));
+  TC_HIP(hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, st));
   TC_HIP(hipStreamSynchronize(st));
   if (h) {
-    const int z = 0;
-    TC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_sort_failed), &z, sizeof(int), 0, hipMemcpyHostToDevice, st));
+    TC_HIP(hipMemsetAsync(fail, 0, sizeof(int), st));
     TC_HIP(hipStreamSynchronize(st));
     throw Error(TC_EDEVICE, "radix sort: a look-back wait exceeded its bound");
   }

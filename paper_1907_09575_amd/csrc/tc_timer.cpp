@@ -40,8 +40,16 @@ TempCtx& temp_ctx() {
 }
 
 TempStream::TempStream(hipStream_t st) : prev(temp_ctx()) {
+  fail_word = cache_alloc(sizeof(int), st);
+  TC_HIP(hipMemsetAsync(fail_word, 0, sizeof(int), st));
   temp_ctx().active = true;
   temp_ctx().st = st;
+  temp_ctx().fail = static_cast<int*>(fail_word);
+}
+
+TempStream::~TempStream() {
+  cache_free(fail_word, temp_ctx().st, false);
+  temp_ctx() = prev;
 }
 
 LaunchScope::LaunchScope(const char* name, hipStream_t s) : st(s) {
