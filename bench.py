@@ -88,6 +88,21 @@ def count_kernel_bytes(stats: dict, cls: str) -> int:
     return 4 * s["probes"] + 4 * s["table_keys"] + 12 * s["tasks"] + 32 * s["rows"]
 
 
+def preprocess_bytes(n: int, m_raw: int, m: int, tasks: int) -> int:
+    """Algorithmic bytes of tc_preprocess (the paper's ppt): read the raw pairs
+    once (8 per pair); an LSD radix sort moves 16 bytes per key per 8-bit
+    pass (read + write of an 8-byte key) over ceil(2 log2 n / 8) passes: the
+    dedup sort over the raw pairs and the orient sort over the simple edges;
+    the rank sort over the n vertices takes ceil(log2 n / 8) passes; then the
+    CSR (4 per edge, 8 per row pointer, 4 per rank-map entry) and the task
+    lists (4 + 8 per task) are written once."""
+    s = max(1, (n - 1).bit_length())
+    p_edge = (2 * s + 7) // 8
+    p_rank = (s + 7) // 8
+    return (8 * m_raw + 16 * p_edge * m_raw + 16 * p_rank * n + 16 * p_edge * m
+            + 4 * m + 8 * (n + 1) + 4 * n + 12 * tasks)
+
+
 def measure_copy_gbs(dev, nbytes=1 << 31, reps=5):
     """On-box reference bandwidth: a plain device-to-device copy of nbytes
     (read + write bytes per second, GB/s, best of reps), reported beside the
@@ -716,6 +731,11 @@ def main():
         "count_median_edges_per_s": info["m"] / (count_median_ms / 1e3) if count_median_ms else None,
         "preprocess_ms": pre_ms,
         "preprocess_kernel_ms": pre_kernel_ms,
+        "preprocess": {"ms": round(pre_ms, 3),
+                       "alg_bytes": preprocess_bytes(n, m_raw, info["m"], info["tasks"]),
+                       "alg_GBps": round(preprocess_bytes(n, m_raw, info["m"], info["tasks"]) / (pre_ms / 1e3) / 1e9, 1),
+                       "frac": round(preprocess_bytes(n, m_raw, info["m"], info["tasks"]) / (pre_ms / 1e3) / 1e9
+                                     / HBM_PEAK_GBS, 4)},
         "count_edges_per_s": info["m"] / (count_ms / 1e3) if count_ms > 0 else None,
         "count_raw_edges_per_s": m_raw / (count_ms / 1e3) if count_ms > 0 else None,
         "count_probes_per_s": info["probes"] / (count_ms / 1e3) if count_ms > 0 else None,

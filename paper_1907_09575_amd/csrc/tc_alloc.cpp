@@ -163,6 +163,80 @@ void cache_free(void* p, hipStream_t st, bool idle) {
   if (c.cached > c.cap) trim_locked(c, c.cap / 2);
 }
 
+// ---- use logs -----------------------------------------------------------------
+
+namespace {
+// A library stream per device on which freed memory waits for the events of
+// its users (never destroyed; default priority).
+hipStream_t release_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  TC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  hipStream_t& st = streams[dev];
+  if (!st) TC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  return st;
+}
+}  // namespace
+
+UseLog::~UseLog() {
+  for (auto& u : uses) (void)hipEventDestroy(u.second);
+}
+
+void UseLog::note(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TC_HIP(hipStreamIsCapturing(st, &cs));
+  std::lock_guard<std::mutex> lk(mu);
+  if (cs != hipStreamCaptureStatusNone) {
+    captured = true;  // the use happens when the caller launches its graph
+    return;
+  }
+  for (auto& u : uses) {
+    if (u.first == st) {
+      TC_HIP(hipEventRecord(u.second, st));
+      return;
+    }
+  }
+  hipEvent_t ev = nullptr;
+  TC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipError_t e = hipEventRecord(ev, st);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    throw Error(TC_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+  }
+  uses.emplace_back(st, ev);
+}
+
+void UseLog::wait_host() {
+  std::lock_guard<std::mutex> lk(mu);
+  if (captured) {
+    (void)hipDeviceSynchronize();
+    return;
+  }
+  for (auto& u : uses) (void)hipEventSynchronize(u.second);
+}
+
+void UseLog::release_after_uses(Owned& owned) {
+  std::lock_guard<std::mutex> lk(mu);
+  if (captured) {
+    (void)hipDeviceSynchronize();
+    owned.release(true);
+    return;
+  }
+  hipStream_t rel = nullptr;
+  try {
+    rel = release_stream();
+    for (auto& u : uses) TC_HIP(hipStreamWaitEvent(rel, u.second, 0));
+  } catch (const Error&) {
+    (void)hipDeviceSynchronize();  // cannot order the release: wait for everything
+    owned.release(true);
+    return;
+  }
+  owned.st = rel;
+  owned.release(false);  // each block's event is recorded on rel, after the waits
+}
+
 void cache_retire_stream(hipStream_t st) {
   if (!st) return;
   (void)hipStreamSynchronize(st);

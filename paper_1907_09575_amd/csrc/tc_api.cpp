@@ -62,14 +62,16 @@ tc_status tc_graph_export(const tc_graph* gh, int64_t* d_row_ptr, int32_t* d_col
       TC_HIP(hipMemcpyAsync(d_col, g.col, sizeof(int32_t) * (size_t)g.m, hipMemcpyDeviceToDevice, st));
     if (d_perm)
       TC_HIP(hipMemcpyAsync(d_perm, g.perm, sizeof(int32_t) * (size_t)g.n, hipMemcpyDeviceToDevice, st));
+    tc::note_use(g, st);
   })
 }
 
 tc_status tc_count(const tc_graph* gh, int64_t* d_count, void* stream) {
   TC_API_GUARD({
     TC_REQUIRE(gh && d_count, TC_EINVAL, "tc_count: null argument");
-    tc::launch_count(tc::graph_view(*tc::G(gh)), tc::MODE_COUNT, d_count, nullptr, nullptr,
-                     static_cast<hipStream_t>(stream));
+    const tc::Graph& g = *tc::G(gh);
+    tc::launch_count(tc::graph_view(g), tc::MODE_COUNT, d_count, nullptr, nullptr, static_cast<hipStream_t>(stream));
+    tc::note_use(g, static_cast<hipStream_t>(stream));
   })
 }
 
@@ -86,6 +88,7 @@ tc_status tc_edge_support(const tc_graph* gh, int mode, int32_t* d_support, int6
     tc::launch_count(tc::graph_view(g),
                      mode == TC_SUPPORT_FULL ? tc::MODE_SUPPORT_FULL : tc::MODE_SUPPORT_ORIENTED, d_count,
                      d_support, nullptr, st);
+    tc::note_use(g, st);
   })
 }
 

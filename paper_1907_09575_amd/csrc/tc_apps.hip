@@ -165,6 +165,7 @@ void vertex_counts(const Graph& g, int64_t* d_tri, double* d_cc, int64_t* d_sums
   TC_LAUNCH("vertex_out", k_vertex_out, dim3(grid_threads(n)), dim3(kAT), 0, st, g.perm, n, t_rank.as<int64_t>(),
             g.row_ptr, L.ptr.as<int64_t>(), d_tri, d_cc, sums);
   TC_HIP(hipGetLastError());
+  note_use(g, st);
   check_sorts(st);
 }
 
@@ -324,6 +325,7 @@ int32_t truss(const Graph& g, int32_t* d_tau, hipStream_t st) {
     ++round;
   }
   TC_HIP(hipStreamSynchronize(st));
+  note_use(g, st);
   return kmax;
 }
 

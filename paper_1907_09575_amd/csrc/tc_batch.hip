@@ -222,6 +222,7 @@ struct BatchPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t* exec_counts = nullptr;
+  UseLog uses;  // streams the plan was launched on
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -402,8 +403,10 @@ void free_plan_idle(BatchPlan* P) {
 
 void free_plan(BatchPlan* P) {
   if (!P) return;
-  // launches of the plan may be queued on any stream: let the device drain
-  (void)hipDeviceSynchronize();
+  // launches of the plan may still be queued on the streams it was launched
+  // on: wait for them (not for the whole device). The graphs' memory stays
+  // valid until then, as the plan's contract requires.
+  P->uses.wait_host();
   free_plan_idle(P);
 }
 
@@ -415,10 +418,12 @@ void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st) {
   if (cs != hipStreamCaptureStatusNone) {
     // the caller is capturing: record the launches into its graph
     plan_launch(P, d_counts, st, false);
+    P.uses.note(st);  // (marks the plan as captured: its free waits for the device)
     return;
   }
   if (!P.tun.graph) {
     plan_launch(P, d_counts, st, true);
+    P.uses.note(st);
     return;
   }
   if (!P.exec || P.exec_counts != d_counts) {
@@ -437,8 +442,11 @@ void plan_count(BatchPlan& P, int64_t* d_counts, hipStream_t st) {
     TC_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
     P.exec_counts = d_counts;
   }
-  LaunchScope ls("batch:graph", st);
-  TC_HIP(hipGraphLaunch(P.exec, st));
+  {
+    LaunchScope ls("batch:graph", st);
+    TC_HIP(hipGraphLaunch(P.exec, st));
+  }
+  P.uses.note(st);
 }
 
 namespace {

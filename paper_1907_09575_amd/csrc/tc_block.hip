@@ -154,6 +154,7 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   CountView v{H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), P.col.as<int32_t>(), P.nnz, &w, q,
               (x + y) % q};
   launch_count(v, MODE_BLOCK, d_count, nullptr, d_per_shift, st);
+  note_use(g, st);
   check_task_sorts(st);
 }
 
@@ -240,6 +241,7 @@ void block_stats(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_out
   LocalRows H, P;
   gather_local(H, g, q, x, st);
   gather_local(P, g, q, y, st);
+  note_use(g, st);  // (the extraction synchronised st; later kernels read only local copies)
   if (P.nnz == 0 || H.nnz == 0) return;
   DevBuf erow(sizeof(uint32_t) * (size_t)P.nnz);
   TC_LAUNCH("block_entry_rows", k_entry_rows, dim3((unsigned)div_up(P.nloc, kBT / 64)), dim3(kBT), 0, st,

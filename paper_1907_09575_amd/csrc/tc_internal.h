@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -178,6 +179,24 @@ struct WorkSet {
   int64_t cls_stats[NUM_CLASSES][4] = {};
 };
 
+// Streams that have used an object's device memory, each with an event
+// recorded after its latest use there: freeing the memory waits for those
+// events (on a library stream), not for the whole device, and does not need
+// the streams to be alive. A use inside a stream capture cannot be recorded
+// that way; it makes the free synchronise the device.
+struct UseLog {
+  std::mutex mu;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+  bool captured = false;
+  ~UseLog();
+  void note(hipStream_t st);
+  // Blocks the host until every recorded use is done.
+  void wait_host();
+  // Returns `owned` memory to the cache, reusable once every recorded use is
+  // done (the host does not wait).
+  void release_after_uses(Owned& owned);
+};
+
 // Device-resident graph: U in CSR (rank space) and its work set.
 // A variant (tc_graph_variant) shares U with the graph it was made from and
 // has a work set of its own: variant holds its TC_VARIANT_* flags and hash
@@ -190,6 +209,8 @@ struct Graph {
   size_t arena_bytes = 0;
   int variant = 0;
   int hash = 0;
+  mutable UseLog uses;         // streams that ran work on the graph (tc_graph_free)
+  const Graph* base = nullptr;  // a variant: the graph whose U it reads
 
   int64_t* row_ptr = nullptr;  // n + 1, U rows
   int32_t* col = nullptr;      // m, rows sorted ascending
@@ -202,15 +223,22 @@ extern const char* const kClassNames[NUM_CLASSES];
 // Build a graph from a device edge list on `st` (tc_preprocess without the
 // argument checks; synchronises st) and free one.
 Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n, hipStream_t st);
-// destroy_graph waits for the device to drain (work using the graph may still
-// be queued on any stream); destroy_graph_idle is for callers that know no
-// such work is pending.
+// destroy_graph returns the graph's memory once the work of every stream that
+// used it (its UseLog) is done; destroy_graph_idle is for callers that know
+// no such work is pending.
 void destroy_graph(Graph* g);
 void destroy_graph_idle(Graph* g);
 // A variant of `base` (TC_VARIANT_* flags) sharing its U (tc_graph_variant).
 Graph* build_variant(const Graph& base, int flags, hipStream_t st);
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
+
+// Record that work reading g (and a variant's base) was enqueued on st; call
+// after enqueuing it.
+inline void note_use(const Graph& g, hipStream_t st) {
+  g.uses.note(st);
+  if (g.base) g.base->uses.note(st);
+}
 
 // ---- launchers implemented in tc_count.hip ---------------------------------
 enum CountMode : int {

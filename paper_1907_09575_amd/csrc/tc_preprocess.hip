@@ -508,9 +508,11 @@ void destroy_graph_idle(Graph* g) {
 }
 
 void destroy_graph(Graph* g) {
-  // work on the graph may be queued on any stream: let the device drain
-  (void)hipDeviceSynchronize();
-  destroy_graph_idle(g);
+  // work on the graph may still be queued on the streams that used it: the
+  // memory goes back to the cache, reusable once that work is done
+  GraphImpl* gi = static_cast<GraphImpl*>(g);
+  gi->uses.release_after_uses(gi->owned);
+  delete gi;
 }
 
 Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, int64_t n,
@@ -665,6 +667,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
              tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st);
   check_sorts(st);
   g->arena_bytes = g->owned.bytes;
+  note_use(*g, st);
   return g.release();
 }
 
@@ -727,6 +730,7 @@ Graph* build_variant(const Graph& base, int flags, hipStream_t st) {
   g->perm = base.perm;
   g->variant = flags;
   g->hash = (flags & TC_VARIANT_MUL_HASH) ? 1 : 0;
+  g->base = &base;
   const bool ijk = (flags & TC_VARIANT_IJK) != 0, no_dcsr = (flags & TC_VARIANT_NO_DCSR) != 0;
   const int64_t n = g->n, m = g->m;
   TaskLists tl;
@@ -748,6 +752,7 @@ Graph* build_variant(const Graph& base, int flags, hipStream_t st) {
              tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st, no_dcsr);
   check_sorts(st);
   g->arena_bytes = g->owned.bytes;
+  note_use(*g, st);  // (and the base, whose U the build read)
   return g.release();
 }
 
