@@ -256,7 +256,6 @@ struct PlanHost {
 
 void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mode, const Tuning& t,
                int device, std::vector<std::pair<int32_t*, int64_t>>* support) {
-  const bool vals = mode == MODE_SUPPORT_FULL;
   H.args.assign((size_t)std::max<int64_t>(num, 1), CountArgs{});
   H.srcs.assign((size_t)std::max<int64_t>(num, 1), BatchSrc{});
   size_t lds = 0;
@@ -299,7 +298,7 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
       s.n_packs[c] = (uint32_t)w.n_packs[c];
       if (w.n_packs[c] == 0) continue;
       s.pack_slots[c] = kPackSlots + (1u << w.pack_log2S[c]);
-      lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], vals));
+      lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], mode));
       off += (uint64_t)w.n_packs[c];
     }
     for (int c = 0; c < kItemClasses; ++c) {
@@ -309,12 +308,12 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
       if (s.n_groups[c] == 0) continue;
       const bool hbm = cls == CLS_GLOBAL || w.cls_log2S[cls] > t.lds_cap_log2;
       s.kind[c] = hbm ? BK_ITEMS_HBM : BK_ITEMS;
-      lds = std::max(lds, items_lds_bytes(hbm ? -1 : w.cls_log2S[cls], vals));
+      lds = std::max(lds, items_lds_bytes(hbm ? -1 : w.cls_log2S[cls], mode));
       if (hbm) hbm_units += s.n_groups[c];
       off += s.n_groups[c];
     }
   }
-  H.lds = std::max(lds, items_lds_bytes(-1, vals));
+  H.lds = std::max(lds, items_lds_bytes(-1, mode));
   H.units = off;
   H.hbm_units = hbm_units;
 }

@@ -57,6 +57,7 @@ constexpr int kU = 8;                   // 64-probe batches per super-batch
 constexpr int kBmWords = 2 * kU;        // per-wave task-end bitmap (64 * kU bits)
 constexpr int kMarkInts = kWaves * kBmWords;          // packs
 constexpr int kItemMarkInts = kWavesBig * kBmWords;   // item work-groups (up to 8 waves)
+
 constexpr int32_t kEmpty = -1;
 // FULL support, single-row LDS tables: a slot's value word is the key's index
 // in its row (< 2^13: such rows have at most 8192 keys) plus its hits in this
@@ -177,11 +178,12 @@ __device__ unsigned int* shift_counters() {
   return s_shift;
 }
 
-// TASK_EDGE: also credit the task's own edge (a, b) here, one atomic per hit;
-// the main probe paths leave it to credit_task instead.
-template <int MODE, int KIND, bool TASK_EDGE>
-__device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos,
-                                       uint32_t ts, int32_t k) {
+// The per-hit credits other than the task's own edge (a, b), which goes
+// through the wave's per-task counters (wave_probe). BLOCK: the shift
+// counter of k; FULL: the probed entry (a, k) of U_a and k's entry (b, k) of
+// U_b.
+template <int MODE, int KIND>
+__device__ __forceinline__ void credit(const Args& A, const TableRef& t, int where, uint32_t pos, int32_t k) {
   // indices are checked against m so that no credit can leave the array
   if (MODE == MODE_BLOCK) {
     // shift z of Eq. 5 closes the triangle with k = x + y + z (mod q)
@@ -189,7 +191,6 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
     if (z < 0) z += A.q;
     atomicAdd(&shift_counters()[z], 1u);
   } else if (MODE == MODE_SUPPORT_FULL) {
-    if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // edge (a, b)
     if (pos < A.m) atomicAdd(&A.support[pos], 1);  // edge (a, k): probed entry of U_a
     // edge (b, k): k's entry in U_b. A single-row table counts it in the
     // slot's LDS word (added to the array once per work-group, after the
@@ -200,32 +201,22 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
       const uint32_t other = (uint32_t)(KIND == TK_GLOBAL ? where : t.val[where]);
       if (other < A.m) atomicAdd(&A.support[other], 1);
     }
-  } else if (MODE == MODE_SUPPORT_ORIENTED) {
-    if (TASK_EDGE && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], 1);  // c(a, b) of Eq. 1
   }
 }
 
-// The task-edge credit of one row of 64 probes (support modes; every lane of
-// the wave calls it). Probes are laid out in task order, so the lanes of one
-// task are contiguous and share ts (the task's own U position + 1, distinct
-// per task): the first lane of each run adds the run's hits with one atomic
-// instead of one atomic per hit, which would serialise on one address.
-template <int MODE>
-__device__ __forceinline__ void credit_task(const Args& A, bool found, uint32_t ts) {
-  if (MODE != MODE_SUPPORT_FULL && MODE != MODE_SUPPORT_ORIENTED) return;
-  const uint64_t hitm = __ballot(found);
-  if (hitm == 0) return;
-  const int lane = lane_id();
-  const uint32_t prev = (uint32_t)__shfl_up((int)ts, 1, 64);
-  const bool head = lane == 0 || prev != ts;
-  const uint64_t headm = __ballot(head);
-  if (head) {
-    const uint64_t from = ~((1ull << lane) - 1ull);     // lanes >= this one
-    const uint64_t above = headm & ~((2ull << lane) - 1ull);  // later heads (none past lane 63)
-    const uint64_t upto = above ? (above & (0ull - above)) - 1ull : ~0ull;  // lanes before the next head
-    const uint32_t c = (uint32_t)__popcll(hitm & from & upto);
-    if (c && ts - 1u < A.m) atomicAdd(&A.support[ts - 1u], (int)c);
-  }
+// Support modes credit every hit to its task's own edge (a, b) through the
+// task window: lane j owns window task j and keeps its hits in a register.
+// The lanes of one task are a contiguous run of each 64-probe batch, so after
+// a batch's lookups lane j adds the hits of its run - the batch's hit ballot
+// masked to the lanes [lo, hi) its task covers; when the window moves on (or
+// the wave's range ends) it adds them to the task's edge with one global
+// atomic. A task cut between waves gets one atomic from each.
+__device__ __forceinline__ uint64_t lane_range_mask(int lo, int hi) {
+  lo = lo < 0 ? 0 : (lo > 64 ? 64 : lo);
+  hi = hi < 0 ? 0 : (hi > 64 ? 64 : hi);
+  if (hi <= lo) return 0;
+  const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+  return below_hi & ~((1ull << lo) - 1ull);
 }
 
 // Count mode needs only whether the bucket holds k: an OR of four compares
@@ -251,7 +242,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)q);
   constexpr bool GLOBAL = KIND == TK_GLOBAL;
   constexpr bool MULTI = KIND == TK_MULTI;
-  constexpr bool kNeedTs = MODE == MODE_SUPPORT_FULL || MODE == MODE_SUPPORT_ORIENTED;
+  constexpr bool kTaskHits = MODE == MODE_SUPPORT_FULL || MODE == MODE_SUPPORT_ORIENTED;
   constexpr uint32_t SB = 64u * kU;
   const int lane = lane_id();
   const int64_t T = A.T;
@@ -275,6 +266,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
   uint32_t P0 = (uint32_t)(A.tprefix[t] - q0);  // start of the window's first task (may wrap)
 
   uint32_t done = 0;
+  uint32_t tcnt = 0;  // support modes: hits of this lane's window task
   while (done < len) {
     const uint32_t rem = len - done;
     // end of the lane's task relative to the current position, within the range
@@ -328,9 +320,10 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
         if (lane < (int)(SB / 32)) bm[lane] = 0;
         wave_sync_lds();
       }
-      uint32_t pos[kU], ts[kU], bbase[kU], bmask[kU];
+      uint32_t pos[kU], bbase[kU], bmask[kU];
       int32_t k[kU];
       bool ok[kU];
+      uint32_t fmask = 0;  // support modes: bit u = this lane's probe of batch u hit
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         // ds_bpermute uses lane index bits only, so lanes past the window
@@ -338,7 +331,6 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
         const uint32_t r = sb + 64u * u + (uint32_t)lane;
         pos[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)cbase) + r;
         ok[u] = r < lim;
-        ts[u] = kNeedTs ? (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)tsj) : 0u;
         if constexpr (MULTI) {
           const uint32_t dsc = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(jl[u] << 2), (int)tdesc);
           bbase[u] = dsc & 0xFFFFu;
@@ -369,18 +361,15 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
 #pragma unroll
           for (int u = g0; u < g0 + kG; ++u) {
             bool found;
-            if constexpr (MODE == MODE_COUNT) {
+            if constexpr (MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED) {
               found = bucket_has(v[u - g0], k[u]);
-              hits += found ? 1u : 0u;
             } else {
               const int j = match_slot(v[u - g0], k[u]);
               found = j >= 0;
-              if (found) {
-                ++hits;
-                credit<MODE, KIND, false>(A, tr, (int)(bk[u] * kBucket + j), pos[u], ts[u], k[u]);
-              }
-              credit_task<MODE>(A, found, ts[u]);
+              if (found) credit<MODE, KIND>(A, tr, (int)(bk[u] * kBucket + j), pos[u], k[u]);
             }
+            hits += found ? 1u : 0u;
+            if (kTaskHits) fmask |= (found ? 1u : 0u) << u;
             unres[u] = ok[u] & !found & (v[u - g0].w != kEmpty);
             any_unres |= unres[u];
           }
@@ -394,14 +383,15 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
               b2 = (b2 + 1) & bmask[u];
               const int4 w = tab4[bbase[u] + b2];
               bool found;
-              if constexpr (MODE == MODE_COUNT) {
+              if constexpr (MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED) {
                 found = bucket_has(w, k[u]);
               } else {
                 const int j = match_slot(w, k[u]);
                 found = j >= 0;
-                if (found) credit<MODE, KIND, true>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], ts[u], k[u]);
+                if (found) credit<MODE, KIND>(A, tr, (int)((bbase[u] + b2) * kBucket + j), pos[u], k[u]);
               }
               hits += found ? 1u : 0u;
+              if (kTaskHits) fmask |= (found ? 1u : 0u) << u;
               unres[u] = !found & (w.w != kEmpty);
             }
           }
@@ -412,11 +402,28 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
           const int64_t where = ok[u] ? hbm_find(A.hcol, tr.rs, tr.d, k[u]) : -1;
           if (where >= 0) {
             ++hits;
-            if (MODE != MODE_COUNT) credit<MODE, TK_GLOBAL, false>(A, tr, (int)where, pos[u], ts[u], k[u]);
+            if (MODE != MODE_COUNT) credit<MODE, TK_GLOBAL>(A, tr, (int)where, pos[u], k[u]);
+            if (kTaskHits) fmask |= 1u << u;
           }
-          credit_task<MODE>(A, where >= 0, ts[u]);
         }
       }
+      if constexpr (kTaskHits) {
+        // this lane's task covers the relative probes [s_rel, e) (s_rel may
+        // be below 0 for lane 0); add the hits of batch u that fall there
+        const int ts0 = (int)s_rel, te0 = (int)e;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint64_t hm = __ballot((fmask >> u) & 1u);
+          if (hm) {
+            const int base = (int)(sb + 64u * (uint32_t)u);
+            tcnt += (uint32_t)__popcll(hm & lane_range_mask(ts0 - base, te0 - base));
+          }
+        }
+      }
+    }
+    if (kTaskHits && tcnt) {  // the window task's own edge
+      if (tsj - 1u < A.m) atomicAdd(&A.support[tsj - 1u], (int)tcnt);
+      tcnt = 0;
     }
     if (more) {
       t += 64;  // a window that is not the last covers exactly its 64 tasks
@@ -576,7 +583,8 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
 constexpr int kOccPacks = 5, kOccBatch = 5;
 
 template <int MODE, bool MH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT ? kOccPacks : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED ? kOccPacks : 4)))
 void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
                    uint32_t pack_slots) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
@@ -648,16 +656,18 @@ void k_count_items(Args A, const CountItem* __restrict__ items) {
 // but 7 waves per SIMD with spill-free registers run faster; wg_huge tables
 // (32 KiB) allow 4-5 work-groups per CU and wg_giant tables (64 KiB) 2.
 // Support modes hold more state per probe and run at 4.
-constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSupport = 4;
+constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSupport = 5;
 
 template <int MODE, bool GLOBAL, bool MH>
 const void* items_kernel(int cls) {
   static_assert(class_waves(CLS_WG_HUGE) == kWavesBig && class_waves(CLS_WG_GIANT) == kWavesBig &&
                     class_waves(CLS_WG_LARGE) == kWaves && class_waves(CLS_GLOBAL) == kWaves,
                 "work-group shapes of the item classes");
+  // oriented support adds only the per-task counters to the count: same budgets
+  constexpr bool kCountLike = MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED;
   if constexpr (GLOBAL) {  // no table: LDS does not limit
-    return (const void*)k_count_items<MODE, GLOBAL, MODE == MODE_COUNT ? kOccSmall : kOccSupport, kWaves, MH>;
-  } else if constexpr (MODE != MODE_COUNT) {
+    return (const void*)k_count_items<MODE, GLOBAL, kCountLike ? kOccSmall : kOccSupport, kWaves, MH>;
+  } else if constexpr (!kCountLike) {
     if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig, MH>;
     return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves, MH>;
   } else {
@@ -692,12 +702,12 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
 template <int MODE, bool MH>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
-  const size_t mark_bytes = items_lds_bytes(-1, VALS);
+  const size_t mark_bytes = items_lds_bytes(-1, MODE);
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
     if (w.n_packs[c] == 0) continue;
     // a pack's tables take at most kPackSlots plus one row's table
     const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
-    const size_t lds = pack_lds_bytes(slots, VALS);
+    const size_t lds = pack_lds_bytes(slots, MODE);
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, MH>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -709,7 +719,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
     const bool global = c == CLS_GLOBAL;
     const void* f = global ? items_kernel<MODE, true, MH>(c) : items_kernel<MODE, false, MH>(c);
-    const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], VALS);
+    const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], MODE);
     if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const CountItem* items = w.items[c];
     void* kargs[] = {const_cast<Args*>(&A), &items};
@@ -785,12 +795,14 @@ void launch_batch_mode(const Args* d_args, const BatchUnit* d_units, int64_t n_u
 
 }  // namespace
 
-size_t pack_lds_bytes(uint32_t slots, bool vals) {
-  return sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 + (size_t)slots * (vals ? 2 : 1));
+size_t pack_lds_bytes(uint32_t slots, int mode) {
+  const size_t vals = mode == MODE_SUPPORT_FULL ? 2 : 1;
+  return sizeof(int32_t) * ((size_t)kMarkInts + kPackMetaWords + 3 + (size_t)slots * vals);
 }
 
-size_t items_lds_bytes(int log2S, bool vals) {
-  return sizeof(int32_t) * ((size_t)kItemMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * (vals ? 2 : 1)));
+size_t items_lds_bytes(int log2S, int mode) {
+  const size_t vals = mode == MODE_SUPPORT_FULL ? 2 : 1;
+  return sizeof(int32_t) * ((size_t)kItemMarkInts + (log2S < 0 ? 0 : ((size_t)1 << log2S) * vals));
 }
 
 void launch_batch(CountMode mode, const CountArgs* d_args, const BatchUnit* d_units, int64_t n_units,

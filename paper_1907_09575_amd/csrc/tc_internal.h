@@ -331,10 +331,10 @@ void free_plan_idle(BatchPlan* P);
 void zero_i32(int32_t* p, int64_t n, hipStream_t st, bool timed);
 
 // Dynamic LDS bytes of a pack work-group with `slots` table slots, and of an
-// item work-group with a 2^log2S-slot table (log2S < 0: no table, HBM lookups);
-// vals: tables also hold U positions (full support).
-size_t pack_lds_bytes(uint32_t slots, bool vals);
-size_t items_lds_bytes(int log2S, bool vals);
+// item work-group with a 2^log2S-slot table (log2S < 0: no table, HBM
+// lookups), in CountMode `mode` (full support tables also hold U positions).
+size_t pack_lds_bytes(uint32_t slots, int mode);
+size_t items_lds_bytes(int log2S, int mode);
 
 inline CountView graph_view(const Graph& g) {
   return CountView{g.row_ptr, g.col, g.col, g.m, &g.w, 1, 0, g.hash};
