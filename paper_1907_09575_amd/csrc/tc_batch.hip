@@ -266,6 +266,8 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
     const Graph& g = *entries[i].g;
     TC_REQUIRE(g.device == device, TC_EINVAL, "batch plan: graph built on another device");
     require_plain(g, "batch plan");
+    TC_REQUIRE(g.m <= kMaxBufferEdges, TC_EOVERFLOW,
+               "batch plan: a graph of 2^30 edges or more (count it with tc_count)");
     const WorkSet& w = g.w;
     CountArgs& A = H.args[(size_t)i];
     std::memset(&A, 0, sizeof(A));

@@ -126,7 +126,7 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   LocalRows H, P;
   gather_local(H, g, q, x, st);  // hash side: rows j == x
   gather_local(P, g, q, y, st);  // probe side: rows i == y
-  TC_REQUIRE(P.nnz <= kMaxEdges, TC_EOVERFLOW, "tc_block_count: probe side exceeds 2^30 entries");
+  TC_REQUIRE(P.nnz <= kMaxBufferEdges, TC_EOVERFLOW, "tc_block_count: a rank's probe side of 2^30 entries or more");
 
   int64_t T = 0;
   TaskLists tl;

@@ -86,6 +86,17 @@ __device__ __forceinline__ int32_t col_load(__amdgpu_buffer_rsrc_t r, uint32_t b
   return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
 }
 
+// Code variants of the count kernels (template argument VAR):
+//   VAR_BASE  - the direct AND of Section 5.2; probes read by raw buffer loads
+//               with 32-bit byte offsets (probe sides of fewer than 2^30
+//               entries);
+//   VAR_MUL   - the ablation of the direct AND (tc_graph_variant): a
+//               multiplicative hash for every table;
+//   VAR_WIDE  - probe sides of 2^30 entries or more: probes read with 64-bit
+//               addresses (positions stay 32-bit), masked for lanes past the
+//               range.
+enum CountVariant : int { VAR_BASE = 0, VAR_MUL = 1, VAR_WIDE = 2 };
+
 // Bucket of key k in a table of bmask + 1 buckets: the direct bitwise AND of
 // Section 5.2 (the key's low bits), or, MH (the ablation of that choice,
 // tc_graph_variant), a multiplicative hash: the top log2(buckets) bits of
@@ -231,7 +242,7 @@ __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
 
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
 // task t contains probe q.
-template <int MODE, int KIND, bool MH>
+template <int MODE, int KIND, int VAR>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
                            uint32_t* bm, uint32_t& hits) {
   // the range is the wave's own (uniform across its lanes): scalar registers
@@ -242,6 +253,7 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)q);
   constexpr bool GLOBAL = KIND == TK_GLOBAL;
   constexpr bool MULTI = KIND == TK_MULTI;
+  constexpr bool MH = VAR == VAR_MUL, WIDE = VAR == VAR_WIDE;
   constexpr bool kTaskHits = MODE == MODE_SUPPORT_FULL || MODE == MODE_SUPPORT_ORIENTED;
   constexpr uint32_t SB = 64u * kU;
   const int lane = lane_id();
@@ -341,7 +353,10 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
         }
       }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) k[u] = col_load(rsrc, ok[u] ? pos[u] * 4u : kOffNone);
+      for (int u = 0; u < kU; ++u) {
+        if constexpr (WIDE) k[u] = ok[u] ? A.col[(uint64_t)pos[u]] : 0;
+        else k[u] = col_load(rsrc, ok[u] ? pos[u] * 4u : kOffNone);
+      }
 
       if constexpr (!GLOBAL) {
         // buckets are read in groups of kG so that the 16-byte results of one
@@ -470,7 +485,7 @@ __device__ __forceinline__ void block_init() {
 // each task looking up its own row's table.
 constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
 
-template <int MODE, bool MH>
+template <int MODE, int VAR>
 __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int32_t* __restrict__ rows,
                                           const uint32_t* __restrict__ pack_ptr, uint32_t pack,
                                           uint32_t pack_slots, int32_t* smem) {
@@ -534,7 +549,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
     const int32_t key = A.hcol[p];
     const uint32_t dsc = row_desc[lo];
     const uint32_t base = dsc & 0xFFFFu, bmask = dsc >> 16;
-    uint32_t bk = bucket_of<MH>(key, bmask);
+    uint32_t bk = bucket_of<VAR == VAR_MUL>(key, bmask);
     int disp = 0, slot = -1;
     while (true) {
 #pragma unroll
@@ -572,7 +587,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
       lo = lo + (c - 1) * step;
       hi = lo + step < hi ? lo + step : hi;
     }
-    wave_probe<MODE, TK_MULTI, MH>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
+    wave_probe<MODE, TK_MULTI, VAR>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
   }
   return block_flush<MODE>(hits, A);
 }
@@ -582,17 +597,17 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
 // CU; 5 with spill-free registers runs faster).
 constexpr int kOccPacks = 5, kOccBatch = 5;
 
-template <int MODE, bool MH>
+template <int MODE, int VAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED ? kOccPacks : 4)))
 void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
                    uint32_t pack_slots) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  pack_body<MODE, MH>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
+  pack_body<MODE, VAR>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
-template <int MODE, bool GLOBAL, bool MH>
+template <int MODE, bool GLOBAL, int VAR>
 __device__ __forceinline__ unsigned long long items_body(const Args& A, const CountItem* __restrict__ grp,
                                                          int32_t* smem) {
   __shared__ int s_D;
@@ -615,7 +630,7 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
     if (tid == 0) s_D = 0;
     __syncthreads();
     const uint32_t bmask = S / kBucket - 1;
-    int md = build_table<VALS, MH>(tab, val, bmask, A.hcol, rs, d, tid, (int)blockDim.x);
+    int md = build_table<VALS, VAR == VAR_MUL>(tab, val, bmask, A.hcol, rs, d, tid, (int)blockDim.x);
     if (md) atomicMax(&s_D, md);  // per lane: see pack_body
     __syncthreads();
     tr.tab = tab;
@@ -625,7 +640,7 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
   }
   wave_sync_lds();
   const CountItem it = grp[wave];
-  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE, MH>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE, VAR>(A, tr, it.t0, it.q0, it.len, bm, hits);
   if constexpr (VALS && !GLOBAL) {
     // the (b, k) credits of the work-group: one atomic per slot that was hit
     __syncthreads();
@@ -644,11 +659,11 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
 // OCC: waves per SIMD the kernel's registers are budgeted for. A class whose
 // tables limit a CU to fewer work-groups gets the registers that would
 // otherwise go unused (fewer spills in the probe loop).
-template <int MODE, bool GLOBAL, int OCC, int WAVES, bool MH>
+template <int MODE, bool GLOBAL, int OCC, int WAVES, int VAR>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(OCC)))
 void k_count_items(Args A, const CountItem* __restrict__ items) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  items_body<MODE, GLOBAL, MH>(A, items + (int64_t)blockIdx.x * WAVES, reinterpret_cast<int32_t*>(smem4));
+  items_body<MODE, GLOBAL, VAR>(A, items + (int64_t)blockIdx.x * WAVES, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Count mode per class (chosen by timing at RMAT scale 24): wg_small and
@@ -658,24 +673,25 @@ void k_count_items(Args A, const CountItem* __restrict__ items) {
 // Support modes hold more state per probe and run at 4.
 constexpr int kOccSmall = 7, kOccLarge = 7, kOccHuge = 5, kOccGiant = 4, kOccSupport = 5;
 
-template <int MODE, bool GLOBAL, bool MH>
+template <int MODE, bool GLOBAL, int VAR>
 const void* items_kernel(int cls) {
   static_assert(class_waves(CLS_WG_HUGE) == kWavesBig && class_waves(CLS_WG_GIANT) == kWavesBig &&
                     class_waves(CLS_WG_LARGE) == kWaves && class_waves(CLS_GLOBAL) == kWaves,
                 "work-group shapes of the item classes");
-  // oriented support adds only the per-task counters to the count: same budgets
-  constexpr bool kCountLike = MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED;
+  // oriented support adds only the per-task counters to the count: same budgets;
+  // wide probe addresses take more registers: the support budget
+  constexpr bool kCountLike = (MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED) && VAR != VAR_WIDE;
   if constexpr (GLOBAL) {  // no table: LDS does not limit
-    return (const void*)k_count_items<MODE, GLOBAL, kCountLike ? kOccSmall : kOccSupport, kWaves, MH>;
+    return (const void*)k_count_items<MODE, GLOBAL, kCountLike ? kOccSmall : kOccSupport, kWaves, VAR>;
   } else if constexpr (!kCountLike) {
-    if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig, MH>;
-    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves, MH>;
+    if (class_waves(cls) == kWavesBig) return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWavesBig, VAR>;
+    return (const void*)k_count_items<MODE, GLOBAL, kOccSupport, kWaves, VAR>;
   } else {
     switch (cls) {
-      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge, kWaves, MH>;
-      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge, kWavesBig, MH>;
-      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant, kWavesBig, MH>;
-      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall, kWaves, MH>;
+      case CLS_WG_LARGE: return (const void*)k_count_items<MODE, GLOBAL, kOccLarge, kWaves, VAR>;
+      case CLS_WG_HUGE: return (const void*)k_count_items<MODE, GLOBAL, kOccHuge, kWavesBig, VAR>;
+      case CLS_WG_GIANT: return (const void*)k_count_items<MODE, GLOBAL, kOccGiant, kWavesBig, VAR>;
+      default: return (const void*)k_count_items<MODE, GLOBAL, kOccSmall, kWaves, VAR>;
     }
   }
 }
@@ -699,7 +715,7 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
     {"block:pack_small", "block:pack_large", "block:wg_small", "block:wg_large", "block:wg_huge",
      "block:wg_giant", "block:global"}};
 
-template <int MODE, bool MH>
+template <int MODE, int VAR>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const size_t mark_bytes = items_lds_bytes(-1, MODE);
@@ -709,16 +725,16 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
     const size_t lds = pack_lds_bytes(slots, MODE);
     if (lds > 65536)
-      TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, MH>,
+      TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, VAR>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, MH>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
+    TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, VAR>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
               st, A, w.pack_rows[c], w.pack_ptr[c], slots);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (w.n_items[c] == 0) continue;
     const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
     const bool global = c == CLS_GLOBAL;
-    const void* f = global ? items_kernel<MODE, true, MH>(c) : items_kernel<MODE, false, MH>(c);
+    const void* f = global ? items_kernel<MODE, true, VAR>(c) : items_kernel<MODE, false, VAR>(c);
     const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], MODE);
     if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const CountItem* items = w.items[c];
@@ -769,11 +785,11 @@ void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__
       Args A = gargs[bu.graph];
       A.count = counts + bu.graph;
       if (bu.kind == BK_PACK) {
-        pack_body<MODE, false>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+        pack_body<MODE, VAR_BASE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
       } else if (bu.kind == BK_ITEMS) {
-        items_body<MODE, false, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+        items_body<MODE, false, VAR_BASE>(A, static_cast<const CountItem*>(bu.p0), smem);
       } else {
-        items_body<MODE, true, false>(A, static_cast<const CountItem*>(bu.p0), smem);
+        items_body<MODE, true, VAR_BASE>(A, static_cast<const CountItem*>(bu.p0), smem);
       }
     }
   }
@@ -842,19 +858,29 @@ void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t*
               reinterpret_cast<unsigned long long*>(d_per_shift), (int64_t)v.q);
   TC_HIP(hipGetLastError());
   if (w.n_tasks == 0) return;
-  TC_REQUIRE(v.pm <= kMaxEdges, TC_EOVERFLOW, "launch_count: probe side exceeds 2^30 entries");
+  TC_REQUIRE(v.pm <= kMaxEdges, TC_EOVERFLOW, "launch_count: probe side of 2^32 - 64 entries or more");
+  const bool wide = v.pm > kMaxBufferEdges;
+  TC_REQUIRE(!wide || mode != MODE_BLOCK, TC_EOVERFLOW, "launch_count: a rank's probe side of 2^30 entries or more");
   Args A{v.hrow_ptr, v.hcol, v.pcol, w.tstart, w.tprefix, w.tbeg, w.tend, w.n_tasks, (uint32_t)v.pm,
          reinterpret_cast<unsigned long long*>(d_count), d_support,
          reinterpret_cast<unsigned long long*>(d_per_shift), v.q, v.xy};
   TC_REQUIRE(v.hash == 0 || mode == MODE_COUNT, TC_EINVAL, "launch_count: multiplicative hashing counts only");
+  TC_REQUIRE(!(wide && v.hash), TC_EOVERFLOW, "launch_count: multiplicative hashing below 2^30 edges only");
   switch (mode) {
     case MODE_COUNT:
-      if (v.hash) launch_mode<MODE_COUNT, true>(w, A, st);
-      else launch_mode<MODE_COUNT, false>(w, A, st);
+      if (v.hash) launch_mode<MODE_COUNT, VAR_MUL>(w, A, st);
+      else if (wide) launch_mode<MODE_COUNT, VAR_WIDE>(w, A, st);
+      else launch_mode<MODE_COUNT, VAR_BASE>(w, A, st);
       break;
-    case MODE_SUPPORT_FULL: launch_mode<MODE_SUPPORT_FULL, false>(w, A, st); break;
-    case MODE_SUPPORT_ORIENTED: launch_mode<MODE_SUPPORT_ORIENTED, false>(w, A, st); break;
-    case MODE_BLOCK: launch_mode<MODE_BLOCK, false>(w, A, st); break;
+    case MODE_SUPPORT_FULL:
+      if (wide) launch_mode<MODE_SUPPORT_FULL, VAR_WIDE>(w, A, st);
+      else launch_mode<MODE_SUPPORT_FULL, VAR_BASE>(w, A, st);
+      break;
+    case MODE_SUPPORT_ORIENTED:
+      if (wide) launch_mode<MODE_SUPPORT_ORIENTED, VAR_WIDE>(w, A, st);
+      else launch_mode<MODE_SUPPORT_ORIENTED, VAR_BASE>(w, A, st);
+      break;
+    case MODE_BLOCK: launch_mode<MODE_BLOCK, VAR_BASE>(w, A, st); break;
   }
 }
 

@@ -90,7 +90,8 @@ constexpr uint64_t kPackTarget = 65536; // target probes per pack of light rows 
 constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + one row's table)
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
-constexpr int64_t kMaxEdges = (1ll << 30) - 64;  // probe reads are 32-bit byte offsets into U
+constexpr int64_t kMaxEdges = (1ll << 32) - 64;        // U positions are 32-bit
+constexpr int64_t kMaxBufferEdges = (1ll << 30) - 64;  // below: probe reads by 32-bit byte offsets
 
 // Waves sharing one table in a work-group of item class c: the classes whose
 // tables allow only a few work-groups per CU get twice the waves per table.

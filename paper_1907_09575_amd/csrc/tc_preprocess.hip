@@ -555,7 +555,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     if (m_raw == 0) TC_HIP(hipStreamSynchronize(st));  // (compact has no sync then)
     m = compact("dedup", m_raw, up, [&](int64_t total, UniquePred& p) {
       TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
-      TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^30 or more edges");
+      TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 64 or more edges");
       E.alloc(sizeof(uint64_t) * (size_t)total);
       Ehi.alloc(sizeof(uint32_t) * (size_t)total);
       p.out = E.as<uint64_t>();

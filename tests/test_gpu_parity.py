@@ -185,6 +185,55 @@ def test_rmat_scale24_full_config(tc):
         assert np.array_equal(ps.cpu().numpy(), shifts)
 
 
+def test_more_than_2_pow_30_edges(tc):
+    # 533,000 disjoint copies of K_64 and one K_300, under a random
+    # relabelling: 1,074,572,850 edges (past 2^30, where probes switch to
+    # 64-bit addresses; the K_300 rows are heavy enough for the item kernels).
+    # Closed forms: T = W+ = probes = copies * C(64, 3) + C(300, 3); a row of
+    # out-degree d holds d - 1 tasks, so tasks = copies * C(63, 2) + C(299, 2);
+    # edges of a K_k lie in k - 2 triangles
+    k, copies, big = 64, 533000, 300
+    iu = np.triu_indices(k, 1)
+    ib = np.triu_indices(big, 1)
+    base = np.arange(copies, dtype=np.int32) * k
+    n = k * copies + big
+    rng = np.random.default_rng(30)
+    relabel = rng.permutation(n).astype(np.int32)
+    s = relabel[np.concatenate([(base[:, None] + iu[0].astype(np.int32)[None, :]).ravel(),
+                                ib[0].astype(np.int32) + k * copies])]
+    d = relabel[np.concatenate([(base[:, None] + iu[1].astype(np.int32)[None, :]).ravel(),
+                                ib[1].astype(np.int32) + k * copies])]
+    del relabel, base
+    m = copies * comb(k, 2) + comb(big, 2)
+    T = copies * comb(k, 3) + comb(big, 3)
+    assert m > (1 << 30) and len(s) == m
+    print("case K64 x %d + K300: m = %d" % (copies, m), flush=True)
+    g = tc.tc_preprocess(torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), n)
+    del s, d
+    info = g.info()
+    assert info["m"] == m
+    assert info["wedges_plus"] == info["probes"] == T
+    assert info["tasks"] == copies * comb(k - 1, 2) + comb(big - 1, 2)
+    cls = tc.tc_graph_class_stats(g)
+    assert sum(v["rows"] for c, v in cls.items() if c.startswith("wg_")) > 0
+    assert gpu_count(tc, g) == T
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    for mode in (tc.TC_SUPPORT_FULL, tc.TC_SUPPORT_ORIENTED):
+        sup, _ = tc.tc_edge_support(g, mode, count=cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == T
+        total = int(sup.sum(dtype=torch.int64).item())
+        if mode == tc.TC_SUPPORT_FULL:
+            assert int(sup.min().item()) == k - 2 and int(sup.max().item()) == big - 2
+            assert int((sup == big - 2).sum().item()) == comb(big, 2)
+            assert total == 3 * T
+        else:
+            assert total == T
+        del sup
+    g.free()
+    torch.cuda.empty_cache()
+
+
 def test_edge_cases(tc):
     # empty edge list
     g = gpu_graph(tc, np.zeros(0, np.int32), np.zeros(0, np.int32), 10)
