@@ -72,8 +72,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     p.add_argument("--batch-graphs", type=int, default=4096)
     p.add_argument("--no-serve", action="store_true", help="skip served vs plain FIFO")
-    p.add_argument("--serve-requests", type=int, default=1000)
-    p.add_argument("--serve-warmup", type=int, default=100)
+    p.add_argument("--serve-requests", type=int, default=10000)
+    p.add_argument("--serve-warmup", type=int, default=1000)
     p.add_argument("--serve-slots", type=int, default=64)
     p.add_argument("--serve-prep-threads", type=int, default=8)
     return p.parse_args()

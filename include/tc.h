@@ -356,8 +356,11 @@ typedef struct {
 } tc_result;
 
 /* options_json (nullable), flat object: "prep_threads" (default: half the
- * host's threads, 1 .. 8),
- * "lds_cap_log2" and "blocks_per_cu" (the batch schedule of every tick). */
+ * host's threads, 1 .. 8), "lds_cap_log2" and "blocks_per_cu" (the batch
+ * schedule of every tick), "lpt" (1: a tick's units largest first, which
+ * costs a sort and a synchronisation of the tick stream; default 0: request
+ * order). A tick takes the ready requests whose share of its batch plans
+ * (kernel arguments and work units) still fits the budget, at least one. */
 tc_status tc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const char* options_json,
                            tc_server** out);
 /* Queue a request; *ticket identifies it. TC_EINVAL for a malformed request. */

@@ -366,22 +366,26 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
     DevBuf dsrc(sizeof(BatchSrc) * (size_t)num);
     TC_HIP(hipMemcpyAsync(dsrc.p, srcs.data(), sizeof(BatchSrc) * (size_t)num, hipMemcpyHostToDevice, st));
     const int64_t n = P->n_units;
-    DevBuf raw(sizeof(BatchUnit) * (size_t)n);
-    DevBuf key(sizeof(uint32_t) * (size_t)n), key2(sizeof(uint32_t) * (size_t)n);
-    DevBuf idx(sizeof(uint32_t) * (size_t)n), idx2(sizeof(uint32_t) * (size_t)n);
-    TC_LAUNCH("batch_units", k_batch_units, dim3((unsigned)num), dim3(256), 0, st, dsrc.as<BatchSrc>(),
-              raw.as<BatchUnit>(), key.as<uint32_t>(), idx.as<uint32_t>());
-    TC_HIP(hipGetLastError());
-    const uint32_t* order = idx.as<uint32_t>();
-    if (t.lpt) {
-      bool alt = radix_sort<uint32_t, uint32_t>(key.as<uint32_t>(), key2.as<uint32_t>(), idx.as<uint32_t>(),
-                                                idx2.as<uint32_t>(), n, 0, 32, st, "batch_lpt");
-      order = alt ? idx2.as<uint32_t>() : idx.as<uint32_t>();
+    if (!t.lpt) {
+      // graph order: the units go straight to the plan (no sort, no sync)
+      TC_LAUNCH("batch_units", k_batch_units, dim3((unsigned)num), dim3(256), 0, st, dsrc.as<BatchSrc>(),
+                P->d_units, (uint32_t*)nullptr, (uint32_t*)nullptr);
+      TC_HIP(hipGetLastError());
+    } else {
+      DevBuf raw(sizeof(BatchUnit) * (size_t)n);
+      DevBuf key(sizeof(uint32_t) * (size_t)n), key2(sizeof(uint32_t) * (size_t)n);
+      DevBuf idx(sizeof(uint32_t) * (size_t)n), idx2(sizeof(uint32_t) * (size_t)n);
+      TC_LAUNCH("batch_units", k_batch_units, dim3((unsigned)num), dim3(256), 0, st, dsrc.as<BatchSrc>(),
+                raw.as<BatchUnit>(), key.as<uint32_t>(), idx.as<uint32_t>());
+      TC_HIP(hipGetLastError());
+      const bool alt = radix_sort<uint32_t, uint32_t>(key.as<uint32_t>(), key2.as<uint32_t>(), idx.as<uint32_t>(),
+                                                      idx2.as<uint32_t>(), n, 0, 32, st, "batch_lpt");
+      const uint32_t* order = alt ? idx2.as<uint32_t>() : idx.as<uint32_t>();
+      TC_LAUNCH("batch_gather", k_gather_units, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st,
+                raw.as<BatchUnit>(), order, n, P->d_units);
+      TC_HIP(hipGetLastError());
+      check_sorts(st);  // (synchronises st)
     }
-    TC_LAUNCH("batch_gather", k_gather_units, dim3((unsigned)div_up(n, 256)), dim3(256), 0, st,
-              raw.as<BatchUnit>(), order, n, P->d_units);
-    TC_HIP(hipGetLastError());
-    if (t.lpt) check_sorts(st);  // (synchronises st; a plan in input order needs no check)
   }
   return P.release();
 }

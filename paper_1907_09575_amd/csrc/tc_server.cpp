@@ -47,8 +47,11 @@ struct Req {
   std::string err;
   enum State { PENDING, PREP, READY, RUNNING, DONE } state = PENDING;
   size_t support_bytes = 0;  // reserved for the device support array
+  size_t plan_bytes = 0;     // reserved for its share of a tick's batch plan
   CacheEntry* ce = nullptr;
   int32_t* d_support = nullptr;
+  tc_status copy_status = TC_OK;  // support copy to the caller's buffer
+  std::string copy_err;
 };
 
 struct CacheEntry {
@@ -73,6 +76,15 @@ struct CacheEntry {
 // graph (CSR, rank map, tasks and work units).
 size_t prep_estimate(int64_t m_raw, int64_t n) {
   return (size_t)(56 * m_raw + 40 * n) + ((size_t)1 << 20);
+}
+
+// Device bytes of a graph's share of a tick's batch plan: its kernel
+// arguments and unit sources, and its work units (the plan's units and, while
+// it is made, their first copy and sort keys).
+size_t plan_estimate(const Graph& g) {
+  int64_t units = g.w.n_packs[0] + g.w.n_packs[1];
+  for (int c = CLS_WG_SMALL; c < NUM_CLASSES; ++c) units += g.w.n_items[c] / kWaves;
+  return (size_t)512 + (size_t)units * (2 * sizeof(BatchUnit) + 4 * sizeof(uint32_t));
 }
 
 // Preprocessing workers by default: half the host's threads, 1 .. 8 (each
@@ -154,8 +166,9 @@ struct Server {
   }
 
   void release(Req* q) {
-    unreserve(q->support_bytes);
+    unreserve(q->support_bytes + q->plan_bytes);
     q->support_bytes = 0;
+    q->plan_bytes = 0;
     if (q->ce) {
       CacheEntry* e = q->ce;
       q->ce = nullptr;
@@ -311,12 +324,19 @@ struct Server {
   void start_tick(Tick& tk) {
     std::vector<Req*> ready;
     {
+      // every ready request whose share of the tick's plans still fits the
+      // budget (at least one, so that a tick always makes progress); the
+      // others wait for the next tick
       std::lock_guard<std::mutex> lk(mu);
-      for (Req* q : active)
-        if (q->state == Req::READY) {
-          q->state = Req::RUNNING;
-          ready.push_back(q);
-        }
+      for (Req* q : active) {
+        if (q->state != Req::READY) continue;
+        const size_t pb = plan_estimate(*q->ce->g);
+        if (!ready.empty() && reserved + pb > (size_t)budget) continue;
+        q->state = Req::RUNNING;
+        q->plan_bytes = pb;
+        reserve(pb);
+        ready.push_back(q);
+      }
     }
     if (ready.empty()) return;
     for (Req* q : ready) tk.reqs[q->r.op].push_back(q);
@@ -365,6 +385,30 @@ struct Server {
     }
   }
 
+  // Support arrays of a finished tick to the callers' host buffers. Runs on
+  // the scheduler thread without the server lock: the tick's requests are
+  // the scheduler's alone until it publishes them, and their graphs stay
+  // resident while they hold a reference.
+  void copy_tick_support(Tick& tk) {
+    for (int op = 1; op < 3; ++op) {
+      for (Req* q : tk.reqs[op]) {
+        const int64_t m = q->ce->g->m;
+        q->copy_status = TC_OK;
+        if (m > q->r.m_raw) {
+          q->copy_status = TC_EINVAL;
+          q->copy_err = "tc_server: support_out (m_raw entries) is smaller than the graph's m";
+        } else if (m > 0) {
+          hipError_t he = hipMemcpy(q->r.support_out, q->d_support, sizeof(int32_t) * (size_t)m,
+                                    hipMemcpyDeviceToHost);
+          if (he != hipSuccess) {
+            q->copy_status = TC_EDEVICE;
+            q->copy_err = std::string("tc_server: support copy: ") + hipGetErrorString(he);
+          }
+        }
+      }
+    }
+  }
+
   void end_tick_locked(Tick& tk, tc_status status, const std::string& err) {
     for (int op = 0; op < 3; ++op) {
       for (size_t i = 0; i < tk.reqs[op].size(); ++i) {
@@ -374,16 +418,9 @@ struct Server {
         if (s == TC_OK) {
           q->res.count = h_counts[(size_t)op * max_slots + i];
           q->res.m = q->ce->g->m;
-          if (op != TC_REQ_COUNT && q->res.m > q->r.m_raw) {
-            s = TC_EINVAL;
-            e = "tc_server: support_out (m_raw entries) is smaller than the graph's m";
-          } else if (op != TC_REQ_COUNT && q->res.m > 0) {
-            hipError_t he = hipMemcpy(q->r.support_out, q->d_support, sizeof(int32_t) * (size_t)q->res.m,
-                                      hipMemcpyDeviceToHost);
-            if (he != hipSuccess) {
-              s = TC_EDEVICE;
-              e = std::string("tc_server: support copy: ") + hipGetErrorString(he);
-            }
+          if (q->copy_status != TC_OK) {  // (copy_tick_support, before the lock)
+            s = q->copy_status;
+            e = q->copy_err;
           }
         }
         if (q->d_support) cache_free(q->d_support, tick_stream, status == TC_OK);
@@ -422,6 +459,7 @@ struct Server {
       if (tk.running) {
         hipError_t q = hipEventQuery(tk.ev);
         if (q == hipSuccess) {
+          copy_tick_support(tk);  // (blocking copies, outside the lock)
           std::lock_guard<std::mutex> lk(mu);
           end_tick_locked(tk, TC_OK, "");
         } else if (q != hipErrorNotReady) {
@@ -467,9 +505,11 @@ tc_status server_guard(F&& f) {
 
 // options: flat JSON with integer values only
 void parse_options(const char* js, int& prep_threads, std::string& tuning) {
+  // tick plans: plain launches (a new plan every tick), units in request
+  // order unless "lpt": 1 (the LPT sort synchronises the tick stream)
   tuning = "{\"graph\": 0";
   if (!js) {
-    tuning += "}";
+    tuning += ", \"order\": \"input\"}";
     return;
   }
   std::string s(js);
@@ -498,7 +538,9 @@ void parse_options(const char* js, int& prep_threads, std::string& tuning) {
     TC_REQUIRE(v >= 0 && v <= 64, TC_EINVAL, "tc_server options: blocks_per_cu outside [0, 64]");
     tuning += ", \"blocks_per_cu\": " + std::to_string(v);
   }
-  tuning += "}";
+  int lpt = 0;
+  get("lpt", lpt);
+  tuning += lpt ? ", \"order\": \"lpt\"}" : ", \"order\": \"input\"}";
 }
 
 }  // namespace
