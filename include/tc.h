@@ -250,12 +250,17 @@ typedef struct tc_batch tc_batch;
  * (host array of handles; graphs may repeat). The work units of every graph
  * (the packs and item groups its own tc_count would launch) are merged into
  * one device queue, by default largest first (longest-processing-time order).
- * tuning_json (nullable) is a flat JSON object choosing the schedule:
+ * tuning_json is a flat JSON object choosing the schedule (NULL or "": the
+ * tuning table's "batch" entry for this many edges, else the defaults):
  *   "blocks_per_cu" (int, 0 = as many as LDS allows), "lds_cap_log2" (int in
  *   [6, 14]: item rows whose table exceeds 2^cap slots are looked up in HBM
  *   instead of LDS), "order" ("lpt" | "input"), "graph" (1 = launch through a
  *   captured HIP graph, 0 = plain launches), "chunk" (int, units taken per
- *   queue atomic, default 1, 0 = about 16 atomics per work-group);
+ *   queue atomic, default 1, 0 = about 16 atomics per work-group), and the
+ *   row-bucket thresholds (see tc_graph_retune; when any is named, the
+ *   unnamed ones take their defaults): graphs cut by others are
+ *   counted through retuned copies the plan builds and holds (about one
+ *   work-decomposition build per distinct graph);
  *   tc_batch_autotune's output is accepted as is. Unknown keys: TC_EINVAL.
  *   The handles must outlive the plan. Synchronises `stream`.
  */
@@ -302,14 +307,81 @@ tc_status tc_count_batched_noalloc(const tc_graph* const* graphs, int32_t num_gr
                                    void* stream);
 
 /*
- * tc_batch_autotune - time candidate schedules (LDS caps that change the
- * plan x unit orders x blocks per CU) on these graphs and write
- * {"best": {...}, "candidates": [...]} into the host buffer out_json[cap];
- * "best" can be passed to tc_batch_create. Synchronises `stream`; allocates
- * and frees its own scratch.
+ * tc_batch_autotune - time candidate schedules on these graphs: LDS caps that
+ * change the plan x unit orders x blocks per CU, then units per queue atomic,
+ * then the row-bucket thresholds one at a time (each candidate counting
+ * retuned copies of the graphs, tc_graph_retune; since a plan with other
+ * thresholds builds such copies when it is created, they are kept only if they
+ * beat the graphs' own by 2% or more). Writes {"key": ..., "best":
+ * {...}, "plan": {...}, "candidates": [...]} into the host buffer
+ * out_json[cap]; "best" (schedule and, if they won, thresholds) can be passed
+ * to tc_batch_create and is stored in the tuning table under "key", the
+ * entry for batches of this many edges. Synchronises `stream`; allocates and
+ * frees its own scratch.
  */
 tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, void* stream,
                             char* out_json, size_t cap);
+
+/* ---- row-bucket thresholds and the tuning table ------------------------------
+ *
+ * The work of a graph is cut into classes (tc_graph_class_stats) by four
+ * thresholds, a flat JSON object of integers:
+ *   "heavy_min"   (0 .. 2^24, default 32768): rows b with fewer probes than
+ *                 this, and tables of at most 2^10 slots, are packed several
+ *                 to a work-group; the others get work-groups of their own;
+ *   "pack_target" (1024 .. 2^24, default 65536): probes per pack (plus one
+ *                 row's);
+ *   "pack_slots"  (1024 .. 16384, default 4096): LDS table slots per pack
+ *                 (plus one row's table);
+ *   "wave_chunk"  (1024 .. 16384, default 16384): probes per wave item of a
+ *                 row with work-groups of its own.
+ * They change how the work is scheduled, never a count. Graphs take theirs
+ * from the tuning table when tc_preprocess builds them (the defaults when the
+ * table has no entry for their size).
+ *
+ * The tuning table maps keys "<arch>/<CUs>cu/<kind>_e<k>" to flat JSON
+ * objects: kind "graph" holds thresholds for graphs of 2^k .. 2^(k+1) - 1
+ * edges, kind "batch" a tc_batch_create schedule for batches of that many
+ * edges in total. A lookup takes the entry of the same arch, CU count and
+ * kind whose k is nearest, at most two classes away (ties: the smaller). The
+ * table starts empty, is read from the file TC_TUNING_FILE names (at the
+ * first lookup; a malformed or unreadable file is an error of the call that
+ * triggered it), and is filled by tc_tuning_load/set and the autotuners.
+ */
+
+/* Merge the entries of a tuning file (one JSON object of key: flat object)
+ * into the table. TC_EINVAL: unreadable or malformed (nothing merged). */
+tc_status tc_tuning_load(const char* path);
+/* Write the whole table to `path` (through a temporary file and a rename). */
+tc_status tc_tuning_save(const char* path);
+/* The entry a lookup of `key` finds (exact, else the nearest class) into
+ * out[cap] as text; "" if none. TC_EINVAL if it does not fit. */
+tc_status tc_tuning_get(const char* key, char* out, size_t cap);
+/* Set the entry of `key` to the flat JSON object `json` (NULL: remove it). */
+tc_status tc_tuning_set(const char* key, const char* json);
+/* The key of the current device for kind "graph" or "batch" and `edges`. */
+tc_status tc_tuning_key(const char* kind, int64_t edges, char* out, size_t cap);
+
+/*
+ * tc_graph_retune - a new handle counting the same graph with its work cut by
+ * other thresholds (params_json: any of the four keys; the others keep g's).
+ * It shares g's U (g must outlive it), owns only its work decomposition, and
+ * is a plain graph for every call. Synchronises `stream`.
+ */
+tc_status tc_graph_retune(const tc_graph* g, const char* params_json, void* stream, tc_graph** out);
+
+/* The thresholds g's work was cut with, as a flat JSON object, into out[cap]. */
+tc_status tc_graph_work_params(const tc_graph* g, char* out, size_t cap);
+
+/*
+ * tc_graph_autotune - time tc_count on g under candidate thresholds (each
+ * parameter in turn over a few values, the others held at the best so far),
+ * store the best in the tuning table under the "graph" key of g's size, so
+ * that later tc_preprocess calls for graphs of that size use it, and write
+ * {"key": ..., "best": {...}, "candidates": [...]} into out_json[cap].
+ * Synchronises `stream`.
+ */
+tc_status tc_graph_autotune(const tc_graph* g, void* stream, char* out_json, size_t cap);
 
 /* ---- served form: a request loop with continuous batching ------------------- */
 

@@ -79,6 +79,14 @@ _sig("tc_clustering", [_P, _P, _P, _P, _P])
 _sig("tc_transitivity", [_P, ctypes.POINTER(ctypes.c_double), _P])
 _sig("tc_truss", [_P, _P, ctypes.POINTER(_I32), _P])
 _sig("tc_graph_class_stats", [_P, _P])
+_sig("tc_tuning_load", [ctypes.c_char_p])
+_sig("tc_tuning_save", [ctypes.c_char_p])
+_sig("tc_tuning_get", [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t])
+_sig("tc_tuning_set", [ctypes.c_char_p, ctypes.c_char_p])
+_sig("tc_tuning_key", [ctypes.c_char_p, _I64, ctypes.c_char_p, ctypes.c_size_t])
+_sig("tc_graph_retune", [_P, ctypes.c_char_p, _P, ctypes.POINTER(_P)])
+_sig("tc_graph_work_params", [_P, ctypes.c_char_p, ctypes.c_size_t])
+_sig("tc_graph_autotune", [_P, _P, ctypes.c_char_p, ctypes.c_size_t])
 _sig("tc_class_name", [_I32], ctypes.c_char_p)
 _sig("tc_timer_create", [_I32, ctypes.POINTER(_P)])
 _sig("tc_timer_attach", [_P])
@@ -253,6 +261,61 @@ def tc_graph_variant(g: Graph, flags: int, stream=None) -> Graph:
     return v
 
 
+def tc_graph_retune(g: Graph, params=None, stream=None) -> Graph:
+    """A handle counting g with its work cut by other row-bucket thresholds
+    (dict or JSON text with heavy_min, pack_target, pack_slots, wave_chunk);
+    it shares g's U, so keep g alive."""
+    out = ctypes.c_void_p()
+    _check(_lib.tc_graph_retune(g.handle, _tuning(params), _stream(stream), ctypes.byref(out)), "tc_graph_retune")
+    v = Graph(out.value)
+    v.base = g
+    return v
+
+
+def tc_graph_work_params(g: Graph) -> dict:
+    """The row-bucket thresholds g's work was cut with."""
+    import json
+    buf = ctypes.create_string_buffer(512)
+    _check(_lib.tc_graph_work_params(g.handle, buf, len(buf)), "tc_graph_work_params")
+    return json.loads(buf.value.decode())
+
+
+def tc_graph_autotune(g: Graph, stream=None) -> dict:
+    """Time tc_count under candidate thresholds; the best goes into the
+    tuning table for graphs of g's size: {"key", "best", "candidates"}."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 14)
+    _check(_lib.tc_graph_autotune(g.handle, _stream(stream), buf, len(buf)), "tc_graph_autotune")
+    return json.loads(buf.value.decode())
+
+
+def tc_tuning_load(path: str):
+    _check(_lib.tc_tuning_load(os.fsencode(path)), "tc_tuning_load")
+
+
+def tc_tuning_save(path: str):
+    _check(_lib.tc_tuning_save(os.fsencode(path)), "tc_tuning_save")
+
+
+def tc_tuning_get(key: str) -> dict | None:
+    """The tuning-table entry a lookup of key finds (None if there is none)."""
+    import json
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.tc_tuning_get(key.encode(), buf, len(buf)), "tc_tuning_get")
+    return json.loads(buf.value.decode()) if buf.value else None
+
+
+def tc_tuning_set(key: str, entry=None):
+    """Set (dict or JSON text) or remove (None) a tuning-table entry."""
+    _check(_lib.tc_tuning_set(key.encode(), _tuning(entry)), "tc_tuning_set")
+
+
+def tc_tuning_key(kind: str, edges: int) -> str:
+    buf = ctypes.create_string_buffer(256)
+    _check(_lib.tc_tuning_key(kind.encode(), int(edges), buf, len(buf)), "tc_tuning_key")
+    return buf.value.decode()
+
+
 def tc_vertex_triangles(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Triangles through every vertex (int64, original ids)."""
     n = g.info()["n"]
@@ -372,7 +435,9 @@ def tc_batch_describe(plan: Batch) -> dict:
 
 
 def tc_batch_autotune(graphs, stream=None) -> dict:
-    """Time candidate schedules on these graphs: {"best": {...}, "candidates": [...]}."""
+    """Time candidate schedules and thresholds on these graphs:
+    {"key", "best", "plan", "candidates"}; "best" is stored in the tuning
+    table for batches of this size."""
     import json
     buf = ctypes.create_string_buffer(1 << 16)
     _check(_lib.tc_batch_autotune(_handles(graphs), len(graphs), _stream(stream), buf, len(buf)),

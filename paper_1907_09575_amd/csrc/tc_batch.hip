@@ -35,60 +35,12 @@ struct Tuning {
   bool lpt = true;
   bool graph = true;
   int chunk = 1;  // units per queue atomic (0: about 16 atomics per work-group)
+  bool has_wp = false;  // row-bucket thresholds named: graphs cut otherwise get a retuned copy
+  WorkParams wp;
 };
 
 constexpr int kMaxBlocksPerCU = 8;
 constexpr size_t kLdsPerCU = 160 * 1024;
-
-// A flat JSON object of integers and strings, e.g.
-// {"blocks_per_cu": 4, "lds_cap_log2": 13, "order": "lpt", "graph": 1}.
-// Unknown keys and malformed text are errors (TC_EINVAL).
-std::map<std::string, std::string> parse_flat_json(const char* js) {
-  std::map<std::string, std::string> kv;
-  const char* p = js;
-  auto ws = [&] { while (*p && std::isspace((unsigned char)*p)) ++p; };
-  auto fail = [&](const char* what) {
-    throw Error(TC_EINVAL, std::string("tuning json: ") + what + " near '" + std::string(p).substr(0, 20) + "'");
-  };
-  auto str = [&]() {
-    if (*p != '"') fail("expected a string");
-    ++p;
-    std::string s;
-    while (*p && *p != '"') s += *p++;
-    if (*p != '"') fail("unterminated string");
-    ++p;
-    return s;
-  };
-  ws();
-  if (*p != '{') fail("expected '{'");
-  ++p;
-  ws();
-  if (*p == '}') return kv;
-  while (true) {
-    ws();
-    std::string k = str();
-    ws();
-    if (*p != ':') fail("expected ':'");
-    ++p;
-    ws();
-    std::string v;
-    if (*p == '"') {
-      v = str();
-    } else {
-      while (*p && (std::isalnum((unsigned char)*p) || *p == '-' || *p == '+' || *p == '.')) v += *p++;
-      if (v.empty()) fail("expected a value");
-    }
-    kv[k] = v;
-    ws();
-    if (*p == ',') {
-      ++p;
-      continue;
-    }
-    if (*p == '}') break;
-    fail("expected ',' or '}'");
-  }
-  return kv;
-}
 
 int to_int(const std::string& k, const std::string& v) {
   char* end = nullptr;
@@ -121,7 +73,10 @@ Tuning parse_tuning(const char* js) {
       TC_REQUIRE(t.chunk >= 0 && t.chunk <= 4096, TC_EINVAL, "tuning json: chunk outside [0, 4096]");
     } else if (k == "waves_per_block") {
       TC_REQUIRE(to_int(k, v) == kWaves, TC_EINVAL, "tuning json: waves_per_block must be 4");
-    } else if (k == "ms" || k == "units" || k == "hbm_units" || k == "grid" || k == "lds_bytes") {
+    } else if (parse_work_key(k, v, t.wp)) {
+      t.has_wp = true;
+    } else if (k == "ms" || k == "units" || k == "hbm_units" || k == "grid" || k == "lds_bytes" ||
+               k == "retuned") {
       // descriptive keys of the tuner's own output, accepted so that it can be passed back
     } else {
       throw Error(TC_EINVAL, "tuning json: unknown key \"" + k + "\"");
@@ -223,6 +178,7 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
   int64_t* exec_counts = nullptr;
   UseLog uses;  // streams the plan was launched on
+  std::vector<Graph*> twins;  // retuned copies of graphs cut by other thresholds
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -237,6 +193,7 @@ struct BatchPlan {
       cache_retire_stream(cap_stream);
       (void)hipStreamDestroy(cap_stream);
     }
+    for (Graph* h : twins) destroy_graph(h);
   }
 };
 
@@ -299,7 +256,7 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
       s.pack_ptr[c] = w.pack_ptr[c];
       s.n_packs[c] = (uint32_t)w.n_packs[c];
       if (w.n_packs[c] == 0) continue;
-      s.pack_slots[c] = kPackSlots + (1u << w.pack_log2S[c]);
+      s.pack_slots[c] = w.wp.pack_slots + (1u << w.pack_log2S[c]);
       lds = std::max(lds, pack_lds_bytes(s.pack_slots[c], mode));
       off += (uint64_t)w.n_packs[c];
     }
@@ -339,14 +296,38 @@ BatchPlan* make_plan(const PlanEntry* entries, int64_t num, CountMode mode, cons
   TC_REQUIRE(num >= 0 && num < (1ll << 31), TC_EINVAL, "batch plan: bad number of graphs");
   std::unique_ptr<BatchPlan> P(new BatchPlan());
   P->own.st = st;
+  std::string looked;
+  if (!tuning_json || !*tuning_json) {
+    // no schedule given: the tuning table's for batches of this size, if any
+    int64_t edges = 0;
+    for (int64_t i = 0; i < num; ++i) edges += entries[i].g ? entries[i].g->m : 0;
+    looked = tuning_lookup(tuning_key("batch", edges));
+    if (!looked.empty()) tuning_json = looked.c_str();
+  }
   P->tun = parse_tuning(tuning_json);
   P->mode = mode;
   TC_HIP(hipGetDevice(&P->device));
   TC_HIP(hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device));
   P->n_graphs = num;
   const Tuning& t = P->tun;
+  std::vector<PlanEntry> ents(entries, entries + num);
+  if (t.has_wp) {
+    // graphs whose work is cut by other thresholds are counted through a
+    // retuned copy (sharing their U), one per distinct graph
+    std::map<const Graph*, Graph*> twin;
+    for (PlanEntry& e : ents) {
+      if (!e.g || e.g->w.wp == t.wp) continue;
+      require_plain(*e.g, "batch plan");
+      auto it = twin.find(e.g);
+      if (it == twin.end()) {
+        P->twins.push_back(build_variant(*e.g, 0, t.wp, st));
+        it = twin.emplace(e.g, P->twins.back()).first;
+      }
+      e.g = it->second;
+    }
+  }
   PlanHost H;
-  plan_host(H, entries, num, mode, t, P->device, &P->support);
+  plan_host(H, ents.data(), num, mode, t, P->device, &P->support);
   std::vector<CountArgs>& args = H.args;
   std::vector<BatchSrc>& srcs = H.srcs;
   const uint64_t off = H.units;
@@ -460,11 +441,14 @@ std::string plan_json(const BatchPlan& P, double ms) {
   char buf[512];
   std::snprintf(buf, sizeof(buf),
                 "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\", \"graph\": %d, "
-                "\"chunk\": %u, \"units\": %lld, \"hbm_units\": %lld, \"grid\": %u, \"lds_bytes\": %zu, "
-                "\"ms\": %.4f}",
-                P.bpc, P.tun.lds_cap_log2, P.tun.lpt ? "lpt" : "input", P.tun.graph ? 1 : 0, P.chunk,
+                "\"chunk\": %d, ",
+                P.bpc, P.tun.lds_cap_log2, P.tun.lpt ? "lpt" : "input", P.tun.graph ? 1 : 0, P.tun.chunk);
+  std::string s = buf;
+  if (P.tun.has_wp) s += work_params_json(P.tun.wp) + ", \"retuned\": " + std::to_string(P.twins.size()) + ", ";
+  std::snprintf(buf, sizeof(buf),
+                "\"units\": %lld, \"hbm_units\": %lld, \"grid\": %u, \"lds_bytes\": %zu, \"ms\": %.4f}",
                 (long long)P.n_units, (long long)P.hbm_units, P.grid, P.lds, ms);
-  return buf;
+  return s + buf;
 }
 
 template <class F>
@@ -656,60 +640,141 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
   return tc::guard("tc_batch_autotune", [&] {
     TC_REQUIRE(num_graphs > 0 && graphs != nullptr, TC_EINVAL, "tc_batch_autotune: no graphs");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // candidate schedules: LDS caps that change the plan, then grid sizes and orders
     int max_log2 = 0;
+    int64_t edges = 0;
     for (int32_t i = 0; i < num_graphs; ++i) {
       TC_REQUIRE(graphs[i] != nullptr, TC_EINVAL, "tc_batch_autotune: null graph handle");
+      tc::require_plain(*tc::G(graphs[i]), "tc_batch_autotune");
       const tc::WorkSet& w = tc::G(graphs[i])->w;
+      edges += tc::G(graphs[i])->m;
       for (int c = tc::CLS_WG_SMALL; c <= tc::CLS_WG_GIANT; ++c)
         if (w.n_items[c]) max_log2 = std::max(max_log2, w.cls_log2S[c]);
     }
-    std::vector<int> caps = {tc::kMaxLog2S};
-    for (int c : {12, 10})
-      if (c < max_log2) caps.push_back(c);
-    const int bpcs[] = {2, 4, 6, 8};
-    std::vector<tc::PlanEntry> ents((size_t)num_graphs);
-    for (int32_t i = 0; i < num_graphs; ++i) ents[(size_t)i] = tc::PlanEntry{tc::G(graphs[i]), nullptr};
+    std::vector<tc::PlanEntry> own_ents((size_t)num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) own_ents[(size_t)i] = tc::PlanEntry{tc::G(graphs[i]), nullptr};
     int64_t* d_counts = nullptr;
     TC_HIP(hipMalloc(&d_counts, sizeof(int64_t) * (size_t)num_graphs));
     std::unique_ptr<int64_t, void (*)(int64_t*)> hold(d_counts, [](int64_t* p) { (void)hipFree(p); });
     hipEvent_t e0, e1;
     TC_HIP(hipEventCreate(&e0));
     TC_HIP(hipEventCreate(&e1));
+    struct EvHold {
+      hipEvent_t a, b;
+      ~EvHold() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } eh{e0, e1};
     std::string best, all = "[";
+    std::string best_sched;  // schedule keys of the best candidate (no thresholds)
+    tc::WorkParams best_wp = tc::G(graphs[0])->w.wp;
+    bool best_has_wp = false;
     double best_ms = 1e30;
-    for (int cap_log2 : caps) {
-      for (int lpt = 1; lpt >= 0; --lpt) {
-        for (int bpc : bpcs) {
+    // A plan with thresholds other than the graphs' own builds a retuned copy
+    // of every graph when it is created (about one work-set build per graph):
+    // such a candidate must beat the best by this factor to be kept.
+    constexpr double kRetuneGain = 0.98;
+    // times one candidate (best of 3 after a warm-up) and keeps the best
+    auto run = [&](const std::vector<tc::PlanEntry>& ents, const std::string& sched, const tc::WorkParams* wp,
+                   size_t retuned) {
+      std::unique_ptr<tc::BatchPlan> P(tc::make_plan(ents.data(), num_graphs, tc::MODE_COUNT, sched.c_str(), st));
+      if (wp) {  // describe the thresholds the entries were retuned with
+        P->tun.has_wp = true;
+        P->tun.wp = *wp;
+      }
+      tc::plan_count(*P, d_counts, st);  // warm-up (and graph capture)
+      double ms = 1e30;
+      for (int r = 0; r < 3; ++r) {
+        TC_HIP(hipEventRecord(e0, st));
+        tc::plan_count(*P, d_counts, st);
+        TC_HIP(hipEventRecord(e1, st));
+        TC_HIP(hipEventSynchronize(e1));
+        float f = 0;
+        TC_HIP(hipEventElapsedTime(&f, e0, e1));
+        ms = std::min(ms, (double)f);
+      }
+      std::string j = tc::plan_json(*P, ms);
+      if (wp) {
+        const std::string k = "\"retuned\": 0";
+        const size_t at = j.find(k);
+        if (at != std::string::npos) j.replace(at, k.size(), "\"retuned\": " + std::to_string(retuned));
+      }
+      all += (all.size() > 1 ? ", " : "") + j;
+      if (ms < (wp && !best_has_wp ? best_ms * kRetuneGain : best_ms)) {
+        best_ms = ms;
+        best = j;
+        best_sched = sched;
+        if (wp) best_wp = *wp;
+        best_has_wp = wp != nullptr;
+      }
+    };
+    // 1: schedules on the graphs' own work: LDS caps that change the plan x
+    // unit orders x grid sizes
+    std::vector<int> caps = {tc::kMaxLog2S};
+    for (int c : {12, 10})
+      if (c < max_log2) caps.push_back(c);
+    for (int cap_log2 : caps)
+      for (int lpt = 1; lpt >= 0; --lpt)
+        for (int bpc : {2, 4, 6, 8}) {
           char js[160];
           std::snprintf(js, sizeof(js), "{\"blocks_per_cu\": %d, \"lds_cap_log2\": %d, \"order\": \"%s\"}", bpc,
                         cap_log2, lpt ? "lpt" : "input");
-          std::unique_ptr<tc::BatchPlan> P(tc::make_plan(ents.data(), num_graphs, tc::MODE_COUNT, js, st));
-          tc::plan_count(*P, d_counts, st);  // warm-up (and graph capture)
-          double ms = 1e30;
-          for (int r = 0; r < 3; ++r) {
-            TC_HIP(hipEventRecord(e0, st));
-            tc::plan_count(*P, d_counts, st);
-            TC_HIP(hipEventRecord(e1, st));
-            TC_HIP(hipEventSynchronize(e1));
-            float f = 0;
-            TC_HIP(hipEventElapsedTime(&f, e0, e1));
-            ms = std::min(ms, (double)f);
-          }
-          std::string j = tc::plan_json(*P, ms);
-          all += (all.size() > 1 ? ", " : "") + j;
-          if (ms < best_ms) {
-            best_ms = ms;
-            best = j;
-          }
+          run(own_ents, js, nullptr, 0);
         }
+    // 2: units per queue atomic, on the best schedule
+    const std::string sched1 = best_sched;
+    for (int chunk : {0, 4}) {
+      std::string js = sched1;
+      js.insert(js.size() - 1, ", \"chunk\": " + std::to_string(chunk));
+      run(own_ents, js, nullptr, 0);
+    }
+    // 3: row-bucket thresholds, one at a time from the graphs' own (each
+    // candidate counts retuned copies of the graphs, built once per candidate)
+    const std::string sched2 = best_sched;
+    const uint64_t heavy[] = {8192, 131072};
+    const uint64_t target[] = {32768, 131072};
+    const uint32_t slots[] = {2048, 8192};
+    const uint32_t chunk[] = {4096, 8192};
+    tc::WorkParams cur = best_wp;
+    for (int param = 0; param < 4; ++param) {
+      const tc::WorkParams start = cur;
+      for (int c = 0; c < 2; ++c) {
+        tc::WorkParams wp = start;
+        if (param == 0) wp.heavy_min = heavy[c];
+        if (param == 1) wp.pack_target = target[c];
+        if (param == 2) wp.pack_slots = slots[c];
+        if (param == 3) wp.wave_chunk = chunk[c];
+        if (wp == start) continue;
+        std::map<const tc::Graph*, tc::Graph*> twin;
+        std::vector<std::unique_ptr<tc::Graph, void (*)(tc::Graph*)>> held;
+        std::vector<tc::PlanEntry> ents = own_ents;
+        for (tc::PlanEntry& e : ents) {
+          if (e.g->w.wp == wp) continue;
+          auto it = twin.find(e.g);
+          if (it == twin.end()) {
+            held.emplace_back(tc::build_variant(*e.g, 0, wp, st), tc::destroy_graph);
+            it = twin.emplace(e.g, held.back().get()).first;
+          }
+          e.g = it->second;
+        }
+        const double before = best_ms;
+        run(ents, sched2, &wp, held.size());
+        if (best_ms < before) cur = wp;  // (kept: the next parameter starts from it)
+        TC_HIP(hipStreamSynchronize(st));  // the plan is gone; the copies go next
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // the best candidate's re-usable keys (schedule and thresholds) go into
+    // the tuning table for batches of this size
+    std::string entry = best_sched;
+    if (best_has_wp) entry.insert(entry.size() - 1, ", " + tc::work_params_json(best_wp));
+    char msb[48];
+    std::snprintf(msb, sizeof(msb), ", \"ms\": %.4f", best_ms);
+    entry.insert(entry.size() - 1, msb);
+    const std::string key = tc::tuning_key("batch", edges);
+    tc::tuning_store(key, entry);
     all += "]";
-    // the best schedule's keys first, then every candidate
-    std::string res = "{\"best\": " + best + ", \"candidates\": " + all + "}";
+    const std::string res =
+        "{\"key\": \"" + key + "\", \"best\": " + entry + ", \"plan\": " + best + ", \"candidates\": " + all + "}";
     tc::copy_out(res, out_json, cap);
   });
 }

@@ -150,7 +150,7 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   }
   WorkSet w;
   build_work(w, own, H.nloc, H.row_ptr.as<int64_t>(), T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
-             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st);
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), WorkParams(), st);
   CountView v{H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), P.col.as<int32_t>(), P.nnz, &w, q,
               (x + y) % q};
   launch_count(v, MODE_BLOCK, d_count, nullptr, d_per_shift, st);

@@ -721,8 +721,8 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   const size_t mark_bytes = items_lds_bytes(-1, MODE);
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
     if (w.n_packs[c] == 0) continue;
-    // a pack's tables take at most kPackSlots plus one row's table
-    const uint32_t slots = kPackSlots + (1u << w.pack_log2S[c]);
+    // a pack's tables take at most wp.pack_slots plus one row's table
+    const uint32_t slots = w.wp.pack_slots + (1u << w.pack_log2S[c]);
     const size_t lds = pack_lds_bytes(slots, MODE);
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, VAR>,

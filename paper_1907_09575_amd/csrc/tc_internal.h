@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -84,10 +85,18 @@ enum ItemClass : int {
 constexpr int kWaves = 4;               // waves per work-group of packs, small item classes, batch units
 constexpr int kWavesBig = 8;            // waves per work-group of wg_huge / wg_giant items
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
+// Default row-bucket thresholds of a work decomposition (WorkParams below).
 constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
 constexpr uint64_t kHeavyMin = 32768;   // rows with fewer probes than this are packed
 constexpr uint64_t kPackTarget = 65536; // target probes per pack of light rows (one work-group)
 constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + one row's table)
+// Their limits: a wave item's probes, times the waves sharing a table, must
+// stay below the hit field of a table's value word (2^18); a pack's table
+// offset is 16 bits of buckets.
+constexpr uint32_t kWaveChunkMin = 1024, kWaveChunkMax = 16384;
+constexpr uint64_t kHeavyMinMax = (uint64_t)1 << 24;
+constexpr uint64_t kPackTargetMin = 1024, kPackTargetMax = (uint64_t)1 << 24;
+constexpr uint32_t kPackSlotsMin = 1024, kPackSlotsMax = 16384;
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
 constexpr int64_t kMaxEdges = (1ll << 32) - 64;        // U positions are 32-bit
@@ -157,8 +166,22 @@ struct Owned {
 // Tasks of a set of hashed rows and the work units of the count kernels.
 // Hashed rows are 0 .. nrows - 1 (ranks for a graph, rank-local rows for one
 // rank's block); a task's probes are entries of the probe-side CSR.
+// Row-bucket thresholds: which rows are packed and how the work is cut.
+struct WorkParams {
+  uint64_t heavy_min = kHeavyMin;     // rows with fewer probes (and tables <= 2^10) go to packs
+  uint64_t pack_target = kPackTarget; // probes per pack (plus one row's)
+  uint32_t pack_slots = kPackSlots;   // table slots per pack (plus one row's table)
+  uint32_t wave_chunk = kWaveChunk;   // probes per wave item of a heavy row
+  bool operator==(const WorkParams& o) const {
+    return heavy_min == o.heavy_min && pack_target == o.pack_target && pack_slots == o.pack_slots &&
+           wave_chunk == o.wave_chunk;
+  }
+  bool operator!=(const WorkParams& o) const { return !(*this == o); }
+};
+
 struct WorkSet {
   int64_t nrows = 0, n_tasks = 0, probes = 0;
+  WorkParams wp;  // the thresholds this decomposition was built with
   uint32_t* tbeg = nullptr;     // nrows, tasks of hashed row b: [tbeg[b], tend[b]) (class-major order)
   uint32_t* tend = nullptr;     // nrows
   uint32_t* tstart = nullptr;   // n_tasks, probe-side index of the task's first probe
@@ -229,8 +252,10 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 // no such work is pending.
 void destroy_graph(Graph* g);
 void destroy_graph_idle(Graph* g);
-// A variant of `base` (TC_VARIANT_* flags) sharing its U (tc_graph_variant).
-Graph* build_variant(const Graph& base, int flags, hipStream_t st);
+// A variant of `base` (TC_VARIANT_* flags) sharing its U (tc_graph_variant);
+// with flags 0 a plain graph whose work is cut by other thresholds
+// (tc_graph_retune).
+Graph* build_variant(const Graph& base, int flags, const WorkParams& wp, hipStream_t st);
 
 inline const Graph* G(const tc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
@@ -358,7 +383,25 @@ inline void require_plain(const Graph& g, const char* where) {
 // ablation of the doubly sparse traversal; they go to pack_small).
 void build_work(WorkSet& w, Owned& own, int64_t nrows, const int64_t* hrow_ptr, int64_t T,
                 const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
-                const uint64_t* tb_prefix, hipStream_t st, bool all_rows = false);
+                const uint64_t* tb_prefix, const WorkParams& wp, hipStream_t st, bool all_rows = false);
+
+// ---- tuning table (tc_tuning.cpp) ----------------------------------------------
+// Tuned settings by key "<arch>/<CUs>cu/<kind>_e<k>" (kind "graph" for one
+// graph of about 2^k edges, "batch" for a batch of about 2^k edges in total),
+// each a flat JSON object. Filled by tc_tuning_load, the TC_TUNING_FILE
+// environment variable (read once, at the first lookup) and the autotuners.
+std::string tuning_key(const char* kind, int64_t edges);
+// The entry for `key`, or "" if there is none.
+std::string tuning_lookup(const std::string& key);
+void tuning_store(const std::string& key, const std::string& json);
+// Parses the threshold keys of a flat JSON object into wp (other keys are
+// left to the caller: `rest` receives them); TC_EINVAL on bad values.
+std::map<std::string, std::string> parse_flat_json(const char* js);
+bool parse_work_key(const std::string& k, const std::string& v, WorkParams& wp);
+std::string work_params_json(const WorkParams& wp);
+// The thresholds for one graph of m edges: the tuning table's entry for its
+// size, else the defaults.
+WorkParams default_work_params(int64_t m);
 
 
 inline int ceil_log2_u64(uint64_t x) {

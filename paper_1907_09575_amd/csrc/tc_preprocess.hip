@@ -247,7 +247,8 @@ __global__ __launch_bounds__(256) void k_row_stats(const int64_t* __restrict__ r
 __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tptr,
                                                   const uint64_t* __restrict__ tprefix,
                                                   const int64_t* __restrict__ row_ptr, int64_t n, bool all_rows,
-                                                  int8_t* __restrict__ cls, int* __restrict__ cls_log2S) {
+                                                  uint64_t heavy_min, int8_t* __restrict__ cls,
+                                                  int* __restrict__ cls_log2S) {
   __shared__ int s_max[NUM_CLASSES];
   if (threadIdx.x < NUM_CLASSES) s_max[threadIdx.x] = 0;
   __syncthreads();
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
       if (l > kMaxLog2S) c = CLS_GLOBAL;
       else if (l > 13) c = CLS_WG_GIANT;
       else if (l > 12) c = CLS_WG_HUGE;
-      else if (W < kHeavyMin && l <= 10) c = l <= 8 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
+      else if (W < heavy_min && l <= 10) c = l <= 8 ? CLS_PACK_SMALL : CLS_PACK_LARGE;
       else c = l <= 10 ? CLS_WG_SMALL : CLS_WG_LARGE;
     } else if (all_rows) {
       // no doubly sparse traversal: a row without work is still visited (a
@@ -324,8 +325,8 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const unsigned long long* _
 
 // Wave items of a heavy row with W probes: a multiple of the class's waves
 // per work-group (each group of `waves` consecutive items shares one table).
-__device__ __forceinline__ uint32_t wg_parts(uint64_t W, int waves) {
-  const uint64_t per = (uint64_t)waves * kWaveChunk;
+__device__ __forceinline__ uint32_t wg_parts(uint64_t W, int waves, uint32_t chunk) {
+  const uint64_t per = (uint64_t)waves * chunk;
   return (uint32_t)(waves * ((W + per - 1) / per));
 }
 
@@ -372,11 +373,12 @@ struct CmItems {
   const int8_t* cls;
   const int64_t* tptr;
   const uint64_t* tprefix;
+  uint32_t chunk;
   __device__ uint32_t operator()(int64_t i) const {
     const uint32_t b = crow[i];
     const int c = cls[b];
     if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) return 0;
-    return wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]], class_waves(c));
+    return wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]], class_waves(c), chunk);
   }
 };
 
@@ -431,14 +433,14 @@ __global__ void k_rows_work(const int32_t* __restrict__ rows, int64_t nr,
 
 // A pack starts at row i when the running probe total, the running table
 // slots or the row index enters a new multiple of its budget; so a pack holds
-// at most kPackRows rows, at most kPackSlots slots plus one row's table, and
-// at most kPackTarget probes plus one row's.
+// at most kPackRows rows, at most `slots` slots plus one row's table, and at
+// most `target` probes plus one row's.
 __global__ void k_pack_flags(const uint64_t* __restrict__ pw, const uint32_t* __restrict__ ps,
-                             int64_t nr, uint32_t* __restrict__ flags) {
+                             int64_t nr, uint64_t target, uint32_t slots, uint32_t* __restrict__ flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nr) return;
-  flags[i] = (i == 0 || pw[i] / kPackTarget != pw[i - 1] / kPackTarget ||
-              ps[i] / kPackSlots != ps[i - 1] / kPackSlots || i / kPackRows != (i - 1) / kPackRows)
+  flags[i] = (i == 0 || pw[i] / target != pw[i - 1] / target || ps[i] / slots != ps[i - 1] / slots ||
+              i / kPackRows != (i - 1) / kPackRows)
                  ? 1u
                  : 0u;
 }
@@ -532,7 +534,6 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   int* d_err = reinterpret_cast<int*>(dscal.as<char>());
   unsigned long long* d_wplus = reinterpret_cast<unsigned long long*>(dscal.as<char>() + 16);
   unsigned int* d_maxd = reinterpret_cast<unsigned int*>(dscal.as<char>() + 24);
-  uint64_t* d_tot64 = reinterpret_cast<uint64_t*>(dscal.as<char>() + 32);
 
   // ---- 1-2: simple graph -------------------------------------------------
   int64_t m = 0;
@@ -664,7 +665,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
   // ---- 6: work classes ------------------------------------------------------
   build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
-             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st);
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), default_work_params(m), st);
   check_sorts(st);
   g->arena_bytes = g->owned.bytes;
   note_use(*g, st);
@@ -713,7 +714,7 @@ struct VariantTaskPred {
 
 }  // namespace
 
-Graph* build_variant(const Graph& base, int flags, hipStream_t st) {
+Graph* build_variant(const Graph& base, int flags, const WorkParams& wp, hipStream_t st) {
   std::unique_ptr<GraphImpl> g(new GraphImpl());
   g->owned.st = st;
   TC_HIP(hipGetDevice(&g->device));
@@ -749,7 +750,7 @@ Graph* build_variant(const Graph& base, int flags, hipStream_t st) {
     if (T > 0) sort_tasks(tl, tk, tv, T, n, g->sbits, st, "variant_tasks");
   }
   build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
-             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), st, no_dcsr);
+             tl.val.as<uint64_t>(), tl.prefix.as<uint64_t>(), wp, st, no_dcsr);
   check_sorts(st);
   g->arena_bytes = g->owned.bytes;
   note_use(*g, st);  // (and the base, whose U the build read)
@@ -792,8 +793,9 @@ void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows,
 
 void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int64_t T,
                 const uint32_t* tb_row, const int64_t* tb_ptr, const uint64_t* tb_val,
-                const uint64_t* tb_prefix, hipStream_t st, bool all_rows) {
+                const uint64_t* tb_prefix, const WorkParams& wp, hipStream_t st, bool all_rows) {
   w.nrows = n;
+  w.wp = wp;
   w.n_tasks = T;
   w.tbeg = own.alloc<uint32_t>(n);
   w.tend = own.alloc<uint32_t>(n);
@@ -817,7 +819,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   DevBuf clsl(sizeof(int) * NUM_CLASSES);
   TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
   TC_LAUNCH("classify", k_classify, dim3(grid_reduce(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
-            all_rows, cls.as<int8_t>(), clsl.as<int>());
+            all_rows, wp.heavy_min, cls.as<int8_t>(), clsl.as<int>());
   TC_HIP(hipGetLastError());
   int h_cl[NUM_CLASSES];
   TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
@@ -826,8 +828,8 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   // ...; each row keeps its tasks in b order, so every class - and every pack
   // of consecutive rows of a class - owns one contiguous task range
   DevBuf ckey, crow_in;
-  WorkRowPred wp{cls.as<int8_t>(), nullptr, nullptr};
-  const int64_t R = compact("work_rows", n, wp, [&](int64_t total, WorkRowPred& p) {
+  WorkRowPred rowp{cls.as<int8_t>(), nullptr, nullptr};
+  const int64_t R = compact("work_rows", n, rowp, [&](int64_t total, WorkRowPred& p) {
     ckey.alloc(sizeof(uint32_t) * (size_t)total);
     crow_in.alloc(sizeof(uint32_t) * (size_t)total);
     p.key = ckey.as<uint32_t>();
@@ -851,7 +853,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     device_excl_scan_f<uint32_t>(CmTasks{crow, tb_ptr}, tsc.as<uint32_t>(), R, tsc.as<uint32_t>() + R, st);
     device_excl_scan_f<uint64_t>(CmProbes{crow, tb_ptr, tb_prefix}, wsc.as<uint64_t>(), R,
                                  wsc.as<uint64_t>() + R, st);
-    device_excl_scan_f<uint32_t>(CmItems{crow, cls.as<int8_t>(), tb_ptr, tb_prefix}, usc.as<uint32_t>(), R,
+    device_excl_scan_f<uint32_t>(CmItems{crow, cls.as<int8_t>(), tb_ptr, tb_prefix, wp.wave_chunk}, usc.as<uint32_t>(), R,
                                  usc.as<uint32_t>() + R, st);
     DevBuf cm_pos(sizeof(uint32_t) * (size_t)n);
     TC_LAUNCH("cm_place", k_cm_place, dim3(grid_for(R)), dim3(kT), 0, st, crow, R, tsc.as<uint32_t>(), w.tbeg,
@@ -890,7 +892,7 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
       pf[c].alloc(sizeof(uint32_t) * (size_t)total);
       pp[c].alloc(sizeof(uint32_t) * (size_t)total);
       TC_LAUNCH("pack_flags", k_pack_flags, dim3(grid_for(total)), dim3(kT), 0, st, pw.as<uint64_t>(),
-                psl.as<uint32_t>(), total, pf[c].as<uint32_t>());
+                psl.as<uint32_t>(), total, wp.pack_target, wp.pack_slots, pf[c].as<uint32_t>());
       device_excl_scan<uint32_t, uint32_t>(pf[c].as<uint32_t>(), pp[c].as<uint32_t>(), total,
                                            ptot.as<uint32_t>() + c, st);
     }
@@ -951,7 +953,7 @@ extern "C" tc_status tc_graph_variant(const tc_graph* gh, int32_t flags, void* s
                "tc_graph_variant: unknown flags");
     const tc::Graph& base = *tc::G(gh);
     tc::require_plain(base, "tc_graph_variant");
-    tc::Graph* g = tc::build_variant(base, flags, static_cast<hipStream_t>(stream));
+    tc::Graph* g = tc::build_variant(base, flags, base.w.wp, static_cast<hipStream_t>(stream));
     *out = reinterpret_cast<tc_graph*>(g);
     tc::set_last_error("");
     return TC_OK;

@@ -136,12 +136,41 @@ def test_batch_captured_by_caller(tc, mixed):
 def test_batch_autotune_roundtrip(tc, mixed):
     graphs, want = mixed
     res = tc.tc_batch_autotune(graphs)
-    best = res["best"]
-    assert len(res["candidates"]) >= 8
-    assert all(c["ms"] > 0 for c in res["candidates"])
-    got, desc = batch_counts(tc, graphs, best)
+    best, key = res["best"], res["key"]
+    try:
+        # schedules, chunks and threshold candidates were all timed
+        assert len(res["candidates"]) >= 8 + 2 + 4
+        assert all(c["ms"] > 0 for c in res["candidates"])
+        assert any("wave_chunk" in c for c in res["candidates"])
+        own = [c["ms"] for c in res["candidates"] if "wave_chunk" not in c]
+        retuned = [c["ms"] for c in res["candidates"] if "wave_chunk" in c]
+        if "wave_chunk" in best:  # thresholds kept only for a clear gain
+            assert best["ms"] <= 0.98 * min(own) + 1e-3
+        else:
+            assert abs(best["ms"] - min(own)) < 1e-3 and min(retuned) > 0.98 * best["ms"] - 1e-3
+        assert tc.tc_tuning_get(key) == best
+        got, desc = batch_counts(tc, graphs, best)
+        assert np.array_equal(got, want)
+        assert desc["lds_cap_log2"] == best["lds_cap_log2"] and desc["order"] == best["order"]
+        # a plan without a schedule takes the stored one
+        got, desc = batch_counts(tc, graphs)
+        assert np.array_equal(got, want)
+        assert desc["lds_cap_log2"] == best["lds_cap_log2"] and desc["blocks_per_cu"] == best["blocks_per_cu"]
+    finally:
+        tc.tc_tuning_set(key, None)
+
+
+@pytest.mark.parametrize("wp", [{"heavy_min": 0, "wave_chunk": 1024},
+                                {"pack_target": 1024, "pack_slots": 1024, "heavy_min": 1 << 24},
+                                {"pack_slots": 16384, "order": "input", "lds_cap_log2": 10}])
+def test_batch_plan_with_thresholds(tc, mixed, wp):
+    graphs, want = mixed
+    got, desc = batch_counts(tc, graphs, wp)
     assert np.array_equal(got, want)
-    assert desc["lds_cap_log2"] == best["lds_cap_log2"] and desc["order"] == best["order"]
+    assert desc["retuned"] == len({id(g) for g in graphs})
+    for k in ("heavy_min", "wave_chunk", "pack_target", "pack_slots"):
+        if k in wp:
+            assert desc[k] == wp[k]
 
 
 def test_batch_invalid_tuning(tc, mixed):
