@@ -18,7 +18,7 @@ and its algorithmic bytes per launch (4 per probe + 4 per hashed-row key +
 
 Beside the step: one rank's block of the 13 x 13 grid (`block`), the
 ablations of Section 7.3 and the per-rank tables of Section 7.2
-(`ablation`), per-edge
+(`ablation`), one step at RMAT scale 26 (`large`), per-edge
 support in both modes on a resident RMAT scale-20 graph (`support`), the
 batched form against the plain launch loop (`batched`) and the served form
 against a plain FIFO (`served`); each is skipped with its --no-* flag.
@@ -67,6 +67,8 @@ def parse():
     p.add_argument("--block-q", type=int, default=13)
     p.add_argument("--no-ablation", action="store_true", help="skip the ablations and per-rank tables")
     p.add_argument("--ablation-q", default="4,5,6,13", help="grid sizes of the per-rank tables")
+    p.add_argument("--no-large", action="store_true", help="skip the RMAT scale 26 step")
+    p.add_argument("--large-scale", type=int, default=26)
     p.add_argument("--no-support", action="store_true", help="skip the per-edge support leg")
     p.add_argument("--support-scale", type=int, default=20)
     p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
@@ -306,6 +308,78 @@ def bench_ablation(tc, g, T, qs):
         prev = inter
     out["rank_tables"] = grid
     return out
+
+
+def bench_large(tc, args):
+    """RMAT scale 26 (2^30 raw pairs, the shape of the paper's g500-s26
+    input): one warm-up, then one timed preprocess + count step, the count
+    alone on the resident graph (median of 5, HIP events) and the dominant
+    count kernel against the HBM roofline. T is checked against the value the
+    oracle stored for this input (tests/golden)."""
+    import numpy as np
+    import torch
+    import graphgen
+    scale = args.large_scale
+    n = 1 << scale
+    print("large: generating RMAT scale %d ..." % scale, file=sys.stderr, flush=True)
+    s, d = graphgen.rmat(scale, edge_factor=args.edge_factor, seed=args.seed, threads=args.gen_threads)
+    m_raw = len(s)
+    src, dst = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    del s, d
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    g = tc.tc_preprocess(src, dst, n)
+    tc.tc_count(g, out)
+    torch.cuda.synchronize()
+    g.free()
+    print("large: timed step ...", file=sys.stderr, flush=True)
+    timer = tc.Timer(capacity=4096)
+    with timer:
+        t0 = time.perf_counter()
+        g = tc.tc_preprocess(src, dst, n)
+        tc.tc_count(g, out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    kern = timer.summary()
+    timer.free()
+    T = int(out.item())
+    info = g.info()
+    cstats = tc.tc_graph_class_stats(g)
+    runs = []
+    for r in range(7):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tc.tc_count(g, out)
+        e1.record()
+        e1.synchronize()
+        assert int(out.item()) == T
+        if r >= 2:
+            runs.append(e0.elapsed_time(e1))
+    g.free()
+    del src, dst
+    torch.cuda.empty_cache()
+    step_ms = (t1 - t0) * 1e3
+    count_ms = sum(v["total_ms"] for k, v in kern.items() if k.startswith("count:"))
+    counts = {k: v for k, v in kern.items() if k.startswith("count:")}
+    dom = max(counts, key=lambda k: counts[k]["total_ms"])
+    cls = dom.split(":", 1)[1]
+    achieved = count_kernel_bytes(cstats, cls) / (counts[dom]["avg_ms"] / 1e3) / 1e9
+    res = {"workload": "rmat%d_ef%d_preprocess_count" % (scale, args.edge_factor), "n": n, "m_raw": m_raw,
+           "m": info["m"], "triangles": T, "wedges_plus": info["wedges_plus"], "step_ms": round(step_ms, 3),
+           "edges_per_s": m_raw / (step_ms / 1e3), "preprocess_ms": round(step_ms - count_ms, 3),
+           "count_ms": round(count_ms, 3), "count_median_ms": round(float(np.median(runs)), 3),
+           "count_median_edges_per_s": info["m"] / (float(np.median(runs)) / 1e3),
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "avg_launch_ms": round(counts[dom]["avg_ms"], 4),
+                        "algorithmic_bytes_per_launch": count_kernel_bytes(cstats, cls)}}
+    fx = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                      "rmat%d_seed%d.json" % (scale, args.seed))
+    if os.path.exists(fx) and args.edge_factor == 16:
+        with open(fx) as f:
+            want = json.load(f)
+        res["oracle_triangles_equal"] = want["triangles"] == T and want["m"] == info["m"]
+    return res
 
 
 def bench_support(tc, args):
@@ -759,6 +833,8 @@ def main():
         g.free()
     del src, dst
     torch.cuda.empty_cache()
+    if not args.no_large:
+        result["large"] = bench_large(tc, args)
     if not args.no_support:
         print("support (RMAT scale %d) ..." % args.support_scale, file=sys.stderr, flush=True)
         result["support"] = bench_support(tc, args)

@@ -333,7 +333,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
  *                 row's);
  *   "pack_slots"  (1024 .. 16384, default 4096): LDS table slots per pack
  *                 (plus one row's table);
- *   "wave_chunk"  (1024 .. 16384, default 16384): probes per wave item of a
+ *   "wave_chunk"  (1024 .. 32767, default 16384): probes per wave item of a
  *                 row with work-groups of its own.
  * They change how the work is scheduled, never a count. Graphs take theirs
  * from the tuning table when tc_preprocess builds them (the defaults when the

@@ -89,8 +89,8 @@ constexpr int kItemClasses = NUM_CLASSES - CLS_WG_SMALL;  // wg_small .. global
 
 // Per graph entry of the plan: where its units come from (device copy).
 struct BatchSrc {
-  const int32_t* pack_rows[2];
-  const uint32_t* pack_ptr[2];
+  const PackRow* pack_recs[2];
+  const PackInfo* pack_info[2];
   const CountItem* items[kItemClasses];  // classes wg_small .. global
   const uint32_t* tbeg;
   const uint32_t* tend;
@@ -119,11 +119,10 @@ __global__ __launch_bounds__(256) void k_batch_units(const BatchSrc* __restrict_
     if (j < np0 + np1) {
       const int c = j < np0 ? 0 : 1;
       const uint32_t p = j < np0 ? j : j - np0;
-      const uint32_t r0 = s.pack_ptr[c][p], r1 = s.pack_ptr[c][p + 1];
-      const int32_t b0 = s.pack_rows[c][r0], b1 = s.pack_rows[c][r1 - 1];
-      wgt = s.tprefix[s.tend[b1]] - s.tprefix[s.tbeg[b0]] + 64ull * (r1 - r0);
-      u.p0 = s.pack_rows[c];
-      u.p1 = s.pack_ptr[c];
+      const PackInfo& pi = s.pack_info[c][p];
+      wgt = pi.q1 - pi.q0 + 64ull * (pi.r1 - pi.r0);
+      u.p0 = s.pack_recs[c];
+      u.p1 = s.pack_info[c];
       u.index = p;
       u.slots = s.pack_slots[c];
       u.kind = BK_PACK;
@@ -252,8 +251,8 @@ void plan_host(PlanHost& H, const PlanEntry* entries, int64_t num, CountMode mod
     s.unit_off = off;
     if (w.n_tasks == 0) continue;  // no units: the count stays 0
     for (int c = 0; c < 2; ++c) {
-      s.pack_rows[c] = w.pack_rows[c];
-      s.pack_ptr[c] = w.pack_ptr[c];
+      s.pack_recs[c] = w.pack_recs[c];
+      s.pack_info[c] = w.pack_info[c];
       s.n_packs[c] = (uint32_t)w.n_packs[c];
       if (w.n_packs[c] == 0) continue;
       s.pack_slots[c] = w.wp.pack_slots + (1u << w.pack_log2S[c]);
@@ -675,9 +674,11 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
     // such a candidate must beat the best by this factor to be kept.
     constexpr double kRetuneGain = 0.98;
     // times one candidate (best of 3 after a warm-up) and keeps the best
+    // (full = false: a sample of the graphs, timed for comparison only)
     auto run = [&](const std::vector<tc::PlanEntry>& ents, const std::string& sched, const tc::WorkParams* wp,
-                   size_t retuned) {
-      std::unique_ptr<tc::BatchPlan> P(tc::make_plan(ents.data(), num_graphs, tc::MODE_COUNT, sched.c_str(), st));
+                   size_t retuned, bool full = true) {
+      std::unique_ptr<tc::BatchPlan> P(
+          tc::make_plan(ents.data(), (int64_t)ents.size(), tc::MODE_COUNT, sched.c_str(), st));
       if (wp) {  // describe the thresholds the entries were retuned with
         P->tun.has_wp = true;
         P->tun.wp = *wp;
@@ -699,7 +700,9 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
         const size_t at = j.find(k);
         if (at != std::string::npos) j.replace(at, k.size(), "\"retuned\": " + std::to_string(retuned));
       }
+      j.insert(j.size() - 1, ", \"graphs\": " + std::to_string(ents.size()));
       all += (all.size() > 1 ? ", " : "") + j;
+      if (!full) return ms;
       if (ms < (wp && !best_has_wp ? best_ms * kRetuneGain : best_ms)) {
         best_ms = ms;
         best = j;
@@ -707,6 +710,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
         if (wp) best_wp = *wp;
         best_has_wp = wp != nullptr;
       }
+      return ms;
     };
     // 1: schedules on the graphs' own work: LDS caps that change the plan x
     // unit orders x grid sizes
@@ -728,14 +732,39 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
       js.insert(js.size() - 1, ", \"chunk\": " + std::to_string(chunk));
       run(own_ents, js, nullptr, 0);
     }
-    // 3: row-bucket thresholds, one at a time from the graphs' own (each
-    // candidate counts retuned copies of the graphs, built once per candidate)
+    // 3: row-bucket thresholds, one at a time from the graphs' own. Each
+    // candidate counts retuned copies of the graphs (a work-set build per
+    // graph), so they are compared on a sample of at most kSample graphs
+    // (every stride-th); thresholds that win there are then timed on the
+    // whole batch.
+    constexpr int64_t kSample = 512;
     const std::string sched2 = best_sched;
+    const int64_t stride = (num_graphs + kSample - 1) / kSample;
+    const bool sampled = stride > 1;
+    std::vector<tc::PlanEntry> sample;
+    for (int64_t i = 0; i < num_graphs; i += stride) sample.push_back(own_ents[(size_t)i]);
+    auto retuned_entries = [&](const std::vector<tc::PlanEntry>& from, const tc::WorkParams& wp,
+                               std::vector<std::unique_ptr<tc::Graph, void (*)(tc::Graph*)>>& held) {
+      std::map<const tc::Graph*, tc::Graph*> twin;
+      std::vector<tc::PlanEntry> ents = from;
+      for (tc::PlanEntry& e : ents) {
+        if (e.g->w.wp == wp) continue;
+        auto it = twin.find(e.g);
+        if (it == twin.end()) {
+          held.emplace_back(tc::build_variant(*e.g, 0, wp, st), tc::destroy_graph);
+          it = twin.emplace(e.g, held.back().get()).first;
+        }
+        e.g = it->second;
+      }
+      return ents;
+    };
     const uint64_t heavy[] = {8192, 131072};
-    const uint64_t target[] = {32768, 131072};
+    const uint64_t target[] = {32768, 262144};
     const uint32_t slots[] = {2048, 8192};
-    const uint32_t chunk[] = {4096, 8192};
-    tc::WorkParams cur = best_wp;
+    const uint32_t chunk[] = {8192, 32767};
+    const tc::WorkParams own = best_wp;
+    tc::WorkParams cur = own;
+    double cur_ms = sampled ? run(sample, sched2, nullptr, 0, false) : best_ms;
     for (int param = 0; param < 4; ++param) {
       const tc::WorkParams start = cur;
       for (int c = 0; c < 2; ++c) {
@@ -745,23 +774,21 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
         if (param == 2) wp.pack_slots = slots[c];
         if (param == 3) wp.wave_chunk = chunk[c];
         if (wp == start) continue;
-        std::map<const tc::Graph*, tc::Graph*> twin;
         std::vector<std::unique_ptr<tc::Graph, void (*)(tc::Graph*)>> held;
-        std::vector<tc::PlanEntry> ents = own_ents;
-        for (tc::PlanEntry& e : ents) {
-          if (e.g->w.wp == wp) continue;
-          auto it = twin.find(e.g);
-          if (it == twin.end()) {
-            held.emplace_back(tc::build_variant(*e.g, 0, wp, st), tc::destroy_graph);
-            it = twin.emplace(e.g, held.back().get()).first;
-          }
-          e.g = it->second;
+        const std::vector<tc::PlanEntry> ents = retuned_entries(sampled ? sample : own_ents, wp, held);
+        const double ms = run(ents, sched2, &wp, held.size(), !sampled);
+        // (the first thresholds other than the graphs' own must win clearly)
+        if (ms < (cur == own ? cur_ms * kRetuneGain : cur_ms)) {
+          cur = wp;  // the next parameter starts from it
+          cur_ms = ms;
         }
-        const double before = best_ms;
-        run(ents, sched2, &wp, held.size());
-        if (best_ms < before) cur = wp;  // (kept: the next parameter starts from it)
         TC_HIP(hipStreamSynchronize(st));  // the plan is gone; the copies go next
       }
+    }
+    if (sampled && cur != own) {
+      std::vector<std::unique_ptr<tc::Graph, void (*)(tc::Graph*)>> held;
+      run(retuned_entries(own_ents, cur, held), sched2, &cur, held.size());
+      TC_HIP(hipStreamSynchronize(st));
     }
     // the best candidate's re-usable keys (schedule and thresholds) go into
     // the tuning table for batches of this size

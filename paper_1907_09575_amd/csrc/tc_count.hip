@@ -62,10 +62,10 @@ constexpr int32_t kEmpty = -1;
 // FULL support, single-row LDS tables: a slot's value word is the key's index
 // in its row (< 2^13: such rows have at most 8192 keys) plus its hits in this
 // work-group times 2^13 (at most one per task, and a work-group holds at most
-// 8 wave items of 16384 probes: < 2^18, so the word stays below 2^31).
+// 8 wave items of at most 32767 probes: < 2^18, so the word stays below 2^31).
 constexpr int kValBits = 13;
 static_assert((1 << kValBits) >= (1 << kMaxLog2S) / 2, "row index of an LDS table below the hit count");
-static_assert((uint64_t)kWavesBig * kWaveChunk < (1ull << (31 - kValBits)),
+static_assert((uint64_t)kWavesBig * kWaveChunkMax < (1ull << (31 - kValBits)),
               "hits of one slot in one work-group keep the value word below 2^31");
 constexpr uint32_t kOffNone = 0xFFFFFFF0u;  // byte offset past any col buffer
 
@@ -240,11 +240,31 @@ __device__ __forceinline__ int match_slot(const int4& v, int32_t k) {
   return v.x == k ? 0 : v.y == k ? 1 : v.z == k ? 2 : v.w == k ? 3 : -1;
 }
 
+// The first window of a wave's probe range [q, q + len) (task t holds probe
+// q): each lane's task end, relative to q and clamped to len, and first-probe
+// position, and the window's own start. Loaded before the table is built, so
+// that these loads overlap the build.
+struct Window {
+  uint32_t Pe, tsj, P0;
+};
+
+__device__ __forceinline__ Window window_first(const Args& A, uint32_t t, uint64_t q, uint32_t len) {
+  const int lane = lane_id();
+  const int64_t T = A.T;
+  const int64_t tj = (int64_t)t + lane;
+  const uint64_t p = A.tprefix[tj + 1 < T ? tj + 1 : T] - q;
+  Window w;
+  w.Pe = p > (uint64_t)len ? len : (uint32_t)p;
+  w.tsj = A.tstart[tj < T ? tj : T - 1];
+  w.P0 = (uint32_t)(A.tprefix[t] - q);  // may wrap (a task starting before q)
+  return w;
+}
+
 // One wave processes the probes [q, q + len) of the tasks of one hashed row;
-// task t contains probe q.
+// task t contains probe q; w0 = window_first(A, t, q, len).
 template <int MODE, int KIND, int VAR>
 __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64_t q, uint32_t len,
-                           uint32_t* bm, uint32_t& hits) {
+                           uint32_t* bm, uint32_t& hits, const Window& w0) {
   // the range is the wave's own (uniform across its lanes): scalar registers
   // (readfirstlane returns int: widen through uint32_t, never sign-extend)
   t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
@@ -272,10 +292,9 @@ __device__ void wave_probe(const Args& A, const TableRef& tr, uint32_t t, uint64
     Pe = p > (uint64_t)len ? len : (uint32_t)p;
     ts = A.tstart[tj < T ? tj : T - 1];
   };
-  uint32_t Pe;
-  uint32_t tsj;
-  fetch((int64_t)t + lane, Pe, tsj);
-  uint32_t P0 = (uint32_t)(A.tprefix[t] - q0);  // start of the window's first task (may wrap)
+  uint32_t Pe = w0.Pe;
+  uint32_t tsj = w0.tsj;
+  uint32_t P0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)w0.P0);  // start of the window's first task
 
   uint32_t done = 0;
   uint32_t tcnt = 0;  // support modes: hits of this lane's window task
@@ -486,12 +505,11 @@ __device__ __forceinline__ void block_init() {
 constexpr int kPackMetaWords = 3 * kPackRows + 1;  // row_t0, row_desc, key prefix (+ end)
 
 template <int MODE, int VAR>
-__device__ __forceinline__ unsigned long long pack_body(const Args& A, const int32_t* __restrict__ rows,
-                                          const uint32_t* __restrict__ pack_ptr, uint32_t pack,
+__device__ __forceinline__ unsigned long long pack_body(const Args& A, const PackRow* __restrict__ recs,
+                                          const PackInfo* __restrict__ info, uint32_t pack,
                                           uint32_t pack_slots, int32_t* smem) {
   __shared__ int s_D;
   __shared__ uint32_t s_w[4], s_w2[4];
-  __shared__ uint32_t s_tend;
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
@@ -503,20 +521,25 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
   if (lane < kBmWords) bm[lane] = 0;
   block_init<MODE>();
 
-  const uint32_t r0 = pack_ptr[pack], r1 = pack_ptr[pack + 1];
+  const PackInfo& pi = info[pack];
+  const uint32_t r0 = pi.r0, r1 = pi.r1;
   const int nr = (int)(r1 - r0);  // 1 .. kPackRows
+  // this wave's quarter of the pack's probes, its first task, and its first
+  // window (in flight while the tables are built)
+  const uint64_t q0 = pi.q0, W = pi.q1 - pi.q0;
+  const uint64_t wq0 = q0 + W * (uint64_t)wave / kWaves, wq1 = q0 + W * (uint64_t)(wave + 1) / kWaves;
+  const uint32_t wt = (uint32_t)__builtin_amdgcn_readfirstlane((int)pi.wt[wave]);
+  const uint32_t wlen = (uint32_t)(wq1 - wq0);
+  const Window w0 = window_first(A, wt, wq0, wlen);
   uint32_t d = 0, S = 0, rs = 0;
   if (tid < nr) {
-    const int32_t b = rows[r0 + tid];
-    const int64_t rs64 = A.row_ptr[b];
-    const uint32_t tb = A.tbeg[b], te = A.tend[b];
-    rs = (uint32_t)rs64;
+    const PackRow pr = recs[r0 + tid];
+    rs = pr.rs;
     // a row without tasks (a pack member only without the doubly sparse
-    // traversal, tc_graph_variant) gets no table
-    d = te > tb ? (uint32_t)(A.row_ptr[b + 1] - rs64) : 0u;
+    // traversal, tc_graph_variant) has d = 0: no table
+    d = pr.d;
     S = 1u << pack_table_log2(d);
-    row_t0[tid] = tb;
-    if (tid == nr - 1) s_tend = te;
+    row_t0[tid] = pr.tb;
   }
   uint32_t S_tot, K_tot;
   const uint32_t off = block_excl_scan(S, s_w, S_tot);
@@ -570,25 +593,8 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const int
   __syncthreads();
 
   TableRef tr{tab, val, 0, s_D, 0, 0, row_t0, row_desc, nr};
-  // the pack's probes [q0, q1), a quarter per wave
-  const uint32_t t_lo = row_t0[0], t_hi = s_tend;
-  const uint64_t q0 = A.tprefix[t_lo], q1 = A.tprefix[t_hi];
-  const uint64_t W = q1 - q0;
-  const uint64_t wq0 = q0 + W * (uint64_t)wave / kWaves, wq1 = q0 + W * (uint64_t)(wave + 1) / kWaves;
   uint32_t hits = 0;
-  if (wq1 > wq0) {
-    // task holding wq0: 64-ary search, tprefix[lo] <= wq0 < tprefix[hi]
-    uint32_t lo = t_lo, hi = t_hi;
-    while (hi - lo > 1) {
-      const uint32_t step = (hi - lo + 63) / 64;
-      const uint32_t idx = lo + (uint32_t)lane * step;
-      const bool le = idx < hi && A.tprefix[idx] <= wq0;
-      const uint32_t c = (uint32_t)__popcll(__ballot(le));  // >= 1: lane 0 samples lo
-      lo = lo + (c - 1) * step;
-      hi = lo + step < hi ? lo + step : hi;
-    }
-    wave_probe<MODE, TK_MULTI, VAR>(A, tr, lo, wq0, (uint32_t)(wq1 - wq0), bm, hits);
-  }
+  if (wlen > 0) wave_probe<MODE, TK_MULTI, VAR>(A, tr, wt, wq0, wlen, bm, hits, w0);
   return block_flush<MODE>(hits, A);
 }
 
@@ -600,10 +606,10 @@ constexpr int kOccPacks = 5, kOccBatch = 5;
 template <int MODE, int VAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     MODE == MODE_COUNT || MODE == MODE_SUPPORT_ORIENTED ? kOccPacks : 4)))
-void k_count_packs(Args A, const int32_t* __restrict__ rows, const uint32_t* __restrict__ pack_ptr,
+void k_count_packs(Args A, const PackRow* __restrict__ recs, const PackInfo* __restrict__ info,
                    uint32_t pack_slots) {
   extern __shared__ int4 smem4[];  // 16-byte aligned: tables are read as int4 buckets
-  pack_body<MODE, VAR>(A, rows, pack_ptr, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
+  pack_body<MODE, VAR>(A, recs, info, blockIdx.x, pack_slots, reinterpret_cast<int32_t*>(smem4));
 }
 
 // Heavy rows: work-group = kWaves consecutive items of the same row b.
@@ -616,6 +622,9 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
   uint32_t* bm = reinterpret_cast<uint32_t*>(smem) + wave * kBmWords;
   const int32_t b = grp[0].b;
   const int64_t rs = A.row_ptr[b], d = A.row_ptr[b + 1] - rs;
+  // this wave's item and its first window (in flight while the table is built)
+  const CountItem it = grp[wave];
+  const Window w0 = window_first(A, it.t0, it.q0, it.len);
   if (lane < kBmWords) bm[lane] = 0;
   block_init<MODE>();
   uint32_t hits = 0;
@@ -639,8 +648,7 @@ __device__ __forceinline__ unsigned long long items_body(const Args& A, const Co
     tr.D = s_D;
   }
   wave_sync_lds();
-  const CountItem it = grp[wave];
-  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE, VAR>(A, tr, it.t0, it.q0, it.len, bm, hits);
+  if (it.len) wave_probe<MODE, GLOBAL ? TK_GLOBAL : TK_SINGLE, VAR>(A, tr, it.t0, it.q0, it.len, bm, hits, w0);
   if constexpr (VALS && !GLOBAL) {
     // the (b, k) credits of the work-group: one atomic per slot that was hit
     __syncthreads();
@@ -728,7 +736,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, VAR>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, VAR>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
-              st, A, w.pack_rows[c], w.pack_ptr[c], slots);
+              st, A, w.pack_recs[c], w.pack_info[c], slots);
   }
   for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
     if (w.n_items[c] == 0) continue;
@@ -785,7 +793,8 @@ void k_count_batch(const Args* __restrict__ gargs, const BatchUnit* __restrict__
       Args A = gargs[bu.graph];
       A.count = counts + bu.graph;
       if (bu.kind == BK_PACK) {
-        pack_body<MODE, VAR_BASE>(A, static_cast<const int32_t*>(bu.p0), bu.p1, bu.index, bu.slots, smem);
+        pack_body<MODE, VAR_BASE>(A, static_cast<const PackRow*>(bu.p0), static_cast<const PackInfo*>(bu.p1),
+                                  bu.index, bu.slots, smem);
       } else if (bu.kind == BK_ITEMS) {
         items_body<MODE, false, VAR_BASE>(A, static_cast<const CountItem*>(bu.p0), smem);
       } else {

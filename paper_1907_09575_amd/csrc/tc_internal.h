@@ -93,7 +93,7 @@ constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + o
 // Their limits: a wave item's probes, times the waves sharing a table, must
 // stay below the hit field of a table's value word (2^18); a pack's table
 // offset is 16 bits of buckets.
-constexpr uint32_t kWaveChunkMin = 1024, kWaveChunkMax = 16384;
+constexpr uint32_t kWaveChunkMin = 1024, kWaveChunkMax = 32767;
 constexpr uint64_t kHeavyMinMax = (uint64_t)1 << 24;
 constexpr uint64_t kPackTargetMin = 1024, kPackTargetMax = (uint64_t)1 << 24;
 constexpr uint32_t kPackSlotsMin = 1024, kPackSlotsMax = 16384;
@@ -166,6 +166,24 @@ struct Owned {
 // Tasks of a set of hashed rows and the work units of the count kernels.
 // Hashed rows are 0 .. nrows - 1 (ranks for a graph, rank-local rows for one
 // rank's block); a task's probes are entries of the probe-side CSR.
+// A row of a pack class, in pack order: all a pack work-group needs of it in
+// one 16-byte load.
+struct alignas(16) PackRow {
+  uint32_t rs;      // start of U_b in col
+  uint32_t d;       // |U_b|, 0 for a row without tasks (it needs no table)
+  uint32_t tb, te;  // its tasks [tb, te) (class-major order)
+};
+// A pack: its rows [r0, r1) of the class, its probes [q0, q1) and, for each
+// of its kWaves equal shares of them, the task holding the share's first
+// probe (computed once when the work is built, instead of searched for by
+// every launch).
+struct alignas(16) PackInfo {
+  uint64_t q0, q1;
+  uint32_t r0, r1;
+  uint32_t wt[kWaves];
+};
+static_assert(sizeof(PackRow) == 16 && sizeof(PackInfo) == 48, "pack record layout");
+
 // Row-bucket thresholds: which rows are packed and how the work is cut.
 struct WorkParams {
   uint64_t heavy_min = kHeavyMin;     // rows with fewer probes (and tables <= 2^10) go to packs
@@ -190,6 +208,8 @@ struct WorkSet {
   // pack classes: pack p covers pack_rows[c][pack_ptr[c][p] .. pack_ptr[c][p+1])
   int32_t* pack_rows[2] = {nullptr, nullptr};   // light rows b of the class, ascending
   uint32_t* pack_ptr[2] = {nullptr, nullptr};
+  PackRow* pack_recs[2] = {nullptr, nullptr};   // the rows' records, same order
+  PackInfo* pack_info[2] = {nullptr, nullptr};  // one per pack
   int64_t n_pack_rows[2] = {0, 0};
   int64_t n_packs[2] = {0, 0};
   int32_t pack_log2S[2] = {0, 0};               // largest row table of the class (log2 slots)
@@ -314,8 +334,8 @@ struct CountArgs {
 enum BatchKind : int32_t { BK_PACK = 0, BK_ITEMS = 1, BK_ITEMS_HBM = 2 };
 
 struct alignas(16) BatchUnit {
-  const void* p0;      // pack: rows of the class; items: the group's first item
-  const uint32_t* p1;  // pack: pack_ptr of the class
+  const void* p0;      // pack: PackRow records of the class; items: the group's first item
+  const void* p1;      // pack: PackInfo records of the class
   uint32_t index;      // pack: pack number
   uint32_t slots;      // pack: table slots reserved for the pack
   int32_t graph;       // entry of the plan's graph list (and of the output)

@@ -445,6 +445,49 @@ __global__ void k_pack_flags(const uint64_t* __restrict__ pw, const uint32_t* __
                  : 0u;
 }
 
+// Records of the pack rows (one thread per row) and of the packs (one thread
+// per pack: probe range and each wave share's first task, by binary search in
+// the pack's task prefixes).
+__global__ void k_pack_recs(const int32_t* __restrict__ rows, int64_t nr, const int64_t* __restrict__ row_ptr,
+                            const uint32_t* __restrict__ tbeg, const uint32_t* __restrict__ tend,
+                            PackRow* __restrict__ recs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  const int32_t b = rows[i];
+  PackRow r;
+  r.rs = (uint32_t)row_ptr[b];
+  r.tb = tbeg[b];
+  r.te = tend[b];
+  r.d = r.te > r.tb ? (uint32_t)(row_ptr[b + 1] - row_ptr[b]) : 0u;
+  recs[i] = r;
+}
+
+__global__ void k_pack_info(const uint32_t* __restrict__ pack_ptr, int64_t np, const PackRow* __restrict__ recs,
+                            const uint64_t* __restrict__ tprefix, PackInfo* __restrict__ info) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  PackInfo pi;
+  pi.r0 = pack_ptr[p];
+  pi.r1 = pack_ptr[p + 1];
+  const uint32_t t_lo = recs[pi.r0].tb, t_hi = recs[pi.r1 - 1].te;
+  pi.q0 = tprefix[t_lo];
+  pi.q1 = tprefix[t_hi];
+  const uint64_t W = pi.q1 - pi.q0;
+  for (int w = 0; w < kWaves; ++w) {
+    const uint64_t wq0 = pi.q0 + W * (uint64_t)w / kWaves;
+    // last task t in [t_lo, t_hi) with tprefix[t] <= wq0 (t_lo when the pack
+    // has no task: the share is then empty and never probed)
+    uint32_t lo = t_lo, hi = t_hi > t_lo ? t_hi : t_lo + 1;
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + (hi - lo) / 2;
+      if (tprefix[mid] <= wq0) lo = mid;
+      else hi = mid;
+    }
+    pi.wt[w] = lo;
+  }
+  info[p] = pi;
+}
+
 __global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
                             int64_t nr, uint32_t* __restrict__ pack_ptr, int64_t np) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -913,6 +956,13 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
         TC_HIP(hipGetLastError());
         w.pack_rows[c] = reinterpret_cast<int32_t*>(crow + r0);
         w.pack_ptr[c] = pack_ptr;
+        w.pack_recs[c] = own.alloc<PackRow>(nr);
+        w.pack_info[c] = own.alloc<PackInfo>(np);
+        TC_LAUNCH("pack_recs", k_pack_recs, dim3(grid_for(nr)), dim3(kT), 0, st, w.pack_rows[c], nr, hrow_ptr,
+                  w.tbeg, w.tend, w.pack_recs[c]);
+        TC_LAUNCH("pack_info", k_pack_info, dim3(grid_for(np)), dim3(kT), 0, st, pack_ptr, np, w.pack_recs[c],
+                  w.tprefix, w.pack_info[c]);
+        TC_HIP(hipGetLastError());
         w.n_pack_rows[c] = nr;
         w.n_packs[c] = np;
         w.pack_log2S[c] = h_cl[c];

@@ -103,4 +103,5 @@ def test_bench_defaults():
         sys.argv = saved
     assert (a.gpus, a.steps, a.warmup, a.scale, a.edge_factor) == (1, 5, 2, 24, 16)
     assert a.support_scale == 20 and a.block_q == 13 and a.batch_graphs == 4096
-    assert not (a.no_block or a.no_support or a.no_batch or a.no_serve or a.no_cpu_baseline)
+    assert not (a.no_block or a.no_support or a.no_batch or a.no_serve or a.no_cpu_baseline or a.no_large)
+    assert a.large_scale == 26
