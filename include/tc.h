@@ -324,7 +324,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
 
 /* ---- row-bucket thresholds and the tuning table ------------------------------
  *
- * The work of a graph is cut into classes (tc_graph_class_stats) by four
+ * The work of a graph is cut into classes (tc_graph_class_stats) by five
  * thresholds, a flat JSON object of integers:
  *   "heavy_min"   (0 .. 2^24, default 32768): rows b with fewer probes than
  *                 this, and tables of at most 2^10 slots, are packed several
@@ -333,8 +333,13 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
  *                 row's);
  *   "pack_slots"  (1024 .. 16384, default 4096): LDS table slots per pack
  *                 (plus one row's table);
- *   "wave_chunk"  (1024 .. 32767, default 16384): probes per wave item of a
- *                 row with work-groups of its own.
+ *   "wave_chunk"  (1024 .. 32767, default 32767): probes per wave item of a
+ *                 row with work-groups of its own, at most;
+ *   "min_groups"  (0 .. 2^22, default 16384): a class of such rows whose
+ *                 probes would fill fewer work-groups than this gets smaller
+ *                 wave items (down to 1024 probes) so that it fills the GPU;
+ *                 a class too small to fill them even then keeps wave_chunk
+ *                 (few large units suit a batch of many small graphs).
  * They change how the work is scheduled, never a count. Graphs take theirs
  * from the tuning table when tc_preprocess builds them (the defaults when the
  * table has no entry for their size).
@@ -364,7 +369,7 @@ tc_status tc_tuning_key(const char* kind, int64_t edges, char* out, size_t cap);
 
 /*
  * tc_graph_retune - a new handle counting the same graph with its work cut by
- * other thresholds (params_json: any of the four keys; the others keep g's).
+ * other thresholds (params_json: any of the five keys; the others keep g's).
  * It shares g's U (g must outlive it), owns only its work decomposition, and
  * is a plain graph for every call. Synchronises `stream`.
  */

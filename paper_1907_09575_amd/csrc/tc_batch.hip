@@ -761,11 +761,12 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
     const uint64_t heavy[] = {8192, 131072};
     const uint64_t target[] = {32768, 262144};
     const uint32_t slots[] = {2048, 8192};
-    const uint32_t chunk[] = {8192, 32767};
+    const uint32_t chunk[] = {8192, 16384};
+    const uint32_t groups[] = {0, 65536};
     const tc::WorkParams own = best_wp;
     tc::WorkParams cur = own;
     double cur_ms = sampled ? run(sample, sched2, nullptr, 0, false) : best_ms;
-    for (int param = 0; param < 4; ++param) {
+    for (int param = 0; param < 5; ++param) {
       const tc::WorkParams start = cur;
       for (int c = 0; c < 2; ++c) {
         tc::WorkParams wp = start;
@@ -773,6 +774,7 @@ tc_status tc_batch_autotune(const tc_graph* const* graphs, int32_t num_graphs, v
         if (param == 1) wp.pack_target = target[c];
         if (param == 2) wp.pack_slots = slots[c];
         if (param == 3) wp.wave_chunk = chunk[c];
+        if (param == 4) wp.min_groups = groups[c];
         if (wp == start) continue;
         std::vector<std::unique_ptr<tc::Graph, void (*)(tc::Graph*)>> held;
         const std::vector<tc::PlanEntry> ents = retuned_entries(sampled ? sample : own_ents, wp, held);

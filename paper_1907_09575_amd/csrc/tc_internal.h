@@ -86,10 +86,11 @@ constexpr int kWaves = 4;               // waves per work-group of packs, small 
 constexpr int kWavesBig = 8;            // waves per work-group of wg_huge / wg_giant items
 constexpr int kMaxLog2S = 14;           // largest LDS table: 16384 slots (64 KiB keys + 64 KiB values)
 // Default row-bucket thresholds of a work decomposition (WorkParams below).
-constexpr uint32_t kWaveChunk = 16384;  // target probes per wave item of a heavy row
+constexpr uint32_t kWaveChunk = 32767;  // target probes per wave item of a heavy row
 constexpr uint64_t kHeavyMin = 32768;   // rows with fewer probes than this are packed
 constexpr uint64_t kPackTarget = 65536; // target probes per pack of light rows (one work-group)
 constexpr uint32_t kPackSlots = 4096;   // target table slots per pack (LDS: + one row's table)
+constexpr uint32_t kMinGroups = 16384;  // work-groups an item class gets at least (chunks shrink)
 // Their limits: a wave item's probes, times the waves sharing a table, must
 // stay below the hit field of a table's value word (2^18); a pack's table
 // offset is 16 bits of buckets.
@@ -97,6 +98,7 @@ constexpr uint32_t kWaveChunkMin = 1024, kWaveChunkMax = 32767;
 constexpr uint64_t kHeavyMinMax = (uint64_t)1 << 24;
 constexpr uint64_t kPackTargetMin = 1024, kPackTargetMax = (uint64_t)1 << 24;
 constexpr uint32_t kPackSlotsMin = 1024, kPackSlotsMax = 16384;
+constexpr uint32_t kMinGroupsMax = 1u << 22;
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
 constexpr int64_t kMaxEdges = (1ll << 32) - 64;        // U positions are 32-bit
@@ -189,10 +191,11 @@ struct WorkParams {
   uint64_t heavy_min = kHeavyMin;     // rows with fewer probes (and tables <= 2^10) go to packs
   uint64_t pack_target = kPackTarget; // probes per pack (plus one row's)
   uint32_t pack_slots = kPackSlots;   // table slots per pack (plus one row's table)
-  uint32_t wave_chunk = kWaveChunk;   // probes per wave item of a heavy row
+  uint32_t wave_chunk = kWaveChunk;   // probes per wave item of a heavy row (at most)
+  uint32_t min_groups = kMinGroups;   // an item class with fewer work-groups gets smaller chunks
   bool operator==(const WorkParams& o) const {
     return heavy_min == o.heavy_min && pack_target == o.pack_target && pack_slots == o.pack_slots &&
-           wave_chunk == o.wave_chunk;
+           wave_chunk == o.wave_chunk && min_groups == o.min_groups;
   }
   bool operator!=(const WorkParams& o) const { return !(*this == o); }
 };
@@ -218,6 +221,7 @@ struct WorkSet {
   CountItem* items[NUM_CLASSES] = {};
   int64_t n_items[NUM_CLASSES] = {};
   int32_t cls_log2S[NUM_CLASSES] = {};
+  uint32_t cls_chunk[NUM_CLASSES] = {};  // probes per wave item of each item class
 
   // per class: rows, table keys, tasks, probes (host copy)
   int64_t cls_stats[NUM_CLASSES][4] = {};

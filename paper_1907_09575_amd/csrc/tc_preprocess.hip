@@ -23,6 +23,8 @@
 //      are packed, heavy rows are cut into per-wave probe ranges.
 #include <algorithm>
 #include <memory>
+#include <mutex>
+#include <set>
 
 #include "tc_prims.h"
 
@@ -137,12 +139,53 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   if (i < n) p[i] = v;
 }
 
-// deg(v) = (edges whose lower endpoint is v) + (edges whose upper endpoint is v),
-// both read off row pointers of sorted key lists.
-__global__ void k_deg_from_bounds(const int64_t* __restrict__ lo_ptr, const int64_t* __restrict__ hi_ptr,
-                                  int64_t n, uint32_t* __restrict__ deg) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) deg[v] = (uint32_t)((lo_ptr[v + 1] - lo_ptr[v]) + (hi_ptr[v + 1] - hi_ptr[v]));
+// deg(v) = (edges whose lower endpoint is v) + (edges whose upper endpoint is
+// v). The first term is a run length of the (lo, hi)-sorted edges (lo_ptr);
+// the upper endpoints arrive partitioned by their top bits (bucket = v >>
+// hshift; bucket j at [start(j), start(j + 1)), start(j) = bs32[j] or bs64[j]
+// for j < nbs, m beyond), and each work-group counts one range of at most
+// kDegBins vertices of one bucket in LDS, reading that bucket's entries
+// (kDegBatch loads in flight per thread before they are counted). It writes
+// the rank keys deg(v) << s | v of its vertices.
+constexpr int kDegBins = 32768;   // LDS counters of one work-group (128 KiB)
+constexpr int kDegThreads = 1024;
+constexpr int kDegBatch = 8;
+
+__global__ __launch_bounds__(kDegThreads) void k_degree_hist(const uint32_t* __restrict__ hi,
+                                                             const uint32_t* __restrict__ bs32,
+                                                             const int64_t* __restrict__ bs64, int64_t nbs, int64_t m,
+                                                             int hshift, int sub, const int64_t* __restrict__ lo_ptr,
+                                                             int64_t n, int s, uint64_t* __restrict__ rk) {
+  extern __shared__ uint32_t h_deg[];
+  const uint32_t bucket = blockIdx.x / (uint32_t)sub, part = blockIdx.x % (uint32_t)sub;
+  const int64_t v0 = ((int64_t)bucket << hshift) + (int64_t)part * kDegBins;
+  const int64_t span_end = (int64_t)(bucket + 1) << hshift;
+  const int64_t v1 = std::min(std::min(v0 + kDegBins, span_end), n);
+  if (v0 >= v1) return;  // (uniform per work-group)
+  const int nv = (int)(v1 - v0);
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) h_deg[j] = 0;
+  __syncthreads();
+  auto start = [&](int64_t j) -> int64_t { return j >= nbs ? m : bs64 ? bs64[j] : (int64_t)bs32[j]; };
+  const int64_t e0 = start(bucket), e1 = start((int64_t)bucket + 1);
+  for (int64_t base = e0 + threadIdx.x; base < e1; base += (int64_t)blockDim.x * kDegBatch) {
+    uint32_t v[kDegBatch];
+#pragma unroll
+    for (int b = 0; b < kDegBatch; ++b) {
+      const int64_t i = base + (int64_t)b * blockDim.x;
+      v[b] = i < e1 ? hi[i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int b = 0; b < kDegBatch; ++b) {
+      const int64_t x = (int64_t)v[b];  // (the fill value is past every range)
+      if (x >= v0 && x < v1) atomicAdd(&h_deg[x - v0], 1u);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    const int64_t v = v0 + j;
+    const uint64_t d = (uint64_t)h_deg[j] + (uint64_t)(lo_ptr[v + 1] - lo_ptr[v]);
+    rk[v] = (d << s) | (uint64_t)v;
+  }
 }
 
 __global__ void k_rank_keys(const uint32_t* __restrict__ deg, int64_t n, int s,
@@ -248,13 +291,22 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
                                                   const uint64_t* __restrict__ tprefix,
                                                   const int64_t* __restrict__ row_ptr, int64_t n, bool all_rows,
                                                   uint64_t heavy_min, int8_t* __restrict__ cls,
-                                                  int* __restrict__ cls_log2S) {
+                                                  int* __restrict__ cls_log2S,
+                                                  unsigned long long* __restrict__ cls_probes) {
   __shared__ int s_max[NUM_CLASSES];
-  if (threadIdx.x < NUM_CLASSES) s_max[threadIdx.x] = 0;
+  __shared__ unsigned long long s_w[NUM_CLASSES];
+  if (threadIdx.x < NUM_CLASSES) {
+    s_max[threadIdx.x] = 0;
+    s_w[threadIdx.x] = 0;
+  }
   __syncthreads();
   int lmax[NUM_CLASSES];
+  unsigned long long lw[NUM_CLASSES];
 #pragma unroll
-  for (int k = 0; k < NUM_CLASSES; ++k) lmax[k] = 0;
+  for (int k = 0; k < NUM_CLASSES; ++k) {
+    lmax[k] = 0;
+    lw[k] = 0;
+  }
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
     int c = -1, l = 0;
     const uint64_t W = tprefix[tptr[b + 1]] - tprefix[tptr[b]];
@@ -273,15 +325,21 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t* __restrict__ tp
     }
     cls[b] = (int8_t)c;
 #pragma unroll
-    for (int k = 0; k < NUM_CLASSES; ++k) lmax[k] = c == k && l > lmax[k] ? l : lmax[k];
+    for (int k = 0; k < NUM_CLASSES; ++k) {
+      lmax[k] = c == k && l > lmax[k] ? l : lmax[k];
+      lw[k] += c == k ? W : 0;
+    }
   }
 #pragma unroll
   for (int k = 0; k < NUM_CLASSES; ++k) {
     const int mk = wave_max(lmax[k]);
+    const unsigned long long wk = wave_sum(lw[k]);
     if (lane_id() == 0 && mk > 0) atomicMax(&s_max[k], mk);
+    if (lane_id() == 0 && wk > 0) atomicAdd(&s_w[k], wk);
   }
   __syncthreads();
   if (threadIdx.x < NUM_CLASSES && s_max[threadIdx.x] > 0) atomicMax(&cls_log2S[threadIdx.x], s_max[threadIdx.x]);
+  if (threadIdx.x < NUM_CLASSES && s_w[threadIdx.x] > 0) atomicAdd(&cls_probes[threadIdx.x], s_w[threadIdx.x]);
 }
 
 // Per-class sums (rows, table keys, tasks, probes): LDS accumulation per
@@ -326,6 +384,7 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const unsigned long long* _
 // Wave items of a heavy row with W probes: a multiple of the class's waves
 // per work-group (each group of `waves` consecutive items shares one table).
 __device__ __forceinline__ uint32_t wg_parts(uint64_t W, int waves, uint32_t chunk) {
+  // (chunk >= kWaveChunkMin: per > 0)
   const uint64_t per = (uint64_t)waves * chunk;
   return (uint32_t)(waves * ((W + per - 1) / per));
 }
@@ -373,12 +432,12 @@ struct CmItems {
   const int8_t* cls;
   const int64_t* tptr;
   const uint64_t* tprefix;
-  uint32_t chunk;
+  uint32_t chunk[NUM_CLASSES];
   __device__ uint32_t operator()(int64_t i) const {
     const uint32_t b = crow[i];
     const int c = cls[b];
     if (c == CLS_PACK_SMALL || c == CLS_PACK_LARGE) return 0;
-    return wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]], class_waves(c), chunk);
+    return wg_parts(tprefix[tptr[b + 1]] - tprefix[tptr[b]], class_waves(c), chunk[c]);
   }
 };
 
@@ -613,27 +672,68 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   // ---- 3: degree order ---------------------------------------------------
   g->perm = g->owned.alloc<int32_t>(n);
   {
-    DevBuf deg(sizeof(uint32_t) * (size_t)n);
-    TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, 0u);
+    DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
     if (m > 0) {
       // E is sorted by (lo, hi): lower-endpoint counts are run lengths; upper
-      // endpoints are counted after a radix sort of their ids (no atomics)
-      DevBuf lo_ptr(sizeof(int64_t) * (size_t)(n + 1)), hi_ptr(sizeof(int64_t) * (size_t)(n + 1));
+      // endpoints are partitioned by one radix pass over their top 8 bits and
+      // counted per bucket in LDS (k_degree_hist, which writes the rank keys)
+      DevBuf lo_ptr(sizeof(int64_t) * (size_t)(n + 1));
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, E.as<uint64_t>(),
                          m, s, n, lo_ptr.as<int64_t>());
+      // one radix pass (8 bits) up to s = 24 (a bucket then spans at most 2
+      // LDS ranges, each reading the bucket's entries), two beyond; the
+      // pass's digit counts, scanned by the sort, are the bucket starts
+      const int hshift = s <= 8 ? 0 : s <= 24 ? s - 8 : s - 16;
       DevBuf hb(sizeof(uint32_t) * (size_t)m);
+      DevBuf dh(sizeof(uint32_t) * 256 * 2);
+      TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
+      if (m > 1) {
+        TC_LAUNCH("rs_digits:degree", (k_rs_digits<uint32_t>),
+                  dim3((unsigned)std::min<int64_t>(2048, div_up(m, 256 * 16))), dim3(256),
+                  digit_lds_bytes(hshift, s), st, Ehi.as<uint32_t>(), m, hshift, s, dh.as<uint32_t>());
+      }
       bool halt = radix_sort<uint32_t, NoVal>(Ehi.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
-                                              0, s, st, "degree");
-      TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st,
-                         halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), m, 0, n, hi_ptr.as<int64_t>());
-      TC_LAUNCH("deg_from_bounds", k_deg_from_bounds, dim3(grid_for(n)), dim3(kT), 0, st, lo_ptr.as<int64_t>(),
-                         hi_ptr.as<int64_t>(), n, deg.as<uint32_t>());
+                                              hshift, s, st, "degree", NoEpi{}, dh.as<uint32_t>());
+      const int passes = digit_passes(hshift, s);
+      const int64_t span = (int64_t)1 << hshift;  // vertices per bucket
+      const int sub = (int)div_up(span, kDegBins);
+      const int64_t nbuckets = div_up(n, span);
+      const int64_t groups = nbuckets * sub;
+      const size_t lds = sizeof(uint32_t) * kDegBins;
+      {
+        // (the attribute is set once per device)
+        static std::mutex mu;
+        static std::set<int> done;
+        std::lock_guard<std::mutex> lk(mu);
+        if (!done.count(g->device)) {
+          TC_HIP(hipFuncSetAttribute((const void*)k_degree_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+          done.insert(g->device);
+        }
+      }
+      // bucket starts: with one digit pass, its counts as the sort scanned
+      // them (256 exclusive starts); else found by binary search
+      DevBuf bp;
+      const uint32_t* bs32 = dh.as<uint32_t>();
+      int64_t nbs = 256;
+      if (passes != 1 || m <= 1) {
+        bp.alloc(sizeof(int64_t) * (size_t)(nbuckets + 1));
+        TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nbuckets + 1)), dim3(kT), 0, st,
+                  halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), m, hshift, nbuckets, bp.as<int64_t>());
+        bs32 = nullptr;
+        nbs = nbuckets + 1;
+      }
+      TC_LAUNCH("degree_hist", k_degree_hist, dim3((unsigned)groups), dim3(kDegThreads), lds, st,
+                halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), bs32, bs32 ? nullptr : bp.as<int64_t>(), nbs, m,
+                hshift, sub, lo_ptr.as<int64_t>(), n, s, ra.as<uint64_t>());
+      TC_HIP(hipGetLastError());
+    } else {
+      DevBuf deg(sizeof(uint32_t) * (size_t)n);
+      TC_LAUNCH("fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, 0u);
+      TC_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
+                ra.as<uint64_t>());
       TC_HIP(hipGetLastError());
     }
-    DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
-    TC_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n)), dim3(kT), 0, st, deg.as<uint32_t>(), n, s,
-                       ra.as<uint64_t>());
-    TC_HIP(hipGetLastError());
     bool alt = radix_sort<uint64_t, NoVal>(ra.as<uint64_t>(), rb.as<uint64_t>(), nullptr, nullptr, n,
                                            s, 2 * s, st, "rank");
     TC_LAUNCH("perm", k_perm, dim3(grid_for(n)), dim3(kT), 0, st,
@@ -859,13 +959,19 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   uint64_t h_probes = 0;
   TC_HIP(hipMemcpyAsync(&h_probes, tb_prefix + T, sizeof(h_probes), hipMemcpyDeviceToHost, st));
   DevBuf cls(sizeof(int8_t) * (size_t)n);
-  DevBuf clsl(sizeof(int) * NUM_CLASSES);
-  TC_HIP(hipMemsetAsync(clsl.p, 0, sizeof(int) * NUM_CLASSES, st));
+  // per class: probes (64-bit counters first: 8-byte aligned for their
+  // atomics), then the largest table (log2 slots)
+  DevBuf clsl(sizeof(unsigned long long) * NUM_CLASSES + sizeof(int) * NUM_CLASSES);
+  TC_HIP(hipMemsetAsync(clsl.p, 0, clsl.bytes, st));
+  unsigned long long* d_cw = clsl.as<unsigned long long>();
+  int* d_cl = reinterpret_cast<int*>(clsl.as<char>() + sizeof(unsigned long long) * NUM_CLASSES);
   TC_LAUNCH("classify", k_classify, dim3(grid_reduce(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
-            all_rows, wp.heavy_min, cls.as<int8_t>(), clsl.as<int>());
+            all_rows, wp.heavy_min, cls.as<int8_t>(), d_cl, d_cw);
   TC_HIP(hipGetLastError());
   int h_cl[NUM_CLASSES];
-  TC_HIP(hipMemcpyAsync(h_cl, clsl.p, sizeof(h_cl), hipMemcpyDeviceToHost, st));
+  unsigned long long h_cw[NUM_CLASSES];
+  TC_HIP(hipMemcpyAsync(h_cl, d_cl, sizeof(h_cl), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipMemcpyAsync(h_cw, d_cw, sizeof(h_cw), hipMemcpyDeviceToHost, st));
 
   // class-major row order: the rows of class 0 (ascending b), then class 1,
   // ...; each row keeps its tasks in b order, so every class - and every pack
@@ -896,7 +1002,19 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
     device_excl_scan_f<uint32_t>(CmTasks{crow, tb_ptr}, tsc.as<uint32_t>(), R, tsc.as<uint32_t>() + R, st);
     device_excl_scan_f<uint64_t>(CmProbes{crow, tb_ptr, tb_prefix}, wsc.as<uint64_t>(), R,
                                  wsc.as<uint64_t>() + R, st);
-    device_excl_scan_f<uint32_t>(CmItems{crow, cls.as<int8_t>(), tb_ptr, tb_prefix, wp.wave_chunk}, usc.as<uint32_t>(), R,
+    // probes per wave item of each item class: wp.wave_chunk, smaller for a
+    // class that would otherwise get fewer than wp.min_groups work-groups,
+    // provided it has the probes to fill them with items of kWaveChunkMin (a
+    // class too small for that stays at wp.wave_chunk: few, large units suit
+    // a batch of many small graphs). h_cw is valid: compact synchronised st.
+    CmItems cmi{crow, cls.as<int8_t>(), tb_ptr, tb_prefix, {}};
+    for (int c = 0; c < NUM_CLASSES; ++c) {
+      const uint64_t per_group = wp.min_groups ? h_cw[c] / ((uint64_t)wp.min_groups * class_waves(c)) : ~0ull;
+      cmi.chunk[c] = per_group < kWaveChunkMin ? wp.wave_chunk
+                                                : (uint32_t)std::min<uint64_t>(wp.wave_chunk, per_group);
+      w.cls_chunk[c] = cmi.chunk[c];
+    }
+    device_excl_scan_f<uint32_t>(cmi, usc.as<uint32_t>(), R,
                                  usc.as<uint32_t>() + R, st);
     DevBuf cm_pos(sizeof(uint32_t) * (size_t)n);
     TC_LAUNCH("cm_place", k_cm_place, dim3(grid_for(R)), dim3(kT), 0, st, crow, R, tsc.as<uint32_t>(), w.tbeg,

@@ -96,6 +96,8 @@ bool parse_work_key(const std::string& k, const std::string& v, WorkParams& wp) 
     wp.pack_slots = (uint32_t)to_i64(k, v, kPackSlotsMin, kPackSlotsMax);
   } else if (k == "wave_chunk") {
     wp.wave_chunk = (uint32_t)to_i64(k, v, kWaveChunkMin, kWaveChunkMax);
+  } else if (k == "min_groups") {
+    wp.min_groups = (uint32_t)to_i64(k, v, 0, kMinGroupsMax);
   } else {
     return false;
   }
@@ -103,10 +105,12 @@ bool parse_work_key(const std::string& k, const std::string& v, WorkParams& wp) 
 }
 
 std::string work_params_json(const WorkParams& wp) {
-  char buf[192];
-  std::snprintf(buf, sizeof(buf), "\"heavy_min\": %llu, \"pack_target\": %llu, \"pack_slots\": %u, \"wave_chunk\": %u",
+  char buf[224];
+  std::snprintf(buf, sizeof(buf),
+                "\"heavy_min\": %llu, \"pack_target\": %llu, \"pack_slots\": %u, \"wave_chunk\": %u, "
+                "\"min_groups\": %u",
                 (unsigned long long)wp.heavy_min, (unsigned long long)wp.pack_target, wp.pack_slots,
-                wp.wave_chunk);
+                wp.wave_chunk, wp.min_groups);
   return buf;
 }
 
@@ -416,9 +420,10 @@ tc_status tc_graph_autotune(const tc_graph* gh, void* stream, char* out_json, si
     const uint64_t heavy[] = {8192, 16384, 32768, 65536, 131072};
     const uint64_t target[] = {16384, 32768, 65536, 131072, 262144};
     const uint32_t slots[] = {2048, 4096, 8192};
-    const uint32_t chunk[] = {4096, 8192, 16384};
-    for (int param = 0; param < 4; ++param) {
-      const int nc = param == 0 ? 5 : param == 1 ? 5 : 3;
+    const uint32_t chunk[] = {8192, 16384, 32767};
+    const uint32_t groups[] = {0, 4096, 16384, 65536};
+    for (int param = 0; param < 5; ++param) {
+      const int nc = param <= 1 ? 5 : param == 4 ? 4 : 3;
       const tc::WorkParams start = best;
       for (int c = 0; c < nc; ++c) {
         tc::WorkParams wp = start;
@@ -426,6 +431,7 @@ tc_status tc_graph_autotune(const tc_graph* gh, void* stream, char* out_json, si
         if (param == 1) wp.pack_target = target[c];
         if (param == 2) wp.pack_slots = slots[c];
         if (param == 3) wp.wave_chunk = chunk[c];
+        if (param == 4) wp.min_groups = groups[c];
         if (wp == start) continue;
         std::unique_ptr<tc::Graph, void (*)(tc::Graph*)> h(tc::build_variant(g, 0, wp, st), tc::destroy_graph);
         const double ms = time_count(*h);

@@ -52,6 +52,8 @@ PARAMS = [
     {"heavy_min": 1 << 24, "pack_target": 1 << 24},      # every row of a small table packed
     {"wave_chunk": 1024, "pack_target": 1024, "pack_slots": 1024},   # finest cuts
     {"pack_slots": 16384, "wave_chunk": 4096, "heavy_min": 8192},
+    {"wave_chunk": 32767, "min_groups": 0},              # largest items, no class-size rule
+    {"min_groups": 1 << 22},                             # every item class at the smallest items
 ]
 
 
@@ -90,6 +92,7 @@ def test_retune_invalid(tc):
     s, d, n = sg.complete(20)
     G = tc.tc_preprocess(dev(s), dev(d), n)
     for bad in ['{"wave_chunk": 512}', '{"wave_chunk": 32768}', '{"pack_slots": 100000}', '{"heavy_min": -1}',
+                '{"min_groups": 4194305}',
                 '{"pack_target": 10}', '{"nope": 1}', 'not json']:
         with pytest.raises(tc.TCError) as e:
             tc.tc_graph_retune(G, bad)
@@ -121,10 +124,10 @@ def test_graph_autotune_feeds_preprocess(tc):
         # a graph of the same size preprocessed now is cut by the tuned thresholds
         G2 = tc.tc_preprocess(dev(s), dev(d), n)
         wp = tc.tc_graph_work_params(G2)
-        assert all(wp[k] == best[k] for k in ("heavy_min", "pack_target", "pack_slots", "wave_chunk"))
+        assert all(wp[k] == best[k] for k in ("heavy_min", "pack_target", "pack_slots", "wave_chunk", "min_groups"))
         assert int(tc.tc_count(G2).item()) == T
     finally:
         tc.tc_tuning_set(key, None)
     G3 = tc.tc_preprocess(dev(s), dev(d), n)
     assert tc.tc_graph_work_params(G3) == {"heavy_min": 32768, "pack_target": 65536, "pack_slots": 4096,
-                                           "wave_chunk": 16384}
+                                           "wave_chunk": 32767, "min_groups": 16384}
