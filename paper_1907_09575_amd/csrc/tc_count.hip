@@ -724,9 +724,66 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
      "block:wg_giant", "block:global"}};
 
 template <int MODE, int VAR>
+void launch_items_class(const WorkSet& w, const Args& A, int c, size_t mark_bytes, hipStream_t st) {
+  if (w.n_items[c] == 0) return;
+  const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
+  const bool global = c == CLS_GLOBAL;
+  const void* f = global ? items_kernel<MODE, true, VAR>(c) : items_kernel<MODE, false, VAR>(c);
+  const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], MODE);
+  if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const CountItem* items = w.items[c];
+  void* kargs[] = {const_cast<Args*>(&A), &items};
+  LaunchScope ls(kLaunchNames[MODE][c], st);
+  TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(64 * class_waves(c)), kargs, lds, st));
+}
+
+// The light classes (packs, wg_small: small tables, few probes per row) run
+// on a side stream beside the heavy ones, so that their launches - short,
+// and ending on a few long work-groups that nothing else overlaps - fill the
+// GPU while the heavy classes stream. One side stream per (device, caller
+// stream), with a fork and a join event; never destroyed; default priority.
+struct SideStream {
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+SideStream& side_stream(hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, SideStream> streams;
+  int dev = 0;
+  TC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  SideStream& s = streams[{dev, st}];
+  if (!s.aux) {
+    TC_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
+    TC_HIP(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+    TC_HIP(hipEventCreateWithFlags(&s.join, hipEventDisableTiming));
+  }
+  return s;
+}
+
+// Probes below which a graph's classes all run on the caller's stream (the
+// fork and join would cost more than they save).
+constexpr int64_t kSideMinProbes = (int64_t)1 << 24;
+
+template <int MODE, int VAR>
 void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
   constexpr bool VALS = MODE == MODE_SUPPORT_FULL;
   const size_t mark_bytes = items_lds_bytes(-1, MODE);
+  // the light classes go to the side stream when both sides have work
+  bool light = false, heavy = false;
+  for (int c = 0; c < NUM_CLASSES; ++c) {
+    const bool any = c <= CLS_PACK_LARGE ? w.n_packs[c] > 0 : w.n_items[c] > 0;
+    (c <= CLS_WG_SMALL ? light : heavy) |= any;
+  }
+  SideStream* side = light && heavy && w.probes >= kSideMinProbes ? &side_stream(st) : nullptr;
+  if (side) {
+    TC_HIP(hipEventRecord(side->fork, st));
+    TC_HIP(hipStreamWaitEvent(side->aux, side->fork, 0));
+  }
+  // heavy classes first (on st), then the light ones (on the side stream)
+  for (int c = CLS_WG_LARGE; c <= CLS_GLOBAL; ++c) launch_items_class<MODE, VAR>(w, A, c, mark_bytes, st);
+  const hipStream_t ls = side ? side->aux : st;
   for (int c = CLS_PACK_SMALL; c <= CLS_PACK_LARGE; ++c) {
     if (w.n_packs[c] == 0) continue;
     // a pack's tables take at most wp.pack_slots plus one row's table
@@ -736,19 +793,12 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, VAR>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, VAR>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
-              st, A, w.pack_recs[c], w.pack_info[c], slots);
+              ls, A, w.pack_recs[c], w.pack_info[c], slots);
   }
-  for (int c = CLS_WG_SMALL; c <= CLS_GLOBAL; ++c) {
-    if (w.n_items[c] == 0) continue;
-    const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
-    const bool global = c == CLS_GLOBAL;
-    const void* f = global ? items_kernel<MODE, true, VAR>(c) : items_kernel<MODE, false, VAR>(c);
-    const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], MODE);
-    if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const CountItem* items = w.items[c];
-    void* kargs[] = {const_cast<Args*>(&A), &items};
-    LaunchScope ls(kLaunchNames[MODE][c], st);
-    TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(64 * class_waves(c)), kargs, lds, st));
+  launch_items_class<MODE, VAR>(w, A, CLS_WG_SMALL, mark_bytes, ls);
+  if (side) {
+    TC_HIP(hipEventRecord(side->join, side->aux));
+    TC_HIP(hipStreamWaitEvent(st, side->join, 0));
   }
   TC_HIP(hipGetLastError());
 }

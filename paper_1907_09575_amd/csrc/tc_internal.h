@@ -212,7 +212,7 @@ struct WorkSet {
   int32_t* pack_rows[2] = {nullptr, nullptr};   // light rows b of the class, ascending
   uint32_t* pack_ptr[2] = {nullptr, nullptr};
   PackRow* pack_recs[2] = {nullptr, nullptr};   // the rows' records, same order
-  PackInfo* pack_info[2] = {nullptr, nullptr};  // one per pack
+  PackInfo* pack_info[2] = {nullptr, nullptr};  // one per pack, heaviest first (launch order)
   int64_t n_pack_rows[2] = {0, 0};
   int64_t n_packs[2] = {0, 0};
   int32_t pack_log2S[2] = {0, 0};               // largest row table of the class (log2 slots)

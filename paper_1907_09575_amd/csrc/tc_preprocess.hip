@@ -547,6 +547,25 @@ __global__ void k_pack_info(const uint32_t* __restrict__ pack_ptr, int64_t np, c
   info[p] = pi;
 }
 
+// Launch order of a class's packs: heaviest first (longest-processing-time
+// order), so that the launch does not end on a few long packs. Key = the
+// complement of the pack's weight (its probes plus 64 per row), so that an
+// ascending sort puts the heaviest first.
+__global__ void k_pack_keys(const PackInfo* __restrict__ info, int64_t np, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ idx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const uint64_t w = info[p].q1 - info[p].q0 + 64ull * (info[p].r1 - info[p].r0);
+  key[p] = 0xFFFFFFFFu - (uint32_t)(w < 0xFFFFFFFFull ? w : 0xFFFFFFFFull);
+  idx[p] = (uint32_t)p;
+}
+
+__global__ void k_pack_gather(const PackInfo* __restrict__ in, const uint32_t* __restrict__ idx, int64_t np,
+                              PackInfo* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) out[p] = in[idx[p]];
+}
+
 __global__ void k_pack_emit(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
                             int64_t nr, uint32_t* __restrict__ pack_ptr, int64_t np) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1078,8 +1097,20 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
         w.pack_info[c] = own.alloc<PackInfo>(np);
         TC_LAUNCH("pack_recs", k_pack_recs, dim3(grid_for(nr)), dim3(kT), 0, st, w.pack_rows[c], nr, hrow_ptr,
                   w.tbeg, w.tend, w.pack_recs[c]);
-        TC_LAUNCH("pack_info", k_pack_info, dim3(grid_for(np)), dim3(kT), 0, st, pack_ptr, np, w.pack_recs[c],
-                  w.tprefix, w.pack_info[c]);
+        {
+          // the class's packs in launch order: heaviest first
+          DevBuf raw(sizeof(PackInfo) * (size_t)np);
+          DevBuf key(sizeof(uint32_t) * (size_t)np), key2(sizeof(uint32_t) * (size_t)np);
+          DevBuf idx(sizeof(uint32_t) * (size_t)np), idx2(sizeof(uint32_t) * (size_t)np);
+          TC_LAUNCH("pack_info", k_pack_info, dim3(grid_for(np)), dim3(kT), 0, st, pack_ptr, np, w.pack_recs[c],
+                    w.tprefix, raw.as<PackInfo>());
+          TC_LAUNCH("pack_keys", k_pack_keys, dim3(grid_for(np)), dim3(kT), 0, st, raw.as<PackInfo>(), np,
+                    key.as<uint32_t>(), idx.as<uint32_t>());
+          const bool alt = radix_sort<uint32_t, uint32_t>(key.as<uint32_t>(), key2.as<uint32_t>(), idx.as<uint32_t>(),
+                                                          idx2.as<uint32_t>(), np, 0, 32, st, "pack_lpt");
+          TC_LAUNCH("pack_gather", k_pack_gather, dim3(grid_for(np)), dim3(kT), 0, st, raw.as<PackInfo>(),
+                    alt ? idx2.as<uint32_t>() : idx.as<uint32_t>(), np, w.pack_info[c]);
+        }
         TC_HIP(hipGetLastError());
         w.n_pack_rows[c] = nr;
         w.n_packs[c] = np;

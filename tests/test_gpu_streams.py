@@ -6,7 +6,8 @@ work of every stream that used the graph, and a plan's free waits for its
 own launches. Here a graph built on one stream is counted repeatedly on a
 second stream, freed at once, and its memory is immediately taken again by
 preprocessing on the first stream; the counts on the second stream must
-still be the oracle's T."""
+still be the oracle's T. The count's side stream (its light classes run
+beside the heavy ones) is also captured into HIP graphs with it."""
 import numpy as np
 import pytest
 
@@ -49,7 +50,9 @@ def test_free_waits_for_the_streams_that_used_the_graph(tc):
     sa.synchronize()
     for out in outs:
         assert out.cpu().tolist() == [T] * 8
-    assert int(tc.tc_count(g, stream=sa).item()) == T
+    c = tc.tc_count(g, stream=sa)
+    sa.synchronize()  # (the count runs on sa; .item() reads on the current stream)
+    assert int(c.item()) == T
     g.free()
 
 
@@ -71,3 +74,39 @@ def test_plan_free_waits_for_its_launches(tc):
     sb.synchronize()
     for out in outs:
         assert out.cpu().tolist() == want
+
+
+def test_count_and_support_captured_in_a_graph(tc):
+    # tc_count and tc_edge_support run their light classes on a side stream
+    # forked from the caller's: captured into a HIP graph, both branches are
+    # recorded, and every replay (with eager work between replays) gives the
+    # eager results
+    s, d = graphgen.rmat(18, seed=4)
+    n = 1 << 18
+    G = tc.tc_preprocess(torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), n)
+    assert G.info()["probes"] >= 1 << 24  # large enough to fork
+    T = int(tc.tc_count(G).item())
+    m = G.info()["m"]
+    full_eager, _ = tc.tc_edge_support(G, tc.TC_SUPPORT_FULL)
+    full_eager = full_eager[:m].clone()
+    torch.cuda.synchronize()
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sup = torch.zeros(m, dtype=torch.int32, device="cuda")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):  # warm-up on the stream before capturing (creates its side stream)
+        tc.tc_count(G, out, stream=st)
+    st.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        tc.tc_count(G, out, stream=st)
+        tc.tc_edge_support(G, tc.TC_SUPPORT_FULL, sup, stream=st)
+    for r in range(4):
+        out.fill_(-1)
+        sup.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(out.item()) == T, "replay %d" % r
+        assert torch.equal(sup, full_eager), "replay %d" % r
+        assert int(tc.tc_count(G).item()) == T  # eager work between replays
+    del graph
+    torch.cuda.synchronize()
