@@ -75,6 +75,8 @@ def parse():
     p.add_argument("--support-scale", type=int, default=20)
     p.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     p.add_argument("--batch-graphs", type=int, default=4096)
+    p.add_argument("--batch-schedule", default=None,
+                   help="tc_batch_create schedule JSON to use instead of autotuning (e.g. for profiles)")
     p.add_argument("--no-serve", action="store_true", help="skip served vs plain FIFO")
     p.add_argument("--serve-requests", type=int, default=10000)
     p.add_argument("--serve-warmup", type=int, default=1000)
@@ -132,7 +134,8 @@ def measure_copy_gbs(dev, nbytes=1 << 31, reps=5):
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
+    """Fabric bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE: L2 misses,
+    served by the Infinity Cache or HBM) from the committed PMC summary, if it
     was taken on the current count-kernel sources; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -142,7 +145,7 @@ def load_traffic(kernel: str):
     from paper_1907_09575_amd.rocprof_summary import source_digest
     if t.get("kernel") != kernel or t.get("source_digest") != source_digest():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("fabric_bytes_per_launch")
 
 
 def host_cpu_model() -> str:
@@ -526,7 +529,10 @@ def bench_batch(tc, args):
         torch.cuda.synchronize()
         plain_times.append(time.perf_counter() - t0)
     t0 = time.perf_counter()
-    tune = tc.tc_batch_autotune(graphs)
+    if args.batch_schedule:
+        tune = {"best": json.loads(args.batch_schedule), "candidates": []}
+    else:
+        tune = tc.tc_batch_autotune(graphs)
     tune_s = time.perf_counter() - t0
     plan = tc.tc_batch_create(graphs, tuning=tune["best"])
     desc = tc.tc_batch_describe(plan)
@@ -797,7 +803,8 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(dom), "algorithmic_bytes_per_launch": bytes_per_launch,
+                    "traffic": load_traffic(dom), "traffic_kind": "fabric (L2 misses: Infinity Cache or HBM)",
+                    "algorithmic_bytes_per_launch": bytes_per_launch,
                     "avg_launch_ms": round(launches[dom]["avg_ms"], 4),
                     "copy_GBps": copy_gbs,
                     "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}

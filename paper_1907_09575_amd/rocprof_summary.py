@@ -7,7 +7,7 @@ and prints short text tables for ``profiles/``.
 
     python paper_1907_09575_amd/rocprof_summary.py stats DIR/NAME_kernel_stats.csv
     python paper_1907_09575_amd/rocprof_summary.py pmc DIR/NAME_counter_collection.csv COUNTER
-    python paper_1907_09575_amd/rocprof_summary.py launches DIR/NAME_kernel_trace.csv
+    python paper_1907_09575_amd/rocprof_summary.py launches DIR/NAME_kernel_trace.csv [SUBSTRING]
     python paper_1907_09575_amd/rocprof_summary.py traffic FETCH.csv WRITE.csv BENCH.json LABEL OUT.json
     python paper_1907_09575_amd/rocprof_summary.py ratios DIR/NAME_counter_collection.csv
 
@@ -20,10 +20,13 @@ LDS-active cycles stalled by bank conflicts) and the L2 hit rate
 the launch classes that share one kernel instantiation.
 
 ``traffic`` turns one FETCH_SIZE run and one WRITE_SIZE run of
-``bench.py --copy-calibration`` into HBM bytes per launch of the count class
+``bench.py --copy-calibration`` into bytes per launch of the count class
 LABEL (e.g. count:wg_large): both counters are scaled by what they read for
 the 1 GiB calibration copy, and the launch is found by kernel name and grid
-size (the class's work-groups from the bench line, 256 threads each).
+size (the class's work-groups from the bench line, 64 threads per wave).
+FETCH_SIZE and WRITE_SIZE count the L2's requests to the fabric: L2 misses,
+served by the Infinity Cache (MALL) or by HBM, so the figure is reported as
+fabric traffic (an upper bound on HBM bytes, not a DRAM measurement).
 
 The PMC summary also reports the counter for the largest plain copy kernel in
 the same run (a known-size calibration copy), so byte counts can be scaled.
@@ -93,10 +96,12 @@ def pmc(path: str, counter: str):
     return "\n".join(lines)
 
 
-def launches(path: str, top: int = 25):
+def launches(path: str, top: int = 25, only: str = ""):
     per = defaultdict(list)
     for r in csv.DictReader(open(path)):
         name = r.get("Kernel_Name", "")
+        if only and only not in name:
+            continue
         grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
         dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         per[(name, grid)].append(dur)
@@ -148,7 +153,8 @@ def _counter_rows(path, counter):
 def traffic(fetch_csv, write_csv, bench_json, label, out_json, commands=()):
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
     cls = label.split(":", 1)[1]
-    grid = bench["classes"][cls]["workgroups"] * 256
+    waves = 8 if cls in ("wg_huge", "wg_giant") else 4
+    grid = bench["classes"][cls]["workgroups"] * 64 * waves
     kname = "k_count_packs" if cls.startswith("pack") else "k_count_items"
     res = {"kernel": label, "workload": bench["config"]["workload"] + " seed %d" % bench["config"]["seed"],
            "source_digest": source_digest()}
@@ -164,8 +170,10 @@ def traffic(fetch_csv, write_csv, bench_json, label, out_json, commands=()):
         res.setdefault("calibration", {"copy_bytes": CALIBRATION_BYTES})
         res["calibration"][key + "_kib"] = cal
         res["calibration"][key + "_scale"] = CALIBRATION_BYTES / 1024.0 / cal
-    hbm = sum(res[k + "_kib_per_launch"] * 1024.0 * res["calibration"][k + "_scale"] for k in ("fetch", "write"))
-    res["hbm_bytes_per_launch"] = hbm
+    fab = sum(res[k + "_kib_per_launch"] * 1024.0 * res["calibration"][k + "_scale"] for k in ("fetch", "write"))
+    res["fabric_bytes_per_launch"] = fab
+    res["note"] = ("FETCH_SIZE + WRITE_SIZE: the L2's requests to the fabric (misses served by the Infinity "
+                   "Cache or HBM), scaled by a 1 GiB copy in the same run")
     res["algorithmic_bytes_per_launch"] = bench["roofline"]["algorithmic_bytes_per_launch"] \
         if bench["roofline"].get("kernel") == label else None
     res["commands"] = list(commands)
@@ -178,7 +186,7 @@ def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats(argv[1]))
     elif len(argv) >= 2 and argv[0] == "launches":
-        print(launches(argv[1]))
+        print(launches(argv[1], only=argv[2] if len(argv) >= 3 else ""))
     elif len(argv) >= 2 and argv[0] == "ratios":
         print(ratios(argv[1]))
     elif len(argv) >= 3 and argv[0] == "pmc":
