@@ -45,7 +45,7 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
                      "count:wg_large", str(tmp_path / "out.json"), ["cmd"])
     assert res["calibration"]["fetch_scale"] == 2.0 and res["calibration"]["write_scale"] == 1.0
     assert res["fetch_kib_per_launch"] == 2000.0 and res["write_kib_per_launch"] == 10.0
-    assert res["hbm_bytes_per_launch"] == 2000.0 * 1024 * 2 + 10.0 * 1024
+    assert res["fabric_bytes_per_launch"] == 2000.0 * 1024 * 2 + 10.0 * 1024
     assert res["algorithmic_bytes_per_launch"] == 4096000
     assert json.loads((tmp_path / "out.json").read_text())["commands"] == ["cmd"]
 
