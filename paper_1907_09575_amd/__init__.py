@@ -23,7 +23,8 @@ __all__ = [
     "tc_batch_describe", "tc_batch_autotune", "tc_count_batched", "tc_count_batched_noalloc", "Server", "tc_release_cached_memory",
     "tc_memory_stats", "tc_graph_free", "tc_graph_class_stats", "tc_vertex_triangles", "tc_clustering",
     "tc_transitivity", "tc_truss", "tc_graph_variant", "tc_block_stats", "TC_VARIANT_IJK", "TC_VARIANT_NO_DCSR",
-    "TC_VARIANT_MUL_HASH", "Timer", "TC_SUPPORT_FULL",
+    "TC_VARIANT_MUL_HASH", "Timer", "TC_SUPPORT_FULL", "tc_graph_retune", "tc_graph_work_params",
+    "tc_graph_autotune", "tc_tuning_load", "tc_tuning_save", "tc_tuning_get", "tc_tuning_set", "tc_tuning_key",
     "TC_SUPPORT_ORIENTED", "TC_NUM_CLASSES", "library_path",
 ]
 
