@@ -382,7 +382,10 @@ def bench_large(tc, args):
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "avg_launch_ms": round(counts[dom]["avg_ms"], 4),
-                        "algorithmic_bytes_per_launch": count_kernel_bytes(cstats, cls)}}
+                        "algorithmic_bytes_per_launch": count_kernel_bytes(cstats, cls)},
+           "kernels_top": {k: {"total_ms": round(v["total_ms"], 3), "launches": v["launches"]}
+                           for k, v in sorted(((k, v) for k, v in kern.items() if not k.startswith("_")),
+                                              key=lambda kv: -kv[1]["total_ms"])[:10]}}
     fx = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
                       "rmat%d_seed%d.json" % (scale, args.seed))
     if os.path.exists(fx) and args.edge_factor == 16:
