@@ -548,9 +548,12 @@ __global__ void k_pack_info(const uint32_t* __restrict__ pack_ptr, int64_t np, c
 }
 
 // Launch order of a class's packs: heaviest first (longest-processing-time
-// order), so that the launch does not end on a few long packs. Key = the
-// complement of the pack's weight (its probes plus 64 per row), so that an
-// ascending sort puts the heaviest first.
+// order), so that the launch does not end on a few long packs. Classes of
+// fewer than kPackLptMin packs keep pack order (their launch is short; the
+// sort would cost more than it saves, and batch plans order units themselves).
+// Key = the complement of the pack's weight (its probes plus 64 per row), so
+// that an ascending sort puts the heaviest first.
+constexpr int64_t kPackLptMin = 2048;
 __global__ void k_pack_keys(const PackInfo* __restrict__ info, int64_t np, uint32_t* __restrict__ key,
                             uint32_t* __restrict__ idx) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1097,7 +1100,11 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
         w.pack_info[c] = own.alloc<PackInfo>(np);
         TC_LAUNCH("pack_recs", k_pack_recs, dim3(grid_for(nr)), dim3(kT), 0, st, w.pack_rows[c], nr, hrow_ptr,
                   w.tbeg, w.tend, w.pack_recs[c]);
-        {
+        if (np < kPackLptMin) {
+          // few packs (a launch of one or two rounds): pack order
+          TC_LAUNCH("pack_info", k_pack_info, dim3(grid_for(np)), dim3(kT), 0, st, pack_ptr, np, w.pack_recs[c],
+                    w.tprefix, w.pack_info[c]);
+        } else {
           // the class's packs in launch order: heaviest first
           DevBuf raw(sizeof(PackInfo) * (size_t)np);
           DevBuf key(sizeof(uint32_t) * (size_t)np), key2(sizeof(uint32_t) * (size_t)np);
