@@ -64,6 +64,9 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     p.add_argument("--gen-threads", type=int, default=16)
+    p.add_argument("--tuning-file", default=None,
+                   help="tuning table to load (default: paper_1907_09575_amd/tuning/<arch>_<CUs>cu.json if present)")
+    p.add_argument("--no-tuning-file", action="store_true", help="run with the default thresholds")
     p.add_argument("--kernels-json", default=None, help="write the full per-kernel timer summary here")
     p.add_argument("--no-block", action="store_true", help="skip the 13x13 block grid of the graph")
     p.add_argument("--block-q", type=int, default=13)
@@ -693,6 +696,18 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    # the committed tuning table of this GPU type (thresholds per graph size,
+    # the batch schedule), written by paper_1907_09575_amd/tune.py
+    tuning_file = None
+    if not args.no_tuning_file:
+        tuning_file = args.tuning_file
+        if tuning_file is None:
+            arch, cus = tc.tc_tuning_key("graph", 1).split("/")[:2]
+            tuning_file = os.path.join(ROOT, "paper_1907_09575_amd", "tuning", "%s_%s.json" % (arch, cus))
+        if os.path.exists(tuning_file):
+            tc.tc_tuning_load(tuning_file)
+        else:
+            tuning_file = None
     n = 1 << args.scale
     print("generating RMAT scale %d ..." % args.scale, file=sys.stderr, flush=True)
     src_h, dst_h = graphgen.rmat(args.scale, edge_factor=args.edge_factor, seed=args.seed,
@@ -833,7 +848,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rmat%d_ef%d_preprocess_count" % (args.scale, args.edge_factor),
                    "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "n": n, "m_raw": m_raw, "seed": args.seed,
-                   "parallelism": "single_gpu"},
+                   "parallelism": "single_gpu",
+                   "tuning_file": os.path.relpath(tuning_file, ROOT) if tuning_file else None,
+                   "work_params": tc.tc_tuning_get(tc.tc_tuning_key("graph", info["m"]))},
         "roofline": roofline,
         "triangles": T,
         "m": info["m"],

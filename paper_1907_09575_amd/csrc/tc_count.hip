@@ -742,24 +742,31 @@ void launch_items_class(const WorkSet& w, const Args& A, int c, size_t mark_byte
 // and ending on a few long work-groups that nothing else overlaps - fill the
 // GPU while the heavy classes stream. One side stream per (device, caller
 // stream), with a fork and a join event; never destroyed; default priority.
+// At most kSideStreams of them exist: calls on further caller streams run
+// every class on the caller's stream.
 struct SideStream {
   hipStream_t aux = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
 };
 
-SideStream& side_stream(hipStream_t st) {
+constexpr size_t kSideStreams = 64;
+
+SideStream* side_stream(hipStream_t st) {
   static std::mutex mu;
   static std::map<std::pair<int, hipStream_t>, SideStream> streams;
   int dev = 0;
   TC_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(mu);
-  SideStream& s = streams[{dev, st}];
-  if (!s.aux) {
+  auto it = streams.find({dev, st});
+  if (it == streams.end()) {
+    if (streams.size() >= kSideStreams) return nullptr;
+    SideStream s;
     TC_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
     TC_HIP(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
     TC_HIP(hipEventCreateWithFlags(&s.join, hipEventDisableTiming));
+    it = streams.emplace(std::make_pair(dev, st), s).first;
   }
-  return s;
+  return &it->second;
 }
 
 // Probes below which a graph's classes all run on the caller's stream (the
@@ -776,7 +783,7 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const bool any = c <= CLS_PACK_LARGE ? w.n_packs[c] > 0 : w.n_items[c] > 0;
     (c <= CLS_WG_SMALL ? light : heavy) |= any;
   }
-  SideStream* side = light && heavy && w.probes >= kSideMinProbes ? &side_stream(st) : nullptr;
+  SideStream* side = light && heavy && w.probes >= kSideMinProbes ? side_stream(st) : nullptr;
   if (side) {
     TC_HIP(hipEventRecord(side->fork, st));
     TC_HIP(hipStreamWaitEvent(side->aux, side->fork, 0));
