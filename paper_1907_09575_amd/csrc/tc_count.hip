@@ -164,10 +164,22 @@ __device__ int build_table(int32_t* tab, int32_t* val, uint32_t bmask, const int
   return md;
 }
 
+// FULL support in packs: a pack of fewer than 2^17 probes keeps its (b, k)
+// credits in LDS, the slot's value word holding the key's index in the pack's
+// key list (kPackValBits, below 2^15 since a pack has at most kPackSlotsMax
+// plus 1024 slots) plus its hits shifted by kPackValBits (at most the pack's
+// probes, so the word stays below 2^32); larger packs hold U positions and
+// credit (b, k) per hit.
+constexpr int kPackValBits = 15;
+static_assert(kPackSlotsMax + 1024 <= (1u << kPackValBits), "a pack's key index fits its field");
+constexpr uint64_t kPackLdsHitsMax = (uint64_t)1 << (32 - kPackValBits);
+
 struct TableRef {
   const int32_t* tab;  // (bmask + 1) * kBucket slots (a pack: all its rows' tables)
-  int32_t* val;        // FULL support: packs hold U positions; single-row tables
-                       // hold row index | hits << kValBits (summed in LDS)
+  int32_t* val;        // FULL support: single-row tables hold row index | hits <<
+                       // kValBits, packs key index | hits << kPackValBits (both
+                       // summed in LDS) or, in packs of 2^17 probes or more, U
+                       // positions
   uint32_t bmask;
   int D;
   int64_t rs, d;  // the row itself (HBM fallback)
@@ -176,6 +188,7 @@ struct TableRef {
   const uint32_t* row_t0;
   const uint32_t* row_desc;
   int nrows;
+  int lds_hits;  // packs, FULL: the (b, k) credits are counted in LDS
 };
 
 enum TableKind : int { TK_SINGLE = 0, TK_MULTI = 1, TK_GLOBAL = 2 };
@@ -208,6 +221,8 @@ __device__ __forceinline__ void credit(const Args& A, const TableRef& t, int whe
     // probe loop of items_body).
     if (KIND == TK_SINGLE) {
       atomicAdd(&t.val[where], 1 << kValBits);
+    } else if (KIND == TK_MULTI && t.lds_hits) {
+      atomicAdd(reinterpret_cast<unsigned int*>(&t.val[where]), 1u << kPackValBits);
     } else {
       const uint32_t other = (uint32_t)(KIND == TK_GLOBAL ? where : t.val[where]);
       if (other < A.m) atomicAdd(&A.support[other], 1);
@@ -531,6 +546,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const Pac
   const uint32_t wt = (uint32_t)__builtin_amdgcn_readfirstlane((int)pi.wt[wave]);
   const uint32_t wlen = (uint32_t)(wq1 - wq0);
   const Window w0 = window_first(A, wt, wq0, wlen);
+  const bool lds_hits = VALS && W < kPackLdsHitsMax;  // (uniform: the pack's probes)
   uint32_t d = 0, S = 0, rs = 0;
   if (tid < nr) {
     const PackRow pr = recs[r0 + tid];
@@ -584,7 +600,7 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const Pac
       bk = (bk + 1) & bmask;
       ++disp;
     }
-    if (VALS) val[slot] = (int32_t)p;  // absolute U position (packs credit (b, k) directly)
+    if (VALS) val[slot] = lds_hits ? (int32_t)x : (int32_t)p;  // key index, or U position
     md = disp > md ? disp : md;
   }
   // (a plain LDS max per lane: a wave reduction here would share its lane
@@ -592,9 +608,31 @@ __device__ __forceinline__ unsigned long long pack_body(const Args& A, const Pac
   if (md) atomicMax(&s_D, md);
   __syncthreads();
 
-  TableRef tr{tab, val, 0, s_D, 0, 0, row_t0, row_desc, nr};
+  TableRef tr{tab, val, 0, s_D, 0, 0, row_t0, row_desc, nr, lds_hits ? 1 : 0};
   uint32_t hits = 0;
   if (wlen > 0) wave_probe<MODE, TK_MULTI, VAR>(A, tr, wt, wq0, wlen, bm, hits, w0);
+  if constexpr (VALS) {
+    if (lds_hits) {
+      // the (b, k) credits of the pack: one atomic per slot that was hit, at
+      // the U position of its key (row found from the key index)
+      __syncthreads();
+      for (uint32_t i = tid; i < S_tot; i += 256) {
+        if (tab[i] == kEmpty) continue;
+        const uint32_t w = (uint32_t)val[i];
+        const uint32_t c = w >> kPackValBits;
+        if (c == 0) continue;
+        const uint32_t x = w & ((1u << kPackValBits) - 1u);
+        int lo = 0, hi = nr;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (row_k0[mid] <= x) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t p = s_rs[lo] + (x - row_k0[lo]);
+        if (p < A.m) atomicAdd(&A.support[p], (int)c);
+      }
+    }
+  }
   return block_flush<MODE>(hits, A);
 }
 
