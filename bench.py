@@ -250,8 +250,15 @@ def bench_block(tc, g, T, q):
         k = timer.summary()
         timer.free()
         count_ms = sum(v["total_ms"] for kk, v in k.items() if kk.startswith("block:")) / reps
+        st = tc.tc_block_stats(g, q, x, y).cpu().tolist()
+        # algorithmic bytes of the rank's count kernels, a lower bound: 4 per
+        # probe and 12 per task (its hashed rows' keys and bounds not counted)
+        alg = 4 * st[1] + 12 * st[0]
         out[name] = {"x": x, "y": y, "count": int(cnt.item()), "per_shift": ps.cpu().tolist(),
-                     "ms_total": round(wall * 1e3, 3), "count_kernel_ms": round(count_ms, 3)}
+                     "ms_total": round(wall * 1e3, 3), "count_kernel_ms": round(count_ms, 3),
+                     "tasks": st[0], "probes": st[1], "alg_bytes_lb": alg,
+                     "count_alg_GBps": round(alg / (count_ms / 1e3) / 1e9, 1) if count_ms > 0 else None,
+                     "count_frac": round(alg / (count_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if count_ms > 0 else None}
     return out
 
 

@@ -821,7 +821,10 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     const bool any = c <= CLS_PACK_LARGE ? w.n_packs[c] > 0 : w.n_items[c] > 0;
     (c <= CLS_WG_SMALL ? light : heavy) |= any;
   }
-  SideStream* side = light && heavy && w.probes >= kSideMinProbes ? side_stream(st) : nullptr;
+  // (one rank's block keeps its classes on the caller's stream: its launches
+  // are small, and its per-class times stay separable)
+  SideStream* side =
+      MODE != MODE_BLOCK && light && heavy && w.probes >= kSideMinProbes ? side_stream(st) : nullptr;
   if (side) {
     TC_HIP(hipEventRecord(side->fork, st));
     TC_HIP(hipStreamWaitEvent(side->aux, side->fork, 0));
