@@ -120,8 +120,15 @@ std::mutex g_tmu;
 std::map<std::string, std::string> g_table;
 bool g_env_read = false;
 
+// An entry must parse, and the thresholds it names must be in range (so that
+// a bad table fails where it is set or loaded, not in a later tc_preprocess).
+void check_entry(const std::string& json) {
+  WorkParams wp;
+  for (const auto& kv : parse_flat_json(json.c_str())) (void)parse_work_key(kv.first, kv.second, wp);
+}
+
 // Entries of a file: one object whose values are flat objects. Each value is
-// kept as its text after checking that it parses.
+// kept as its text after checking it (check_entry).
 std::map<std::string, std::string> parse_table(const std::string& text) {
   std::map<std::string, std::string> out;
   size_t i = 0;
@@ -152,7 +159,7 @@ std::map<std::string, std::string> parse_table(const std::string& text) {
     if (i >= text.size()) fail("unterminated object");
     ++i;
     const std::string val = text.substr(v0, i - v0);
-    (void)parse_flat_json(val.c_str());
+    check_entry(val);
     out[key] = val;
     ws();
     if (i < text.size() && text[i] == ',') {
@@ -230,7 +237,7 @@ std::string tuning_lookup(const std::string& key) {
 }
 
 void tuning_store(const std::string& key, const std::string& json) {
-  (void)parse_flat_json(json.c_str());
+  check_entry(json);
   std::lock_guard<std::mutex> lk(g_tmu);
   read_env_locked();
   g_table[key] = json;

@@ -63,7 +63,8 @@ def test_set_get_nearest_class(lib, clean):
 
 
 def test_bad_entries_rejected(lib, clean):
-    for bad in [b"not json", b'{"a": }', b'{"a": 1,}', b'{"a": 1} trailing', b"[1, 2]"]:
+    for bad in [b"not json", b'{"a": }', b'{"a": 1,}', b'{"a": 1} trailing', b"[1, 2]",
+                b'{"wave_chunk": 999999}', b'{"pack_slots": 12}', b'{"heavy_min": "x"}']:
         assert lib.tc_tuning_set(b"testarch/7cu/graph_e20", bad) == 1, bad
     assert get(lib, "testarch/7cu/graph_e20") is None
     assert lib.tc_tuning_set(b"", b"{}") == 1
@@ -92,7 +93,8 @@ def test_save_load_roundtrip(lib, clean, tmp_path):
 
 def test_bad_files_rejected(lib, clean, tmp_path):
     assert lib.tc_tuning_load(str(tmp_path / "missing.json").encode()) == 1
-    for text in ["", "[]", '{"k": 1}', '{"k": {"a": 1}', '{"testarch/7cu/graph_e20": {"a": }}']:
+    for text in ["", "[]", '{"k": 1}', '{"k": {"a": 1}', '{"testarch/7cu/graph_e20": {"a": }}',
+                 '{"testarch/7cu/graph_e20": {"min_groups": -5}}']:
         f = tmp_path / "bad.json"
         f.write_text(text)
         assert lib.tc_tuning_load(str(f).encode()) == 1, text
