@@ -35,41 +35,62 @@ namespace {
 constexpr int kT = 256;
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, div_up(n, kT)); }
 
-// Elementwise kernels over m elements take kEw consecutive-stride elements
-// per thread (i = block * 256 * kEw + j * 256 + thread): their loads are
-// issued together, which keeps more bytes in flight per wave.
+// Elementwise gathers take 2 * kEw elements per thread, issued together
+// (more bytes in flight per wave).
 constexpr int kEw = 4;
-inline unsigned grid_ew(int64_t m) { return (unsigned)std::max<int64_t>(1, div_up(m, (int64_t)kT * kEw)); }
 // Grid of a key producer that also counts digits (grid-stride loop; one LDS
 // histogram flush per work-group).
 constexpr unsigned kProducerBlocks = 2048;
 
-__global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                                               int64_t m, int64_t n, int s, uint64_t sent,
-                                               uint64_t* __restrict__ keys, int* __restrict__ err) {
-  const int64_t i0 = (int64_t)blockIdx.x * (kT * kEw) + threadIdx.x;
-  int64_t u[kEw], v[kEw];
-#pragma unroll
-  for (int j = 0; j < kEw; ++j) {
-    const int64_t i = i0 + (int64_t)j * kT;
-    u[j] = i < m ? src[i] : 0;
-    v[j] = i < m ? dst[i] : 0;
+// The dedup sort's source: raw pair i as its canonical key (lo << s | hi),
+// or the sentinel for a self loop or an id outside [0, n) (the digit
+// counting kernel reports the latter).
+struct CanonSrc {
+  const int32_t* src;
+  const int32_t* dst;
+  int64_t n;
+  int s;
+  uint64_t sent;
+  __device__ uint64_t key(int64_t i, bool& bad) const {
+    const int64_t u = src[i], v = dst[i];
+    bad = (u < 0) | (u >= n) | (v < 0) | (v >= n);
+    const uint64_t lo = (uint64_t)(u < v ? u : v), hi = (uint64_t)(u < v ? v : u);
+    return bad | (u == v) ? sent : (lo << s) | hi;
   }
-  bool bad = false;
+  __device__ bool operator()(int64_t i, uint64_t& k, char&) const {
+    bool bad;
+    k = key(i, bad);
+    return true;
+  }
+};
+
+// Digit counts of the canonical keys for every pass of the dedup sort, and
+// the id check, in one read of the raw pairs (grid-stride, kDigitBatch pairs
+// in flight per thread; one LDS histogram flush per work-group).
+__global__ __launch_bounds__(256) void k_canon_digits(CanonSrc cs, int64_t m, int key_bits,
+                                                      uint32_t* __restrict__ ghist, int* __restrict__ err) {
+  extern __shared__ uint32_t h_dyn[];
+  DigitCounter dc;
+  dc.init(h_dyn, 0, key_bits);
+  bool bad_any = false;
+  const int64_t stride = (int64_t)gridDim.x * 256 * kDigitBatch;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * kDigitBatch + threadIdx.x; base < m; base += stride) {
+    uint64_t k[kDigitBatch];
 #pragma unroll
-  for (int j = 0; j < kEw; ++j) {
-    const int64_t i = i0 + (int64_t)j * kT;
-    if (i >= m) break;
-    uint64_t key = sent;
-    if (u[j] < 0 || u[j] >= n || v[j] < 0 || v[j] >= n) {
-      bad = true;
-    } else if (u[j] != v[j]) {
-      const uint64_t lo = (uint64_t)(u[j] < v[j] ? u[j] : v[j]), hi = (uint64_t)(u[j] < v[j] ? v[j] : u[j]);
-      key = (lo << s) | hi;
+    for (int j = 0; j < kDigitBatch; ++j) {
+      const int64_t i = base + (int64_t)j * 256;
+      bool bad;
+      k[j] = cs.key(i < m ? i : m - 1, bad);  // (no branch around the loads)
+      bad_any |= bad;
     }
-    keys[i] = key;
+#pragma unroll
+    for (int j = 0; j < kDigitBatch; ++j) {
+      if (base + (int64_t)j * 256 >= m) break;
+      dc.add(k[j]);
+    }
   }
-  if (bad) atomicOr(err, 1);
+  if (bad_any) atomicOr(err, 1);
+  dc.flush(ghist);
 }
 
 // Distinct keys of a sorted key array (the sentinel marks dropped self loops);
@@ -113,13 +134,61 @@ struct TaskPred {
     const int64_t a = (int64_t)(k >> s);
     it.b = (uint32_t)(k & ((1ull << s) - 1));
     it.end = (uint32_t)row_ptr[a + 1];
-    return (int64_t)it.end - i - 1 > 0 && ((nonempty[it.b >> 6] >> (it.b & 63)) & 1ull);
+    // (no short circuit: the loads of several entries can then be in flight)
+    return ((int64_t)it.end - i - 1 > 0) & (bool)((nonempty[it.b >> 6] >> (it.b & 63)) & 1ull);
   }
   __device__ void emit(int64_t i, const Item& it, uint32_t pos) const {
     tkey[pos] = it.b;
     tval[pos] = (uint64_t)(i + 1) | ((uint64_t)it.end << 32);
   }
 };
+
+// The task sort's source: entry i of U gives the task (key b, value first
+// probe | end << 32) when TaskPred selects it.
+struct TaskSrc {
+  TaskPred p;
+  __device__ bool operator()(int64_t i, uint32_t& b, uint64_t& v) const {
+    TaskPred::Item it;
+    const bool ok = p(i, it);
+    b = it.b;
+    v = (uint64_t)(i + 1) | ((uint64_t)it.end << 32);
+    return ok;
+  }
+};
+
+// Tasks of U counted, with the digit counts of their keys for every pass of
+// the task sort, in one read of U (grid-stride, kDigitBatch entries in
+// flight per thread; one LDS histogram flush and one count per work-group).
+__global__ __launch_bounds__(256) void k_task_digits(TaskSrc src, int64_t m, int key_bits,
+                                                     uint32_t* __restrict__ ghist, uint32_t* __restrict__ total) {
+  extern __shared__ uint32_t h_dyn[];
+  __shared__ uint32_t s_c;
+  if (threadIdx.x == 0) s_c = 0;
+  DigitCounter dc;
+  dc.init(h_dyn, 0, key_bits);  // (ends with a barrier)
+  uint32_t c = 0;
+  const int64_t stride = (int64_t)gridDim.x * 256 * kDigitBatch;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * kDigitBatch + threadIdx.x; base < m; base += stride) {
+    uint32_t b[kDigitBatch];
+    bool ok[kDigitBatch];
+#pragma unroll
+    for (int j = 0; j < kDigitBatch; ++j) {
+      const int64_t i = base + (int64_t)j * 256;
+      uint64_t v;
+      ok[j] = src(i < m ? i : m - 1, b[j], v) & (i < m);  // (no branch around the loads)
+    }
+#pragma unroll
+    for (int j = 0; j < kDigitBatch; ++j) {
+      if (ok[j]) {
+        dc.add(b[j]);
+        ++c;
+      }
+    }
+  }
+  if (c) atomicAdd(&s_c, c);
+  dc.flush(ghist);  // (starts with a barrier: s_c is complete)
+  if (threadIdx.x == 0 && s_c) atomicAdd(total, s_c);
+}
 
 // Bit r of the bitmap: row r of a CSR is not empty.
 __global__ __launch_bounds__(256) void k_nonempty_bits(const int64_t* __restrict__ row_ptr, int64_t n,
@@ -665,16 +734,26 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   {
     DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
+    // canonical keys are built by the first pass of the dedup sort from the
+    // raw pairs (7168-pair tiles: the largest whose registers allow two
+    // waves per SIMD); one read of the pairs before it counts their digits
+    // and checks the ids
+    const CanonSrc csrc{d_src, d_dst, n, s, sent};
+    DevBuf dh(sizeof(uint32_t) * 256 * kSortPassesMax);
+    bool alt = false;
     if (m_raw > 0) {
-      TC_LAUNCH("canon", k_canon, dim3(grid_ew(m_raw)), dim3(kT), 0, st, d_src, d_dst, m_raw, n, s,
-                         sent, ka.as<uint64_t>(), d_err);
+      TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
+      TC_LAUNCH("canon_digits", k_canon_digits,
+                dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
+                digit_lds_bytes(0, 2 * s), st, csrc, m_raw, 2 * s, dh.as<uint32_t>(), d_err);
       TC_HIP(hipGetLastError());
+      alt = radix_sort_from<uint64_t, NoVal, CanonSrc, 28>(csrc, m_raw, ka.as<uint64_t>(), kb.as<uint64_t>(),
+                                                           nullptr, nullptr, m_raw, 0, 2 * s, dh.as<uint32_t>(),
+                                                           st, "dedup");
     }
     // the id check is read back with the dedup count (one host sync for both)
     int h_err = 0;
     TC_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    bool alt = radix_sort<uint64_t, NoVal>(ka.as<uint64_t>(), kb.as<uint64_t>(), nullptr, nullptr,
-                                           m_raw, 0, 2 * s, st, "dedup");
     const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
     UniquePred up{sorted, sent, s, nullptr, nullptr};
     if (m_raw == 0) TC_HIP(hipStreamSynchronize(st));  // (compact has no sync then)
@@ -804,24 +883,45 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   TC_HIP(hipMemcpyAsync(&h_maxd, d_maxd, sizeof(h_maxd), hipMemcpyDeviceToHost, st));
 
   // ---- 5: tasks grouped by hashed row b -----------------------------------
+  // one read of U counts the tasks and their key digits; the first pass of
+  // the task sort reads U again and builds the tasks it ranks (no task list
+  // is written in U order)
   TaskLists tl;
   {
-    int64_t T = 0;
-    DevBuf tk, tv;
+    uint32_t h_T = 0;
+    DevBuf ne, th;
+    TaskSrc src{};
     if (m > 0) {
-      DevBuf ne(sizeof(uint64_t) * (size_t)div_up(n, 64));
+      ne.alloc(sizeof(uint64_t) * (size_t)div_up(n, 64));
       TC_LAUNCH("nonempty_bits", k_nonempty_bits, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n,
                 ne.as<uint64_t>());
-      TaskPred tp{okey, s, g->row_ptr, ne.as<uint64_t>(), nullptr, nullptr};
-      T = compact("tasks", m, tp, [&](int64_t total, TaskPred& p) {
-        tk.alloc(sizeof(uint32_t) * (size_t)total);
-        tv.alloc(sizeof(uint64_t) * (size_t)total);
-        p.tkey = tk.as<uint32_t>();
-        p.tval = tv.as<uint64_t>();
-      }, st);
+      src.p = TaskPred{okey, s, g->row_ptr, ne.as<uint64_t>(), nullptr, nullptr};
+      th.alloc(sizeof(uint32_t) * (256 * kSortPassesMax + 1));  // digit counts, then the task count
+      TC_HIP(hipMemsetAsync(th.p, 0, th.bytes, st));
+      uint32_t* d_T = th.as<uint32_t>() + 256 * kSortPassesMax;
+      TC_LAUNCH("task_digits", k_task_digits,
+                dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m, kT * kDigitBatch))), dim3(kT),
+                digit_lds_bytes(0, s), st, src, m, s, th.as<uint32_t>(), d_T);
+      TC_HIP(hipGetLastError());
+      TC_HIP(hipMemcpyAsync(&h_T, d_T, sizeof(h_T), hipMemcpyDeviceToHost, st));
     }
-    if (m == 0) TC_HIP(hipStreamSynchronize(st));  // (no task count then)
-    if (T > 0) sort_tasks(tl, tk, tv, T, n, s, st, "tasks");
+    TC_HIP(hipStreamSynchronize(st));  // the task count, W+ and the largest d+
+    const int64_t T = h_T;
+    tl.T = T;
+    tl.ptr.alloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (T > 0) {
+      tl.row.alloc(sizeof(uint32_t) * (size_t)T);
+      tl.val.alloc(sizeof(uint64_t) * (size_t)T);
+      DevBuf tk(sizeof(uint32_t) * (size_t)T), tv(sizeof(uint64_t) * (size_t)T);
+      const bool alt = radix_sort_from<uint32_t, uint64_t>(src, m, tl.row.as<uint32_t>(), tk.as<uint32_t>(),
+                                                           tl.val.as<uint64_t>(), tv.as<uint64_t>(), T, 0, s,
+                                                           th.as<uint32_t>(), st, "tasks");
+      if (alt) {
+        tl.row.swap(tk);
+        tl.val.swap(tv);
+      }
+    }
+    finish_tasks(tl, n, st);
     g->wedges_plus = (int64_t)h_wplus;
     g->max_dplus = (int64_t)h_maxd;
   }
@@ -931,29 +1031,39 @@ struct TaskLenLoad {
   }
 };
 
-void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows, int key_bits,
-                hipStream_t st, const char* name) {
-  tl.T = T;
-  tl.ptr.alloc(sizeof(int64_t) * (size_t)(nrows + 1));
+// Probe prefixes and row pointers of the tasks in tl.row / tl.val (tl.T of
+// them, sorted by row; tl.ptr allocated with nrows + 1 entries).
+void finish_tasks(TaskLists& tl, int64_t nrows, hipStream_t st) {
+  const int64_t T = tl.T;
   if (T == 0) {
     TC_LAUNCH("fill_i64", k_fill_i64, dim3(grid_for(nrows + 1)), dim3(kT), 0, st, tl.ptr.as<int64_t>(),
               nrows + 1, (int64_t)0);
     return;
   }
-  tl.row.alloc(sizeof(uint32_t) * (size_t)T);
-  tl.val.alloc(sizeof(uint64_t) * (size_t)T);
   tl.prefix.alloc(sizeof(uint64_t) * (size_t)(T + 1));
-  const bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tl.row.as<uint32_t>(), tv.as<uint64_t>(),
-                                                  tl.val.as<uint64_t>(), T, 0, key_bits, st, name);
-  if (!alt) {  // sorted data ended in the input buffers: take them over
-    tl.row.swap(tk);
-    tl.val.swap(tv);
-  }
   device_excl_scan_f<uint64_t>(TaskLenLoad{tl.val.as<uint64_t>()}, tl.prefix.as<uint64_t>(), T,
                                tl.prefix.as<uint64_t>() + T, st);
   TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nrows + 1)), dim3(kT), 0, st,
             tl.row.as<uint32_t>(), T, 0, nrows, tl.ptr.as<int64_t>());
   TC_HIP(hipGetLastError());
+}
+
+void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows, int key_bits,
+                hipStream_t st, const char* name) {
+  tl.T = T;
+  tl.ptr.alloc(sizeof(int64_t) * (size_t)(nrows + 1));
+  if (T > 0) {
+    tl.row.alloc(sizeof(uint32_t) * (size_t)T);
+    tl.val.alloc(sizeof(uint64_t) * (size_t)T);
+    const bool alt = radix_sort<uint32_t, uint64_t>(tk.as<uint32_t>(), tl.row.as<uint32_t>(),
+                                                    tv.as<uint64_t>(), tl.val.as<uint64_t>(), T, 0, key_bits, st,
+                                                    name);
+    if (!alt) {  // sorted data ended in the input buffers: take them over
+      tl.row.swap(tk);
+      tl.val.swap(tv);
+    }
+  }
+  finish_tasks(tl, nrows, st);
 }
 
 void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int64_t T,

@@ -356,8 +356,15 @@ int64_t compact(const char* name, int64_t m, P pred, F&& prepare, hipStream_t st
 //     when the sort holds fewer than 2^31 keys, else one 64-bit atomic. The
 //     wait is bounded: past the spin budget the kernel records a failure
 //     (sort_failed) and goes on, so every wave always finishes.
+// The first pass may read its elements through a source functor instead of
+// the key and value arrays (radix_sort_from): it selects some of n_in input
+// positions and builds their keys and values, and the pass ranks and writes
+// only the selected ones, in input order within each digit.
 // ---------------------------------------------------------------------------
 struct NoVal {};
+
+// Source of a pass that reads the key and value arrays.
+struct NoSrc {};
 
 // Epilogue of a sort's last pass: called with every key and its final
 // position as it is written (NoEpi: nothing).
@@ -492,14 +499,14 @@ static __global__ __launch_bounds__(256) void k_rs_buckets(uint32_t* __restrict_
   }
 }
 
-template <class K, class V, int KPT, class W, int WIN, class Epi>
+template <class K, class V, int KPT, class W, int WIN, class Epi, class Src = NoSrc>
 __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                      const V* __restrict__ vin, V* __restrict__ vout,
                                                      int64_t n, int shift, uint32_t dmask,
                                                      const uint32_t* __restrict__ bucket,
                                                      W* __restrict__ status,
                                                      uint32_t* __restrict__ ticket, int* __restrict__ fail,
-                                                     Epi epi) {
+                                                     Epi epi, Src src = Src{}) {
   constexpr int TILE = 256 * KPT;
   constexpr int WCH = 64 * KPT;  // keys of the tile each wave ranks (a contiguous quarter)
   constexpr bool HV = !std::is_same<V, NoVal>::value;
@@ -519,15 +526,31 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
   const uint32_t tile = s_tile;
   const int64_t wbase = (int64_t)tile * TILE + (int64_t)wave * WCH;
 
-  // the wave's quarter in registers: item i of lane l is key wbase + 64 i + l
+  // the wave's quarter in registers: item i of lane l is input position
+  // wbase + 64 i + l; with a source, bit i of vmask says whether the item is
+  // a key of the sort (without one, the positions below n are)
+  constexpr bool FROM_SRC = !std::is_same<Src, NoSrc>::value;
   K k[KPT];
   VS v[KPT];
+  static_assert(KPT <= 32, "one mask bit per item");
+  uint32_t vmask = 0;
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
     const int64_t idx = wbase + 64 * i + lane;
-    k[i] = idx < n ? kin[idx] : K(0);
-    if constexpr (HV) v[i] = idx < n ? vin[idx] : V{};
+    if constexpr (!FROM_SRC) {
+      k[i] = idx < n ? kin[idx] : K(0);
+      if constexpr (HV) v[i] = idx < n ? vin[idx] : V{};
+    } else {
+      // evaluated at a position in bounds (n >= 1) without a branch, so that
+      // the loads of all items are issued together
+      const bool ok = src(idx < n ? idx : n - 1, k[i], v[i]);
+      vmask |= (uint32_t)(ok & (idx < n)) << i;
+    }
   }
+  auto is_key = [&](int i) -> bool {
+    if constexpr (FROM_SRC) return (vmask >> i) & 1u;
+    else return wbase + 64 * i + lane < n;
+  };
   // stable rank within the wave's quarter; the wave's own LDS counters carry
   // the counts from item to item (a wave's LDS accesses complete in order)
   uint32_t rank[KPT];
@@ -535,7 +558,7 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
   uint32_t* cnt_w = s_cnt[wave];
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
-    const bool valid = wbase + 64 * i + lane < n;
+    const bool valid = is_key(i);
     const uint32_t d = rs_digit(k[i], shift, dmask);
     const uint64_t peers = rs_peers(d, valid);
     const uint32_t before = cnt_w[d];
@@ -567,7 +590,7 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
-    if (wbase + 64 * i + lane < n) {
+    if (is_key(i)) {
       const uint32_t d = rs_digit(k[i], shift, dmask);
       const uint32_t lp = s_tstart[d] + s_cnt[wave][d] + rank[i];
       s_k[lp] = k[i];
@@ -615,8 +638,14 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(const K* __restrict__ kin, 
     s_goff[tid] = bucket[tid] + (uint32_t)excl;
   }
   __syncthreads();
-  const int64_t rem = n - (int64_t)tile * TILE;
-  const int tile_n = rem < TILE ? (int)rem : TILE;
+  // keys of the tile
+  int tile_n;
+  if constexpr (FROM_SRC) {
+    tile_n = (int)tot;
+  } else {
+    const int64_t rem = n - (int64_t)tile * TILE;
+    tile_n = rem < TILE ? (int)rem : TILE;
+  }
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
     const int lp = i * 256 + tid;
@@ -650,23 +679,41 @@ constexpr int rs_default_kpt() {
 // pass runs, and epi is not called, when n <= 1). hist: the keys' digit
 // counts ([passes][256], from a DigitCounter in the producing kernel; it is
 // scanned in place), or nullptr to count them here.
-template <class K, class V, int KPT, class W, int WIN = kLbWin, class Epi = NoEpi>
+//
+// With a source (src != nullptr), the n keys are those that *src selects
+// from the input positions [0, n_in): the first pass reads them through
+// *src and writes them to keys/vals, later passes ping-pong as above, and
+// hist is required. Src is a functor
+//   __device__ bool operator()(int64_t i, K& key, V& val) const
+// (false: position i holds no key), evaluated once per position; it should
+// not branch around its loads (compute the selection with & rather than &&),
+// so that a tile's loads are issued together.
+template <class K, class V, int KPT, class W, int WIN = kLbWin, class Epi = NoEpi, class Src = NoSrc,
+          int KPT_SRC = KPT>
 bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
-                    hipStream_t st, const char* name, Epi epi = Epi{}, uint32_t* hist = nullptr) {
+                    hipStream_t st, const char* name, Epi epi = Epi{}, uint32_t* hist = nullptr,
+                    const Src* src = nullptr, int64_t n_in = 0) {
   constexpr int TILE = 256 * KPT;
   const char* n_digits = intern_name(std::string("rs_digits:") + name);
   const char* n_pass = intern_name(std::string("rs_pass:") + name);
-  if (n <= 1 || bit_hi <= bit_lo) return false;
-  TC_REQUIRE(n < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW, "radix_sort: more than 2^32-1 keys");
+  if (src) {
+    if (n <= 0) return false;
+    TC_REQUIRE(hist != nullptr && bit_hi > bit_lo && n <= n_in, TC_EINVAL, "radix_sort: bad source sort");
+  } else if (n <= 1 || bit_hi <= bit_lo) {
+    return false;
+  }
+  TC_REQUIRE(n < (int64_t)0xFFFFFFFFLL && n_in < (int64_t)0xFFFFFFFFLL, TC_EOVERFLOW,
+             "radix_sort: more than 2^32-1 keys");
   TC_REQUIRE(sizeof(W) == 8 || n < ((int64_t)1 << 31), TC_EINVAL, "radix_sort: 32-bit look-back words");
   TC_REQUIRE(bit_hi - bit_lo <= 8 * kSortPassesMax, TC_EINVAL, "radix_sort: key range too wide");
   const int passes = (bit_hi - bit_lo + 7) / 8;
   const int64_t ntiles = div_up(n, TILE);
+  const int64_t ntiles_in = src ? div_up(n_in, 256 * KPT_SRC) : ntiles;  // (the source pass: KPT_SRC per thread)
   int* fail = temp_ctx().fail;
   TC_REQUIRE(fail != nullptr, TC_EDEVICE, "radix_sort: called outside a TempStream scope");
-  // per pass: ticket counter (padded to 256 bytes) + ntiles * 256 look-back words
+  // per pass: ticket counter (padded to 256 bytes) + tiles * 256 look-back words
   const int64_t pad = 256 / (int64_t)sizeof(W);
-  const int64_t pass_words = pad + ntiles * 256;
+  const int64_t pass_words = pad + std::max(ntiles, ntiles_in) * 256;
   DevBuf own_hist;
   DevBuf lb(sizeof(W) * (size_t)pass_words);
   uint32_t* gh = hist;
@@ -688,16 +735,27 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     const int shift = bit_lo + 8 * p;
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
+    const bool last = p + 1 == passes;
     TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(W) * (size_t)pass_words, st));
     W* words = lb.as<W>();
-    if (p + 1 < passes)
+    uint32_t* ticket = reinterpret_cast<uint32_t*>(words);
+    if (p == 0 && src) {  // from the source into keys/vals
+      if (last)
+        TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT_SRC, W, WIN, Epi, Src>), dim3((unsigned)ntiles_in), dim3(256), 0,
+                  st, nullptr, ka, nullptr, va, n_in, shift, dmask, gh, words + pad, ticket, fail, epi, *src);
+      else
+        TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT_SRC, W, WIN, NoEpi, Src>), dim3((unsigned)ntiles_in), dim3(256),
+                  0, st, nullptr, ka, nullptr, va, n_in, shift, dmask, gh, words + pad, ticket, fail, NoEpi{},
+                  *src);
+      TC_HIP(hipGetLastError());
+      continue;
+    }
+    if (!last)
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, NoEpi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
-                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
-                reinterpret_cast<uint32_t*>(words), fail, NoEpi{});
+                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad, ticket, fail, NoEpi{});
     else
       TC_LAUNCH(n_pass, (k_rs_onesweep<K, V, KPT, W, WIN, Epi>), dim3((unsigned)ntiles), dim3(256), 0, st, ka,
-                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad,
-                reinterpret_cast<uint32_t*>(words), fail, epi);
+                kb, va, vb, n, shift, dmask, gh + 256 * p, words + pad, ticket, fail, epi);
     TC_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
@@ -720,6 +778,27 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
                                                             st, name, epi, hist);
   return radix_sort_cfg<K, V, KPT, uint64_t, kLbWin, Epi>(keys, keys_alt, vals, vals_alt, n, bit_lo, bit_hi, st,
                                                           name, epi, hist);
+}
+
+// Stable sort of the n keys (and values) that src selects from the input
+// positions [0, n_in) (the source form of radix_sort_cfg): they end in
+// keys/vals if this returns false, else in keys_alt/vals_alt, each buffer
+// holding n elements. hist: their digit counts ([passes][256]), taken by the
+// kernel that counted the selected positions (a DigitCounter).
+// KPT_SRC: items per thread of the source pass (a source that loads more
+// than the key and value may need smaller tiles to keep its registers).
+template <class K, class V, class Src, int KPT_SRC = rs_default_kpt<K, V>(), class Epi = NoEpi>
+bool radix_sort_from(const Src& src, int64_t n_in, K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n,
+                     int bit_lo, int bit_hi, uint32_t* hist, hipStream_t st, const char* name,
+                     Epi epi = Epi{}) {
+  constexpr int KPT = rs_default_kpt<K, V>();
+  if (n < ((int64_t)1 << 31) && !sort_wide_words_forced())
+    return radix_sort_cfg<K, V, KPT, uint32_t, kLbWin, Epi, Src, KPT_SRC>(keys, keys_alt, vals, vals_alt, n,
+                                                                          bit_lo, bit_hi, st, name, epi, hist,
+                                                                          &src, n_in);
+  return radix_sort_cfg<K, V, KPT, uint64_t, kLbWin, Epi, Src, KPT_SRC>(keys, keys_alt, vals, vals_alt, n,
+                                                                        bit_lo, bit_hi, st, name, epi, hist,
+                                                                        &src, n_in);
 }
 
 // Throws TC_EDEVICE if a sort of the current TempStream scope gave up waiting
@@ -777,6 +856,10 @@ struct TaskLists {
 // sort buffers (tl may take them over).
 void sort_tasks(TaskLists& tl, DevBuf& tk, DevBuf& tv, int64_t T, int64_t nrows, int key_bits,
                 hipStream_t st, const char* name);
+// Probe prefixes (tl.prefix) and row pointers (tl.ptr, allocated by the
+// caller with nrows + 1 entries) of the tl.T tasks in tl.row / tl.val,
+// sorted by row; the tail of sort_tasks.
+void finish_tasks(TaskLists& tl, int64_t nrows, hipStream_t st);
 // check_sorts for the task sorts of sort_tasks (synchronises st).
 void check_task_sorts(hipStream_t st);
 
