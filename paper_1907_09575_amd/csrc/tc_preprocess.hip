@@ -308,6 +308,67 @@ __global__ __launch_bounds__(256) void k_orient(const uint64_t* __restrict__ E, 
 }
 
 // Column of a sorted orient key, written by the orient sort's last pass.
+// Orientation in two steps, so that no rank is read at random from the
+// whole rank map. (1) One radix pass partitions the edges by the top 8 bits
+// of their upper endpoint (the last digit pass of the degree count's
+// partition, whose scanned digit starts it reuses); its source reads E in
+// order, so the lower endpoints' ranks are read in nondecreasing vertex
+// order: element = rank(lo) << 32 | hi. (2) k_orient_hi reads the ranks of
+// the upper endpoints bucket by bucket (a bucket spans 2^(s-8) vertices: a
+// 256 KiB slice of the rank map at s = 24, 1 MiB at s = 26, which stays in
+// L2) and writes the oriented key in place.
+struct LoRankSrc {
+  const uint64_t* E;
+  const int32_t* perm;
+  int s;
+  __device__ bool operator()(int64_t i, uint64_t& k, char&) const {
+    const uint64_t e = E[i];
+    k = ((uint64_t)(uint32_t)perm[e >> s] << 32) | (e & ((1ull << s) - 1));
+    return true;
+  }
+};
+
+// XCD-aware grid-stride sweep: work-groups are dealt to the 8 XCDs in turn,
+// so work-group b sweeps the chunks of the b % 8-th eighth of [0, chunks)
+// and each XCD's L2 holds the rank slices of its own eighth only. The grid
+// is a multiple of 8.
+__global__ __launch_bounds__(256) void k_orient_hi(uint64_t* __restrict__ pk, int64_t m, int s,
+                                                   const int32_t* __restrict__ perm, uint32_t* __restrict__ hist) {
+  extern __shared__ uint32_t h_dyn[];
+  constexpr int kI = 2 * kEw;  // gathers: more in flight
+  constexpr int64_t kChunk = (int64_t)kT * kI;
+  DigitCounter dc;
+  dc.init(h_dyn, 0, 2 * s);
+  const uint64_t mask = (1ull << s) - 1;
+  const int64_t chunks = (m + kChunk - 1) / kChunk;
+  const int64_t per_xcd = (chunks + 7) / 8;
+  const int64_t c0 = (int64_t)(blockIdx.x & 7) * per_xcd;
+  const int64_t c1 = c0 + per_xcd < chunks ? c0 + per_xcd : chunks;
+  for (int64_t c = c0 + (blockIdx.x >> 3); c < c1; c += gridDim.x >> 3) {
+    const int64_t i0 = c * kChunk + threadIdx.x;
+    uint64_t e[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int64_t i = i0 + (int64_t)j * kT;
+      e[j] = pk[i < m ? i : m - 1];
+    }
+    uint32_t rv[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) rv[j] = (uint32_t)perm[e[j] & mask];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int64_t i = i0 + (int64_t)j * kT;
+      if (i < m) {
+        const uint64_t a = e[j] >> 32, b = rv[j];
+        const uint64_t k = a < b ? ((a << s) | b) : ((b << s) | a);
+        pk[i] = k;
+        dc.add(k);
+      }
+    }
+  }
+  dc.flush(hist);
+}
+
 struct ColEpi {
   int32_t* col;
   int s;
@@ -772,6 +833,9 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
   // ---- 3: degree order ---------------------------------------------------
   g->perm = g->owned.alloc<int32_t>(n);
+  // exclusive starts of the last digit pass (top 8 bits of hi) of the degree
+  // count's partition: the orientation's partition pass reuses them
+  DevBuf hi_starts;
   {
     DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
     if (m > 0) {
@@ -796,6 +860,11 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       bool halt = radix_sort<uint32_t, NoVal>(Ehi.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
                                               hshift, s, st, "degree", NoEpi{}, dh.as<uint32_t>());
       const int passes = digit_passes(hshift, s);
+      if (m > 1) {
+        hi_starts.alloc(sizeof(uint32_t) * 256);
+        TC_HIP(hipMemcpyAsync(hi_starts.p, dh.as<uint32_t>() + 256 * (passes - 1), sizeof(uint32_t) * 256,
+                              hipMemcpyDeviceToDevice, st));
+      }
       const int64_t span = (int64_t)1 << hshift;  // vertices per bucket
       const int sub = (int)div_up(span, kDegBins);
       const int64_t nbuckets = div_up(n, span);
@@ -851,13 +920,27 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   const uint64_t* okey = ok.as<uint64_t>();
   {
     if (m > 0) {
-      DevBuf ohist(sizeof(uint32_t) * 256 * kSortPassesMax);  // digit counts, from k_orient
+      DevBuf ohist(sizeof(uint32_t) * 256 * kSortPassesMax);  // digit counts, from the orientation
       TC_HIP(hipMemsetAsync(ohist.p, 0, ohist.bytes, st));
-      TC_LAUNCH("orient", k_orient,
-                dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw))), dim3(kT),
-                digit_lds_bytes(0, 2 * s), st, E.as<uint64_t>(), m, s, g->perm, ok.as<uint64_t>(),
-                ohist.as<uint32_t>());
+      if (m > 1) {
+        // partition by the top 8 bits of hi (one pass, into ok), then the
+        // oriented keys in place
+        const LoRankSrc lsrc{E.as<uint64_t>(), g->perm, s};
+        // (28 edges per thread, as the canonicalising pass: a source that
+        // loads twice per element needs the registers)
+        const bool palt = radix_sort_from<uint64_t, NoVal, LoRankSrc, 28>(
+            lsrc, m, ok.as<uint64_t>(), nullptr, nullptr, nullptr, m, s > 8 ? s - 8 : 0, s,
+            hi_starts.as<uint32_t>(), st, "orient_part", NoEpi{}, true);
+        TC_REQUIRE(!palt, TC_EDEVICE, "tc_preprocess: the orientation partition is one pass");
+        const int64_t og = std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw));
+        TC_LAUNCH("orient", k_orient_hi, dim3((unsigned)(div_up(og, 8) * 8)), dim3(kT), digit_lds_bytes(0, 2 * s),
+                  st, ok.as<uint64_t>(), m, s, g->perm, ohist.as<uint32_t>());
+      } else {
+        TC_LAUNCH("orient", k_orient, dim3(1), dim3(kT), digit_lds_bytes(0, 2 * s), st, E.as<uint64_t>(), m, s,
+                  g->perm, ok.as<uint64_t>(), ohist.as<uint32_t>());
+      }
       TC_HIP(hipGetLastError());
+      hi_starts.release();
       // E's buffer is the ping-pong partner
       // (the last pass also writes each key's column: U's col array)
       bool alt = radix_sort<uint64_t, NoVal, ColEpi>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,

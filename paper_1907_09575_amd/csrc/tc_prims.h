@@ -678,7 +678,8 @@ constexpr int rs_default_kpt() {
 // buffers. The last pass calls epi(final position, key) for every key (no
 // pass runs, and epi is not called, when n <= 1). hist: the keys' digit
 // counts ([passes][256], from a DigitCounter in the producing kernel; it is
-// scanned in place), or nullptr to count them here.
+// scanned in place; hist_scanned: it already holds each pass's exclusive
+// digit starts, as a sort leaves them), or nullptr to count them here.
 //
 // With a source (src != nullptr), the n keys are those that *src selects
 // from the input positions [0, n_in): the first pass reads them through
@@ -692,7 +693,7 @@ template <class K, class V, int KPT, class W, int WIN = kLbWin, class Epi = NoEp
           int KPT_SRC = KPT>
 bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_lo, int bit_hi,
                     hipStream_t st, const char* name, Epi epi = Epi{}, uint32_t* hist = nullptr,
-                    const Src* src = nullptr, int64_t n_in = 0) {
+                    const Src* src = nullptr, int64_t n_in = 0, bool hist_scanned = false) {
   constexpr int TILE = 256 * KPT;
   const char* n_digits = intern_name(std::string("rs_digits:") + name);
   const char* n_pass = intern_name(std::string("rs_pass:") + name);
@@ -725,7 +726,7 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), digit_lds_bytes(bit_lo, bit_hi), st, keys,
               n, bit_lo, bit_hi, gh);
   }
-  TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, gh, passes);
+  if (!hist_scanned) TC_LAUNCH("rs_buckets", k_rs_buckets, dim3(1), dim3(256), 0, st, gh, passes);
   K* ka = keys;
   K* kb = keys_alt;
   V* va = vals;
@@ -790,15 +791,15 @@ bool radix_sort(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int bit_l
 template <class K, class V, class Src, int KPT_SRC = rs_default_kpt<K, V>(), class Epi = NoEpi>
 bool radix_sort_from(const Src& src, int64_t n_in, K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n,
                      int bit_lo, int bit_hi, uint32_t* hist, hipStream_t st, const char* name,
-                     Epi epi = Epi{}) {
+                     Epi epi = Epi{}, bool hist_scanned = false) {
   constexpr int KPT = rs_default_kpt<K, V>();
   if (n < ((int64_t)1 << 31) && !sort_wide_words_forced())
     return radix_sort_cfg<K, V, KPT, uint32_t, kLbWin, Epi, Src, KPT_SRC>(keys, keys_alt, vals, vals_alt, n,
                                                                           bit_lo, bit_hi, st, name, epi, hist,
-                                                                          &src, n_in);
+                                                                          &src, n_in, hist_scanned);
   return radix_sort_cfg<K, V, KPT, uint64_t, kLbWin, Epi, Src, KPT_SRC>(keys, keys_alt, vals, vals_alt, n,
                                                                         bit_lo, bit_hi, st, name, epi, hist,
-                                                                        &src, n_in);
+                                                                        &src, n_in, hist_scanned);
 }
 
 // Throws TC_EDEVICE if a sort of the current TempStream scope gave up waiting
