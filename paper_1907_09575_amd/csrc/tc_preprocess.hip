@@ -3,10 +3,13 @@
 // Pipeline, all on the caller's stream:
 //   1. canonical keys: each pair {u, v}, u != v, becomes min(u,v) * 2^s + max(u,v)
 //      (s = ceil(log2 n)); self loops and invalid ids become a sentinel.
-//   2. stable LSD radix sort of the 2s-bit keys, adjacent-unique compaction:
-//      the simple undirected graph of Section 2 / Section 6.1.
-//   3. degrees from run lengths of the sorted keys (lower endpoints) and of a
-//      radix-sorted copy of the upper endpoints; rank = position in the order (degree, id)
+//   2. stable LSD radix sort of the 2s-bit keys: the distinct keys (those
+//      that differ from their predecessor and are not the sentinel) are the
+//      simple undirected graph of Section 2 / Section 6.1; they are selected
+//      from the sorted keys by each later reader, never copied out.
+//   3. degrees counted in LDS per vertex range: lower endpoints from the
+//      sorted keys, upper endpoints from a radix partition of them by their
+//      top bits; rank = position in the order (degree, id)
 //      (a stable radix sort of degree * 2^s + id on the degree bits): the
 //      non-decreasing degree relabelling of Section 5.3.
 //   4. orientation by rank (Section 5.3: the global position stands in for the
@@ -93,28 +96,66 @@ __global__ __launch_bounds__(256) void k_canon_digits(CanonSrc cs, int64_t m, in
   dc.flush(ghist);
 }
 
-// Distinct keys of a sorted key array (the sentinel marks dropped self loops);
-// each is written out with its upper endpoint (low s bits) beside it, the
-// input of the upper-endpoint degree count.
-struct UniquePred {
-  const uint64_t* keys;
+// Distinct keys of the sorted canonical keys S (duplicates adjacent, the
+// sentinel for dropped self loops last): position i holds one iff S[i] is
+// not the sentinel and differs from S[i - 1]. The distinct keys are never
+// written out; the degree count, its partition and the orientation select
+// them from S. (Evaluated without branches around the loads.)
+struct DistinctSel {
+  const uint64_t* S;
   uint64_t sent;
-  int s;
-  uint64_t* out;
-  uint32_t* out_hi;
-  struct Item {
-    uint64_t k;
-  };
-  __device__ bool operator()(int64_t i, Item& it) const {
-    const uint64_t k = keys[i];
-    it.k = k;
-    return k != sent && (i == 0 || keys[i - 1] != k);
-  }
-  __device__ void emit(int64_t, const Item& it, uint32_t pos) const {
-    out[pos] = it.k;
-    out_hi[pos] = (uint32_t)(it.k & ((1ull << s) - 1));
+  __device__ bool operator()(int64_t i, uint64_t& k) const {
+    k = S[i];
+    const uint64_t prev = S[i > 0 ? i - 1 : 0];
+    return (k != sent) & ((i == 0) | (prev != k));
   }
 };
+
+// The degree partition's source: the upper endpoint of each distinct key.
+struct DistinctHiSrc {
+  DistinctSel d;
+  int s;
+  __device__ bool operator()(int64_t i, uint32_t& hi, char&) const {
+    uint64_t k;
+    const bool ok = d(i, k);
+    hi = (uint32_t)(k & ((1ull << s) - 1));
+    return ok;
+  }
+};
+
+// Distinct keys counted, with the digit counts of their upper endpoints for
+// the degree partition's passes (bits [bit_lo, s)), in one read of S.
+__global__ __launch_bounds__(256) void k_distinct_digits(DistinctSel d, int64_t m_raw, int bit_lo, int s,
+                                                         uint32_t* __restrict__ ghist,
+                                                         unsigned long long* __restrict__ total) {
+  extern __shared__ uint32_t h_dyn[];
+  __shared__ uint32_t s_c;
+  if (threadIdx.x == 0) s_c = 0;
+  DigitCounter dc;
+  dc.init(h_dyn, bit_lo, s);  // (ends with a barrier)
+  uint32_t c = 0;
+  const uint64_t mask = (1ull << s) - 1;
+  const int64_t stride = (int64_t)gridDim.x * 256 * kDigitBatch;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * kDigitBatch + threadIdx.x; base < m_raw; base += stride) {
+    uint64_t k[kDigitBatch];
+    bool ok[kDigitBatch];
+#pragma unroll
+    for (int j = 0; j < kDigitBatch; ++j) {
+      const int64_t i = base + (int64_t)j * 256;
+      ok[j] = d(i < m_raw ? i : m_raw - 1, k[j]) & (i < m_raw);
+    }
+#pragma unroll
+    for (int j = 0; j < kDigitBatch; ++j) {
+      if (ok[j]) {
+        dc.add((uint32_t)(k[j] & mask));
+        ++c;
+      }
+    }
+  }
+  if (c) atomicAdd(&s_c, c);
+  dc.flush(ghist);  // (starts with a barrier: s_c is complete)
+  if (threadIdx.x == 0 && s_c) atomicAdd(total, (unsigned long long)s_c);
+}
 
 // Entry i of U (row a, column b) starts a task iff U_a has entries after i
 // and U_b is not empty (one bit per row); the task's key is b and its value
@@ -209,23 +250,36 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 }
 
 // deg(v) = (edges whose lower endpoint is v) + (edges whose upper endpoint is
-// v). The first term is a run length of the (lo, hi)-sorted edges (lo_ptr);
-// the upper endpoints arrive partitioned by their top bits (bucket = v >>
+// v). The upper endpoints arrive partitioned by their top bits (bucket = v >>
 // hshift; bucket j at [start(j), start(j + 1)), start(j) = bs32[j] or bs64[j]
-// for j < nbs, m beyond), and each work-group counts one range of at most
-// kDegBins vertices of one bucket in LDS, reading that bucket's entries
-// (kDegBatch loads in flight per thread before they are counted). It writes
-// the rank keys deg(v) << s | v of its vertices.
+// for j < nbs, m beyond). Each work-group counts one range [v0, v1) of at
+// most kDegBins vertices of one bucket in LDS: the upper endpoints from that
+// bucket's entries, the lower endpoints from the distinct keys of S in
+// [v0 << s, v1 << s) (S is sorted by lower endpoint; the range is found by
+// binary search), with kDegBatch loads in flight per thread before they are
+// counted. It writes the rank keys deg(v) << s | v of its vertices.
 constexpr int kDegBins = 32768;   // LDS counters of one work-group (128 KiB)
 constexpr int kDegThreads = 1024;
 constexpr int kDegBatch = 8;
 
+// First position of the sorted S[0, n) whose key is >= x.
+__device__ int64_t lower_bound_u64(const uint64_t* __restrict__ S, int64_t n, uint64_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (S[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kDegThreads) void k_degree_hist(const uint32_t* __restrict__ hi,
                                                              const uint32_t* __restrict__ bs32,
                                                              const int64_t* __restrict__ bs64, int64_t nbs, int64_t m,
-                                                             int hshift, int sub, const int64_t* __restrict__ lo_ptr,
+                                                             int hshift, int sub, DistinctSel d, int64_t m_raw,
                                                              int64_t n, int s, uint64_t* __restrict__ rk) {
   extern __shared__ uint32_t h_deg[];
+  __shared__ int64_t s_r[2];
   const uint32_t bucket = blockIdx.x / (uint32_t)sub, part = blockIdx.x % (uint32_t)sub;
   const int64_t v0 = ((int64_t)bucket << hshift) + (int64_t)part * kDegBins;
   const int64_t span_end = (int64_t)(bucket + 1) << hshift;
@@ -233,7 +287,9 @@ __global__ __launch_bounds__(kDegThreads) void k_degree_hist(const uint32_t* __r
   if (v0 >= v1) return;  // (uniform per work-group)
   const int nv = (int)(v1 - v0);
   for (int j = threadIdx.x; j < nv; j += blockDim.x) h_deg[j] = 0;
+  if (threadIdx.x < 2) s_r[threadIdx.x] = lower_bound_u64(d.S, m_raw, (uint64_t)(threadIdx.x ? v1 : v0) << s);
   __syncthreads();
+  // upper endpoints
   auto start = [&](int64_t j) -> int64_t { return j >= nbs ? m : bs64 ? bs64[j] : (int64_t)bs32[j]; };
   const int64_t e0 = start(bucket), e1 = start((int64_t)bucket + 1);
   for (int64_t base = e0 + threadIdx.x; base < e1; base += (int64_t)blockDim.x * kDegBatch) {
@@ -249,11 +305,42 @@ __global__ __launch_bounds__(kDegThreads) void k_degree_hist(const uint32_t* __r
       if (x >= v0 && x < v1) atomicAdd(&h_deg[x - v0], 1u);
     }
   }
+  // lower endpoints: the distinct keys among S[r0, r1) all have lo in [v0, v1).
+  // A wave's 64 consecutive positions hold runs of equal lo (S is sorted):
+  // the first lane of each run adds the run's distinct keys with one atomic
+  // (one atomic per lane would serialise on a high-degree vertex's counter).
+  const int64_t r0 = s_r[0], r1 = s_r[1];
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
+  // (wb, a wave's first position, is uniform across the wave: every lane
+  // takes part in the ballots; lanes past r1 read S[r1 - 1] and select nothing)
+  for (int64_t wb = r0 + (int64_t)(threadIdx.x - lane) * kDegBatch; wb < r1;
+       wb += (int64_t)blockDim.x * kDegBatch) {
+    uint64_t k[kDegBatch];
+    bool ok[kDegBatch];
+#pragma unroll
+    for (int b = 0; b < kDegBatch; ++b) {
+      const int64_t i = wb + (int64_t)b * 64 + lane;
+      ok[b] = d(i < r1 ? i : r1 - 1, k[b]) & (i < r1);
+    }
+#pragma unroll
+    for (int b = 0; b < kDegBatch; ++b) {
+      const uint32_t lo = (uint32_t)(k[b] >> s);
+      const uint32_t prev = (uint32_t)__shfl_up((int)lo, 1);
+      const uint64_t heads = __ballot(lane == 0 || prev != lo);
+      const uint64_t oks = __ballot(ok[b]);
+      if ((heads >> lane) & 1ull) {
+        const uint64_t after = heads & ~below & ~(1ull << lane);  // later heads
+        const uint64_t run = (after ? (after & (~after + 1ull)) - 1ull : ~0ull) & ~below;
+        const uint32_t c = (uint32_t)__popcll(oks & run);
+        if (c) atomicAdd(&h_deg[(int64_t)lo - v0], c);
+      }
+    }
+  }
   __syncthreads();
   for (int j = threadIdx.x; j < nv; j += blockDim.x) {
     const int64_t v = v0 + j;
-    const uint64_t d = (uint64_t)h_deg[j] + (uint64_t)(lo_ptr[v + 1] - lo_ptr[v]);
-    rk[v] = (d << s) | (uint64_t)v;
+    rk[v] = ((uint64_t)h_deg[j] << s) | (uint64_t)v;
   }
 }
 
@@ -268,63 +355,26 @@ __global__ void k_perm(const uint64_t* __restrict__ rk, int64_t n, int s, int32_
   if (r < n) perm[rk[r] & ((1ull << s) - 1)] = (int32_t)r;
 }
 
-// Orient keys (rank_lo << s | rank_hi) and, for the orient sort, the digit
-// counts of every key written.
-__global__ __launch_bounds__(256) void k_orient(const uint64_t* __restrict__ E, int64_t m, int s,
-                                                const int32_t* __restrict__ perm, uint64_t* __restrict__ okey,
-                                                uint32_t* __restrict__ hist) {
-  extern __shared__ uint32_t h_dyn[];
-  constexpr int kI = 2 * kEw;  // gathers: more in flight
-  DigitCounter dc;
-  dc.init(h_dyn, 0, 2 * s);
-  const uint64_t mask = (1ull << s) - 1;
-  for (int64_t base = (int64_t)blockIdx.x * (kT * kI); base < m; base += (int64_t)gridDim.x * (kT * kI)) {
-    const int64_t i0 = base + threadIdx.x;
-    uint64_t e[kI];
-#pragma unroll
-    for (int j = 0; j < kI; ++j) {
-      const int64_t i = i0 + (int64_t)j * kT;
-      e[j] = i < m ? E[i] : 0;
-    }
-    uint32_t ru[kI], rv[kI];
-#pragma unroll
-    for (int j = 0; j < kI; ++j) {
-      const bool in = i0 + (int64_t)j * kT < m;
-      ru[j] = in ? (uint32_t)perm[e[j] >> s] : 0u;
-      rv[j] = in ? (uint32_t)perm[e[j] & mask] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kI; ++j) {
-      const int64_t i = i0 + (int64_t)j * kT;
-      if (i < m) {
-        const uint64_t a = ru[j], b = rv[j];
-        const uint64_t k = a < b ? ((a << s) | b) : ((b << s) | a);
-        okey[i] = k;
-        dc.add(k);
-      }
-    }
-  }
-  dc.flush(hist);
-}
-
-// Column of a sorted orient key, written by the orient sort's last pass.
 // Orientation in two steps, so that no rank is read at random from the
-// whole rank map. (1) One radix pass partitions the edges by the top 8 bits
-// of their upper endpoint (the last digit pass of the degree count's
-// partition, whose scanned digit starts it reuses); its source reads E in
-// order, so the lower endpoints' ranks are read in nondecreasing vertex
+// whole rank map. (1) One radix pass partitions the distinct edges by the
+// top 8 bits of their upper endpoint (the last digit pass of the degree
+// count's partition, whose scanned digit starts it reuses); its source reads
+// S in order, so the lower endpoints' ranks are read in nondecreasing vertex
 // order: element = rank(lo) << 32 | hi. (2) k_orient_hi reads the ranks of
 // the upper endpoints bucket by bucket (a bucket spans 2^(s-8) vertices: a
 // 256 KiB slice of the rank map at s = 24, 1 MiB at s = 26, which stays in
 // L2) and writes the oriented key in place.
 struct LoRankSrc {
-  const uint64_t* E;
+  DistinctSel d;
   const int32_t* perm;
   int s;
   __device__ bool operator()(int64_t i, uint64_t& k, char&) const {
-    const uint64_t e = E[i];
-    k = ((uint64_t)(uint32_t)perm[e >> s] << 32) | (e & ((1ull << s) - 1));
-    return true;
+    uint64_t e;
+    const bool ok = d(i, e);
+    // (an unselected position may hold the sentinel, whose lower endpoint
+    // 2^s - 1 can lie past the rank map: read vertex 0 for it instead)
+    k = ((uint64_t)(uint32_t)perm[ok ? e >> s : 0] << 32) | (e & ((1ull << s) - 1));
+    return ok;
   }
 };
 
@@ -369,6 +419,7 @@ __global__ __launch_bounds__(256) void k_orient_hi(uint64_t* __restrict__ pk, in
   dc.flush(hist);
 }
 
+// Column of a sorted orient key, written by the orient sort's last pass.
 struct ColEpi {
   int32_t* col;
   int s;
@@ -790,81 +841,77 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   unsigned int* d_maxd = reinterpret_cast<unsigned int*>(dscal.as<char>() + 24);
 
   // ---- 1-2: simple graph -------------------------------------------------
+  // The canonical keys are sorted (duplicates adjacent, self loops as the
+  // sentinel, which sorts last) into S; the distinct keys are never written
+  // out: the degree count, its partition and the orientation select them
+  // from S (DistinctSel). The other sort buffer later holds the oriented
+  // keys, and S's buffer is the orient sort's ping-pong partner.
   int64_t m = 0;
-  DevBuf E, Ehi;  // distinct keys (lo << s | hi) and their upper endpoints
+  DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
+  DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
+  bool salt = false;  // S is in kb
+  // degree partition: one radix pass (8 bits) up to s = 24 (a bucket then
+  // spans at most 2 LDS ranges, each reading the bucket's entries), two
+  // beyond; dh: its digit counts, which the sort scans into digit starts
+  // (the bucket starts of the degree count; the last pass's are reused by
+  // the orientation's partition)
+  const int hshift = s <= 8 ? 0 : s <= 24 ? s - 8 : s - 16;
+  const int hpasses = digit_passes(hshift, s);
+  DevBuf dh(sizeof(uint32_t) * 256 * 2 + sizeof(unsigned long long));
+  unsigned long long* d_m = reinterpret_cast<unsigned long long*>(dh.as<uint32_t>() + 256 * 2);
+  TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
   {
-    DevBuf ka(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
-    DevBuf kb(sizeof(uint64_t) * (size_t)std::max<int64_t>(m_raw, 1));
     // canonical keys are built by the first pass of the dedup sort from the
     // raw pairs (7168-pair tiles: the largest whose registers allow two
     // waves per SIMD); one read of the pairs before it counts their digits
     // and checks the ids
     const CanonSrc csrc{d_src, d_dst, n, s, sent};
-    DevBuf dh(sizeof(uint32_t) * 256 * kSortPassesMax);
-    bool alt = false;
+    DevBuf ch(sizeof(uint32_t) * 256 * kSortPassesMax);
     if (m_raw > 0) {
-      TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
+      TC_HIP(hipMemsetAsync(ch.p, 0, ch.bytes, st));
       TC_LAUNCH("canon_digits", k_canon_digits,
                 dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
-                digit_lds_bytes(0, 2 * s), st, csrc, m_raw, 2 * s, dh.as<uint32_t>(), d_err);
+                digit_lds_bytes(0, 2 * s), st, csrc, m_raw, 2 * s, ch.as<uint32_t>(), d_err);
       TC_HIP(hipGetLastError());
-      alt = radix_sort_from<uint64_t, NoVal, CanonSrc, 28>(csrc, m_raw, ka.as<uint64_t>(), kb.as<uint64_t>(),
-                                                           nullptr, nullptr, m_raw, 0, 2 * s, dh.as<uint32_t>(),
-                                                           st, "dedup");
+      salt = radix_sort_from<uint64_t, NoVal, CanonSrc, 28>(csrc, m_raw, ka.as<uint64_t>(), kb.as<uint64_t>(),
+                                                            nullptr, nullptr, m_raw, 0, 2 * s, ch.as<uint32_t>(),
+                                                            st, "dedup");
+      // distinct keys counted, with their upper endpoints' partition digits
+      TC_LAUNCH("distinct_digits", k_distinct_digits,
+                dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
+                digit_lds_bytes(hshift, s), st, DistinctSel{salt ? kb.as<uint64_t>() : ka.as<uint64_t>(), sent},
+                m_raw, hshift, s, dh.as<uint32_t>(), d_m);
+      TC_HIP(hipGetLastError());
     }
-    // the id check is read back with the dedup count (one host sync for both)
+    // the id check and the distinct count: one host sync for both
     int h_err = 0;
+    unsigned long long h_m = 0;
     TC_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    const uint64_t* sorted = alt ? kb.as<uint64_t>() : ka.as<uint64_t>();
-    UniquePred up{sorted, sent, s, nullptr, nullptr};
-    if (m_raw == 0) TC_HIP(hipStreamSynchronize(st));  // (compact has no sync then)
-    m = compact("dedup", m_raw, up, [&](int64_t total, UniquePred& p) {
-      TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
-      TC_REQUIRE(total <= kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 64 or more edges");
-      E.alloc(sizeof(uint64_t) * (size_t)total);
-      Ehi.alloc(sizeof(uint32_t) * (size_t)total);
-      p.out = E.as<uint64_t>();
-      p.out_hi = Ehi.as<uint32_t>();
-    }, st);
+    TC_HIP(hipMemcpyAsync(&h_m, d_m, sizeof(h_m), hipMemcpyDeviceToHost, st));
+    TC_HIP(hipStreamSynchronize(st));
     TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
-    if (m == 0) E.alloc(sizeof(uint64_t));
+    TC_REQUIRE(h_m <= (unsigned long long)kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 64 or more edges");
+    m = (int64_t)h_m;
   }
   g->m = m;
+  DevBuf& sbuf = salt ? kb : ka;     // S
+  DevBuf& obuf = salt ? ka : kb;     // free: the oriented keys go here
+  const DistinctSel dsel{sbuf.as<uint64_t>(), sent};
 
   // ---- 3: degree order ---------------------------------------------------
   g->perm = g->owned.alloc<int32_t>(n);
-  // exclusive starts of the last digit pass (top 8 bits of hi) of the degree
-  // count's partition: the orientation's partition pass reuses them
-  DevBuf hi_starts;
+  const uint32_t* hi_starts = dh.as<uint32_t>() + 256 * (hpasses - 1);  // valid once m > 0
   {
     DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
     if (m > 0) {
-      // E is sorted by (lo, hi): lower-endpoint counts are run lengths; upper
-      // endpoints are partitioned by one radix pass over their top 8 bits and
-      // counted per bucket in LDS (k_degree_hist, which writes the rank keys)
-      DevBuf lo_ptr(sizeof(int64_t) * (size_t)(n + 1));
-      TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, E.as<uint64_t>(),
-                         m, s, n, lo_ptr.as<int64_t>());
-      // one radix pass (8 bits) up to s = 24 (a bucket then spans at most 2
-      // LDS ranges, each reading the bucket's entries), two beyond; the
-      // pass's digit counts, scanned by the sort, are the bucket starts
-      const int hshift = s <= 8 ? 0 : s <= 24 ? s - 8 : s - 16;
-      DevBuf hb(sizeof(uint32_t) * (size_t)m);
-      DevBuf dh(sizeof(uint32_t) * 256 * 2);
-      TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
-      if (m > 1) {
-        TC_LAUNCH("rs_digits:degree", (k_rs_digits<uint32_t>),
-                  dim3((unsigned)std::min<int64_t>(2048, div_up(m, 256 * 16))), dim3(256),
-                  digit_lds_bytes(hshift, s), st, Ehi.as<uint32_t>(), m, hshift, s, dh.as<uint32_t>());
-      }
-      bool halt = radix_sort<uint32_t, NoVal>(Ehi.as<uint32_t>(), hb.as<uint32_t>(), nullptr, nullptr, m,
-                                              hshift, s, st, "degree", NoEpi{}, dh.as<uint32_t>());
-      const int passes = digit_passes(hshift, s);
-      if (m > 1) {
-        hi_starts.alloc(sizeof(uint32_t) * 256);
-        TC_HIP(hipMemcpyAsync(hi_starts.p, dh.as<uint32_t>() + 256 * (passes - 1), sizeof(uint32_t) * 256,
-                              hipMemcpyDeviceToDevice, st));
-      }
+      // upper endpoints partitioned by their top bits (read from S through
+      // the distinct keys) and counted per bucket in LDS with the lower
+      // endpoints (k_degree_hist, which writes the rank keys)
+      DevBuf hb(sizeof(uint32_t) * (size_t)m), hb2(hpasses > 1 ? sizeof(uint32_t) * (size_t)m : 0);
+      const bool halt = radix_sort_from<uint32_t, NoVal>(DistinctHiSrc{dsel, s}, m_raw, hb.as<uint32_t>(),
+                                                         hb2.as<uint32_t>(), nullptr, nullptr, m, hshift, s,
+                                                         dh.as<uint32_t>(), st, "degree");
+      const uint32_t* hsorted = halt ? hb2.as<uint32_t>() : hb.as<uint32_t>();
       const int64_t span = (int64_t)1 << hshift;  // vertices per bucket
       const int sub = (int)div_up(span, kDegBins);
       const int64_t nbuckets = div_up(n, span);
@@ -881,21 +928,20 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
           done.insert(g->device);
         }
       }
-      // bucket starts: with one digit pass, its counts as the sort scanned
-      // them (256 exclusive starts); else found by binary search
+      // bucket starts: with one digit pass, its digit starts as the sort
+      // scanned them (256 exclusive starts); else found by binary search
       DevBuf bp;
       const uint32_t* bs32 = dh.as<uint32_t>();
       int64_t nbs = 256;
-      if (passes != 1 || m <= 1) {
+      if (hpasses != 1) {
         bp.alloc(sizeof(int64_t) * (size_t)(nbuckets + 1));
-        TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nbuckets + 1)), dim3(kT), 0, st,
-                  halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), m, hshift, nbuckets, bp.as<int64_t>());
+        TC_LAUNCH("bounds", (k_bounds<uint32_t>), dim3(grid_for(nbuckets + 1)), dim3(kT), 0, st, hsorted, m,
+                  hshift, nbuckets, bp.as<int64_t>());
         bs32 = nullptr;
         nbs = nbuckets + 1;
       }
-      TC_LAUNCH("degree_hist", k_degree_hist, dim3((unsigned)groups), dim3(kDegThreads), lds, st,
-                halt ? hb.as<uint32_t>() : Ehi.as<uint32_t>(), bs32, bs32 ? nullptr : bp.as<int64_t>(), nbs, m,
-                hshift, sub, lo_ptr.as<int64_t>(), n, s, ra.as<uint64_t>());
+      TC_LAUNCH("degree_hist", k_degree_hist, dim3((unsigned)groups), dim3(kDegThreads), lds, st, hsorted, bs32,
+                bs32 ? nullptr : bp.as<int64_t>(), nbs, m, hshift, sub, dsel, m_raw, n, s, ra.as<uint64_t>());
       TC_HIP(hipGetLastError());
     } else {
       DevBuf deg(sizeof(uint32_t) * (size_t)n);
@@ -911,42 +957,32 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     TC_HIP(hipGetLastError());
   }
 
-  Ehi.release();
-
   // ---- 4: orient, U in CSR -------------------------------------------------
   g->row_ptr = g->owned.alloc<int64_t>(n + 1);
   g->col = g->owned.alloc<int32_t>(m);
-  DevBuf ok(sizeof(uint64_t) * (size_t)std::max<int64_t>(m, 1));
-  const uint64_t* okey = ok.as<uint64_t>();
+  const uint64_t* okey = obuf.as<uint64_t>();
   {
     if (m > 0) {
       DevBuf ohist(sizeof(uint32_t) * 256 * kSortPassesMax);  // digit counts, from the orientation
       TC_HIP(hipMemsetAsync(ohist.p, 0, ohist.bytes, st));
-      if (m > 1) {
-        // partition by the top 8 bits of hi (one pass, into ok), then the
-        // oriented keys in place
-        const LoRankSrc lsrc{E.as<uint64_t>(), g->perm, s};
-        // (28 edges per thread, as the canonicalising pass: a source that
-        // loads twice per element needs the registers)
-        const bool palt = radix_sort_from<uint64_t, NoVal, LoRankSrc, 28>(
-            lsrc, m, ok.as<uint64_t>(), nullptr, nullptr, nullptr, m, s > 8 ? s - 8 : 0, s,
-            hi_starts.as<uint32_t>(), st, "orient_part", NoEpi{}, true);
-        TC_REQUIRE(!palt, TC_EDEVICE, "tc_preprocess: the orientation partition is one pass");
-        const int64_t og = std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw));
-        TC_LAUNCH("orient", k_orient_hi, dim3((unsigned)(div_up(og, 8) * 8)), dim3(kT), digit_lds_bytes(0, 2 * s),
-                  st, ok.as<uint64_t>(), m, s, g->perm, ohist.as<uint32_t>());
-      } else {
-        TC_LAUNCH("orient", k_orient, dim3(1), dim3(kT), digit_lds_bytes(0, 2 * s), st, E.as<uint64_t>(), m, s,
-                  g->perm, ok.as<uint64_t>(), ohist.as<uint32_t>());
-      }
+      // partition by the top 8 bits of hi (one pass from S into the free
+      // buffer), then the oriented keys in place
+      // (28 edges per thread, as the canonicalising pass: a source that
+      // loads twice per element needs the registers)
+      const bool palt = radix_sort_from<uint64_t, NoVal, LoRankSrc, 28>(
+          LoRankSrc{dsel, g->perm, s}, m_raw, obuf.as<uint64_t>(), nullptr, nullptr, nullptr, m,
+          s > 8 ? s - 8 : 0, s, const_cast<uint32_t*>(hi_starts), st, "orient_part", NoEpi{}, true);
+      TC_REQUIRE(!palt, TC_EDEVICE, "tc_preprocess: the orientation partition is one pass");
+      const int64_t og = std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw));
+      TC_LAUNCH("orient", k_orient_hi, dim3((unsigned)(div_up(og, 8) * 8)), dim3(kT), digit_lds_bytes(0, 2 * s),
+                st, obuf.as<uint64_t>(), m, s, g->perm, ohist.as<uint32_t>());
       TC_HIP(hipGetLastError());
-      hi_starts.release();
-      // E's buffer is the ping-pong partner
-      // (the last pass also writes each key's column: U's col array)
-      bool alt = radix_sort<uint64_t, NoVal, ColEpi>(ok.as<uint64_t>(), E.as<uint64_t>(), nullptr, nullptr, m,
-                                                     0, 2 * s, st, "orient", ColEpi{g->col, s},
+      // S's buffer is the ping-pong partner (S is not read after the
+      // partition); the last pass also writes each key's column: U's col
+      bool alt = radix_sort<uint64_t, NoVal, ColEpi>(obuf.as<uint64_t>(), sbuf.as<uint64_t>(), nullptr, nullptr,
+                                                     m, 0, 2 * s, st, "orient", ColEpi{g->col, s},
                                                      ohist.as<uint32_t>());
-      if (alt) okey = E.as<uint64_t>();
+      if (alt) okey = sbuf.as<uint64_t>();
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
       if (m == 1)  // no sort pass ran
@@ -959,6 +995,9 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
               d_maxd);
     TC_HIP(hipGetLastError());
   }
+  dh.release();
+  // the buffer that does not hold the oriented keys is free now
+  (okey == sbuf.as<uint64_t>() ? obuf : sbuf).release();
   // read back with the task count below (one host sync)
   unsigned long long h_wplus = 0;
   unsigned int h_maxd = 0;
@@ -1008,8 +1047,8 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     g->wedges_plus = (int64_t)h_wplus;
     g->max_dplus = (int64_t)h_maxd;
   }
-  E.release();
-  ok.release();
+  ka.release();
+  kb.release();
 
   // ---- 6: work classes ------------------------------------------------------
   build_work(g->w, g->owned, n, g->row_ptr, tl.T, tl.row.as<uint32_t>(), tl.ptr.as<int64_t>(),
