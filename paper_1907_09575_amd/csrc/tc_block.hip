@@ -44,17 +44,49 @@ __global__ void k_local_deg(const int64_t* __restrict__ row_ptr, int64_t nloc, i
   deg[lv] = (uint32_t)(row_ptr[v + 1] - row_ptr[v]);
 }
 
-// Copy of the local rows, one wave per row (coalesced runs).
+// Copy of the local rows, four per wave: rows of at most 64 entries are
+// copied by 16 lanes each (rows here hold ~16 entries on average, so a wave
+// per row would leave most lanes idle), longer rows then one after another
+// by the whole wave. With erow, it also writes each entry's local row.
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) {
+  const int lo = __shfl((int)(uint32_t)v, src, 64), hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __global__ __launch_bounds__(256) void k_gather_rows(const int64_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col, int64_t nloc,
                                                      int32_t q, int32_t r,
                                                      const int64_t* __restrict__ lrow_ptr,
-                                                     int32_t* __restrict__ lcol) {
-  const int64_t lv = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (lv >= nloc) return;
-  const int64_t v = lv * q + r;
-  const int64_t s = row_ptr[v], d = row_ptr[v + 1] - s, o = lrow_ptr[lv];
-  for (int64_t i = threadIdx.x & 63; i < d; i += 64) lcol[o + i] = col[s + i];
+                                                     int32_t* __restrict__ lcol, uint32_t* __restrict__ erow) {
+  const int lane = lane_id(), grp = lane >> 4, sub = lane & 15;
+  const int64_t lv0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 4;
+  if (lv0 >= nloc) return;  // (uniform per wave; no barrier follows)
+  const int64_t lv = lv0 + grp;
+  int64_t s0 = 0, len = 0, o = 0;
+  if (lv < nloc) {
+    const int64_t v = lv * q + r;
+    s0 = row_ptr[v];
+    len = row_ptr[v + 1] - s0;
+    o = lrow_ptr[lv];
+  }
+  if (len <= 64) {
+    for (int64_t i = sub; i < len; i += 16) {
+      lcol[o + i] = col[s0 + i];
+      if (erow) erow[o + i] = (uint32_t)lv;
+    }
+  }
+  // long rows (lane 16 g stands for group g), by the whole wave
+  uint64_t longs = __ballot(len > 64 && sub == 0);
+  while (longs) {
+    const int src = __ffsll((long long)longs) - 1;
+    longs &= longs - 1;
+    const int64_t ls = shfl_i64(s0, src), ll = shfl_i64(len, src), lo = shfl_i64(o, src);
+    const uint32_t lrow = (uint32_t)(lv0 + (src >> 4));
+    for (int64_t i = lane; i < ll; i += 64) {
+      lcol[lo + i] = col[ls + i];
+      if (erow) erow[lo + i] = lrow;
+    }
+  }
 }
 
 // Entry p of local probe row a (= erow[p]) holding b starts a task iff
@@ -94,7 +126,8 @@ struct LocalRows {
   DevBuf col;      // int32 [nnz], global ids
 };
 
-void gather_local(LocalRows& L, const Graph& g, int32_t q, int32_t r, hipStream_t st) {
+// Row pointers of the local rows of residue r (their total at [nloc]).
+void local_ptrs(LocalRows& L, const Graph& g, int32_t q, int32_t r, hipStream_t st) {
   L.nloc = residue_rows(g.n, q, r);
   L.row_ptr.alloc(sizeof(int64_t) * (size_t)(L.nloc + 1));
   int64_t* lp = L.row_ptr.as<int64_t>();
@@ -108,12 +141,34 @@ void gather_local(LocalRows& L, const Graph& g, int32_t q, int32_t r, hipStream_
   device_excl_scan<uint32_t, uint64_t>(deg.as<uint32_t>(), reinterpret_cast<uint64_t*>(lp), L.nloc,
                                        reinterpret_cast<uint64_t*>(lp) + L.nloc, st);
   TC_HIP(hipGetLastError());
-  L.nnz = read_dev(lp + L.nloc, st);
+}
+
+// Columns of the local rows (L.nnz known), with each entry's local row in
+// erow if given (erow->alloc'd here).
+void local_gather(LocalRows& L, const Graph& g, int32_t q, int32_t r, DevBuf* erow, hipStream_t st) {
   L.col.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(L.nnz, 1));
+  if (erow) erow->alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(L.nnz, 1));
   if (L.nnz > 0)
-    TC_LAUNCH("block_gather", k_gather_rows, dim3((unsigned)div_up(L.nloc, kBT / 64)), dim3(kBT), 0, st,
-              g.row_ptr, g.col, L.nloc, q, r, lp, L.col.as<int32_t>());
+    TC_LAUNCH("block_gather", k_gather_rows, dim3((unsigned)div_up(L.nloc, 4 * (kBT / 64))), dim3(kBT), 0, st,
+              g.row_ptr, g.col, L.nloc, q, r, L.row_ptr.as<int64_t>(), L.col.as<int32_t>(),
+              erow ? erow->as<uint32_t>() : nullptr);
   TC_HIP(hipGetLastError());
+}
+
+// The rank's hashed rows H (residue x) and probe rows P (residue y), with
+// one host synchronisation for both sizes; erow_p: P's entry rows.
+void gather_pair(LocalRows& H, LocalRows& P, const Graph& g, int32_t q, int32_t x, int32_t y, DevBuf* erow_p,
+                 hipStream_t st) {
+  local_ptrs(H, g, q, x, st);
+  local_ptrs(P, g, q, y, st);
+  int64_t h[2] = {0, 0};
+  TC_HIP(hipMemcpyAsync(&h[0], H.row_ptr.as<int64_t>() + H.nloc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipMemcpyAsync(&h[1], P.row_ptr.as<int64_t>() + P.nloc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TC_HIP(hipStreamSynchronize(st));
+  H.nnz = h[0];
+  P.nnz = h[1];
+  local_gather(H, g, q, x, nullptr, st);
+  local_gather(P, g, q, y, erow_p, st);
 }
 
 }  // namespace
@@ -123,17 +178,14 @@ void block_count(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_cou
   TempStream temps(st);
   Owned own;
   own.st = st;
-  LocalRows H, P;
-  gather_local(H, g, q, x, st);  // hash side: rows j == x
-  gather_local(P, g, q, y, st);  // probe side: rows i == y
+  LocalRows H, P;  // hash side: rows j == x; probe side: rows i == y
+  DevBuf erow;      // local row of each probe-side entry
+  gather_pair(H, P, g, q, x, y, &erow, st);
   TC_REQUIRE(P.nnz <= kMaxBufferEdges, TC_EOVERFLOW, "tc_block_count: a rank's probe side of 2^30 entries or more");
 
   int64_t T = 0;
   TaskLists tl;
   if (P.nnz > 0 && H.nnz > 0) {
-    DevBuf erow(sizeof(uint32_t) * (size_t)P.nnz);
-    TC_LAUNCH("block_entry_rows", k_entry_rows, dim3((unsigned)div_up(P.nloc, kBT / 64)), dim3(kBT), 0,
-              st, P.row_ptr.as<int64_t>(), P.nloc, erow.as<uint32_t>());
     DevBuf tk, tv;
     BlockTaskPred bp{P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), H.row_ptr.as<int64_t>(),
                      H.nloc, q, x, nullptr, nullptr};
@@ -239,13 +291,10 @@ void block_stats(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_out
   auto* out = reinterpret_cast<unsigned long long*>(d_out);
   TC_LAUNCH("zero_stats", k_zero_n, dim3(1), dim3(192), 0, st, out, 2 + 2 * q);
   LocalRows H, P;
-  gather_local(H, g, q, x, st);
-  gather_local(P, g, q, y, st);
-  note_use(g, st);  // (the extraction synchronised st; later kernels read only local copies)
+  DevBuf erow;
+  gather_pair(H, P, g, q, x, y, &erow, st);
+  note_use(g, st);  // (later kernels read only the local copies)
   if (P.nnz == 0 || H.nnz == 0) return;
-  DevBuf erow(sizeof(uint32_t) * (size_t)P.nnz);
-  TC_LAUNCH("block_entry_rows", k_entry_rows, dim3((unsigned)div_up(P.nloc, kBT / 64)), dim3(kBT), 0, st,
-            P.row_ptr.as<int64_t>(), P.nloc, erow.as<uint32_t>());
   DevBuf tk, tv;
   BlockTaskPred bp{P.col.as<int32_t>(), erow.as<uint32_t>(), P.row_ptr.as<int64_t>(), H.row_ptr.as<int64_t>(),
                    H.nloc, q, x, nullptr, nullptr};
