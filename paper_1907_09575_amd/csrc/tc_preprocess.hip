@@ -99,15 +99,19 @@ __global__ __launch_bounds__(256) void k_canon_digits(CanonSrc cs, int64_t m, in
 // Distinct keys of the sorted canonical keys S (duplicates adjacent, the
 // sentinel for dropped self loops last): position i holds one iff S[i] is
 // not the sentinel and differs from S[i - 1]. The distinct keys are never
-// written out; the degree count, its partition and the orientation select
-// them from S. (Evaluated without branches around the loads.)
+// written out. k_distinct_mark finds them by comparing neighbours and marks
+// every other key with bit 63 (keys take at most 62 bits: s <= 31); later
+// readers (the degree count, its partition and the orientation) then select
+// a key by its own word alone (DistinctSel) and mask the mark off where
+// they use an unselected key's bits.
+constexpr uint64_t kDupMark = 1ull << 63;
+
 struct DistinctSel {
   const uint64_t* S;
   uint64_t sent;
   __device__ bool operator()(int64_t i, uint64_t& k) const {
     k = S[i];
-    const uint64_t prev = S[i > 0 ? i - 1 : 0];
-    return (k != sent) & ((i == 0) | (prev != k));
+    return ((k & kDupMark) == 0) & (k != sent);
   }
 };
 
@@ -123,11 +127,13 @@ struct DistinctHiSrc {
   }
 };
 
-// Distinct keys counted, with the digit counts of their upper endpoints for
-// the degree partition's passes (bits [bit_lo, s)), in one read of S.
-__global__ __launch_bounds__(256) void k_distinct_digits(DistinctSel d, int64_t m_raw, int bit_lo, int s,
-                                                         uint32_t* __restrict__ ghist,
-                                                         unsigned long long* __restrict__ total) {
+// Distinct keys of S marked (see above) and counted, with the digit counts
+// of their upper endpoints for the degree partition's passes (bits
+// [bit_lo, s)), in one read of S. A neighbour may have marked S[i - 1]
+// already: keys are compared with the mark masked off.
+__global__ __launch_bounds__(256) void k_distinct_mark(uint64_t* __restrict__ S, uint64_t sent, int64_t m_raw,
+                                                       int bit_lo, int s, uint32_t* __restrict__ ghist,
+                                                       unsigned long long* __restrict__ total) {
   extern __shared__ uint32_t h_dyn[];
   __shared__ uint32_t s_c;
   if (threadIdx.x == 0) s_c = 0;
@@ -137,18 +143,23 @@ __global__ __launch_bounds__(256) void k_distinct_digits(DistinctSel d, int64_t 
   const uint64_t mask = (1ull << s) - 1;
   const int64_t stride = (int64_t)gridDim.x * 256 * kDigitBatch;
   for (int64_t base = (int64_t)blockIdx.x * 256 * kDigitBatch + threadIdx.x; base < m_raw; base += stride) {
-    uint64_t k[kDigitBatch];
-    bool ok[kDigitBatch];
+    uint64_t k[kDigitBatch], prev[kDigitBatch];
 #pragma unroll
     for (int j = 0; j < kDigitBatch; ++j) {
       const int64_t i = base + (int64_t)j * 256;
-      ok[j] = d(i < m_raw ? i : m_raw - 1, k[j]) & (i < m_raw);
+      const int64_t ic = i < m_raw ? i : m_raw - 1;
+      k[j] = S[ic];
+      prev[j] = S[ic > 0 ? ic - 1 : 0];
     }
 #pragma unroll
     for (int j = 0; j < kDigitBatch; ++j) {
-      if (ok[j]) {
+      const int64_t i = base + (int64_t)j * 256;
+      if (i >= m_raw) break;
+      if (k[j] != sent && (i == 0 || (prev[j] & ~kDupMark) != k[j])) {
         dc.add((uint32_t)(k[j] & mask));
         ++c;
+      } else if (k[j] != sent) {
+        S[i] = k[j] | kDupMark;
       }
     }
   }
@@ -262,12 +273,13 @@ constexpr int kDegBins = 32768;   // LDS counters of one work-group (128 KiB)
 constexpr int kDegThreads = 1024;
 constexpr int kDegBatch = 8;
 
-// First position of the sorted S[0, n) whose key is >= x.
+// First position of the sorted S[0, n) whose key (duplicate mark masked
+// off) is >= x.
 __device__ int64_t lower_bound_u64(const uint64_t* __restrict__ S, int64_t n, uint64_t x) {
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (S[mid] < x) lo = mid + 1;
+    if ((S[mid] & ~kDupMark) < x) lo = mid + 1;
     else hi = mid;
   }
   return lo;
@@ -325,7 +337,7 @@ __global__ __launch_bounds__(kDegThreads) void k_degree_hist(const uint32_t* __r
     }
 #pragma unroll
     for (int b = 0; b < kDegBatch; ++b) {
-      const uint32_t lo = (uint32_t)(k[b] >> s);
+      const uint32_t lo = (uint32_t)((k[b] & ~kDupMark) >> s);
       const uint32_t prev = (uint32_t)__shfl_up((int)lo, 1);
       const uint64_t heads = __ballot(lane == 0 || prev != lo);
       const uint64_t oks = __ballot(ok[b]);
@@ -876,11 +888,12 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       salt = radix_sort_from<uint64_t, NoVal, CanonSrc, 28>(csrc, m_raw, ka.as<uint64_t>(), kb.as<uint64_t>(),
                                                             nullptr, nullptr, m_raw, 0, 2 * s, ch.as<uint32_t>(),
                                                             st, "dedup");
-      // distinct keys counted, with their upper endpoints' partition digits
-      TC_LAUNCH("distinct_digits", k_distinct_digits,
+      // duplicates marked, distinct keys counted, with their upper
+      // endpoints' partition digits
+      TC_LAUNCH("distinct_mark", k_distinct_mark,
                 dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
-                digit_lds_bytes(hshift, s), st, DistinctSel{salt ? kb.as<uint64_t>() : ka.as<uint64_t>(), sent},
-                m_raw, hshift, s, dh.as<uint32_t>(), d_m);
+                digit_lds_bytes(hshift, s), st, salt ? kb.as<uint64_t>() : ka.as<uint64_t>(), sent, m_raw, hshift,
+                s, dh.as<uint32_t>(), d_m);
       TC_HIP(hipGetLastError());
     }
     // the id check and the distinct count: one host sync for both
