@@ -80,8 +80,8 @@ typedef struct {
  * Vertices are ranked by non-decreasing degree, ties by original id (the
  * counting-sort relabelling of Section 5.3 with a fixed tie order); each edge
  * {u, v} becomes the nonzero (min rank, max rank) of U (the upper/lower split
- * of Section 5.3 by global position); rows of U are sorted ascending (required
- * by Section 5.2, "Eliminating unnecessary intersection operations").
+ * of Section 5.3 by global position); rows of U are sorted ascending (which
+ * Section 5.2's pruning of needless intersections relies on).
  *
  * Output: *out receives a new handle (free with tc_graph_free). The handle
  * owns its device memory. The call synchronises `stream` once it has read
@@ -113,8 +113,8 @@ tc_status tc_graph_export(const tc_graph* g, int64_t* d_row_ptr, int32_t* d_col,
  * tc_count - exact number of triangles, T of Eq. 2, written to the device
  * int64 *d_count. Runs the <j,i,k> map-based intersection of Section 3.1: for
  * every row j of U that some task needs, U_j is hashed in LDS (direct
- * low-bit addressing with linear probing, Section 5.2 "Modifying the hashing
- * routine"), and for each nonzero (i, j) the entries of U_i after j are looked
+ * low-bit addressing with linear probing: Section 5.2's change to the
+ * hashing routine), and for each nonzero (i, j) the entries of U_i after j are looked
  * up in it. Asynchronous on `stream`; allocates nothing.
  */
 tc_status tc_count(const tc_graph* g, int64_t* d_count, void* stream);
@@ -157,8 +157,8 @@ enum {
   TC_VARIANT_NO_DCSR = 2,  /* no doubly sparse traversal (Section 5.2): every hashed row is
                               visited, also rows without work, and intersections whose hashed
                               list is empty are kept */
-  TC_VARIANT_MUL_HASH = 4  /* no direct-AND addressing (Section 5.2, "Modifying the hashing
-                              routine"): every table is addressed by a multiplicative hash
+  TC_VARIANT_MUL_HASH = 4  /* no direct-AND addressing (Section 5.2's hashing
+                              change undone): every table is addressed by a multiplicative hash
                               (top bits of k * 0x9E3779B1) with linear probing */
 };
 

@@ -18,10 +18,10 @@
  *                     non-decreasing degree"): rank = position after sorting by
  *                     degree; ties broken by original id (the paper leaves the
  *                     tie order open; any total order gives the same count).
- *   oc_build_upper    Section 5.3 ("Create the upper and the lower triangular
- *                     portion"): each edge goes to the row of its lower-ranked
- *                     endpoint, rows sorted ascending (Section 5.2, "Eliminating
- *                     unnecessary intersection operations", requires sorted rows).
+ *   oc_build_upper    Section 5.3 (the split into upper and lower triangular
+ *                     parts): each edge goes to the row of its lower-ranked
+ *                     endpoint, rows sorted ascending (Section 5.2's pruning of
+ *                     needless intersections relies on sorted rows).
  *   oc_count          Eq. 1 and Eq. 2: c(i,j) = |Adj>(i) & Adj>(j)| for every
  *                     nonzero (i,j) of U, T = sum c(i,j). The intersection uses
  *                     the list-based method of Section 3.1 (a joint traversal of

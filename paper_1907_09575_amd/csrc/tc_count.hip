@@ -8,7 +8,7 @@
 // range of the global probe index space (tasks grouped by b, prefix-summed by
 // preprocessing).
 //
-// Hash table (Section 5.2, "Modifying the hashing routine"): U_b in LDS in
+// Hash table (Section 5.2's change to the hashing routine): U_b in LDS in
 // buckets of four 32-bit slots, bucket = k & (buckets - 1) (the direct bitwise
 // AND of the paper), at least 4 |U_b| slots (2 |U_b| for rows of more than
 // 2048 keys). A key goes to the first free slot of its bucket or, if the
