@@ -400,13 +400,13 @@ __device__ __forceinline__ uint64_t rs_peers(uint32_t d, bool valid) {
   return peers;
 }
 
-// Digit counts of every pass in one read of the keys. Each thread loads 8
+// Digit counts of every pass in one read of the keys. Each thread loads 16
 // keys before counting them (memory parallelism), and the work-group keeps 8
 // copies of each histogram, lane l counting into copy l % 8, so that the many
 // equal digits of skewed keys (the high bits of power-law vertex ids) do not
 // serialise on one LDS word. Dynamic LDS: passes * 256 * 8 words.
 constexpr int kDigitCopies = 8;
-constexpr int kDigitBatch = 8;
+constexpr int kDigitBatch = 16;
 
 template <class K>
 __global__ __launch_bounds__(256) void k_rs_digits(const K* __restrict__ kin, int64_t n, int bit_lo,
