@@ -89,7 +89,7 @@ typedef struct {
  *
  * Errors: TC_EINVAL for null pointers, n < 1, m_raw < 0 or an id outside
  * [0, n) (no handle is returned); TC_EOVERFLOW if m_raw >= 2^32 - 1 or the
- * simple graph has 2^32 - 64 or more edges (positions in U are 32-bit);
+ * simple graph has 2^32 - 256 or more edges (positions in U are 32-bit);
  * TC_ENOMEM / TC_EDEVICE on allocation or runtime failure. Graphs of 2^30
  * edges or more are counted with 64-bit probe addresses; batch plans and one
  * rank's block take probe sides below 2^30 entries (TC_EOVERFLOW otherwise).

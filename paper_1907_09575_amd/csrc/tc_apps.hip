@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kAT = 256;
 inline unsigned grid_threads(int64_t n) { return (unsigned)std::max<int64_t>(1, div_up(n, kAT)); }
-inline unsigned grid_waves(int64_t n) { return (unsigned)std::max<int64_t>(1, div_up(n, kAT / 64)); }
+inline unsigned grid_waves(int64_t n) { return wave_grid(n); }  // (one wave per item, grid-stride)
 
 // ---- lower adjacency ---------------------------------------------------------
 
@@ -102,14 +102,15 @@ __global__ __launch_bounds__(256) void k_vertex_tri(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ leid,
                                                     const int32_t* __restrict__ sup, int64_t n,
                                                     int64_t* __restrict__ t_rank) {
-  const int64_t v = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (v >= n) return;
   const int lane = lane_id();
-  uint64_t s = 0;
-  for (int64_t p = row_ptr[v] + lane; p < row_ptr[v + 1]; p += 64) s += (uint32_t)sup[p];
-  for (int64_t i = lptr[v] + lane; i < lptr[v + 1]; i += 64) s += (uint32_t)sup[leid[i]];
-  s = wave_sum(s);
-  if (lane == 0) t_rank[v] = (int64_t)(s / 2);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += stride) {
+    uint64_t s = 0;
+    for (int64_t p = row_ptr[v] + lane; p < row_ptr[v + 1]; p += 64) s += (uint32_t)sup[p];
+    for (int64_t i = lptr[v] + lane; i < lptr[v + 1]; i += 64) s += (uint32_t)sup[leid[i]];
+    s = wave_sum(s);
+    if (lane == 0) t_rank[v] = (int64_t)(s / 2);
+  }
 }
 
 // Per original vertex u (rank r = perm[u]): t, the local clustering
@@ -234,11 +235,9 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* __restrict__ a, in
 // other's (binary search in its L or U part); each triangle (e, e1, e2) still
 // whole before this round, and whose removed edge of smallest id is e, takes
 // one from the support of each of e1, e2 still alive.
-__global__ __launch_bounds__(256) void k_truss_peel(FullAdj A, const uint32_t* __restrict__ erow,
-                                                    const int32_t* __restrict__ F, int64_t nF, int32_t round,
-                                                    const int32_t* __restrict__ state, int32_t* __restrict__ sup) {
-  const int64_t f = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (f >= nF) return;
+__device__ void truss_peel_one(const FullAdj& A, const uint32_t* __restrict__ erow,
+                               const int32_t* __restrict__ F, int64_t f, int32_t round,
+                               const int32_t* __restrict__ state, int32_t* __restrict__ sup) {
   const int lane = lane_id();
   const int32_t e = F[f];
   const int32_t a = (int32_t)erow[e], b = A.col[e];
@@ -272,6 +271,14 @@ __global__ __launch_bounds__(256) void k_truss_peel(FullAdj A, const uint32_t* _
     if (s1 == kAlive) atomicSub(&sup[e1], 1);
     if (s2 == kAlive) atomicSub(&sup[e2], 1);
   }
+}
+
+__global__ __launch_bounds__(256) void k_truss_peel(FullAdj A, const uint32_t* __restrict__ erow,
+                                                    const int32_t* __restrict__ F, int64_t nF, int32_t round,
+                                                    const int32_t* __restrict__ state, int32_t* __restrict__ sup) {
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t f = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); f < nF; f += stride)
+    truss_peel_one(A, erow, F, f, round, state, sup);
 }
 
 template <class T>

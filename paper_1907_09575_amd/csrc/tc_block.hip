@@ -59,32 +59,34 @@ __global__ __launch_bounds__(256) void k_gather_rows(const int64_t* __restrict__
                                                      const int64_t* __restrict__ lrow_ptr,
                                                      int32_t* __restrict__ lcol, uint32_t* __restrict__ erow) {
   const int lane = lane_id(), grp = lane >> 4, sub = lane & 15;
-  const int64_t lv0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 4;
-  if (lv0 >= nloc) return;  // (uniform per wave; no barrier follows)
-  const int64_t lv = lv0 + grp;
-  int64_t s0 = 0, len = 0, o = 0;
-  if (lv < nloc) {
-    const int64_t v = lv * q + r;
-    s0 = row_ptr[v];
-    len = row_ptr[v + 1] - s0;
-    o = lrow_ptr[lv];
-  }
-  if (len <= 64) {
-    for (int64_t i = sub; i < len; i += 16) {
-      lcol[o + i] = col[s0 + i];
-      if (erow) erow[o + i] = (uint32_t)lv;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64) * 4;  // (grid-stride over groups of 4 rows)
+  for (int64_t lv0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 4; lv0 < nloc;
+       lv0 += stride) {
+    const int64_t lv = lv0 + grp;
+    int64_t s0 = 0, len = 0, o = 0;
+    if (lv < nloc) {
+      const int64_t v = lv * q + r;
+      s0 = row_ptr[v];
+      len = row_ptr[v + 1] - s0;
+      o = lrow_ptr[lv];
     }
-  }
-  // long rows (lane 16 g stands for group g), by the whole wave
-  uint64_t longs = __ballot(len > 64 && sub == 0);
-  while (longs) {
-    const int src = __ffsll((long long)longs) - 1;
-    longs &= longs - 1;
-    const int64_t ls = shfl_i64(s0, src), ll = shfl_i64(len, src), lo = shfl_i64(o, src);
-    const uint32_t lrow = (uint32_t)(lv0 + (src >> 4));
-    for (int64_t i = lane; i < ll; i += 64) {
-      lcol[lo + i] = col[ls + i];
-      if (erow) erow[lo + i] = lrow;
+    if (len <= 64) {
+      for (int64_t i = sub; i < len; i += 16) {
+        lcol[o + i] = col[s0 + i];
+        if (erow) erow[o + i] = (uint32_t)lv;
+      }
+    }
+    // long rows (lane 16 g stands for group g), by the whole wave
+    uint64_t longs = __ballot(len > 64 && sub == 0);
+    while (longs) {
+      const int src = __ffsll((long long)longs) - 1;
+      longs &= longs - 1;
+      const int64_t ls = shfl_i64(s0, src), ll = shfl_i64(len, src), lo = shfl_i64(o, src);
+      const uint32_t lrow = (uint32_t)(lv0 + (src >> 4));
+      for (int64_t i = lane; i < ll; i += 64) {
+        lcol[lo + i] = col[ls + i];
+        if (erow) erow[lo + i] = lrow;
+      }
     }
   }
 }
@@ -149,7 +151,7 @@ void local_gather(LocalRows& L, const Graph& g, int32_t q, int32_t r, DevBuf* er
   L.col.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(L.nnz, 1));
   if (erow) erow->alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(L.nnz, 1));
   if (L.nnz > 0)
-    TC_LAUNCH("block_gather", k_gather_rows, dim3((unsigned)div_up(L.nloc, 4 * (kBT / 64))), dim3(kBT), 0, st,
+    TC_LAUNCH("block_gather", k_gather_rows, dim3(wave_grid(div_up(L.nloc, 4))), dim3(kBT), 0, st,
               g.row_ptr, g.col, L.nloc, q, r, L.row_ptr.as<int64_t>(), L.col.as<int32_t>(),
               erow ? erow->as<uint32_t>() : nullptr);
   TC_HIP(hipGetLastError());
@@ -218,17 +220,18 @@ namespace {
 __global__ __launch_bounds__(256) void k_row_shift_mask(const int64_t* __restrict__ hrow_ptr,
                                                         const int32_t* __restrict__ hcol, int64_t nloc,
                                                         int32_t q, int32_t xy, uint64_t* __restrict__ mask) {
-  const int64_t lb = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (lb >= nloc) return;
-  uint64_t mk = 0;
-  for (int64_t i = hrow_ptr[lb] + lane_id(); i < hrow_ptr[lb + 1]; i += 64) {
-    int z = (int)((uint32_t)hcol[i] % (uint32_t)q) - xy;
-    if (z < 0) z += q;
-    mk |= 1ull << z;
-  }
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t lb = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); lb < nloc; lb += stride) {
+    uint64_t mk = 0;
+    for (int64_t i = hrow_ptr[lb] + lane_id(); i < hrow_ptr[lb + 1]; i += 64) {
+      int z = (int)((uint32_t)hcol[i] % (uint32_t)q) - xy;
+      if (z < 0) z += q;
+      mk |= 1ull << z;
+    }
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) mk |= (uint64_t)__shfl_xor((unsigned long long)mk, d, 64);
-  if (lane_id() == 0) mask[lb] = mk;
+    for (int d = 32; d >= 1; d >>= 1) mk |= (uint64_t)__shfl_xor((unsigned long long)mk, d, 64);
+    if (lane_id() == 0) mask[lb] = mk;
+  }
 }
 
 // Work of the rank's tasks (tkey = local hashed row, tval = first probe | end
@@ -307,7 +310,7 @@ void block_stats(const Graph& g, int32_t q, int32_t x, int32_t y, int64_t* d_out
   if (T == 0) return;
   DevBuf hmask(sizeof(uint64_t) * (size_t)H.nloc);
   const int32_t xy = (x + y) % q;
-  TC_LAUNCH("block_row_mask", k_row_shift_mask, dim3((unsigned)div_up(H.nloc, kBT / 64)), dim3(kBT), 0, st,
+  TC_LAUNCH("block_row_mask", k_row_shift_mask, dim3(wave_grid(H.nloc)), dim3(kBT), 0, st,
             H.row_ptr.as<int64_t>(), H.col.as<int32_t>(), H.nloc, q, xy, hmask.as<uint64_t>());
   const unsigned grid = (unsigned)std::min<int64_t>(4096, div_up(T, kBT / 64));
   TC_LAUNCH("block_work", k_block_work, dim3(grid), dim3(kBT), 0, st, tk.as<uint32_t>(), tv.as<uint64_t>(), T,

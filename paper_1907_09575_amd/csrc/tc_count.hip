@@ -761,18 +761,26 @@ const char* const kLaunchNames[4][NUM_CLASSES] = {
     {"block:pack_small", "block:pack_large", "block:wg_small", "block:wg_large", "block:wg_huge",
      "block:wg_giant", "block:global"}};
 
+// Work-groups per launch of one class: a dispatch holds fewer than 2^32
+// work-items (a class of more groups, e.g. small wave items on a very large
+// graph, is launched in pieces; each group finds its data by its index).
+constexpr int64_t kClassLaunchMax = (int64_t)1 << 22;
+
 template <int MODE, int VAR>
 void launch_items_class(const WorkSet& w, const Args& A, int c, size_t mark_bytes, hipStream_t st) {
   if (w.n_items[c] == 0) return;
-  const unsigned grid = (unsigned)(w.n_items[c] / class_waves(c));
+  const int64_t groups = w.n_items[c] / class_waves(c);
   const bool global = c == CLS_GLOBAL;
   const void* f = global ? items_kernel<MODE, true, VAR>(c) : items_kernel<MODE, false, VAR>(c);
   const size_t lds = global ? mark_bytes : items_lds_bytes(w.cls_log2S[c], MODE);
   if (lds > 65536) TC_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const CountItem* items = w.items[c];
-  void* kargs[] = {const_cast<Args*>(&A), &items};
   LaunchScope ls(kLaunchNames[MODE][c], st);
-  TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(64 * class_waves(c)), kargs, lds, st));
+  for (int64_t g0 = 0; g0 < groups; g0 += kClassLaunchMax) {
+    const unsigned grid = (unsigned)std::min<int64_t>(kClassLaunchMax, groups - g0);
+    const CountItem* items = w.items[c] + g0 * class_waves(c);
+    void* kargs[] = {const_cast<Args*>(&A), &items};
+    TC_HIP(hipLaunchKernel(f, dim3(grid), dim3(64 * class_waves(c)), kargs, lds, st));
+  }
 }
 
 // The light classes (packs, wg_small: small tables, few probes per row) run
@@ -840,8 +848,10 @@ void launch_mode(const WorkSet& w, const Args& A, hipStream_t st) {
     if (lds > 65536)
       TC_HIP(hipFuncSetAttribute((const void*)k_count_packs<MODE, VAR>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, VAR>), dim3((unsigned)w.n_packs[c]), dim3(256), lds,
-              ls, A, w.pack_recs[c], w.pack_info[c], slots);
+    for (int64_t p0 = 0; p0 < w.n_packs[c]; p0 += kClassLaunchMax)  // (pieces: see kClassLaunchMax)
+      TC_LAUNCH(kLaunchNames[MODE][c], (k_count_packs<MODE, VAR>),
+                dim3((unsigned)std::min<int64_t>(kClassLaunchMax, w.n_packs[c] - p0)), dim3(256), lds, ls, A,
+                w.pack_recs[c], w.pack_info[c] + p0, slots);
   }
   launch_items_class<MODE, VAR>(w, A, CLS_WG_SMALL, mark_bytes, ls);
   if (side) {
@@ -965,7 +975,7 @@ void launch_count(const CountView& v, CountMode mode, int64_t* d_count, int32_t*
               reinterpret_cast<unsigned long long*>(d_per_shift), (int64_t)v.q);
   TC_HIP(hipGetLastError());
   if (w.n_tasks == 0) return;
-  TC_REQUIRE(v.pm <= kMaxEdges, TC_EOVERFLOW, "launch_count: probe side of 2^32 - 64 entries or more");
+  TC_REQUIRE(v.pm < kMaxEdges, TC_EOVERFLOW, "launch_count: probe side of 2^32 - 256 entries or more");
   const bool wide = v.pm > kMaxBufferEdges;
   TC_REQUIRE(!wide || mode != MODE_BLOCK, TC_EOVERFLOW, "launch_count: a rank's probe side of 2^30 entries or more");
   Args A{v.hrow_ptr, v.hcol, v.pcol, w.tstart, w.tprefix, w.tbeg, w.tend, w.n_tasks, (uint32_t)v.pm,

@@ -101,7 +101,9 @@ constexpr uint32_t kPackSlotsMin = 1024, kPackSlotsMax = 16384;
 constexpr uint32_t kMinGroupsMax = 1u << 22;
 constexpr int kPackRows = 256;          // rows per pack at most (one per thread)
 constexpr int kBucket = 4;              // slots per hash bucket (one 16-byte LDS read)
-constexpr int64_t kMaxEdges = (1ll << 32) - 64;        // U positions are 32-bit
+// U positions are 32-bit, and an elementwise launch over U's entries (rounded
+// up to 256 threads) must stay below 2^32 work-items: fewer than kMaxEdges.
+constexpr int64_t kMaxEdges = (1ll << 32) - 256;
 constexpr int64_t kMaxBufferEdges = (1ll << 30) - 64;  // below: probe reads by 32-bit byte offsets
 
 // Waves sharing one table in a work-group of item class c: the classes whose

@@ -903,7 +903,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
     TC_HIP(hipMemcpyAsync(&h_m, d_m, sizeof(h_m), hipMemcpyDeviceToHost, st));
     TC_HIP(hipStreamSynchronize(st));
     TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
-    TC_REQUIRE(h_m <= (unsigned long long)kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 64 or more edges");
+    TC_REQUIRE(h_m < (unsigned long long)kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 256 or more edges");
     m = (int64_t)h_m;
   }
   g->m = m;
@@ -1137,8 +1137,8 @@ Graph* build_variant(const Graph& base, int flags, const WorkParams& wp, hipStre
   TaskLists tl;
   if (m > 0) {
     DevBuf erow(sizeof(uint32_t) * (size_t)m);
-    TC_LAUNCH("entry_rows", k_entry_rows, dim3((unsigned)std::max<int64_t>(1, div_up(n, kT / 64))), dim3(kT), 0,
-              st, g->row_ptr, n, erow.as<uint32_t>());
+    TC_LAUNCH("entry_rows", k_entry_rows, dim3(wave_grid(n)), dim3(kT), 0, st, g->row_ptr, n,
+              erow.as<uint32_t>());
     DevBuf tk, tv;
     VariantTaskPred vp{g->row_ptr, g->col, erow.as<uint32_t>(), ijk, no_dcsr, nullptr, nullptr};
     const int64_t T = compact("variant_tasks", m, vp, [&](int64_t total, VariantTaskPred& pr) {

@@ -833,14 +833,24 @@ __global__ void k_bounds(const K* __restrict__ keys, int64_t m, int s, int64_t n
   row_ptr[r] = lo;
 }
 
+// Work-groups of a 256-thread launch that gives one wave to each of `items`
+// items: at most kWaveGridMax, the kernel striding over the rest (one
+// dispatch holds fewer than 2^32 work-items: a wave per row of a 2^26-vertex
+// graph would be exactly 2^32).
+constexpr int64_t kWaveGridMax = (int64_t)1 << 20;
+inline unsigned wave_grid(int64_t items) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kWaveGridMax, div_up(items, 4)));
+}
+
 // Row of every entry of a CSR: erow[i] = r for row_ptr[r] <= i < row_ptr[r + 1]
-// (one wave per row, coalesced writes; grid: div_up(nrows, 4) x 256).
+// (one wave per row, coalesced writes; grid: wave_grid(nrows) x 256).
 static __global__ __launch_bounds__(256) void k_entry_rows(const int64_t* __restrict__ row_ptr, int64_t nrows,
                                                            uint32_t* __restrict__ erow) {
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (r >= nrows) return;
-  const int64_t s = row_ptr[r], e = row_ptr[r + 1];
-  for (int64_t i = s + (threadIdx.x & 63); i < e; i += 64) erow[i] = (uint32_t)r;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); r < nrows; r += stride) {
+    const int64_t s = row_ptr[r], e = row_ptr[r + 1];
+    for (int64_t i = s + (threadIdx.x & 63); i < e; i += 64) erow[i] = (uint32_t)r;
+  }
 }
 
 // Tasks in hashed-row order (the input of build_work).
