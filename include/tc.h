@@ -436,8 +436,11 @@ typedef struct {
  * host's threads, 1 .. 8), "lds_cap_log2" and "blocks_per_cu" (the batch
  * schedule of every tick), "lpt" (1: a tick's units largest first, which
  * costs a sort and a synchronisation of the tick stream; default 0: request
- * order). A tick takes the ready requests whose share of its batch plans
- * (kernel arguments and work units) still fits the budget, at least one. */
+ * order), "ticks" (ticks in flight, 1 or 2; default 1; with 2, a tick of at
+ * least two ready requests is planned and launched while one runs, both on
+ * the tick stream). A tick
+ * takes the ready requests whose share of its batch plans (kernel arguments
+ * and work units) still fits the budget, at least one. */
 tc_status tc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const char* options_json,
                            tc_server** out);
 /* Queue a request; *ticket identifies it. TC_EINVAL for a malformed request. */

@@ -8,13 +8,18 @@
 //      budget, evicting unused cached graphs (least recently used) for room;
 //   2. hands graphs that are not resident to the workers (upload + the same
 //      preprocessing as tc_preprocess), several at once;
-//   3. when no tick is running, starts one over every request whose graph is
-//      ready: one batch plan and one persistent launch per operation on the
-//      tick stream, then copies the counts to pinned host memory;
-//   4. when the tick's event has completed, publishes the results (support
+//   3. when a tick slot is free (at most `ticks` ticks in flight, 1 by
+//      default), starts a tick over every request whose graph is ready: one
+//      batch plan and one persistent launch per operation on the tick
+//      stream, then copies the counts to the slot's pinned host memory;
+//   4. when a tick's event has completed, publishes its results (support
 //      arrays copied to the caller's host buffers) and releases memory.
-// Preprocessing of newly arrived requests overlaps the running tick on the
-// device; they join the next tick.
+// Preprocessing of newly arrived requests overlaps the running ticks on the
+// device; they join the next tick. With two slots, a tick of at least two
+// requests is planned and launched while the previous one runs (both on the
+// tick stream, so the device runs them one after the other without waiting
+// for the host); on the benchmark's serving mix this measured no gain (open
+// loop at 0.8 x capacity: 1529 against 1591 graphs/s), hence one by default.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,6 +103,7 @@ struct Server {
   int device = 0;
   int64_t budget = 0;
   int max_slots = 1;
+  int ticks_max = 1;  // ticks in flight (option "ticks": 1 or 2)
   int prep_threads = default_prep_threads();
   std::string tuning;  // batch schedule of every tick
 
@@ -307,6 +313,11 @@ struct Server {
     }
   }
 
+  // Tick slots (ticks in flight at most), and the ready requests a tick
+  // started beside a running one takes at least.
+  static constexpr int kTickSlots = 2;
+  static constexpr int kSecondTickMin = 2;
+
   // One tick: plans and launches over the ready requests, then (after the
   // event) results. Runs on the scheduler thread without holding the lock
   // except to read and publish request state.
@@ -315,11 +326,13 @@ struct Server {
     BatchPlan* plans[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev = nullptr;
     bool running = false;
+    int64_t* d_counts = nullptr;  // this slot's 3 * max_slots counts
+    int64_t* h_counts = nullptr;  // (pinned)
   };
 
   hipStream_t tick_stream = nullptr;
-  int64_t* d_counts = nullptr;   // 3 * max_slots
-  int64_t* h_counts = nullptr;   // pinned, 3 * max_slots
+  int64_t* d_counts = nullptr;   // kTickSlots * 3 * max_slots
+  int64_t* h_counts = nullptr;   // pinned, kTickSlots * 3 * max_slots
 
   void start_tick(Tick& tk) {
     std::vector<Req*> ready;
@@ -360,10 +373,10 @@ struct Server {
                                : op == TC_REQ_SUPPORT_FULL ? MODE_SUPPORT_FULL
                                                            : MODE_SUPPORT_ORIENTED;
         tk.plans[op] = make_plan(ents.data(), (int64_t)ents.size(), mode, tuning.c_str(), tick_stream);
-        plan_count(*tk.plans[op], d_counts + (size_t)op * max_slots, tick_stream);
+        plan_count(*tk.plans[op], tk.d_counts + (size_t)op * max_slots, tick_stream);
         units += plan_units(*tk.plans[op]);
       }
-      TC_HIP(hipMemcpyAsync(h_counts, d_counts, sizeof(int64_t) * 3 * (size_t)max_slots,
+      TC_HIP(hipMemcpyAsync(tk.h_counts, tk.d_counts, sizeof(int64_t) * 3 * (size_t)max_slots,
                             hipMemcpyDeviceToHost, tick_stream));
       TC_HIP(hipEventRecord(tk.ev, tick_stream));
       tk.running = true;
@@ -416,7 +429,7 @@ struct Server {
         tc_status s = status;
         std::string e = err;
         if (s == TC_OK) {
-          q->res.count = h_counts[(size_t)op * max_slots + i];
+          q->res.count = tk.h_counts[(size_t)op * max_slots + i];
           q->res.m = q->ce->g->m;
           if (q->copy_status != TC_OK) {  // (copy_tick_support, before the lock)
             s = q->copy_status;
@@ -438,41 +451,63 @@ struct Server {
 
   void sched_main() {
     (void)hipSetDevice(device);
-    Tick tk;
-    if (hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming) != hipSuccess) tk.ev = nullptr;
+    Tick tks[kTickSlots];
+    for (int t = 0; t < kTickSlots; ++t) {
+      if (hipEventCreateWithFlags(&tks[t].ev, hipEventDisableTiming) != hipSuccess) tks[t].ev = nullptr;
+      tks[t].d_counts = d_counts + (size_t)t * 3 * max_slots;
+      tks[t].h_counts = h_counts + (size_t)t * 3 * max_slots;
+    }
     for (;;) {
       std::vector<Graph*> to_free;
-      bool want_tick = false, exit_now = false;
+      bool exit_now = false, any_running = false;
+      int n_ready = 0;
+      for (int t = 0; t < ticks_max; ++t) any_running |= tks[t].running;
       {
         std::unique_lock<std::mutex> lk(mu);
         admit_locked(to_free);
         to_free.insert(to_free.end(), graveyard.begin(), graveyard.end());
         graveyard.clear();
-        for (Req* q : active)
-          if (q->state == Req::READY) want_tick = true;
-        exit_now = stop && active.empty() && prep_jobs.empty() && !tk.running;
-        if (!exit_now && !want_tick && !tk.running && to_free.empty())
+        for (Req* q : active) n_ready += q->state == Req::READY;
+        exit_now = stop && active.empty() && prep_jobs.empty() && !any_running;
+        if (!exit_now && n_ready == 0 && !any_running && to_free.empty())
           cv_sched.wait_for(lk, std::chrono::milliseconds(2));
       }
       for (Graph* g : to_free) destroy_graph_idle(g);  // no request and no tick uses them
       if (exit_now) break;
-      if (tk.running) {
+      // finished ticks first (in slot order; the tick stream ran them in order)
+      bool progressed = false;
+      for (int t = 0; t < ticks_max; ++t) {
+        Tick& tk = tks[t];
+        if (!tk.running) continue;
         hipError_t q = hipEventQuery(tk.ev);
         if (q == hipSuccess) {
           copy_tick_support(tk);  // (blocking copies, outside the lock)
           std::lock_guard<std::mutex> lk(mu);
           end_tick_locked(tk, TC_OK, "");
+          progressed = true;
         } else if (q != hipErrorNotReady) {
           std::lock_guard<std::mutex> lk(mu);
           end_tick_locked(tk, TC_EDEVICE, std::string("tc_server: tick: ") + hipGetErrorString(q));
-        } else {
-          std::this_thread::sleep_for(std::chrono::microseconds(50));
+          progressed = true;
         }
-        continue;
       }
-      if (want_tick) start_tick(tk);
+      // a tick when requests are ready and a slot is free; beside a running
+      // tick only for at least kSecondTickMin ready requests (a lone request
+      // waits to share the next tick, which keeps ticks batched)
+      int running = 0;
+      for (int t = 0; t < ticks_max; ++t) running += tks[t].running;
+      if (n_ready > 0 && (running == 0 || n_ready >= kSecondTickMin)) {
+        for (int t = 0; t < ticks_max; ++t) {
+          if (tks[t].running) continue;
+          start_tick(tks[t]);
+          progressed = true;
+          break;
+        }
+      }
+      if (!progressed && any_running) std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
-    if (tk.ev) (void)hipEventDestroy(tk.ev);
+    for (int t = 0; t < kTickSlots; ++t)
+      if (tks[t].ev) (void)hipEventDestroy(tks[t].ev);
   }
 };
 
@@ -504,7 +539,7 @@ tc_status server_guard(F&& f) {
 }
 
 // options: flat JSON with integer values only
-void parse_options(const char* js, int& prep_threads, std::string& tuning) {
+void parse_options(const char* js, int& prep_threads, int& ticks, std::string& tuning) {
   // tick plans: plain launches (a new plan every tick), units in request
   // order unless "lpt": 1 (the LPT sort synchronises the tick stream)
   tuning = "{\"graph\": 0";
@@ -538,6 +573,10 @@ void parse_options(const char* js, int& prep_threads, std::string& tuning) {
     TC_REQUIRE(v >= 0 && v <= 64, TC_EINVAL, "tc_server options: blocks_per_cu outside [0, 64]");
     tuning += ", \"blocks_per_cu\": " + std::to_string(v);
   }
+  if (get("ticks", v)) {
+    TC_REQUIRE(v >= 1 && v <= 2, TC_EINVAL, "tc_server options: ticks outside [1, 2]");
+    ticks = v;
+  }
   int lpt = 0;
   get("lpt", lpt);
   tuning += lpt ? ", \"order\": \"lpt\"}" : ", \"order\": \"input\"}";
@@ -557,12 +596,12 @@ tc_status tc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const ch
     std::unique_ptr<tc::Server> s(new tc::Server());
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
-    parse_options(options_json, s->prep_threads, s->tuning);
+    parse_options(options_json, s->prep_threads, s->ticks_max, s->tuning);
     TC_HIP(hipGetDevice(&s->device));
     TC_HIP(hipStreamCreateWithFlags(&s->tick_stream, hipStreamNonBlocking));
-    TC_HIP(hipMalloc(&s->d_counts, sizeof(int64_t) * 3 * (size_t)max_slots));
-    TC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_counts), sizeof(int64_t) * 3 * (size_t)max_slots,
-                         hipHostMallocDefault));
+    const size_t nc = (size_t)tc::Server::kTickSlots * 3 * (size_t)max_slots;  // counts of every tick slot
+    TC_HIP(hipMalloc(&s->d_counts, sizeof(int64_t) * nc));
+    TC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->h_counts), sizeof(int64_t) * nc, hipHostMallocDefault));
     tc::Server* sp = s.get();
     for (int i = 0; i < s->prep_threads; ++i) s->workers.emplace_back([sp] { sp->worker_main(); });
     s->sched = std::thread([sp] { sp->sched_main(); });
@@ -658,12 +697,12 @@ tc_status tc_server_stats(tc_server* srv, char* out, size_t cap) {
                   "\"cache_hits\": %lld, \"evicted\": %lld, \"cached_graphs\": %lld, \"resident_bytes\": %zu, "
                   "\"reserved_bytes\": %zu, \"peak_reserved_bytes\": %zu, \"budget_bytes\": %lld, "
                   "\"ticks\": %lld, \"tick_requests\": %lld, \"max_tick_requests\": %lld, \"tick_units\": %lld, "
-                  "\"pending\": %zu, \"active\": %zu, \"prep_threads\": %d, \"max_slots\": %d}",
+                  "\"pending\": %zu, \"active\": %zu, \"prep_threads\": %d, \"max_slots\": %d, \"tick_slots\": %d}",
                   (long long)s.n_submitted, (long long)s.n_done, (long long)s.n_failed, (long long)s.n_canceled,
                   (long long)s.n_hits, (long long)s.n_evicted, (long long)cached, resident, s.reserved,
                   s.peak_reserved, (long long)s.budget, (long long)s.n_ticks, (long long)s.tick_requests,
                   (long long)s.max_tick_requests, (long long)s.tick_units, s.pending.size(), s.active.size(),
-                  s.prep_threads, s.max_slots);
+                  s.prep_threads, s.max_slots, s.ticks_max);
     TC_REQUIRE(cap > std::strlen(buf), TC_EINVAL, "tc_server_stats: buffer too small");
     std::memcpy(out, buf, std::strlen(buf) + 1);
   });

@@ -184,6 +184,22 @@ def test_server_cancel_and_shutdown(tc):
     srv.close()
 
 
+def test_server_one_and_two_ticks_in_flight_agree(tc, trace):
+    reqs, graphs = trace
+    res = {}
+    for ticks in (1, 2):
+        with tc.Server(64 * GiB, max_slots=32, options={"ticks": ticks}) as srv:
+            res[ticks] = run_trace(tc, srv, reqs, graphs, paced=False)
+            st = srv.stats()
+        print(ticks, st, flush=True)
+        assert st["tick_slots"] == ticks and st["done"] == len(reqs) and st["failed"] == 0
+    for r, a, b in zip(reqs, res[1], res[2]):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["count"] == b["count"] and a["m"] == b["m"], r
+        if r.op != "count":
+            assert np.array_equal(a["support"], b["support"]), r
+
+
 def test_server_rejects_bad_requests(tc):
     with tc.Server(GiB, max_slots=2) as srv:
         with pytest.raises(tc.TCError):
@@ -196,3 +212,5 @@ def test_server_rejects_bad_requests(tc):
         tc.Server(0, max_slots=2)
     with pytest.raises(tc.TCError):
         tc.Server(GiB, max_slots=2, options={"prep_threads": 99})
+    with pytest.raises(tc.TCError):
+        tc.Server(GiB, max_slots=2, options={"ticks": 3})
