@@ -58,7 +58,7 @@ struct CanonSrc {
     const int64_t u = src[i], v = dst[i];
     bad = (u < 0) | (u >= n) | (v < 0) | (v >= n);
     const uint64_t lo = (uint64_t)(u < v ? u : v), hi = (uint64_t)(u < v ? v : u);
-    return bad | (u == v) ? sent : (lo << s) | hi;
+    return (bad | (u == v)) ? sent : ((lo << s) | hi);
   }
   __device__ bool operator()(int64_t i, uint64_t& k, char&) const {
     bool bad;
@@ -154,12 +154,13 @@ __global__ __launch_bounds__(256) void k_distinct_mark(uint64_t* __restrict__ S,
 #pragma unroll
     for (int j = 0; j < kDigitBatch; ++j) {
       const int64_t i = base + (int64_t)j * 256;
-      if (i >= m_raw) break;
-      if (k[j] != sent && (i == 0 || (prev[j] & ~kDupMark) != k[j])) {
-        dc.add((uint32_t)(k[j] & mask));
-        ++c;
-      } else if (k[j] != sent) {
-        S[i] = k[j] | kDupMark;
+      if (i < m_raw && k[j] != sent) {
+        if (i == 0 || (prev[j] & ~kDupMark) != k[j]) {
+          dc.add((uint32_t)(k[j] & mask));
+          ++c;
+        } else {
+          S[i] = k[j] | kDupMark;
+        }
       }
     }
   }
