@@ -8,9 +8,15 @@
 // are rounded up to 2 MiB above 1 MiB, to powers of two below). When a block
 // is freed, an event is recorded on the stream of its last use; reusing it on
 // another stream first makes that stream wait for the event, on the same
-// stream ordering is implicit. Cached free bytes are bounded (a quarter of
-// the device's memory by default); beyond that, and whenever hipMalloc runs
-// out of memory, cached blocks are released (after their events complete).
+// stream ordering is implicit. Among the cached blocks that fit, one last
+// used on the requesting stream (or idle) is taken first: with several
+// streams allocating at once (concurrent preprocessing), taking the oldest
+// block of a size would make nearly every reuse wait for another stream's
+// work and chain the streams into one. The HIP calls of a reuse or a free
+// (event record, stream wait) run outside the cache's lock. Cached free
+// bytes are bounded (a quarter of the device's memory by default); beyond
+// that, and whenever hipMalloc runs out of memory, cached blocks are
+// released (after their events complete).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,34 +88,52 @@ void trim_locked(DeviceCache& c, size_t keep) {
 
 }  // namespace
 
+// Cached blocks of one size looked at for one last used on the requesting
+// stream before the smallest fitting one is taken.
+constexpr int kReuseScan = 32;
+
 void* cache_alloc(size_t bytes, hipStream_t st) {
   int dev = 0;
   TC_HIP(hipGetDevice(&dev));
   const size_t rb = round_size(bytes ? bytes : 1);
+  Block b;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCache& c = cache_for(dev);
-    auto it = c.free.lower_bound(rb);
-    if (it != c.free.end() && it->first <= rb + rb / 4) {
-      Block b = it->second;
-      c.free.erase(it);
-      c.cached -= b.size;
-      if (b.ev) {
-        if (b.st != st) {
-          hipError_t e = hipStreamWaitEvent(st, b.ev, 0);
-          if (e != hipSuccess) {
-            c.free.emplace(b.size, b);
-            c.cached += b.size;
-            throw Error(TC_EDEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
-          }
-        }
-        c.events.push_back(b.ev);
+    const auto lo = c.free.lower_bound(rb);
+    const auto hi = c.free.upper_bound(rb + rb / 4);
+    auto pick = lo;
+    int looked = 0;
+    for (auto it = lo; it != hi && looked < kReuseScan; ++it, ++looked) {
+      if (!it->second.ev || it->second.st == st) {
+        pick = it;
+        break;
       }
+    }
+    if (pick != hi) {
+      b = pick->second;
+      c.free.erase(pick);
+      c.cached -= b.size;
       c.live[b.p] = b.size;
       c.in_use += b.size;
       c.peak = std::max(c.peak, c.in_use);
-      return b.p;
     }
+  }
+  if (b.p) {
+    hipError_t e = hipSuccess;
+    if (b.ev && b.st != st) e = hipStreamWaitEvent(st, b.ev, 0);
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache& c = cache_for(dev);
+    if (e != hipSuccess) {
+      // back to the cache as it was
+      c.live.erase(b.p);
+      c.in_use -= b.size;
+      c.free.emplace(b.size, b);
+      c.cached += b.size;
+      throw Error(TC_EDEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
+    }
+    if (b.ev) c.events.push_back(b.ev);  // the wait (if any) is queued: the event is free again
+    return b.p;
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, rb);
@@ -136,28 +160,34 @@ void cache_free(void* p, hipStream_t st, bool idle) {
   if (!p) return;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  DeviceCache& c = cache_for(dev);
-  auto it = c.live.find(p);
-  if (it == c.live.end()) return;  // not ours
   Block b;
   b.p = p;
-  b.size = it->second;
   b.st = st;
-  c.live.erase(it);
-  c.in_use -= b.size;
-  if (!idle) {
-    if (c.events.empty()) {
-      hipEvent_t ev = nullptr;
-      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) c.events.push_back(ev);
-    }
-    if (!c.events.empty() && hipEventRecord(c.events.back(), st) == hipSuccess) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache& c = cache_for(dev);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;  // not ours
+    b.size = it->second;
+    c.live.erase(it);
+    c.in_use -= b.size;
+    if (!idle && !c.events.empty()) {
       b.ev = c.events.back();
       c.events.pop_back();
-    } else {
-      (void)hipStreamSynchronize(st);  // could not record: make the block idle
     }
   }
+  // (the block is in neither map meanwhile: nobody else can hand it out)
+  if (!idle) {
+    if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) b.ev = nullptr;
+    if (b.ev && hipEventRecord(b.ev, st) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      cache_for(dev).events.push_back(b.ev);
+      b.ev = nullptr;
+    }
+    if (!b.ev) (void)hipStreamSynchronize(st);  // could not record: make the block idle
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCache& c = cache_for(dev);
   c.free.emplace(b.size, b);
   c.cached += b.size;
   if (c.cached > c.cap) trim_locked(c, c.cap / 2);

@@ -847,11 +847,25 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   g->sbits = s;
   const uint64_t sent = (2 * s >= 64) ? ~0ull : ((1ull << (2 * s)) - 1);
 
-  DevBuf dscal(64);  // device scalars: [0] err (int), [16] wplus, [24] maxd
-  TC_HIP(hipMemsetAsync(dscal.p, 0, 64, st));
-  int* d_err = reinterpret_cast<int*>(dscal.as<char>());
-  unsigned long long* d_wplus = reinterpret_cast<unsigned long long*>(dscal.as<char>() + 16);
-  unsigned int* d_maxd = reinterpret_cast<unsigned int*>(dscal.as<char>() + 24);
+  // Everything below that starts at zero, in one buffer cleared by one
+  // memset: 64 bytes of scalars (id error (int) at 0, distinct count m
+  // (u64) at 8, W+ (u64) at 16, largest d+ (u32) at 24, task count (u32) at
+  // 28: two host reads of 16 bytes), then the digit counts of the degree
+  // partition (2 x 256), of the canonical keys, of the oriented keys and of
+  // the tasks (kSortPassesMax x 256 each).
+  constexpr size_t kHistWords = 256 * kSortPassesMax;
+  DevBuf zs(64 + sizeof(uint32_t) * (256 * 2 + 3 * kHistWords));
+  TC_HIP(hipMemsetAsync(zs.p, 0, zs.bytes, st));
+  char* const zb = zs.as<char>();
+  int* d_err = reinterpret_cast<int*>(zb);
+  unsigned long long* d_m = reinterpret_cast<unsigned long long*>(zb + 8);
+  unsigned long long* d_wplus = reinterpret_cast<unsigned long long*>(zb + 16);
+  unsigned int* d_maxd = reinterpret_cast<unsigned int*>(zb + 24);
+  uint32_t* d_T = reinterpret_cast<uint32_t*>(zb + 28);
+  uint32_t* const dh = reinterpret_cast<uint32_t*>(zb + 64);
+  uint32_t* const ch = dh + 256 * 2;
+  uint32_t* const ohist = ch + kHistWords;
+  uint32_t* const th = ohist + kHistWords;
 
   // ---- 1-2: simple graph -------------------------------------------------
   // The canonical keys are sorted (duplicates adjacent, self loops as the
@@ -870,40 +884,39 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   // the orientation's partition)
   const int hshift = s <= 8 ? 0 : s <= 24 ? s - 8 : s - 16;
   const int hpasses = digit_passes(hshift, s);
-  DevBuf dh(sizeof(uint32_t) * 256 * 2 + sizeof(unsigned long long));
-  unsigned long long* d_m = reinterpret_cast<unsigned long long*>(dh.as<uint32_t>() + 256 * 2);
-  TC_HIP(hipMemsetAsync(dh.p, 0, dh.bytes, st));
   {
     // canonical keys are built by the first pass of the dedup sort from the
     // raw pairs (7168-pair tiles: the largest whose registers allow two
     // waves per SIMD); one read of the pairs before it counts their digits
     // and checks the ids
     const CanonSrc csrc{d_src, d_dst, n, s, sent};
-    DevBuf ch(sizeof(uint32_t) * 256 * kSortPassesMax);
     if (m_raw > 0) {
-      TC_HIP(hipMemsetAsync(ch.p, 0, ch.bytes, st));
       TC_LAUNCH("canon_digits", k_canon_digits,
                 dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
-                digit_lds_bytes(0, 2 * s), st, csrc, m_raw, 2 * s, ch.as<uint32_t>(), d_err);
+                digit_lds_bytes(0, 2 * s), st, csrc, m_raw, 2 * s, ch, d_err);
       TC_HIP(hipGetLastError());
       salt = radix_sort_from<uint64_t, NoVal, CanonSrc, 28>(csrc, m_raw, ka.as<uint64_t>(), kb.as<uint64_t>(),
-                                                            nullptr, nullptr, m_raw, 0, 2 * s, ch.as<uint32_t>(),
+                                                            nullptr, nullptr, m_raw, 0, 2 * s, ch,
                                                             st, "dedup");
       // duplicates marked, distinct keys counted, with their upper
       // endpoints' partition digits
       TC_LAUNCH("distinct_mark", k_distinct_mark,
                 dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m_raw, kT * kDigitBatch))), dim3(kT),
                 digit_lds_bytes(hshift, s), st, salt ? kb.as<uint64_t>() : ka.as<uint64_t>(), sent, m_raw, hshift,
-                s, dh.as<uint32_t>(), d_m);
+                s, dh, d_m);
       TC_HIP(hipGetLastError());
     }
     // the id check and the distinct count: one host sync for both
-    int h_err = 0;
-    unsigned long long h_m = 0;
-    TC_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    TC_HIP(hipMemcpyAsync(&h_m, d_m, sizeof(h_m), hipMemcpyDeviceToHost, st));
+    struct {
+      int err;
+      int pad;
+      unsigned long long m;
+    } h;
+    static_assert(sizeof(h) == 16, "scalar layout");
+    TC_HIP(hipMemcpyAsync(&h, zb, sizeof(h), hipMemcpyDeviceToHost, st));
     TC_HIP(hipStreamSynchronize(st));
-    TC_REQUIRE(h_err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
+    const unsigned long long h_m = h.m;
+    TC_REQUIRE(h.err == 0, TC_EINVAL, "tc_preprocess: vertex id outside [0, n)");
     TC_REQUIRE(h_m < (unsigned long long)kMaxEdges, TC_EOVERFLOW, "tc_preprocess: 2^32 - 256 or more edges");
     m = (int64_t)h_m;
   }
@@ -914,7 +927,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
 
   // ---- 3: degree order ---------------------------------------------------
   g->perm = g->owned.alloc<int32_t>(n);
-  const uint32_t* hi_starts = dh.as<uint32_t>() + 256 * (hpasses - 1);  // valid once m > 0
+  const uint32_t* hi_starts = dh + 256 * (hpasses - 1);  // valid once m > 0
   {
     DevBuf ra(sizeof(uint64_t) * (size_t)n), rb(sizeof(uint64_t) * (size_t)n);
     if (m > 0) {
@@ -924,7 +937,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       DevBuf hb(sizeof(uint32_t) * (size_t)m), hb2(hpasses > 1 ? sizeof(uint32_t) * (size_t)m : 0);
       const bool halt = radix_sort_from<uint32_t, NoVal>(DistinctHiSrc{dsel, s}, m_raw, hb.as<uint32_t>(),
                                                          hb2.as<uint32_t>(), nullptr, nullptr, m, hshift, s,
-                                                         dh.as<uint32_t>(), st, "degree");
+                                                         dh, st, "degree");
       const uint32_t* hsorted = halt ? hb2.as<uint32_t>() : hb.as<uint32_t>();
       const int64_t span = (int64_t)1 << hshift;  // vertices per bucket
       const int sub = (int)div_up(span, kDegBins);
@@ -945,7 +958,7 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       // bucket starts: with one digit pass, its digit starts as the sort
       // scanned them (256 exclusive starts); else found by binary search
       DevBuf bp;
-      const uint32_t* bs32 = dh.as<uint32_t>();
+      const uint32_t* bs32 = dh;
       int64_t nbs = 256;
       if (hpasses != 1) {
         bp.alloc(sizeof(int64_t) * (size_t)(nbuckets + 1));
@@ -977,8 +990,6 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   const uint64_t* okey = obuf.as<uint64_t>();
   {
     if (m > 0) {
-      DevBuf ohist(sizeof(uint32_t) * 256 * kSortPassesMax);  // digit counts, from the orientation
-      TC_HIP(hipMemsetAsync(ohist.p, 0, ohist.bytes, st));
       // partition by the top 8 bits of hi (one pass from S into the free
       // buffer), then the oriented keys in place
       // (28 edges per thread, as the canonicalising pass: a source that
@@ -989,13 +1000,13 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       TC_REQUIRE(!palt, TC_EDEVICE, "tc_preprocess: the orientation partition is one pass");
       const int64_t og = std::min<int64_t>(kProducerBlocks, div_up(m, kT * 2 * kEw));
       TC_LAUNCH("orient", k_orient_hi, dim3((unsigned)(div_up(og, 8) * 8)), dim3(kT), digit_lds_bytes(0, 2 * s),
-                st, obuf.as<uint64_t>(), m, s, g->perm, ohist.as<uint32_t>());
+                st, obuf.as<uint64_t>(), m, s, g->perm, ohist);
       TC_HIP(hipGetLastError());
       // S's buffer is the ping-pong partner (S is not read after the
       // partition); the last pass also writes each key's column: U's col
       bool alt = radix_sort<uint64_t, NoVal, ColEpi>(obuf.as<uint64_t>(), sbuf.as<uint64_t>(), nullptr, nullptr,
                                                      m, 0, 2 * s, st, "orient", ColEpi{g->col, s},
-                                                     ohist.as<uint32_t>());
+                                                     ohist);
       if (alt) okey = sbuf.as<uint64_t>();
       TC_LAUNCH("bounds", (k_bounds<uint64_t>), dim3(grid_for(n + 1)), dim3(kT), 0, st, okey, m, s, n,
                          g->row_ptr);
@@ -1009,14 +1020,10 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
               d_maxd);
     TC_HIP(hipGetLastError());
   }
-  dh.release();
   // the buffer that does not hold the oriented keys is free now
   (okey == sbuf.as<uint64_t>() ? obuf : sbuf).release();
-  // read back with the task count below (one host sync)
-  unsigned long long h_wplus = 0;
-  unsigned int h_maxd = 0;
-  TC_HIP(hipMemcpyAsync(&h_wplus, d_wplus, sizeof(h_wplus), hipMemcpyDeviceToHost, st));
-  TC_HIP(hipMemcpyAsync(&h_maxd, d_maxd, sizeof(h_maxd), hipMemcpyDeviceToHost, st));
+  // (W+ and the largest d+ are read back with the task count below: one
+  // host sync)
 
   // ---- 5: tasks grouped by hashed row b -----------------------------------
   // one read of U counts the tasks and their key digits; the first pass of
@@ -1024,25 +1031,27 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
   // is written in U order)
   TaskLists tl;
   {
-    uint32_t h_T = 0;
-    DevBuf ne, th;
+    DevBuf ne;
     TaskSrc src{};
     if (m > 0) {
       ne.alloc(sizeof(uint64_t) * (size_t)div_up(n, 64));
       TC_LAUNCH("nonempty_bits", k_nonempty_bits, dim3(grid_for(n)), dim3(kT), 0, st, g->row_ptr, n,
                 ne.as<uint64_t>());
       src.p = TaskPred{okey, s, g->row_ptr, ne.as<uint64_t>(), nullptr, nullptr};
-      th.alloc(sizeof(uint32_t) * (256 * kSortPassesMax + 1));  // digit counts, then the task count
-      TC_HIP(hipMemsetAsync(th.p, 0, th.bytes, st));
-      uint32_t* d_T = th.as<uint32_t>() + 256 * kSortPassesMax;
       TC_LAUNCH("task_digits", k_task_digits,
                 dim3((unsigned)std::min<int64_t>(kProducerBlocks, div_up(m, kT * kDigitBatch))), dim3(kT),
-                digit_lds_bytes(0, s), st, src, m, s, th.as<uint32_t>(), d_T);
+                digit_lds_bytes(0, s), st, src, m, s, th, d_T);
       TC_HIP(hipGetLastError());
-      TC_HIP(hipMemcpyAsync(&h_T, d_T, sizeof(h_T), hipMemcpyDeviceToHost, st));
     }
+    struct {
+      unsigned long long wplus;
+      unsigned int maxd;
+      uint32_t T;
+    } h;
+    static_assert(sizeof(h) == 16, "scalar layout");
+    TC_HIP(hipMemcpyAsync(&h, zb + 16, sizeof(h), hipMemcpyDeviceToHost, st));
     TC_HIP(hipStreamSynchronize(st));  // the task count, W+ and the largest d+
-    const int64_t T = h_T;
+    const int64_t T = h.T;
     tl.T = T;
     tl.ptr.alloc(sizeof(int64_t) * (size_t)(n + 1));
     if (T > 0) {
@@ -1051,15 +1060,15 @@ Graph* build_graph(const int32_t* d_src, const int32_t* d_dst, int64_t m_raw, in
       DevBuf tk(sizeof(uint32_t) * (size_t)T), tv(sizeof(uint64_t) * (size_t)T);
       const bool alt = radix_sort_from<uint32_t, uint64_t>(src, m, tl.row.as<uint32_t>(), tk.as<uint32_t>(),
                                                            tl.val.as<uint64_t>(), tv.as<uint64_t>(), T, 0, s,
-                                                           th.as<uint32_t>(), st, "tasks");
+                                                           th, st, "tasks");
       if (alt) {
         tl.row.swap(tk);
         tl.val.swap(tv);
       }
     }
     finish_tasks(tl, n, st);
-    g->wedges_plus = (int64_t)h_wplus;
-    g->max_dplus = (int64_t)h_maxd;
+    g->wedges_plus = (int64_t)h.wplus;
+    g->max_dplus = (int64_t)h.maxd;
   }
   ka.release();
   kb.release();
@@ -1236,10 +1245,15 @@ void build_work(WorkSet& w, Owned& own, int64_t n, const int64_t* hrow_ptr, int6
   TC_LAUNCH("classify", k_classify, dim3(grid_reduce(n)), dim3(kT), 0, st, tb_ptr, tb_prefix, hrow_ptr, n,
             all_rows, wp.heavy_min, cls.as<int8_t>(), d_cl, d_cw);
   TC_HIP(hipGetLastError());
-  int h_cl[NUM_CLASSES];
-  unsigned long long h_cw[NUM_CLASSES];
-  TC_HIP(hipMemcpyAsync(h_cl, d_cl, sizeof(h_cl), hipMemcpyDeviceToHost, st));
-  TC_HIP(hipMemcpyAsync(h_cw, d_cw, sizeof(h_cw), hipMemcpyDeviceToHost, st));
+  struct {
+    unsigned long long cw[NUM_CLASSES];
+    int cl[NUM_CLASSES];
+  } hc;
+  static_assert(sizeof(hc.cw) + sizeof(hc.cl) == sizeof(unsigned long long) * NUM_CLASSES + sizeof(int) * NUM_CLASSES,
+                "class scalars layout");
+  TC_HIP(hipMemcpyAsync(&hc, clsl.p, sizeof(hc.cw) + sizeof(hc.cl), hipMemcpyDeviceToHost, st));
+  const unsigned long long* h_cw = hc.cw;
+  const int* h_cl = hc.cl;
 
   // class-major row order: the rows of class 0 (ascending b), then class 1,
   // ...; each row keeps its tasks in b order, so every class - and every pack

@@ -164,6 +164,50 @@ __global__ __launch_bounds__(256) void k_scan_final(L load, int64_t n, const Tou
   }
 }
 
+// Exclusive scan of at most kScanSmallTiles tiles by one work-group: the
+// tiles of k_scan_final in order, each with the running total of the ones
+// before it as its carry-in; writes the grand total too. One launch instead
+// of three for the short arrays (tile counts, per-class rows, the vertices
+// of a small graph) that most scans of a small graph's preprocessing cover.
+constexpr int kScanSmallTiles = 4;
+
+template <class L, class Tout>
+__global__ __launch_bounds__(256) void k_scan_small(L load, int64_t n, Tout* __restrict__ out,
+                                                    Tout* __restrict__ total) {
+  __shared__ Tout s_w[kScanItems][4];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  Tout off = 0;  // the same in every thread
+  for (int64_t base = 0; base < n; base += kScanTile) {
+    Tout v[kScanItems], inc[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + (int64_t)i * kPrimThreads + threadIdx.x;
+      v[i] = idx < n ? load(idx) : Tout(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      inc[i] = wave_incl_scan(v[i]);
+      if (lane == 63) s_w[i][wave] = inc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      Tout before = 0, row = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const Tout x = s_w[i][w];
+        if (w < wave) before += x;
+        row += x;
+      }
+      const int64_t idx = base + (int64_t)i * kPrimThreads + threadIdx.x;
+      if (idx < n) out[idx] = off + before + inc[i] - v[i];
+      off += row;
+    }
+    __syncthreads();  // s_w is written again by the next tile
+  }
+  if (total && threadIdx.x == 0) *total = off;
+}
+
 // Stream that preprocessing temporaries are ordered on (set by TempStream).
 // DevBuf allocates from the caching allocator on it and returns blocks to
 // the cache with an event recorded on it, so freeing a temporary needs no
@@ -235,6 +279,11 @@ void device_excl_scan_f(L load, Tout* out, int64_t n, Tout* total, hipStream_t s
     return;
   }
   int64_t nb = div_up(n, kScanTile);
+  if (nb <= kScanSmallTiles) {
+    TC_LAUNCH("scan_small", (k_scan_small<L, Tout>), dim3(1), dim3(256), 0, st, load, n, out, total);
+    TC_HIP(hipGetLastError());
+    return;
+  }
   DevBuf part(sizeof(Tout) * (size_t)nb);
   TC_LAUNCH("scan_reduce", (k_scan_reduce<L, Tout>), dim3((unsigned)nb), dim3(256), 0, st, load, n,
             part.as<Tout>());
@@ -374,6 +423,9 @@ struct NoEpi {
 };
 
 constexpr int kSortPassesMax = 8;
+// Look-back words of all passes of a sort up to this size are cleared by
+// one memset (see radix_sort_cfg).
+constexpr size_t kLbClearOnceBytes = (size_t)4 << 20;
 constexpr uint32_t kLbSpinMax = 1u << 16;
 constexpr int kLbWin = 4;  // predecessors read per look-back step
 
@@ -712,16 +764,23 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
   const int64_t ntiles_in = src ? div_up(n_in, 256 * KPT_SRC) : ntiles;  // (the source pass: KPT_SRC per thread)
   int* fail = temp_ctx().fail;
   TC_REQUIRE(fail != nullptr, TC_EDEVICE, "radix_sort: called outside a TempStream scope");
-  // per pass: ticket counter (padded to 256 bytes) + tiles * 256 look-back words
+  // per pass: ticket counter (padded to 256 bytes) + tiles * 256 look-back
+  // words. Up to kLbClearOnceBytes for all passes, each pass has a region of
+  // its own and one memset clears them all (with the digit counts when the
+  // sort counts them itself); else the passes share one region, cleared
+  // before each pass.
   const int64_t pad = 256 / (int64_t)sizeof(W);
   const int64_t pass_words = pad + std::max(ntiles, ntiles_in) * 256;
-  DevBuf own_hist;
-  DevBuf lb(sizeof(W) * (size_t)pass_words);
+  const size_t region = sizeof(W) * (size_t)pass_words;
+  const bool clear_once = (size_t)passes * region <= kLbClearOnceBytes;
+  const size_t hist_bytes = hist ? 0 : sizeof(uint32_t) * 256 * kSortPassesMax;
+  DevBuf work(hist_bytes + (clear_once ? (size_t)passes : 1) * region);
+  char* lb0 = work.as<char>() + hist_bytes;
+  if (clear_once) TC_HIP(hipMemsetAsync(work.p, 0, work.bytes, st));
   uint32_t* gh = hist;
   if (!gh) {
-    own_hist.alloc(sizeof(uint32_t) * 256 * kSortPassesMax);
-    gh = own_hist.as<uint32_t>();
-    TC_HIP(hipMemsetAsync(gh, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
+    gh = work.as<uint32_t>();
+    if (!clear_once) TC_HIP(hipMemsetAsync(gh, 0, sizeof(uint32_t) * 256 * (size_t)passes, st));
     const unsigned dgrid = (unsigned)std::min<int64_t>(2048, div_up(n, 256 * 16));
     TC_LAUNCH(n_digits, (k_rs_digits<K>), dim3(dgrid), dim3(256), digit_lds_bytes(bit_lo, bit_hi), st, keys,
               n, bit_lo, bit_hi, gh);
@@ -737,8 +796,8 @@ bool radix_sort_cfg(K* keys, K* keys_alt, V* vals, V* vals_alt, int64_t n, int b
     const int bits = bit_hi - shift < 8 ? bit_hi - shift : 8;
     const uint32_t dmask = (1u << bits) - 1u;
     const bool last = p + 1 == passes;
-    TC_HIP(hipMemsetAsync(lb.p, 0, sizeof(W) * (size_t)pass_words, st));
-    W* words = lb.as<W>();
+    if (!clear_once) TC_HIP(hipMemsetAsync(lb0, 0, region, st));
+    W* words = reinterpret_cast<W*>(lb0 + (clear_once ? (size_t)p * region : 0));
     uint32_t* ticket = reinterpret_cast<uint32_t*>(words);
     if (p == 0 && src) {  // from the source into keys/vals
       if (last)

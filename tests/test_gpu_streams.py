@@ -7,7 +7,10 @@ own launches. Here a graph built on one stream is counted repeatedly on a
 second stream, freed at once, and its memory is immediately taken again by
 preprocessing on the first stream; the counts on the second stream must
 still be the oracle's T. The count's side stream (its light classes run
-beside the heavy ones) is also captured into HIP graphs with it."""
+beside the heavy ones) is also captured into HIP graphs with it. Threads
+that preprocess, count and free at once, each on its own stream, take one
+another's freed blocks from the cache (a reuse on another stream waits for
+that stream's work): their counts must all be the oracle's."""
 import numpy as np
 import pytest
 
@@ -54,6 +57,45 @@ def test_free_waits_for_the_streams_that_used_the_graph(tc):
     sa.synchronize()  # (the count runs on sa; .item() reads on the current stream)
     assert int(c.item()) == T
     g.free()
+
+
+def test_threads_preprocessing_on_their_own_streams(tc):
+    import threading
+    scales = [10 + k % 4 for k in range(12)]
+    lists = [graphgen.rmat(sc, seed=20 + k) for k, sc in enumerate(scales)]
+    want = [oracle.count(oracle.preprocess(s, d, 1 << sc)) for (s, d), sc in zip(lists, scales)]
+    dev = [(torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), 1 << sc) for (s, d), sc in zip(lists, scales)]
+    torch.cuda.synchronize()
+    nthreads, reps = 4, 3
+    got = [[] for _ in range(nthreads)]
+    errors = []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            order = [(k + j) % len(dev) for j in range(len(dev))]
+            for _ in range(reps):
+                for i in order:
+                    s, d, n = dev[i]
+                    g = tc.tc_preprocess(s, d, n, stream=st)
+                    c = tc.tc_count(g, stream=st)
+                    g.free()  # no host wait: another thread may take its blocks
+                    st.synchronize()
+                    got[k].append((i, int(c.item())))
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    print("%d threads x %d graphs x %d rounds" % (nthreads, len(dev), reps), flush=True)
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(nthreads)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for k in range(nthreads):
+        assert len(got[k]) == reps * len(dev)
+        for i, c in got[k]:
+            assert c == want[i], (k, i, c, want[i])
 
 
 def test_plan_free_waits_for_its_launches(tc):
