@@ -69,7 +69,8 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
 // ---------------------------------------------------------------------------
 // Exclusive scan of a device array: out[i] = sum_{j<i} in[j]; optionally
 // *total = sum of all. Three kernels: tile reduce, scan of tile sums (one
-// block), tile scan with carry-in.
+// block), tile scan with carry-in; one (k_scan_small) for at most
+// kScanSmallTiles tiles.
 // ---------------------------------------------------------------------------
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kPrimThreads * kScanItems;
